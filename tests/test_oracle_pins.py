@@ -1,0 +1,493 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself.
+
+Each test checks the oracle against a closed form, a textbook identity, a
+library routine on an independently assembled operator, or a published
+test vector, so that a dropped term, a sign or index slip, or a transposed
+operand in ``oracle/les_oracle.cpp`` fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import FREESLIP, INFLOW, NOSLIP, OUTFLOW, URBAN_BC
+
+ALL_WALLS = (FREESLIP, FREESLIP, FREESLIP, FREESLIP, FREESLIP, FREESLIP)
+
+
+def make(nx, ny, nz, dx=4.0, dy=4.0, dz=2.0, dt=0.05, mask=None, **kw):
+    return oracle.Oracle(nx, ny, nz, dx, dy, dz, dt, mask, **kw)
+
+
+def zeros_faces(o):
+    su, sv, sw, _ = o.shapes
+    return np.zeros(su), np.zeros(sv), np.zeros(sw)
+
+
+def assemble_DG(o):
+    """Matrix of div(grad p) built from the oracle's projection and divergence."""
+    n = o.nx * o.ny * o.nz
+    M = np.zeros((n, n))
+    zu, zv, zw = zeros_faces(o)
+    for c in range(n):
+        p = np.zeros(n)
+        p[c] = 1.0
+        u, v, w = o.project(zu, zv, zw, p.reshape(o.shapes[3]))   # u = -dt G p
+        M[:, c] = -o.divergence(u, v, w).ravel() / o.dt
+    return M
+
+
+def assemble_A(o):
+    """Matrix of the SOR operator (neighbour weights minus diagonal)."""
+    n = o.nx * o.ny * o.nz
+    M = np.zeros((n, n))
+    for c in range(n):
+        p = np.zeros(n)
+        p[c] = 1.0
+        M[:, c] = o.apply_A(p.reshape(o.shapes[3])).ravel()
+    return M
+
+
+def eig1d(n, h, dirichlet_high):
+    """Closed-form eigenvalues of the 1-D cell-centred second difference.
+
+    Neumann at both ends: -(4/h^2) sin^2(pi m / (2n)), m = 0..n-1.
+    Neumann low / Dirichlet-on-the-face high: -(4/h^2) sin^2(pi (2m+1) / (4n)).
+    """
+    m = np.arange(n)
+    if dirichlet_high:
+        return -(4.0 / h**2) * np.sin(np.pi * (2 * m + 1) / (4 * n)) ** 2
+    return -(4.0 / h**2) * np.sin(np.pi * m / (2 * n)) ** 2
+
+
+# ---------------------------------------------------------------- P2, P2b
+@pytest.mark.parametrize("bc", [URBAN_BC, ALL_WALLS])
+@pytest.mark.parametrize("shape", [(6, 5, 4), (5, 4, 3)])
+def test_operator_is_div_grad(bc, shape):
+    """P2: the SOR operator equals D G assembled from projection + divergence."""
+    o = make(*shape, dx=1.5, dy=2.0, dz=0.7, bc=bc)
+    DG = assemble_DG(o)
+    A = assemble_A(o)
+    scale = np.abs(A).max()
+    assert np.abs(DG - A).max() <= 1e-14 * scale * 10
+    assert np.allclose(A, A.T, atol=1e-14 * scale)
+
+
+@pytest.mark.parametrize("bc", [URBAN_BC, ALL_WALLS])
+def test_operator_spectrum_closed_form(bc):
+    """P2b: eigenvalues of A are sums of the closed-form 1-D eigenvalues."""
+    nx, ny, nz, dx, dy, dz = 7, 5, 4, 1.3, 0.9, 0.6
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, bc=bc)
+    A = assemble_A(o)
+    ev = np.sort(np.linalg.eigvalsh(A))
+    ex = eig1d(nx, dx, bc[1] == OUTFLOW)
+    ey = eig1d(ny, dy, False)
+    ez = eig1d(nz, dz, False)
+    want = np.sort((ez[:, None, None] + ey[None, :, None] + ex[None, None, :]).ravel())
+    assert np.allclose(ev, want, rtol=1e-12, atol=1e-12 * abs(want).max())
+
+
+# -------------------------------------------------------------------- P1
+@pytest.mark.parametrize("shape", [(6, 5, 4), (8, 6, 4), (12, 8, 6)])
+@pytest.mark.parametrize("bc", [URBAN_BC, ALL_WALLS])
+def test_sor_matches_dense_solve(shape, bc):
+    """P1: SOR to 1e-13 equals a dense LAPACK solve of the assembled D G."""
+    o = make(*shape, dx=2.0, dy=2.0, dz=1.0, bc=bc)
+    rng = np.random.default_rng(7)
+    rhs = rng.standard_normal(o.shapes[3])
+    DG = assemble_DG(o)
+    if bc[1] == OUTFLOW:
+        want = np.linalg.solve(DG, rhs.ravel())
+        r = rhs
+    else:
+        r = rhs - rhs.mean()
+        want = np.linalg.lstsq(DG, r.ravel(), rcond=None)[0]
+        want -= want.mean()
+    p, st, rc = o.pressure_solve(rhs, tol=1e-13, max_iter=200000)
+    assert rc == 0 and st["converged"] == 1
+    got = p.ravel()
+    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+
+
+# -------------------------------------------------------------------- P3
+def test_sor_colour_order_delta():
+    """P3: one iteration from p = 0 with a point source has a closed form.
+
+    Colour 0 (0-based i+j+k even) is updated first, so the source cell gets
+    -omega/d and its six neighbours (colour 1) then see it:
+    -omega^2 c_nb / (d d_nb).  Cells two steps away stay 0.
+    """
+    nx, ny, nz, dx, dy, dz = 8, 8, 8, 1.0, 2.0, 0.5
+    om = 1.8
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, omega=om)
+    cx, cy, cz = 1 / dx**2, 1 / dy**2, 1 / dz**2
+    d = 2 * (cx + cy + cz)
+    rhs = np.zeros(o.shapes[3])
+    k0, j0, i0 = 4, 3, 3          # 0-based sum 10: colour 0
+    rhs[k0, j0, i0] = 1.0
+    p, s = o.sor_iterations(rhs, np.zeros_like(rhs), 1)
+    want = np.zeros_like(rhs)
+    want[k0, j0, i0] = -om / d
+    for (dk, dj, di), c in [((0, 0, 1), cx), ((0, 0, -1), cx), ((0, 1, 0), cy),
+                            ((0, -1, 0), cy), ((1, 0, 0), cz), ((-1, 0, 0), cz)]:
+        want[k0 + dk, j0 + dj, i0 + di] = -om * om * c / (d * d)
+    assert np.allclose(p, want, rtol=1e-14, atol=1e-300)
+    s_want = (om / d) ** 2 + 2 * sum((om * om * c / (d * d)) ** 2 for c in (cx, cy, cz))
+    assert math.isclose(s, s_want, rel_tol=1e-13)
+    # the same source on a colour-1 cell is updated in the second half-sweep
+    rhs2 = np.zeros_like(rhs)
+    rhs2[k0, j0, i0 + 1] = 1.0
+    p2, _ = o.sor_iterations(rhs2, np.zeros_like(rhs), 1)
+    assert p2[k0, j0, i0 + 1] == pytest.approx(-om / d, rel=1e-14)
+    assert np.count_nonzero(p2) == 1
+
+
+def test_sor_omega_one_is_gauss_seidel_fixed_point():
+    """omega = 1 iterates converge to the same dense solution (P1 at omega 1)."""
+    o = make(6, 5, 4, dx=1.0, dy=1.0, dz=1.0, omega=1.0)
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal(o.shapes[3])
+    p, st, rc = o.pressure_solve(rhs, tol=1e-13, max_iter=200000)
+    want = np.linalg.solve(assemble_A(o), rhs.ravel())
+    assert np.linalg.norm(p.ravel() - want) <= 1e-10 * np.linalg.norm(want)
+
+
+# -------------------------------------------------------------------- P4
+def test_sor_rate_matches_young():
+    """P4: asymptotic SOR factor equals Young's formula from the Jacobi radius."""
+    nx, ny, nz = 16, 12, 6
+    om = 1.5
+    o = make(nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, omega=om)
+    A = assemble_A(o)
+    dgl = -np.diag(A)
+    J = np.eye(A.shape[0]) + A / dgl[:, None]
+    rho_j = np.max(np.abs(np.linalg.eigvals(J)))
+    om_opt = 2 / (1 + math.sqrt(1 - rho_j**2))
+    assert om < om_opt
+    rho = ((om * rho_j + math.sqrt(om * om * rho_j * rho_j - 4 * (om - 1))) / 2) ** 2
+    rng = np.random.default_rng(1)
+    p = rng.standard_normal(o.shapes[3])
+    z = np.zeros_like(p)
+    p, _ = o.sor_iterations(z, p, 600)
+    n0 = np.linalg.norm(p)
+    p, _ = o.sor_iterations(z, p, 100)
+    obs = (np.linalg.norm(p) / n0) ** (1 / 100)
+    assert abs(obs - rho) <= 0.01 * rho
+
+
+# -------------------------------------------------------------------- P11
+def test_divergence_of_linear_field():
+    """P11: u = a x, v = b y, w = c z gives div = a + b + c at every cell."""
+    nx, ny, nz, dx, dy, dz = 5, 4, 3, 1.5, 0.5, 2.0
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz)
+    a, b, c = 0.3, -1.7, 2.5
+    xu = np.arange(nx + 1) * dx
+    yv = np.arange(ny + 1) * dy
+    zw = np.arange(nz + 1) * dz
+    u = np.broadcast_to(a * xu[None, None, :], (nz, ny, nx + 1))
+    v = np.broadcast_to(b * yv[None, :, None], (nz, ny + 1, nx))
+    w = np.broadcast_to(c * zw[:, None, None], (nz + 1, ny, nx))
+    div = o.divergence(u, v, w)
+    assert np.allclose(div, a + b + c, rtol=1e-13)
+
+
+# -------------------------------------------------------------------- P5
+def test_projection_identity():
+    """P5: ||div u^{n+1}|| / ||div u*|| equals the final SOR residual."""
+    from les_inputs import building_heights, building_mask, log_law_profile
+    nx, ny, nz = 24, 20, 12
+    h = building_heights(nx, ny, nz, 0.15, 2, 4, 2, 6, seed=5, margin_x=4, margin_y=2)
+    mask = building_mask(h, nz)
+    o = make(nx, ny, nz, mask=mask)
+    o.set_inflow(log_law_profile(nz, 2.0), 0.01, 9)
+    for _ in range(2):
+        rc, st = o.step(1)
+        assert rc == 0
+        assert st["div_new"] / st["div_star"] == pytest.approx(st["resid"], rel=1e-8)
+        assert st["resid"] <= 1e-5
+
+
+# -------------------------------------------------------------------- P14
+def test_mass_balance():
+    """P14: after projection the outflow flux equals the inflow flux.
+
+    Summing div over all cells telescopes to (outflow - inflow flux)/volume;
+    the sum is bounded by sqrt(N) ||div||.
+    """
+    from les_inputs import building_heights, building_mask, log_law_profile
+    nx, ny, nz, dx, dy, dz = 24, 16, 12, 4.0, 4.0, 2.0
+    h = building_heights(nx, ny, nz, 0.2, 2, 4, 2, 6, seed=2, margin_x=4, margin_y=2)
+    o = make(nx, ny, nz, mask=building_mask(h, nz))
+    o.set_inflow(log_law_profile(nz, dz), 0.01, 3)
+    rc, st = o.step(3)
+    u, v, w, p = o.get_fields()
+    fin = u[:, :, 0].sum() * dy * dz
+    fout = u[:, :, nx].sum() * dy * dz
+    bound = math.sqrt(nx * ny * nz) * st["div_new"] * dx * dy * dz
+    assert abs(fout - fin) <= bound * (1 + 1e-9) + 1e-12
+    assert abs(fout - fin) <= 1e-5 * abs(fin)
+
+
+# -------------------------------------------------------------------- P6
+def test_uniform_flow_preserved():
+    """P6: no buildings, free-slip ground, constant inflow, no noise: u = U."""
+    nx, ny, nz = 16, 12, 8
+    bc = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, FREESLIP, FREESLIP)
+    o = make(nx, ny, nz, bc=bc)
+    U = 3.25
+    o.set_inflow(np.full(nz, U, np.float32), 0.0, 1)
+    rc, st = o.step(10)
+    u, v, w, p = o.get_fields()
+    assert np.abs(u - U).max() <= 1e-14 * U
+    assert np.abs(v).max() <= 1e-14 and np.abs(w).max() <= 1e-14
+    assert np.abs(p).max() <= 1e-14
+    assert st["total_iters"] == 0
+
+
+# -------------------------------------------------------------------- P7
+def _tgv(o, A, my, mz):
+    nx, ny, nz, dy, dz = o.nx, o.ny, o.nz, o.dy, o.dz
+    Ly, Lz = ny * dy, nz * dz
+    ky, kz = my * math.pi / Ly, mz * math.pi / Lz
+    B = A * (math.sin(ky * dy / 2) / dy) / (math.sin(kz * dz / 2) / dz)
+    yf = np.arange(ny + 1) * dy
+    yc = (np.arange(ny) + 0.5) * dy
+    zf = np.arange(nz + 1) * dz
+    zc = (np.arange(nz) + 0.5) * dz
+    v = A * np.sin(ky * yf)[None, :, None] * np.cos(kz * zc)[:, None, None] * np.ones((1, 1, nx))
+    w = -B * np.cos(ky * yc)[None, :, None] * np.sin(kz * zf)[:, None, None] * np.ones((1, 1, nx))
+    lam = -(4 / dy**2) * math.sin(ky * dy / 2) ** 2 - (4 / dz**2) * math.sin(kz * dz / 2) ** 2
+    return v, w, lam, ky, kz
+
+
+def test_taylor_green_decay():
+    """P7: a free-slip y-z Taylor-Green mode decays by the AB2 recursion.
+
+    The mode is an exact eigenvector of the discrete Laplacian (eigenvalue
+    lam) with zero discrete divergence.  With Cs = 0 and a tiny amplitude
+    the nonlinear terms are negligible, so the amplitude follows
+    a1 = (1 + mu) a0 (Euler first step), a_{n+1} = a_n + mu (1.5 a_n - 0.5 a_{n-1}),
+    mu = nu lam dt; and tends to exp(nu lam_cont t) up to O((k h)^2).
+    """
+    nx, ny, nz, dx, dy, dz, dt, nu = 4, 16, 16, 1.0, 1.0, 1.0, 0.1, 1.0
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, dt=dt, bc=ALL_WALLS, cs=0.0, nu=nu)
+    A = 1e-6
+    v0, w0, lam, ky, kz = _tgv(o, A, 1, 1)
+    su = o.shapes[0]
+    o.set_fields(np.zeros(su), v0, w0, np.zeros(o.shapes[3]))
+    mu = nu * lam * dt
+    a = [1.0, 1.0 + mu]
+    nsteps = 8
+    for n in range(1, nsteps):
+        a.append(a[n] + mu * (1.5 * a[n] - 0.5 * a[n - 1]))
+    for n in range(1, nsteps + 1):
+        rc, st = o.step(1)
+        u, v, w, p = o.get_fields()
+        amp_v = np.vdot(v, v0) / np.vdot(v0, v0)
+        amp_w = np.vdot(w, w0) / np.vdot(w0, w0)
+        assert amp_v == pytest.approx(a[n], rel=1e-6, abs=0)
+        assert amp_w == pytest.approx(a[n], rel=1e-6, abs=0)
+        resid_v = np.linalg.norm(v - amp_v * v0) / np.linalg.norm(v0)
+        assert resid_v <= 1e-6
+    lam_c = -(ky**2 + kz**2)
+    t = nsteps * dt
+    kh2 = (ky * dy) ** 2
+    assert a[nsteps] == pytest.approx(math.exp(nu * lam_c * t), rel=2 * kh2 * abs(nu * lam_c * t))
+
+
+# -------------------------------------------------------------------- P8
+def test_smagorinsky_linear_shear():
+    """P8: u = g z gives |S| = g, so nu_t = (Cs Delta)^2 g away from walls."""
+    nx, ny, nz, dx, dy, dz = 6, 5, 8, 2.0, 3.0, 1.0
+    cs = 0.17
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=cs)
+    g = 0.8
+    zc = (np.arange(nz) + 0.5) * dz
+    u = np.broadcast_to(g * zc[:, None, None], (nz, ny, nx + 1)).copy()
+    su, sv, sw, sc = o.shapes
+    nut = o.nut_of(u, np.zeros(sv), np.zeros(sw))
+    want = (cs * (dx * dy * dz) ** (1 / 3)) ** 2 * g
+    assert np.allclose(nut[1:-1], want, rtol=1e-13)
+    # constant nu_t on a linear field: zero SGS force, zero advection,
+    # zero Laplacian -> zero tendency away from the z walls
+    fu, fv, fw = o.force_of(u, np.zeros(sv), np.zeros(sw))
+    assert np.abs(fu[2:-2]).max() <= 1e-13 * g
+    assert np.abs(fv[2:-2]).max() <= 1e-13 * g
+    assert np.abs(fw[2:-2]).max() <= 1e-13 * g
+
+
+def test_smagorinsky_solid_rotation():
+    """P8: solid-body rotation in x-y has zero strain, hence nu_t = 0."""
+    nx, ny, nz, dx, dy, dz = 8, 8, 4, 1.0, 1.0, 1.0
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=0.2)
+    Om = 0.5
+    yc = (np.arange(ny) + 0.5) * dy - 4
+    xc = (np.arange(nx) + 0.5) * dx - 4
+    xf = np.arange(nx + 1) * dx - 4
+    yf = np.arange(ny + 1) * dy - 4
+    u = np.broadcast_to(-Om * yc[None, :, None], (nz, ny, nx + 1)).copy()
+    v = np.broadcast_to(Om * xc[None, None, :], (nz, ny + 1, nx)).copy()
+    nut = o.nut_of(u, v, np.zeros(o.shapes[2]))
+    assert np.abs(nut[1:-1, 1:-1, 1:-1]).max() <= 1e-14
+
+
+# ------------------------------------------------------ advection closed forms
+def test_advection_closed_forms():
+    """Second-order central advection is exact on these polynomial fields.
+
+    u = a + b x (v = w = 0): -(u du/dx) = -b u at every interior u-face.
+    u = q(y) quadratic, v = V constant on interior faces: -V q'(y) exactly
+    (and nu q'' from the Laplacian).
+    """
+    nx, ny, nz, dx, dy, dz = 8, 8, 6, 0.5, 0.25, 1.0
+    bc = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, FREESLIP, FREESLIP)
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, bc=bc, cs=0.0, nu=0.0)
+    a, b = 1.2, 0.3
+    xf = np.arange(nx + 1) * dx
+    u = np.broadcast_to((a + b * xf)[None, None, :], (nz, ny, nx + 1)).copy()
+    su, sv, sw, sc = o.shapes
+    fu, fv, fw = o.force_of(u, np.zeros(sv), np.zeros(sw))
+    want = -b * (a + b * xf)
+    assert np.allclose(fu[:, :, 1:nx], want[None, None, 1:nx], rtol=1e-13)
+    # shear advected by a uniform cross flow
+    nu = 0.01
+    o2 = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, bc=bc, cs=0.0, nu=nu)
+    yc = (np.arange(ny) + 0.5) * dy
+    c0, c1, c2 = 0.4, -0.7, 0.9
+    q = c0 + c1 * yc + c2 * yc**2
+    u2 = np.broadcast_to(q[None, :, None], (nz, ny, nx + 1)).copy()
+    V = 0.6
+    v2 = np.full(sv, V)
+    v2[:, 0, :] = 0.0
+    v2[:, ny, :] = 0.0
+    fu2, _, _ = o2.force_of(u2, v2, np.zeros(sw))
+    dq = c1 + 2 * c2 * yc
+    want2 = -V * dq + nu * 2 * c2
+    jin = slice(2, ny - 2)
+    assert np.allclose(fu2[:, jin, 1:nx], want2[None, jin, None], rtol=1e-12)
+
+
+# -------------------------------------------------------------------- P9
+def test_feedback_forcing_single_solid_cell():
+    """P9: on a solid face F = adv/diff part + alpha usum + beta u, usum = dt u.
+
+    With a uniform flow the advective and diffusive parts vanish on the
+    faces around an isolated solid cell at the first step, so the stored
+    tendency there is exactly (alpha dt + beta) U and usum = dt U; the
+    second step accumulates usum by dt times the projected velocity.
+    """
+    nx, ny, nz = 12, 10, 8
+    bc = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, FREESLIP, FREESLIP)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[4, 5, 6] = 1
+    al, be, dt, U = -10.0, -1.0, 0.05, 2.0
+    o = make(nx, ny, nz, dt=dt, mask=mask, bc=bc, alpha=al, beta=be, cs=0.0, nu=0.0)
+    o.set_inflow(np.full(nz, U, np.float32), 0.0, 1)
+    # initial state: the two u-faces of the solid cell start at 0 (solid)
+    u0 = o.get_fields()[0]
+    assert u0[4, 5, 6] == 0.0 and u0[4, 5, 7] == 0.0 and u0[4, 5, 5] == 2.0
+    # impose the uniform flow everywhere, faces of the solid cell included
+    su, sv, sw, sc = o.shapes
+    o.set_fields(np.full(su, U), np.zeros(sv), np.zeros(sw), np.zeros(sc))
+    o.step(1)
+    fu, fv, fw = o.get_force()
+    s_u, s_v, s_w = o.get_usum()
+    # u-faces of the solid cell (0-based cell 6): face 6 (west) and 7 (east)
+    for i in (6, 7):
+        assert s_u[4, 5, i] == pytest.approx(dt * U, rel=1e-15)
+        assert fu[4, 5, i] == pytest.approx((al * dt + be) * U, rel=1e-13)
+    assert s_u[4, 5, 5] == 0.0 and s_u[4, 5, 8] == 0.0
+    u1 = o.get_fields()[0]
+    o.step(1)
+    s_u2 = o.get_usum()[0]
+    for i in (6, 7):
+        assert s_u2[4, 5, i] == pytest.approx(dt * U + dt * u1[4, 5, i], rel=1e-13)
+
+
+# ------------------------------------------------------------------- P12
+def test_splitmix64_published_vectors():
+    """P12: splitmix64 from state 0, gamma, 2 gamma (Steele-Lea-Flood 2014)."""
+    g = 0x9E3779B97F4A7C15
+    assert oracle.splitmix64(0) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix64(g) == 0x6E789E6AA1B965F4
+    assert oracle.splitmix64((2 * g) % 2**64) == 0x06C45D188009454F
+
+
+def test_inflow_noise_definition():
+    """P12: inflow = U(k)(1 + a(2 xi - 1)), xi the top 24 bits of splitmix64."""
+    nx, ny, nz = 12, 6, 5
+    o = make(nx, ny, nz)
+    prof = np.linspace(1, 3, nz).astype(np.float32)
+    o.set_inflow(prof, 0.01, 12345)
+    vals = []
+    for k in range(1, nz + 1):
+        for j in range(1, ny + 1):
+            for s in (1, 7):
+                ctr = (s << 40) + ((k - 1) << 20) + (j - 1)
+                xi = (oracle.splitmix64(12345 ^ ctr) >> 40) / 2.0**24
+                want = float(prof[k - 1]) * (1 + 0.01 * (2 * xi - 1))
+                got = o.inflow_value(j, k, s)
+                assert got == pytest.approx(want, rel=1e-15)
+                vals.append(xi)
+    vals = np.array(vals)
+    assert vals.min() >= 0 and vals.max() < 1
+
+
+def test_profiles_closed_forms():
+    """P12: log-law and power-law profiles at their cell-centre heights."""
+    from les_inputs import log_law_profile, power_law_profile
+    p = log_law_profile(32, 2.0)
+    assert p[0] == pytest.approx(0.75 * math.log(1.0 / 0.1), rel=1e-7)     # z = 1 m
+    assert p[31] == pytest.approx(0.75 * math.log(63.0 / 0.1), rel=1e-7)   # z = 63 m
+    assert p[0] == pytest.approx(1.727, abs=1e-3) and p[31] == pytest.approx(4.834, abs=1e-3)
+    q = power_law_profile(90, 2.0, 6.0, 0.2)
+    assert q[-1] == pytest.approx(6.0 * (179.0 / 180.0) ** 0.2, rel=1e-7)
+    assert q[0] == pytest.approx(6.0 * (1.0 / 180.0) ** 0.2, rel=1e-7)
+
+
+# -------------------------------------------------------------- BC table
+def test_ghost_rules_urban():
+    """Ghost values follow the per-face rules, edges and corners included."""
+    nx, ny, nz = 6, 5, 4
+    o = make(nx, ny, nz)
+    u, v, w, p = oracle_random_state(o, 11)
+    o.set_fields(u, v, w, p)
+    U, V, W = o.get_ghosted()      # [k][j][i] over the ghosted box
+    # u: x+ outflow copies, y free slip mirrors, z- no slip anti-mirrors,
+    # z+ free slip mirrors
+    assert np.array_equal(U[1:-1, 1:-1, nx + 1], U[1:-1, 1:-1, nx])
+    assert np.array_equal(U[:, 0, :], U[:, 1, :]) and np.array_equal(U[:, ny + 1, :], U[:, ny, :])
+    assert np.array_equal(U[0], -U[1]) and np.array_equal(U[nz + 1], U[nz])
+    # v: inflow anti-mirror on x-, outflow copy on x+, walls zero
+    assert np.array_equal(V[1:-1, :ny + 1, 0], -V[1:-1, :ny + 1, 1])
+    assert np.array_equal(V[1:-1, :ny + 1, nx + 1], V[1:-1, :ny + 1, nx])
+    assert np.all(V[:, 0, :] == 0) and np.all(V[:, ny, :] == 0)
+    # w: ground and top faces zero, y ghosts mirror
+    assert np.all(W[0] == 0) and np.all(W[nz] == 0)
+    assert np.array_equal(W[:nz + 1, 0, :], W[:nz + 1, 1, :])
+    # a corner composes the three rules: u(nx+1, 0, 0) = -u(nx, 1, 1)
+    assert U[0, 0, nx + 1] == -U[1, 1, nx]
+
+
+def oracle_random_state(o, seed):
+    from les_inputs import random_fields
+    u, v, w, p = random_fields(o.nx, o.ny, o.nz, seed)
+    return u.astype(np.float64), v.astype(np.float64), w.astype(np.float64), p.astype(np.float64)
+
+
+# ------------------------------------------------------------- replay mode
+def test_replay_mode_reproduces_free_run():
+    """Replaying the iteration counts of a free run gives identical fields."""
+    from les_inputs import log_law_profile
+    nx, ny, nz = 16, 12, 8
+    a = make(nx, ny, nz)
+    b = make(nx, ny, nz)
+    prof = log_law_profile(nz, 2.0)
+    a.set_inflow(prof, 0.01, 4)
+    b.set_inflow(prof, 0.01, 4)
+    a.step(3)
+    iters = a.last_iters
+    b.step(3, forced=iters)
+    for x, y in zip(a.get_fields(), b.get_fields()):
+        assert np.array_equal(x, y)

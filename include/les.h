@@ -1,0 +1,245 @@
+/*
+ * les.h -- C ABI of the MI355X urban-LES time step.
+ *
+ * One handle holds one building-resolving LES instance on one GPU: an
+ * incompressible flow on a staggered (MAC) grid of nx * ny * nz cells.  A
+ * time step follows the per-step subroutine list of the paper
+ * (Vanderbauwhede 2014, section 2.1): Smagorinsky viscosity (les), body
+ * force from advection and diffusion (velfg), building feedback forcing
+ * (feedbf), Adams-Bashforth update (adam), inflow boundary (bondv1), the
+ * pressure Poisson equation by red-black SOR (press, section 2.6), the
+ * velocity update by the pressure gradient (velnw) and the ghost refresh
+ * (bondv1, launched over the boundary range of section 2.4).
+ *
+ * Conventions shared by every call
+ *   - Every function except les_destroy / les_last_error returns an int
+ *     status: LES_OK (0), a warning (> 0) or an error (< 0).  No call
+ *     aborts or prints.  Arguments are validated before any device work.
+ *   - Host arrays are C order with i fastest and carry no ghosts:
+ *       u [nz][ny][nx+1]  x-velocity on x-faces, face i = 0 is the x- boundary
+ *       v [nz][ny+1][nx]  y-velocity on y-faces, faces 0 and ny are walls
+ *       w [nz+1][ny][nx]  z-velocity on z-faces, faces 0 and nz are walls
+ *       p, rhs, mask [nz][ny][nx]  cell centres
+ *   - Host-pointer calls copy in/out and are synchronous on return.
+ *     Device-pointer (_dev) calls borrow the pointers for the duration of
+ *     the call, are ordered on the given stream and do not synchronise
+ *     (NULL stream = the handle's stream).
+ *   - All field arithmetic is float32; norms and residuals are accumulated
+ *     in float64.
+ *   - One handle per host thread.  Two handles may share a GPU.
+ */
+#ifndef LES_H_
+#define LES_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ statuses */
+enum {
+    LES_OK = 0,
+    LES_NOT_CONVERGED = 1,   /* warning: an SOR solve hit max_iter; fields valid */
+    LES_EINVAL = -1,         /* bad argument (NULL, size, non-finite, bad BC set) */
+    LES_ENOMEM = -2,         /* device or host allocation failed */
+    LES_EDEVICE = -3,        /* a HIP runtime error; text in les_last_error */
+    LES_ENONFINITE = -4,     /* a float64 norm came out NaN or Inf */
+    LES_ESTATE = -5          /* call out of order (e.g. step before set_inflow) */
+};
+
+/* Boundary-condition kinds, one per domain face (les_params.bc). */
+enum {
+    LES_BC_FREESLIP = 0,     /* wall: zero normal velocity, mirrored tangential */
+    LES_BC_NOSLIP = 1,       /* wall: zero normal velocity, anti-mirrored tangential */
+    LES_BC_INFLOW = 2,       /* x- only: prescribed u profile plus noise */
+    LES_BC_OUTFLOW = 3       /* x+ only: zero-gradient velocity, p = 0 on the face */
+};
+enum { LES_XM = 0, LES_XP = 1, LES_YM = 2, LES_YP = 3, LES_ZM = 4, LES_ZP = 5 };
+
+typedef struct les_handle les_handle;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* cells; each >= 4 */
+} les_grid;
+
+typedef struct {
+    double dx, dy, dz;       /* uniform spacing [m]; > 0 and finite */
+} les_spacing;
+
+typedef struct {
+    double omega;            /* SOR relaxation factor, 0 < omega < 2 (default 1.8) */
+    double tol;              /* relative residual ||rhs - A p|| / ||rhs|| (1e-5) */
+    int32_t check_every;     /* residual checked every K full iterations (4) */
+    int32_t max_iter;        /* per solve (20000) */
+    double cs;               /* Smagorinsky constant (0.1) */
+    double nu;               /* molecular viscosity [m^2/s] (1.5e-5) */
+    double alpha;            /* feedback forcing integral gain [1/s^2] (-10) */
+    double beta;             /* feedback forcing proportional gain [1/s] (-1) */
+    int32_t bc[6];           /* per face, LES_XM..LES_ZP (urban default:
+                                INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP) */
+    int32_t zero_guess;      /* 1: each solve starts from p = 0 (default 0: previous p) */
+    int32_t rebase_every;    /* fold the correction into the base pressure every
+                                R residual checks (4); see les_pressure_solve */
+    int32_t diagnostics;     /* 1: compute ||div u^{n+1}|| and max CFL on the last
+                                step of each les_step call (default 1) */
+    int32_t pad_;
+} les_params;
+
+/* Per-call statistics of les_step.  Scalars describe the last step of the
+ * call unless named _total. */
+typedef struct {
+    int32_t steps;           /* steps advanced */
+    int32_t not_converged;   /* solves of this call that hit max_iter */
+    int64_t sor_iters_total; /* SOR iterations summed over the steps */
+    int32_t sor_iters_last;
+    int32_t pad_;
+    double resid_last;       /* final relative residual (float64) */
+    double reltmp2_last;     /* sum of reltmp^2 over the last SOR iteration */
+    double rhs_norm_last;    /* ||rhs||_2 */
+    double div_star_last;    /* ||div u*||_2 = dt ||rhs|| (outflow case) */
+    double div_new_last;     /* ||div u^{n+1}||_2 (diagnostics on), else -1 */
+    double cfl_last;         /* max CFL of u^{n+1} (diagnostics on), else -1 */
+    double ms_total;         /* host wall time of the call */
+    int32_t* iters_out;      /* optional, caller-owned: n per-step iteration counts */
+} les_step_stats;
+
+typedef struct {
+    int32_t iters;           /* SOR iterations performed */
+    int32_t converged;       /* 1 if resid <= tol (or rhs == 0) */
+    double resid;            /* final relative residual (float64) */
+    double rhs_norm;         /* ||rhs||_2 after any mean removal */
+    double reltmp2;          /* sum of reltmp^2 over the last iteration */
+} les_solve_stats;
+
+/* Fill *p with the defaults listed in les_params.  LES_EINVAL if p is NULL. */
+int les_default_params(les_params* p);
+
+/*
+ * Create an instance.  building_mask (nullable = no buildings) is a uint8
+ * cell mask [nz][ny][nx], 1 = solid, copied.  prm NULL = defaults.
+ * Allocates every device field on the current HIP device, zeroes the state
+ * and marks the Adams-Bashforth history as unset.  The caller owns *out
+ * until les_destroy.  Requires nx, ny, nz >= 4, dx, dy, dz, dt > 0 and
+ * finite, x- in {INFLOW, FREESLIP, NOSLIP}, x+ in {OUTFLOW, FREESLIP,
+ * NOSLIP}, other faces walls.  Errors: LES_EINVAL, LES_ENOMEM, LES_EDEVICE.
+ */
+int les_create(const les_grid* g, const les_spacing* s, double dt, const uint8_t* building_mask,
+               const les_params* prm, les_handle** out);
+
+/* Free everything.  NULL is a no-op. */
+void les_destroy(les_handle* h);
+
+/* Text of the last error on this handle ("" if none).  Never NULL. */
+const char* les_last_error(const les_handle* h);
+
+/* Run the handle's work on this stream (a hipStream_t; NULL = the handle's
+ * own stream, created at les_create).  The caller keeps it alive. */
+int les_set_stream(les_handle* h, void* stream);
+
+/*
+ * Set the x- inflow profile: nz float32 speeds U(k) at the cell-centre
+ * heights (k + 1/2) dz, and the relative noise amplitude a >= 0.  The
+ * inflow face then carries U(k) (1 + a (2 xi - 1)) at every step, with xi a
+ * counter-based uniform number from splitmix64(seed ^ (step 2^40 + k 2^20
+ * + j)) (0-based j, k; top 24 bits).  On the first call it also sets the
+ * initial state: u = U(k) on fluid u-faces, 0 on faces touching a solid
+ * cell, v = w = p = 0 (section 2.1, bondv1: "initial wind profile").
+ * Required before les_step (else LES_ESTATE).  Later calls only replace
+ * the profile, amplitude and seed.
+ */
+int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_t seed);
+
+/*
+ * Advance n >= 0 steps.  Each step: nu_t, tendency with feedback forcing and
+ * AB2 (u*), inflow, rhs = div(u*)/dt, red-black SOR to tol (checked every
+ * check_every iterations, at most max_iter), projection u = u* - dt grad p,
+ * ghost refresh.  st (nullable) receives the statistics.  Host-synchronous.
+ * Returns LES_NOT_CONVERGED if any solve hit max_iter (fields still valid),
+ * LES_ENONFINITE if a norm became NaN/Inf.
+ */
+int les_step(les_handle* h, int32_t n, les_step_stats* st);
+
+/*
+ * Stand-alone Poisson solve A p = rhs with the handle's operator (its
+ * boundary conditions folded into the SOR coefficients, section 2.6).
+ * rhs, p: host float32 [nz][ny][nx]; p is the initial guess on entry and
+ * the solution on exit.  Without an outflow face the operator is singular:
+ * the rhs mean is removed first and the p mean afterwards.  tol <= 0 or
+ * max_iter < 0 is LES_EINVAL; max_iter = 0 returns the guess.  Does not
+ * touch the time-stepping state.  LES_NOT_CONVERGED if max_iter was hit.
+ *
+ * The iterates are those of plain red-black SOR; internally p is held as a
+ * float32 base plus a float32 correction that the sweeps update against a
+ * float64-evaluated residual, so float32 storage does not stall the
+ * iteration.
+ */
+int les_pressure_solve(les_handle* h, const float* rhs, float* p, double tol, int32_t max_iter,
+                       les_solve_stats* st);
+
+/* Same with device pointers (float32, [nz][ny][nx], contiguous). */
+int les_pressure_solve_dev(les_handle* h, const float* d_rhs, float* d_p, double tol,
+                           int32_t max_iter, les_solve_stats* st, void* stream);
+
+/* Copy the state out (ghost-free layouts above).  NULL skips a field. */
+int les_get_fields(les_handle* h, float* u, float* v, float* w, float* p);
+
+/* Same into device buffers, ordered on stream. */
+int les_get_fields_dev(les_handle* h, float* d_u, float* d_v, float* d_w, float* d_p,
+                       void* stream);
+
+/*
+ * Overwrite the state from host arrays (NULL keeps a field).  Wall-normal
+ * faces are forced to zero, ghosts refreshed.  reset_history = 1 makes the
+ * next step a forward-Euler start.  Marks the inflow as set.
+ */
+int les_set_fields(les_handle* h, const float* u, const float* v, const float* w, const float* p,
+                   int32_t reset_history);
+
+/*
+ * Intermediates of the most recent step, for inspection:
+ *   which 0: nu_t at cell centres [nz][ny][nx]            -> a
+ *   which 1: Poisson rhs = div(u*)/dt [nz][ny][nx]        -> a
+ *   which 2: tendency F^n on u, v, w faces                -> a, b, c
+ *   which 3: feedback integral usum on u, v, w faces      -> a, b, c
+ * NULL pointers skip.  LES_EINVAL for an unknown which.
+ */
+int les_get_aux(les_handle* h, int32_t which, float* a, float* b, float* c);
+
+/* Full ghosted velocity boxes, float32 [nz+2][ny+2][nx+2] each (index 0 and
+ * n+1 are ghosts / boundary faces), for boundary-condition checks. */
+int les_get_ghosted(les_handle* h, float* u, float* v, float* w);
+
+/* Step counter (completed steps). */
+int les_get_step(const les_handle* h, int64_t* step);
+
+/*
+ * Checkpoint.  les_state_size gives the byte size of the opaque blob;
+ * les_get_state fills it (u, v, w, p as base + correction, AB2 history,
+ * feedback integral, step counter, flags, inflow settings); les_set_state
+ * restores it into a handle of the same grid and BC set, so that the runs
+ * continue bitwise identically.  LES_EINVAL on a size or grid mismatch.
+ */
+int les_state_size(const les_handle* h, int64_t* bytes);
+int les_get_state(les_handle* h, void* buf, int64_t bytes);
+int les_set_state(les_handle* h, const void* buf, int64_t bytes);
+
+/*
+ * Boundary-range mapping of the ghost-refresh launch (section 2.4),
+ * exposed for host-side tests; no device work.  les_bc_range gives the
+ * launch size for grid g: (ny+2)(nz+2) x-face items + nx(nz+2) y-face items
+ * + nx ny z-face items, padded up to whole 256-thread blocks (0 if g is
+ * NULL or not >= 1 per axis).  les_bc_map maps an item id to its family
+ * (0 = x faces over ghosted (j, k); 1 = y faces over (i, k), i interior;
+ * 2 = z faces over interior (i, j)) and the two in-plane ghosted indices
+ * (a, b); ids in the padding return family -1 (the guarded tail).
+ * LES_EINVAL on NULL pointers or a negative item.
+ */
+int64_t les_bc_range(const les_grid* g);
+int les_bc_map(const les_grid* g, int64_t item, int32_t* family, int32_t* a, int32_t* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LES_H_ */

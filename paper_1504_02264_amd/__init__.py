@@ -1,0 +1,294 @@
+"""Thin Python binding of the MI355X urban-LES library (``libles.so``).
+
+Argument marshalling only: every step of the time step runs in the HIP
+kernels behind the C ABI declared in ``include/les.h``.  The names follow
+that header (``les_create`` -> :class:`LES`, ``les_step`` -> :meth:`LES.step`
+...).  There is no CPU fallback: importing works without a GPU, but any
+call that reaches the library fails loudly if ``libles.so`` is missing or
+no HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libles.so")
+
+LES_OK, LES_NOT_CONVERGED = 0, 1
+LES_EINVAL, LES_ENOMEM, LES_EDEVICE, LES_ENONFINITE, LES_ESTATE = -1, -2, -3, -4, -5
+FREESLIP, NOSLIP, INFLOW, OUTFLOW = 0, 1, 2, 3
+URBAN_BC = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP)
+
+# every function include/les.h declares
+EXPORTS = (
+    "les_default_params", "les_create", "les_destroy", "les_last_error", "les_set_stream",
+    "les_set_inflow", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
+    "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
+    "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
+    "les_bc_map",
+)
+
+
+class LesError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"LES error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class Spacing(C.Structure):
+    _fields_ = [("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("omega", C.c_double), ("tol", C.c_double),
+        ("check_every", C.c_int32), ("max_iter", C.c_int32),
+        ("cs", C.c_double), ("nu", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+        ("bc", C.c_int32 * 6), ("zero_guess", C.c_int32), ("rebase_every", C.c_int32),
+        ("diagnostics", C.c_int32), ("pad_", C.c_int32),
+    ]
+
+
+class StepStats(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int32), ("not_converged", C.c_int32), ("sor_iters_total", C.c_int64),
+        ("sor_iters_last", C.c_int32), ("pad_", C.c_int32),
+        ("resid_last", C.c_double), ("reltmp2_last", C.c_double), ("rhs_norm_last", C.c_double),
+        ("div_star_last", C.c_double), ("div_new_last", C.c_double), ("cfl_last", C.c_double),
+        ("ms_total", C.c_double), ("iters_out", C.POINTER(C.c_int32)),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("pad_", "iters_out")}
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("resid", C.c_double),
+                ("rhs_norm", C.c_double), ("reltmp2", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libles.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1504_02264_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.les_default_params.argtypes = [C.POINTER(Params)]
+    L.les_create.argtypes = [C.POINTER(Grid), C.POINTER(Spacing), C.c_double, P,
+                             C.POINTER(Params), C.POINTER(P)]
+    L.les_destroy.argtypes = [P]
+    L.les_destroy.restype = None
+    L.les_last_error.argtypes = [P]
+    L.les_last_error.restype = C.c_char_p
+    L.les_set_stream.argtypes = [P, P]
+    L.les_set_inflow.argtypes = [P, P, C.c_float, C.c_uint64]
+    L.les_step.argtypes = [P, C.c_int32, C.POINTER(StepStats)]
+    L.les_pressure_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats)]
+    L.les_pressure_solve_dev.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
+    L.les_get_fields.argtypes = [P, P, P, P, P]
+    L.les_get_fields_dev.argtypes = [P, P, P, P, P, P]
+    L.les_set_fields.argtypes = [P, P, P, P, P, C.c_int32]
+    L.les_get_aux.argtypes = [P, C.c_int32, P, P, P]
+    L.les_get_ghosted.argtypes = [P, P, P, P]
+    L.les_get_step.argtypes = [P, C.POINTER(C.c_int64)]
+    L.les_state_size.argtypes = [P, C.POINTER(C.c_int64)]
+    L.les_get_state.argtypes = [P, P, C.c_int64]
+    L.les_set_state.argtypes = [P, P, C.c_int64]
+    L.les_bc_range.argtypes = [C.POINTER(Grid)]
+    L.les_bc_range.restype = C.c_int64
+    L.les_bc_map.argtypes = [C.POINTER(Grid), C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32)]
+    _lib = L
+    return L
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().les_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "bc":
+            for f, b in enumerate(v):
+                p.bc[f] = b
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+class LES:
+    """One LES instance on the current HIP device (``les_create``)."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, dt, mask=None, params: Optional[Params] = None,
+                 **kw):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dt = float(dt)
+        self.params = params if params is not None else default_params(**kw)
+        m = None
+        if mask is not None:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            if m.shape != (nz, ny, nx):
+                raise ValueError("mask must be [nz, ny, nx]")
+        h = C.c_void_p()
+        rc = lib().les_create(C.byref(Grid(nx, ny, nz)), C.byref(Spacing(dx, dy, dz)), dt,
+                              _ptr(m), C.byref(self.params), C.byref(h))
+        if rc != LES_OK:
+            raise LesError(rc, "les_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().les_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc, ok=(LES_OK,)):
+        if rc not in ok:
+            raise LesError(rc, lib().les_last_error(self.h).decode())
+        return rc
+
+    @property
+    def shapes(self):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return (nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx), (nz, ny, nx)
+
+    def set_stream(self, stream_handle: int):
+        return self._check(lib().les_set_stream(self.h, C.c_void_p(stream_handle)))
+
+    def set_inflow(self, profile, noise_amp=0.01, seed=0):
+        prof = _f32(profile, (self.nz,))
+        return self._check(lib().les_set_inflow(self.h, _ptr(prof), float(noise_amp), int(seed)))
+
+    def step(self, n=1, allow_not_converged=True):
+        """Advance n steps; returns (status, stats dict, per-step SOR iterations)."""
+        st = StepStats()
+        iters = np.zeros(max(int(n), 1), dtype=np.int32)
+        st.iters_out = iters.ctypes.data_as(C.POINTER(C.c_int32))
+        ok = (LES_OK, LES_NOT_CONVERGED) if allow_not_converged else (LES_OK,)
+        rc = self._check(lib().les_step(self.h, int(n), C.byref(st)), ok)
+        return rc, st.as_dict(), iters[:n].copy()
+
+    def pressure_solve(self, rhs, p0=None, tol=1e-5, max_iter=20000):
+        sc = self.shapes[3]
+        r = _f32(rhs, sc)
+        p = np.zeros(sc, np.float32) if p0 is None else _f32(p0, sc).copy()
+        st = SolveStats()
+        rc = self._check(lib().les_pressure_solve(self.h, _ptr(r), _ptr(p), float(tol),
+                                                  int(max_iter), C.byref(st)),
+                         (LES_OK, LES_NOT_CONVERGED))
+        return p, st.as_dict(), rc
+
+    def pressure_solve_dev(self, d_rhs, d_p, tol=1e-5, max_iter=20000, stream=None):
+        """Device-pointer solve; d_rhs / d_p are contiguous float32 torch tensors."""
+        st = SolveStats()
+        s = None if stream is None else C.c_void_p(stream)
+        rc = self._check(lib().les_pressure_solve_dev(self.h, C.c_void_p(d_rhs.data_ptr()),
+                                                      C.c_void_p(d_p.data_ptr()), float(tol),
+                                                      int(max_iter), C.byref(st), s),
+                         (LES_OK, LES_NOT_CONVERGED))
+        return st.as_dict(), rc
+
+    def get_fields(self):
+        su, sv, sw, sp = self.shapes
+        u, v, w, p = (np.zeros(s, np.float32) for s in (su, sv, sw, sp))
+        self._check(lib().les_get_fields(self.h, _ptr(u), _ptr(v), _ptr(w), _ptr(p)))
+        return u, v, w, p
+
+    def get_fields_dev(self, d_u, d_v, d_w, d_p, stream=None):
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        s = None if stream is None else C.c_void_p(stream)
+        return self._check(lib().les_get_fields_dev(self.h, ptr(d_u), ptr(d_v), ptr(d_w),
+                                                    ptr(d_p), s))
+
+    def set_fields(self, u=None, v=None, w=None, p=None, reset_history=True):
+        su, sv, sw, sp = self.shapes
+        a = [None if x is None else _f32(x, s) for x, s in zip((u, v, w, p), (su, sv, sw, sp))]
+        return self._check(lib().les_set_fields(self.h, *[_ptr(x) for x in a],
+                                                int(bool(reset_history))))
+
+    def get_nut(self):
+        a = np.zeros(self.shapes[3], np.float32)
+        self._check(lib().les_get_aux(self.h, 0, _ptr(a), None, None))
+        return a
+
+    def get_rhs(self):
+        a = np.zeros(self.shapes[3], np.float32)
+        self._check(lib().les_get_aux(self.h, 1, _ptr(a), None, None))
+        return a
+
+    def _faces(self, which):
+        su, sv, sw, _ = self.shapes
+        a, b, c = np.zeros(su, np.float32), np.zeros(sv, np.float32), np.zeros(sw, np.float32)
+        self._check(lib().les_get_aux(self.h, which, _ptr(a), _ptr(b), _ptr(c)))
+        return a, b, c
+
+    def get_force(self):
+        return self._faces(2)
+
+    def get_usum(self):
+        return self._faces(3)
+
+    def get_ghosted(self):
+        s = (self.nz + 2, self.ny + 2, self.nx + 2)
+        u, v, w = (np.zeros(s, np.float32) for _ in range(3))
+        self._check(lib().les_get_ghosted(self.h, _ptr(u), _ptr(v), _ptr(w)))
+        return u, v, w
+
+    def get_step(self):
+        s = C.c_int64()
+        self._check(lib().les_get_step(self.h, C.byref(s)))
+        return s.value
+
+    def get_state(self) -> bytes:
+        n = C.c_int64()
+        self._check(lib().les_state_size(self.h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().les_get_state(self.h, buf, n))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        return self._check(lib().les_set_state(self.h, buf, len(blob)))
+
+
+
+def bc_range(nx: int, ny: int, nz: int) -> int:
+    """Launch size of the boundary-range ghost refresh (les_bc_range)."""
+    return int(lib().les_bc_range(C.byref(Grid(nx, ny, nz))))
+
+
+def bc_map(nx: int, ny: int, nz: int, item: int):
+    """(family, a, b) of a boundary-range item (les_bc_map)."""
+    f, a, b = C.c_int32(), C.c_int32(), C.c_int32()
+    rc = lib().les_bc_map(C.byref(Grid(nx, ny, nz)), int(item), C.byref(f), C.byref(a), C.byref(b))
+    if rc != LES_OK:
+        raise LesError(rc, "les_bc_map")
+    return f.value, a.value, b.value

@@ -1,0 +1,96 @@
+// Device helpers: XCD-aware block numbering, wavefront/block reductions in
+// float64 and the "last block finishes the reduction" pattern.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "les_impl.h"
+
+namespace les {
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs,
+// each with a private L2.  Renumber so that every XCD owns one contiguous
+// range of logical blocks: stencil neighbours (the k-1 and k+1 planes) are
+// then fetched into the same L2 instead of into three different ones.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned q = nb / kNumXcd, r = nb % kNumXcd;
+    const unsigned x = b % kNumXcd, l = b / kNumXcd;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum over a block of kBlock threads in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+    }
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double redm[kBlock / 64];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) redm[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) t = fmax(t, redm[i]);
+    }
+    __syncthreads();
+    return t;
+}
+
+// Called by every thread after thread 0 stored this block's partial.
+// Returns true in exactly one block: the last to arrive, which then sees
+// every other block's partial.  The counter is reset for the next use.
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
+    __shared__ int is_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == nblocks - 1) ? 1 : 0;
+        if (is_last) {
+            __threadfence();
+            *counter = 0u;
+        }
+    }
+    __syncthreads();
+    return is_last != 0;
+}
+
+// Fixed-order sum of n partials by one block (result valid in thread 0).
+__device__ __forceinline__ double sum_partials(const double* part, int n) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+    return block_sum(s);
+}
+
+__device__ __forceinline__ double max_partials(const double* part, int n) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, part[i]);
+    return block_max(s);
+}
+
+}  // namespace les

@@ -1,0 +1,845 @@
+// Host runtime of the MI355X LES library: the C ABI of include/les.h.
+//
+// Owns one arena of device memory per handle (every field at a 256-byte
+// aligned offset), the handle's stream, the pinned control-block mirror and
+// the SOR driver, which enqueues check intervals ahead of the convergence
+// test and reads the device's stop flag one batch behind, so the GPU never
+// waits for the host between SOR iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "les_impl.h"
+
+using namespace les;
+
+namespace {
+
+constexpr uint32_t kStateMagic = 0x4C455331u;   // "LES1"
+
+int set_err(les_handle* h, int code, const char* what, hipError_t e = hipSuccess) {
+    if (h) {
+        char buf[512];
+        if (e != hipSuccess)
+            std::snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+        else
+            std::snprintf(buf, sizeof buf, "%s", what);
+        h->err = buf;
+    }
+    return code;
+}
+
+#define CK(expr)                                                   \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return set_err(h, LES_EDEVICE, #expr, e_); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+bool valid_params(const les_params& p) {
+    if (!(p.omega > 0.0 && p.omega < 2.0)) return false;
+    if (!finite_pos(p.tol)) return false;
+    if (p.check_every < 1 || p.max_iter < 0 || p.rebase_every < 1) return false;
+    if (!(std::isfinite(p.cs) && p.cs >= 0.0)) return false;
+    if (!(std::isfinite(p.nu) && p.nu >= 0.0)) return false;
+    if (!std::isfinite(p.alpha) || !std::isfinite(p.beta)) return false;
+    if (!(p.bc[LES_XM] == LES_BC_INFLOW || p.bc[LES_XM] == LES_BC_FREESLIP ||
+          p.bc[LES_XM] == LES_BC_NOSLIP))
+        return false;
+    if (!(p.bc[LES_XP] == LES_BC_OUTFLOW || p.bc[LES_XP] == LES_BC_FREESLIP ||
+          p.bc[LES_XP] == LES_BC_NOSLIP))
+        return false;
+    for (int f = LES_YM; f <= LES_ZP; ++f)
+        if (p.bc[f] != LES_BC_FREESLIP && p.bc[f] != LES_BC_NOSLIP) return false;
+    return true;
+}
+
+float tsign(int bc) { return (bc == LES_BC_FREESLIP || bc == LES_BC_OUTFLOW) ? 1.f : -1.f; }
+
+Geo make_geo(int nx, int ny, int nz, const les_spacing& s, double dt, const les_params& p) {
+    Geo g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.sx = round_up(nx + 2, 32);
+    g.sxy = (long long)g.sx * (ny + 2);
+    g.ntot = g.sxy * (nz + 2);
+    g.H = (nx + 1) / 2;
+    g.S = round_up(g.H + 1, 32);
+    g.SP = (long long)g.S * (ny + 2);
+    g.ctot = g.SP * (nz + 2) + 2LL * g.S;   // guard row in front and behind
+    g.dx = (float)s.dx; g.dy = (float)s.dy; g.dz = (float)s.dz; g.dt = (float)dt;
+    g.idx = (float)(1.0 / s.dx); g.idy = (float)(1.0 / s.dy); g.idz = (float)(1.0 / s.dz);
+    g.idt = (float)(1.0 / dt);
+    g.cx = (float)(1.0 / (s.dx * s.dx));
+    g.cy = (float)(1.0 / (s.dy * s.dy));
+    g.cz = (float)(1.0 / (s.dz * s.dz));
+    g.outflow = p.bc[LES_XP] == LES_BC_OUTFLOW;
+    g.inflow = p.bc[LES_XM] == LES_BC_INFLOW;
+    g.u_last = g.outflow ? nx : nx - 1;
+    g.s_xm = tsign(p.bc[LES_XM]); g.s_xp = tsign(p.bc[LES_XP]);
+    g.s_ym = tsign(p.bc[LES_YM]); g.s_yp = tsign(p.bc[LES_YP]);
+    g.s_zm = tsign(p.bc[LES_ZM]); g.s_zp = tsign(p.bc[LES_ZP]);
+    return g;
+}
+
+bool singular(const les_handle* h) { return !h->g.outflow; }
+
+// --- host-side packing of owned arrays into / out of the ghosted layout
+// (pure data movement, no arithmetic)
+void pack_u(const Geo& g, const float* src, float* box) {
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i <= g.nx; ++i)
+                box[g.nat(i, j + 1, k + 1)] = src[((size_t)k * g.ny + j) * (g.nx + 1) + i];
+}
+void pack_v(const Geo& g, const float* src, float* box) {
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j <= g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i)
+                box[g.nat(i + 1, j, k + 1)] = src[((size_t)k * (g.ny + 1) + j) * g.nx + i];
+}
+void pack_w(const Geo& g, const float* src, float* box) {
+    for (int k = 0; k <= g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i)
+                box[g.nat(i + 1, j + 1, k)] = src[((size_t)k * g.ny + j) * g.nx + i];
+}
+void unpack_u(const Geo& g, const float* box, float* dst) {
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i <= g.nx; ++i)
+                dst[((size_t)k * g.ny + j) * (g.nx + 1) + i] = box[g.nat(i, j + 1, k + 1)];
+}
+void unpack_v(const Geo& g, const float* box, float* dst) {
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j <= g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i)
+                dst[((size_t)k * (g.ny + 1) + j) * g.nx + i] = box[g.nat(i + 1, j, k + 1)];
+}
+void unpack_w(const Geo& g, const float* box, float* dst) {
+    for (int k = 0; k <= g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i)
+                dst[((size_t)k * g.ny + j) * g.nx + i] = box[g.nat(i + 1, j + 1, k)];
+}
+void unpack_cells(const Geo& g, const float* box, float* dst) {
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i)
+                dst[((size_t)k * g.ny + j) * g.nx + i] = box[g.nat(i + 1, j + 1, k + 1)];
+}
+// Wall-normal faces carry zero normal velocity.
+void zero_walls(const Geo& g, const les_params& p, float* u, float* v, float* w) {
+    for (int k = 0; k < g.nz + 2; ++k)
+        for (int i = 0; i < g.nx + 2; ++i) {
+            v[g.nat(i, 0, k)] = 0.f;
+            v[g.nat(i, g.ny, k)] = 0.f;
+        }
+    for (int j = 0; j < g.ny + 2; ++j)
+        for (int i = 0; i < g.nx + 2; ++i) {
+            w[g.nat(i, j, 0)] = 0.f;
+            w[g.nat(i, j, g.nz)] = 0.f;
+        }
+    for (int k = 0; k < g.nz + 2; ++k)
+        for (int j = 0; j < g.ny + 2; ++j) {
+            if (p.bc[LES_XM] != LES_BC_INFLOW) u[g.nat(0, j, k)] = 0.f;
+            if (p.bc[LES_XP] != LES_BC_OUTFLOW) u[g.nat(g.nx, j, k)] = 0.f;
+        }
+}
+
+// Per-cell flag byte: cell solid, and solidity of the east / north / top
+// face (a face is solid when either cell it separates is solid; a boundary
+// face looks at its one cell).
+std::vector<uint8_t> build_flags(const Geo& g, const std::vector<uint8_t>& mask) {
+    std::vector<uint8_t> fl((size_t)g.ntot, 0);
+    auto solid = [&](int i, int j, int k) {   // 1-based, clamped
+        i = std::min(std::max(i, 1), g.nx);
+        j = std::min(std::max(j, 1), g.ny);
+        k = std::min(std::max(k, 1), g.nz);
+        return mask[((size_t)(k - 1) * g.ny + (j - 1)) * g.nx + (i - 1)] != 0;
+    };
+    for (int k = 1; k <= g.nz; ++k)
+        for (int j = 1; j <= g.ny; ++j)
+            for (int i = 0; i <= g.nx; ++i) {
+                uint8_t b = 0;
+                if (i >= 1 && solid(i, j, k)) b |= F_CSOLID;
+                if (solid(i, j, k) || solid(i + 1, j, k)) b |= F_USOLID;
+                if (i >= 1 && (solid(i, j, k) || solid(i, j + 1, k))) b |= F_VSOLID;
+                if (i >= 1 && (solid(i, j, k) || solid(i, j, k + 1))) b |= F_WSOLID;
+                fl[g.nat(i, j, k)] = b;
+            }
+    return fl;
+}
+
+int upload_velocity(les_handle* h, const std::vector<float>& u, const std::vector<float>& v,
+                    const std::vector<float>& w) {
+    const size_t bytes = (size_t)h->g.ntot * sizeof(float);
+    for (int b = 0; b < 2; ++b) {
+        CK(hipMemcpyAsync(h->f.u[b], u.data(), bytes, hipMemcpyHostToDevice, h->stream));
+        CK(hipMemcpyAsync(h->f.v[b], v.data(), bytes, hipMemcpyHostToDevice, h->stream));
+        CK(hipMemcpyAsync(h->f.w[b], w.data(), bytes, hipMemcpyHostToDevice, h->stream));
+        CK(launch_bc(h->g, h->stream, h->f.u[b], h->f.v[b], h->f.w[b]));
+    }
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+int download(les_handle* h, const float* dev, std::vector<float>& host) {
+    host.resize((size_t)h->g.ntot);
+    CK(hipMemcpyAsync(host.data(), dev, host.size() * sizeof(float), hipMemcpyDeviceToHost,
+                      h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+// ------------------------------------------------------------- SOR driver
+// Preconditions: ctl initialised, P.rhs filled, ctl->rhs2 computed.
+// Runs the set-up rebase, then check intervals of K iterations (two
+// half-sweeps each) followed by a residual check, folding the correction
+// into the base every rebase_every checks.  Batches of checks are enqueued
+// ahead; the device sets ctl->done and every later kernel of the batch
+// returns at once.  The host reads the flag one batch behind.
+int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve_stats* out) {
+    const Geo& g = h->g;
+    hipStream_t st = h->stream;
+    Ctl* ctl = h->f.ctl;
+    const int K = h->prm.check_every;
+    const int R = h->prm.rebase_every;
+    const float omega = (float)h->prm.omega;
+    const int nrel = sor_blocks(g);
+    double* part = h->f.part[0];
+    double* rel0 = h->f.part[1];
+    double* rel1 = h->f.part[2];
+
+    CK(launch_fold(g, st, P, ctl));
+    CK(launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0));
+    const long long n_checks = max_iter > 0 ? ((long long)max_iter + K - 1) / K : 0;
+    long long c = 0;
+    int batch = 2;
+    int slot = 0;
+    bool pending = false;
+    while (c < n_checks) {
+        const long long nb = std::min<long long>(batch, n_checks - c);
+        for (long long q = 0; q < nb; ++q) {
+            for (int it = 0; it < K; ++it) {
+                CK(launch_sor(g, st, P, 0, omega, it, rel0, ctl));
+                CK(launch_sor(g, st, P, 1, omega, it, rel1, ctl));
+            }
+            const long long cidx = c + q + 1;
+            if (cidx % R == 0) {
+                CK(launch_fold(g, st, P, ctl));
+                CK(launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1));
+            } else {
+                CK(launch_check(g, st, P, part, rel0, rel1, nrel, ctl));
+            }
+        }
+        c += nb;
+        CK(hipMemcpyAsync(&h->h_flag[slot], &ctl->done, sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(hipEventRecord(h->ev[slot], st));
+        if (pending) {
+            CK(hipEventSynchronize(h->ev[1 - slot]));
+            if (h->h_flag[1 - slot] != 0) break;
+        }
+        pending = true;
+        slot = 1 - slot;
+        batch = std::min(batch * 2, 64);
+    }
+    CK(hipMemcpyAsync(h->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const Ctl& hc = *h->h_ctl;
+    if (out) {
+        out->iters = hc.m;
+        out->resid = hc.resid;
+        out->rhs_norm = std::sqrt(hc.rhs2);
+        out->reltmp2 = hc.reltmp2;
+        out->converged = (hc.done == 1 || (hc.done == 0 && hc.resid <= tol)) ? 1 : 0;
+    }
+    if (hc.done == 3 || !std::isfinite(hc.rhs2)) return set_err(h, LES_ENONFINITE, "non-finite residual norm");
+    if (hc.done == 2 || (hc.done == 0 && !(hc.resid <= tol))) return LES_NOT_CONVERGED;
+    return LES_OK;
+}
+
+int ensure_solve_arena(les_handle* h) {
+    if (h->solve_arena) return LES_OK;
+    const size_t cb = align256((size_t)h->g.ctot * sizeof(float));
+    const size_t total = 8 * cb;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) return set_err(h, LES_ENOMEM, "hipMalloc(solve workspace)", e);
+    h->solve_arena = p;
+    CK(hipMemsetAsync(p, 0, total, h->stream));
+    char* b = (char*)p;
+    for (int c = 0; c < 2; ++c) {
+        h->S.ph[c] = (float*)(b + (0 + c) * cb);
+        h->S.pd[c] = (float*)(b + (2 + c) * cb);
+        h->S.r0[c] = (float*)(b + (4 + c) * cb);
+        h->S.rhs[c] = (float*)(b + (6 + c) * cb);
+    }
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+extern "C" {
+
+int les_default_params(les_params* p) {
+    if (!p) return LES_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->omega = 1.8;
+    p->tol = 1e-5;
+    p->check_every = 4;
+    p->max_iter = 20000;
+    p->cs = 0.1;
+    p->nu = 1.5e-5;
+    p->alpha = -10.0;
+    p->beta = -1.0;
+    p->bc[LES_XM] = LES_BC_INFLOW;
+    p->bc[LES_XP] = LES_BC_OUTFLOW;
+    p->bc[LES_YM] = LES_BC_FREESLIP;
+    p->bc[LES_YP] = LES_BC_FREESLIP;
+    p->bc[LES_ZM] = LES_BC_NOSLIP;
+    p->bc[LES_ZP] = LES_BC_FREESLIP;
+    p->zero_guess = 0;
+    p->rebase_every = 4;
+    p->diagnostics = 1;
+    return LES_OK;
+}
+
+int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_t* building_mask,
+               const les_params* prm, les_handle** out) {
+    if (!gr || !s || !out) return LES_EINVAL;
+    *out = nullptr;
+    if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return LES_EINVAL;
+    if (gr->nx > (1 << 20) || gr->ny > (1 << 20) || gr->nz > (1 << 20)) return LES_EINVAL;
+    if (!finite_pos(s->dx) || !finite_pos(s->dy) || !finite_pos(s->dz) || !finite_pos(dt))
+        return LES_EINVAL;
+    les_params p;
+    if (prm) p = *prm;
+    else les_default_params(&p);
+    if (!valid_params(p)) return LES_EINVAL;
+    const long long ncell = (long long)gr->nx * gr->ny * gr->nz;
+    if (ncell > (1LL << 31)) return LES_EINVAL;
+
+    les_handle* h = new (std::nothrow) les_handle();
+    if (!h) return LES_ENOMEM;
+    h->prm = p;
+    h->g = make_geo(gr->nx, gr->ny, gr->nz, *s, dt, p);
+    h->mask.assign((size_t)ncell, 0);
+    if (building_mask) std::memcpy(h->mask.data(), building_mask, (size_t)ncell);
+    auto fail = [&](int code) {
+        les_destroy(h);
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return fail(LES_EDEVICE);
+    if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(LES_EDEVICE);
+    h->stream = h->own_stream;
+
+    const Geo& g = h->g;
+    const size_t nb = align256((size_t)g.ntot * sizeof(float));
+    const size_t cb = align256((size_t)g.ctot * sizeof(float));
+    const size_t fb = align256((size_t)g.ntot);
+    const size_t ncells = align256((size_t)ncell * sizeof(float));
+    const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * sor_blocks(g)) + 64;
+    const size_t pb = align256(nparts * sizeof(double));
+    const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 8 * cb +
+                         3 * pb + align256(sizeof(Ctl));
+    void* arena = nullptr;
+    if (hipMalloc(&arena, total) != hipSuccess) return fail(LES_ENOMEM);
+    h->arena = arena;
+    h->arena_bytes = total;
+    char* b = (char*)arena;
+    auto take = [&](size_t bytes) {
+        char* r = b;
+        b += bytes;
+        return r;
+    };
+    for (int q = 0; q < 2; ++q) {
+        h->f.u[q] = (float*)take(nb);
+        h->f.v[q] = (float*)take(nb);
+        h->f.w[q] = (float*)take(nb);
+    }
+    h->f.nut = (float*)take(nb);
+    h->f.fu = (float*)take(nb); h->f.fv = (float*)take(nb); h->f.fw = (float*)take(nb);
+    h->f.su = (float*)take(nb); h->f.sv = (float*)take(nb); h->f.sw = (float*)take(nb);
+    h->f.flags = (uint8_t*)take(fb);
+    h->f.prof = (float*)take(align256((size_t)g.nz * sizeof(float)));
+    h->f.stage = (float*)take(ncells);
+    for (int c = 0; c < 2; ++c) h->f.P.ph[c] = (float*)take(cb);
+    for (int c = 0; c < 2; ++c) h->f.P.pd[c] = (float*)take(cb);
+    for (int c = 0; c < 2; ++c) h->f.P.r0[c] = (float*)take(cb);
+    for (int c = 0; c < 2; ++c) h->f.P.rhs[c] = (float*)take(cb);
+    for (int q = 0; q < 3; ++q) h->f.part[q] = (double*)take(pb);
+    h->f.ctl = (Ctl*)take(align256(sizeof(Ctl)));
+
+    if (hipMemsetAsync(arena, 0, total, h->stream) != hipSuccess) return fail(LES_EDEVICE);
+    std::vector<uint8_t> flags = build_flags(g, h->mask);
+    if (hipMemcpyAsync(h->f.flags, flags.data(), flags.size(), hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+        return fail(LES_EDEVICE);
+    if (hipHostMalloc((void**)&h->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+        return fail(LES_ENOMEM);
+    if (hipHostMalloc((void**)&h->h_flag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return fail(LES_ENOMEM);
+    for (int q = 0; q < 2; ++q)
+        if (hipEventCreateWithFlags(&h->ev[q], hipEventDisableTiming) != hipSuccess)
+            return fail(LES_EDEVICE);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(LES_EDEVICE);
+    h->prof.assign((size_t)g.nz, 0.f);
+    *out = h;
+    return LES_OK;
+}
+
+void les_destroy(les_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->arena) (void)hipFree(h->arena);
+    if (h->solve_arena) (void)hipFree(h->solve_arena);
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+    if (h->h_flag) (void)hipHostFree(h->h_flag);
+    for (int q = 0; q < 2; ++q)
+        if (h->ev[q]) (void)hipEventDestroy(h->ev[q]);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    delete h;
+}
+
+const char* les_last_error(const les_handle* h) { return h ? h->err.c_str() : ""; }
+
+int les_set_stream(les_handle* h, void* stream) {
+    if (!h) return LES_EINVAL;
+    CK(hipStreamSynchronize(h->stream));
+    h->stream = stream ? (hipStream_t)stream : h->own_stream;
+    return LES_OK;
+}
+
+int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_t seed) {
+    if (!h || !profile) return LES_EINVAL;
+    if (!(std::isfinite(noise_amp) && noise_amp >= 0.f)) return set_err(h, LES_EINVAL, "noise_amp");
+    const Geo& g = h->g;
+    for (int k = 0; k < g.nz; ++k)
+        if (!std::isfinite(profile[k])) return set_err(h, LES_EINVAL, "profile not finite");
+    std::memcpy(h->prof.data(), profile, (size_t)g.nz * sizeof(float));
+    h->amp = noise_amp;
+    h->seed = seed;
+    CK(hipMemcpyAsync(h->f.prof, h->prof.data(), (size_t)g.nz * sizeof(float),
+                      hipMemcpyHostToDevice, h->stream));
+    if (!h->have_inflow) {
+        // initial wind profile on fluid u-faces, zero on solid ones
+        std::vector<float> u((size_t)g.ntot, 0.f), v((size_t)g.ntot, 0.f), w((size_t)g.ntot, 0.f);
+        std::vector<uint8_t> flags = build_flags(g, h->mask);
+        for (int k = 1; k <= g.nz; ++k)
+            for (int j = 1; j <= g.ny; ++j)
+                for (int i = 0; i <= g.nx; ++i)
+                    u[g.nat(i, j, k)] = (flags[g.nat(i, j, k)] & F_USOLID) ? 0.f : profile[k - 1];
+        zero_walls(g, h->prm, u.data(), v.data(), w.data());
+        int rc = upload_velocity(h, u, v, w);
+        if (rc != LES_OK) return rc;
+        for (int c = 0; c < 2; ++c) {
+            CK(launch_fill(h->stream, h->f.P.ph[c], g.ctot, 0.f));
+            CK(launch_fill(h->stream, h->f.P.pd[c], g.ctot, 0.f));
+        }
+        h->have_inflow = true;
+    }
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+int les_step(les_handle* h, int32_t n, les_step_stats* st) {
+    if (!h || n < 0) return LES_EINVAL;
+    if (!h->have_inflow) return set_err(h, LES_ESTATE, "les_set_inflow (or les_set_fields) first");
+    auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = h->g;
+    const les_params& p = h->prm;
+    hipStream_t s = h->stream;
+    const double delta = std::cbrt((double)g.dx * g.dy * g.dz);
+    const float c2 = (float)((p.cs * delta) * (p.cs * delta));
+    les_step_stats acc{};
+    if (st) acc.iters_out = st->iters_out;
+    acc.div_new_last = -1.0;
+    acc.cfl_last = -1.0;
+    int worst = LES_OK;
+    for (int q = 0; q < n; ++q) {
+        const int a = h->cur, b = 1 - h->cur;
+        CK(launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2));
+        CK(launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu, h->f.fv,
+                           h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags, h->f.u[b], h->f.v[b],
+                           h->f.w[b], (float)p.nu, (float)p.alpha, (float)p.beta,
+                           h->have_old ? 0 : 1));
+        h->have_old = true;
+        if (g.inflow) CK(launch_inflow(g, s, h->f.u[b], h->f.prof, h->f.flags, h->amp, h->seed, h->step + 1));
+        CK(launch_ctl_init(s, h->f.ctl, p.tol, p.max_iter, p.check_every));
+        CK(launch_rhs(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P.rhs, h->f.part[0], h->f.ctl,
+                      singular(h) ? 1 : 0));
+        if (singular(h)) CK(launch_remove_mean_rhs(g, s, h->f.P.rhs, h->f.part[0], h->f.ctl));
+        if (p.zero_guess)
+            for (int c = 0; c < 2; ++c) {
+                CK(launch_fill(s, h->f.P.ph[c], g.ctot, 0.f));
+                CK(launch_fill(s, h->f.P.pd[c], g.ctot, 0.f));
+            }
+        les_solve_stats ss{};
+        int rc = run_solve(h, h->f.P, p.tol, p.max_iter, &ss);
+        if (rc < 0) return rc;
+        if (rc == LES_NOT_CONVERGED) {
+            acc.not_converged += 1;
+            worst = LES_NOT_CONVERGED;
+        }
+        if (singular(h)) CK(launch_remove_mean_p(g, s, h->f.P, h->f.part[0], h->f.ctl));
+        CK(launch_project(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P));
+        CK(launch_bc(g, s, h->f.u[b], h->f.v[b], h->f.w[b]));
+        h->cur = b;
+        h->step += 1;
+        acc.steps += 1;
+        acc.sor_iters_total += ss.iters;
+        acc.sor_iters_last = ss.iters;
+        acc.resid_last = ss.resid;
+        acc.reltmp2_last = ss.reltmp2;
+        acc.rhs_norm_last = ss.rhs_norm;
+        acc.div_star_last = (double)g.dt * ss.rhs_norm;
+        if (acc.iters_out) acc.iters_out[q] = ss.iters;
+        if (p.diagnostics && q == n - 1) {
+            CK(launch_diag(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.part[0], h->f.ctl));
+            CK(hipMemcpyAsync(h->h_ctl, h->f.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            CK(hipStreamSynchronize(s));
+            acc.div_new_last = std::sqrt(h->h_ctl->div2);
+            acc.cfl_last = h->h_ctl->cfl;
+            if (!std::isfinite(acc.div_new_last) || !std::isfinite(acc.cfl_last)) {
+                if (st) *st = acc;
+                return set_err(h, LES_ENONFINITE, "non-finite divergence or CFL");
+            }
+        }
+    }
+    CK(hipStreamSynchronize(s));
+    acc.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = acc;
+    return worst;
+}
+
+static int solve_common(les_handle* h, double tol, int32_t max_iter, les_solve_stats* st) {
+    const Geo& g = h->g;
+    hipStream_t s = h->stream;
+    CK(launch_ctl_init(s, h->f.ctl, tol, max_iter, h->prm.check_every));
+    if (singular(h)) {
+        CK(launch_colour_norm(g, s, h->S.rhs, h->f.part[0], h->f.ctl, 1));
+        CK(launch_remove_mean_rhs(g, s, h->S.rhs, h->f.part[0], h->f.ctl));
+    } else {
+        CK(launch_colour_norm(g, s, h->S.rhs, h->f.part[0], h->f.ctl, 0));
+    }
+    int rc = run_solve(h, h->S, tol, max_iter, st);
+    if (rc < 0) return rc;
+    if (singular(h)) CK(launch_remove_mean_p(g, s, h->S, h->f.part[0], h->f.ctl));
+    return rc;
+}
+
+int les_pressure_solve(les_handle* h, const float* rhs, float* p, double tol, int32_t max_iter,
+                       les_solve_stats* st) {
+    if (!h || !rhs || !p) return LES_EINVAL;
+    if (!finite_pos(tol) || max_iter < 0) return set_err(h, LES_EINVAL, "tol/max_iter");
+    int rc = ensure_solve_arena(h);
+    if (rc != LES_OK) return rc;
+    const Geo& g = h->g;
+    hipStream_t s = h->stream;
+    const size_t bytes = (size_t)g.nx * g.ny * g.nz * sizeof(float);
+    // stage holds one cell array: load rhs, scatter, load p, scatter
+    CK(hipMemcpyAsync(h->f.stage, rhs, bytes, hipMemcpyHostToDevice, s));
+    CK(launch_cells_to_colour(g, s, h->f.stage, h->S.rhs));
+    CK(hipMemcpyAsync(h->f.stage, p, bytes, hipMemcpyHostToDevice, s));
+    CK(launch_cells_to_colour(g, s, h->f.stage, h->S.ph));
+    for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->S.pd[c], g.ctot, 0.f));
+    rc = solve_common(h, tol, max_iter, st);
+    if (rc < 0) return rc;
+    CK(launch_pair_to_cells(g, s, h->S, h->f.stage));
+    CK(hipMemcpyAsync(p, h->f.stage, bytes, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return rc;
+}
+
+int les_pressure_solve_dev(les_handle* h, const float* d_rhs, float* d_p, double tol,
+                           int32_t max_iter, les_solve_stats* st, void* stream) {
+    if (!h || !d_rhs || !d_p) return LES_EINVAL;
+    if (!finite_pos(tol) || max_iter < 0) return set_err(h, LES_EINVAL, "tol/max_iter");
+    int rc = ensure_solve_arena(h);
+    if (rc != LES_OK) return rc;
+    hipStream_t saved = h->stream;
+    if (stream) h->stream = (hipStream_t)stream;
+    const Geo& g = h->g;
+    hipStream_t s = h->stream;
+    auto body = [&]() -> int {
+        CK(launch_cells_to_colour(g, s, d_rhs, h->S.rhs));
+        CK(launch_cells_to_colour(g, s, d_p, h->S.ph));
+        for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->S.pd[c], g.ctot, 0.f));
+        int r = solve_common(h, tol, max_iter, st);
+        if (r < 0) return r;
+        CK(launch_pair_to_cells(g, s, h->S, d_p));
+        return r;
+    };
+    rc = body();
+    h->stream = saved;
+    return rc;
+}
+
+int les_get_fields(les_handle* h, float* u, float* v, float* w, float* p) {
+    if (!h) return LES_EINVAL;
+    const Geo& g = h->g;
+    std::vector<float> box;
+    int rc;
+    if (u) {
+        if ((rc = download(h, h->f.u[h->cur], box)) != LES_OK) return rc;
+        unpack_u(g, box.data(), u);
+    }
+    if (v) {
+        if ((rc = download(h, h->f.v[h->cur], box)) != LES_OK) return rc;
+        unpack_v(g, box.data(), v);
+    }
+    if (w) {
+        if ((rc = download(h, h->f.w[h->cur], box)) != LES_OK) return rc;
+        unpack_w(g, box.data(), w);
+    }
+    if (p) {
+        CK(launch_pair_to_cells(g, h->stream, h->f.P, h->f.stage));
+        CK(hipMemcpyAsync(p, h->f.stage, (size_t)g.nx * g.ny * g.nz * sizeof(float),
+                          hipMemcpyDeviceToHost, h->stream));
+        CK(hipStreamSynchronize(h->stream));
+    }
+    return LES_OK;
+}
+
+int les_get_fields_dev(les_handle* h, float* d_u, float* d_v, float* d_w, float* d_p,
+                       void* stream) {
+    if (!h) return LES_EINVAL;
+    const Geo& g = h->g;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    // owned sub-boxes copied row by row with 3-D copies
+    auto copy3 = [&](float* dst, const float* src, int nxo, int nyo, int nzo, int i0, int j0,
+                     int k0) -> hipError_t {
+        hipMemcpy3DParms prm{};
+        prm.srcPtr = make_hipPitchedPtr((void*)src, (size_t)g.sx * sizeof(float), g.sx, g.ny + 2);
+        prm.srcPos = make_hipPos((size_t)i0 * sizeof(float), (size_t)j0, (size_t)k0);
+        prm.dstPtr = make_hipPitchedPtr(dst, (size_t)nxo * sizeof(float), nxo, nyo);
+        prm.dstPos = make_hipPos(0, 0, 0);
+        prm.extent = make_hipExtent((size_t)nxo * sizeof(float), (size_t)nyo, (size_t)nzo);
+        prm.kind = hipMemcpyDeviceToDevice;
+        return hipMemcpy3DAsync(&prm, s);
+    };
+    if (d_u) CK(copy3(d_u, h->f.u[h->cur], g.nx + 1, g.ny, g.nz, 0, 1, 1));
+    if (d_v) CK(copy3(d_v, h->f.v[h->cur], g.nx, g.ny + 1, g.nz, 1, 0, 1));
+    if (d_w) CK(copy3(d_w, h->f.w[h->cur], g.nx, g.ny, g.nz + 1, 1, 1, 0));
+    if (d_p) CK(launch_pair_to_cells(g, s, h->f.P, d_p));
+    return LES_OK;
+}
+
+int les_set_fields(les_handle* h, const float* u, const float* v, const float* w, const float* p,
+                   int32_t reset_history) {
+    if (!h) return LES_EINVAL;
+    const Geo& g = h->g;
+    std::vector<float> U, V, W;
+    int rc;
+    if ((rc = download(h, h->f.u[h->cur], U)) != LES_OK) return rc;
+    if ((rc = download(h, h->f.v[h->cur], V)) != LES_OK) return rc;
+    if ((rc = download(h, h->f.w[h->cur], W)) != LES_OK) return rc;
+    if (u) pack_u(g, u, U.data());
+    if (v) pack_v(g, v, V.data());
+    if (w) pack_w(g, w, W.data());
+    zero_walls(g, h->prm, U.data(), V.data(), W.data());
+    if ((rc = upload_velocity(h, U, V, W)) != LES_OK) return rc;
+    if (p) {
+        const size_t bytes = (size_t)g.nx * g.ny * g.nz * sizeof(float);
+        CK(hipMemcpyAsync(h->f.stage, p, bytes, hipMemcpyHostToDevice, h->stream));
+        CK(launch_cells_to_colour(g, h->stream, h->f.stage, h->f.P.ph));
+        for (int c = 0; c < 2; ++c) CK(launch_fill(h->stream, h->f.P.pd[c], g.ctot, 0.f));
+        CK(hipStreamSynchronize(h->stream));
+    }
+    if (reset_history) h->have_old = false;
+    h->have_inflow = true;
+    return LES_OK;
+}
+
+int les_get_aux(les_handle* h, int32_t which, float* a, float* b, float* c) {
+    if (!h) return LES_EINVAL;
+    const Geo& g = h->g;
+    std::vector<float> box;
+    int rc;
+    switch (which) {
+        case 0:
+            if (!a) return LES_OK;
+            if ((rc = download(h, h->f.nut, box)) != LES_OK) return rc;
+            unpack_cells(g, box.data(), a);
+            return LES_OK;
+        case 1:
+            if (!a) return LES_OK;
+            CK(launch_colour_to_cells(g, h->stream, h->f.P.rhs, h->f.stage));
+            CK(hipMemcpyAsync(a, h->f.stage, (size_t)g.nx * g.ny * g.nz * sizeof(float),
+                              hipMemcpyDeviceToHost, h->stream));
+            CK(hipStreamSynchronize(h->stream));
+            return LES_OK;
+        case 2:
+        case 3: {
+            float* src[3] = {which == 2 ? h->f.fu : h->f.su, which == 2 ? h->f.fv : h->f.sv,
+                             which == 2 ? h->f.fw : h->f.sw};
+            if (a) {
+                if ((rc = download(h, src[0], box)) != LES_OK) return rc;
+                unpack_u(g, box.data(), a);
+            }
+            if (b) {
+                if ((rc = download(h, src[1], box)) != LES_OK) return rc;
+                unpack_v(g, box.data(), b);
+            }
+            if (c) {
+                if ((rc = download(h, src[2], box)) != LES_OK) return rc;
+                unpack_w(g, box.data(), c);
+            }
+            return LES_OK;
+        }
+        default:
+            return set_err(h, LES_EINVAL, "les_get_aux: unknown which");
+    }
+}
+
+int les_get_ghosted(les_handle* h, float* u, float* v, float* w) {
+    if (!h) return LES_EINVAL;
+    const Geo& g = h->g;
+    std::vector<float> box;
+    float* dst[3] = {u, v, w};
+    float* src[3] = {h->f.u[h->cur], h->f.v[h->cur], h->f.w[h->cur]};
+    for (int q = 0; q < 3; ++q) {
+        if (!dst[q]) continue;
+        int rc = download(h, src[q], box);
+        if (rc != LES_OK) return rc;
+        for (int k = 0; k < g.nz + 2; ++k)
+            for (int j = 0; j < g.ny + 2; ++j)
+                for (int i = 0; i < g.nx + 2; ++i)
+                    dst[q][((size_t)k * (g.ny + 2) + j) * (g.nx + 2) + i] = box[g.nat(i, j, k)];
+    }
+    return LES_OK;
+}
+
+int les_get_step(const les_handle* h, int64_t* step) {
+    if (!h || !step) return LES_EINVAL;
+    *step = h->step;
+    return LES_OK;
+}
+
+// ------------------------------------------------------------ checkpoint
+namespace {
+struct StateHeader {
+    uint32_t magic;
+    int32_t nx, ny, nz;
+    int32_t bc[6];
+    int64_t step;
+    int32_t have_old, have_inflow;
+    float amp;
+    int32_t pad;
+    uint64_t seed;
+    int64_t ntot, ctot;
+};
+}  // namespace
+
+int les_state_size(const les_handle* h, int64_t* bytes) {
+    if (!h || !bytes) return LES_EINVAL;
+    const Geo& g = h->g;
+    *bytes = (int64_t)sizeof(StateHeader) + (int64_t)g.nz * 4 + 9LL * g.ntot * 4 + 4LL * g.ctot * 4;
+    return LES_OK;
+}
+
+int les_get_state(les_handle* h, void* buf, int64_t bytes) {
+    int64_t need = 0;
+    if (!h || !buf || les_state_size(h, &need) != LES_OK || bytes != need) return LES_EINVAL;
+    const Geo& g = h->g;
+    StateHeader hd{};
+    hd.magic = kStateMagic;
+    hd.nx = g.nx; hd.ny = g.ny; hd.nz = g.nz;
+    for (int f = 0; f < 6; ++f) hd.bc[f] = h->prm.bc[f];
+    hd.step = h->step;
+    hd.have_old = h->have_old;
+    hd.have_inflow = h->have_inflow;
+    hd.amp = h->amp;
+    hd.seed = h->seed;
+    hd.ntot = g.ntot;
+    hd.ctot = g.ctot;
+    char* b = (char*)buf;
+    std::memcpy(b, &hd, sizeof hd);
+    b += sizeof hd;
+    std::memcpy(b, h->prof.data(), (size_t)g.nz * 4);
+    b += (size_t)g.nz * 4;
+    const float* nat[9] = {h->f.u[h->cur], h->f.v[h->cur], h->f.w[h->cur], h->f.fu, h->f.fv,
+                           h->f.fw, h->f.su, h->f.sv, h->f.sw};
+    for (const float* src : nat) {
+        CK(hipMemcpyAsync(b, src, (size_t)g.ntot * 4, hipMemcpyDeviceToHost, h->stream));
+        b += (size_t)g.ntot * 4;
+    }
+    const float* col[4] = {h->f.P.ph[0], h->f.P.ph[1], h->f.P.pd[0], h->f.P.pd[1]};
+    for (const float* src : col) {
+        CK(hipMemcpyAsync(b, src, (size_t)g.ctot * 4, hipMemcpyDeviceToHost, h->stream));
+        b += (size_t)g.ctot * 4;
+    }
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+int les_set_state(les_handle* h, const void* buf, int64_t bytes) {
+    int64_t need = 0;
+    if (!h || !buf || les_state_size(h, &need) != LES_OK || bytes != need) return LES_EINVAL;
+    const Geo& g = h->g;
+    StateHeader hd;
+    const char* b = (const char*)buf;
+    std::memcpy(&hd, b, sizeof hd);
+    if (hd.magic != kStateMagic || hd.nx != g.nx || hd.ny != g.ny || hd.nz != g.nz ||
+        hd.ntot != g.ntot || hd.ctot != g.ctot)
+        return set_err(h, LES_EINVAL, "checkpoint does not match this grid");
+    for (int f = 0; f < 6; ++f)
+        if (hd.bc[f] != h->prm.bc[f]) return set_err(h, LES_EINVAL, "checkpoint BC set differs");
+    b += sizeof hd;
+    std::memcpy(h->prof.data(), b, (size_t)g.nz * 4);
+    b += (size_t)g.nz * 4;
+    CK(hipMemcpyAsync(h->f.prof, h->prof.data(), (size_t)g.nz * 4, hipMemcpyHostToDevice, h->stream));
+    float* nat[9] = {h->f.u[h->cur], h->f.v[h->cur], h->f.w[h->cur], h->f.fu, h->f.fv,
+                     h->f.fw, h->f.su, h->f.sv, h->f.sw};
+    for (float* dst : nat) {
+        CK(hipMemcpyAsync(dst, b, (size_t)g.ntot * 4, hipMemcpyHostToDevice, h->stream));
+        b += (size_t)g.ntot * 4;
+    }
+    // the other velocity buffer gets the same walls / boundary faces
+    const int o = 1 - h->cur;
+    CK(hipMemcpyAsync(h->f.u[o], h->f.u[h->cur], (size_t)g.ntot * 4, hipMemcpyDeviceToDevice, h->stream));
+    CK(hipMemcpyAsync(h->f.v[o], h->f.v[h->cur], (size_t)g.ntot * 4, hipMemcpyDeviceToDevice, h->stream));
+    CK(hipMemcpyAsync(h->f.w[o], h->f.w[h->cur], (size_t)g.ntot * 4, hipMemcpyDeviceToDevice, h->stream));
+    float* col[4] = {h->f.P.ph[0], h->f.P.ph[1], h->f.P.pd[0], h->f.P.pd[1]};
+    for (float* dst : col) {
+        CK(hipMemcpyAsync(dst, b, (size_t)g.ctot * 4, hipMemcpyHostToDevice, h->stream));
+        b += (size_t)g.ctot * 4;
+    }
+    CK(hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    h->have_old = hd.have_old != 0;
+    h->have_inflow = hd.have_inflow != 0;
+    h->amp = hd.amp;
+    h->seed = hd.seed;
+    return LES_OK;
+}
+
+int64_t les_bc_range(const les_grid* gr) {
+    if (!gr || gr->nx < 1 || gr->ny < 1 || gr->nz < 1) return 0;
+    const long long n = bc_items(gr->nx, gr->ny, gr->nz);
+    return (int64_t)nblk(n) * kBlock;   // launch size, padded to whole blocks
+}
+
+int les_bc_map(const les_grid* gr, int64_t item, int32_t* family, int32_t* a, int32_t* b) {
+    if (!gr || !family || !a || !b || item < 0) return LES_EINVAL;
+    int f, x, y;
+    bc_item(gr->nx, gr->ny, gr->nz, item, f, x, y);
+    *family = f;
+    *a = x;
+    *b = y;
+    return LES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Internal declarations of the MI355X LES library: grid geometry, device
+// field table, control block, kernel launchers.  Not part of the public ABI
+// (include/les.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/les.h"
+
+namespace les {
+
+constexpr int kBlock = 256;     // threads per block for the 1-D launches
+constexpr int kNumXcd = 8;      // MI355X: 8 XCDs, blocks dispatched round-robin
+constexpr int kMaxPartials = 1 << 20;
+
+// Geometry, passed by value to every kernel.
+//
+// Natural ("box") layout for u, v, w and cell fields: index (i, j, k) with
+// 1-based cells and one ghost layer, i in [0, nx+1], j in [0, ny+1],
+// k in [0, nz+1]; x fastest, rows padded to sx floats (128-byte multiple).
+//   u(i,j,k): east face of cell i (i = 0 is the x- boundary face)
+//   v(i,j,k): north face of cell j, w(i,j,k): top face of cell k
+//
+// Colour-split layout for the pressure system (the red-black SOR of
+// section 2.6 with the cells of one colour stored contiguously, so both
+// half-sweeps are unit-stride): 0-based cell (i0, j0, k0) has colour
+// c = (i0 + j0 + k0) & 1 and lives in colour array c at half-index
+// ii = i0 >> 1 of row (j0, k0).  Rows have H = ceil(nx/2) entries and a
+// pitch S >= H + 1 (128-byte multiple), with a zero ghost row before and
+// after every plane, a zero ghost plane below and above, and a guard row
+// in front, so every neighbour read of an SOR sweep lands in the array and
+// reads exact zeros outside the domain.
+struct Geo {
+    int nx, ny, nz;
+    int sx;             // natural row pitch (floats)
+    long long sxy;      // natural plane pitch
+    long long ntot;     // natural field length
+    int H;              // colour row length
+    int S;              // colour row pitch
+    long long SP;       // colour plane pitch = S * (ny + 2)
+    long long ctot;     // colour array length (incl. guard rows)
+    float dx, dy, dz, dt;
+    float idx, idy, idz, idt;
+    float cx, cy, cz;   // 1/h^2
+    int outflow;        // x+ is OUTFLOW (Dirichlet p on that face)
+    int inflow;         // x- is INFLOW
+    int u_last;         // last u-face index whose tendency is computed
+    float s_xm, s_xp, s_ym, s_yp, s_zm, s_zp;  // tangential ghost signs
+
+    __host__ __device__ long long nat(int i, int j, int k) const {
+        return (long long)k * sxy + (long long)j * sx + i;
+    }
+    // colour-array element of 0-based cell row (j0, k0), half-index ii
+    __host__ __device__ long long col(int ii, int j0, int k0) const {
+        return (long long)S + ((long long)(k0 + 1) * (ny + 2) + (j0 + 1)) * S + ii;
+    }
+};
+
+// Control block of one pressure solve (device memory).
+struct Ctl {
+    int done;           // 0 running, 1 converged, 2 hit max_iter, 3 non-finite
+    int m;              // SOR iterations completed
+    int K;              // check interval
+    int max_iter;
+    unsigned cnt[4];    // last-block counters of the reductions
+    double tol;
+    double rhs2;        // sum rhs^2 (after mean removal)
+    double rhs_sum;     // sum rhs (singular case)
+    double resid;       // relative residual at the last check
+    double reltmp2;     // sum reltmp^2 over the last iteration before the last check
+    double div2;        // diagnostics: sum div(u)^2
+    double cfl;         // diagnostics: max CFL
+    double pad[4];
+};
+
+// Bits of the per-cell flag byte.
+enum : uint8_t { F_USOLID = 1, F_VSOLID = 2, F_WSOLID = 4, F_CSOLID = 8 };
+
+struct PBufs {           // one pressure system in colour layout
+    float* ph[2];        // base pressure
+    float* pd[2];        // correction
+    float* r0[2];        // residual of the base, float32
+    float* rhs[2];
+};
+
+struct DevFields {
+    float* u[2];
+    float* v[2];
+    float* w[2];
+    float* nut;
+    float* fu; float* fv; float* fw;     // AB2 history F^{n-1}
+    float* su; float* sv; float* sw;     // feedback integral
+    uint8_t* flags;
+    float* prof;                         // inflow profile [nz]
+    float* stage;                        // natural-order staging (I/O)
+    PBufs P;                             // time-stepping pressure system
+    double* part[3];                     // reduction partials
+    Ctl* ctl;
+};
+
+struct SolveParams {
+    float omega;
+    int K;
+    int max_iter;
+    double tol;
+    int rebase_every;
+};
+
+}  // namespace les
+
+struct les_handle {
+    int device = 0;
+    les::Geo g{};
+    les_params prm{};
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    les::DevFields f{};
+    // lazily allocated workspace of les_pressure_solve
+    void* solve_arena = nullptr;
+    les::PBufs S{};
+    int cur = 0;               // index of u^n in f.u/v/w
+    bool have_inflow = false;
+    bool have_old = false;
+    int64_t step = 0;
+    float amp = 0.f;
+    uint64_t seed = 0;
+    std::vector<float> prof;
+    std::vector<uint8_t> mask;
+    les::Ctl* h_ctl = nullptr;   // pinned mirror of the control block
+    int* h_flag = nullptr;       // pinned, 2 slots for pipelined flag reads
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace les {
+
+// ---- kernel launchers (kernels_*.hip) ----
+hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
+                      const float* w, float* nut, float c2);
+hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const float* v,
+                           const float* w, const float* nut, float* fu, float* fv, float* fw,
+                           float* su, float* sv, float* sw, const uint8_t* flags, float* us,
+                           float* vs, float* ws, float nu, float alpha, float beta, int first);
+hipError_t launch_inflow(const Geo& g, hipStream_t st, float* us, const float* prof,
+                         const uint8_t* flags, float amp, uint64_t seed, int64_t step);
+hipError_t launch_ctl_init(hipStream_t st, Ctl* ctl, double tol, int max_iter, int K);
+hipError_t launch_rhs(const Geo& g, hipStream_t st, const float* us, const float* vs,
+                      const float* ws, float* const rhs[2], double* part, Ctl* ctl,
+                      int singular);
+hipError_t launch_remove_mean_rhs(const Geo& g, hipStream_t st, float* const rhs[2],
+                                  double* part, Ctl* ctl);
+hipError_t launch_fold(const Geo& g, hipStream_t st, const PBufs& P, const Ctl* ctl);
+hipError_t launch_colour_norm(const Geo& g, hipStream_t st, float* const a[2], double* part,
+                              Ctl* ctl, int mode);
+hipError_t launch_rebase(const Geo& g, hipStream_t st, const PBufs& P, double* part,
+                         const double* rel0, const double* rel1, int nrel, Ctl* ctl, int decide);
+hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* part,
+                        const double* rel0, const double* rel1, int nrel, Ctl* ctl);
+hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, float omega,
+                      int local_iter, double* rel_part, const Ctl* ctl);
+int sor_blocks(const Geo& g);
+hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
+                          const PBufs& P);
+hipError_t launch_bc(const Geo& g, hipStream_t st, float* u, float* v, float* w);
+hipError_t launch_diag(const Geo& g, hipStream_t st, const float* u, const float* v,
+                       const float* w, double* part, Ctl* ctl);
+hipError_t launch_remove_mean_p(const Geo& g, hipStream_t st, const PBufs& P, double* part,
+                                Ctl* ctl);
+// natural-order [nz][ny][nx] <-> colour layout
+hipError_t launch_cells_to_colour(const Geo& g, hipStream_t st, const float* src, float* const dst[2]);
+hipError_t launch_pair_to_cells(const Geo& g, hipStream_t st, const PBufs& P, float* dst);
+hipError_t launch_colour_to_cells(const Geo& g, hipStream_t st, float* const src[2], float* dst);
+hipError_t launch_fill(hipStream_t st, float* p, long long n, float v);
+
+// boundary-range item -> (family, a, b); family -1 for padding
+__host__ __device__ inline void bc_item(int nx, int ny, int nz, long long id, int& fam, int& a,
+                                        int& b) {
+    const long long jp = ny + 2, kp = nz + 2, ip = nx;
+    const long long n0 = jp * kp, n1 = ip * kp, n2 = (long long)ip * ny;
+    if (id < n0) {                       // x faces: (j, k) over the full ghosted plane
+        fam = 0; b = (int)(id / jp); a = (int)(id % jp);
+    } else if (id < n0 + n1) {           // y faces: (i, k), i interior, k ghosted
+        long long t = id - n0;
+        fam = 1; b = (int)(t / ip); a = 1 + (int)(t % ip);
+    } else if (id < n0 + n1 + n2) {      // z faces: (i, j), both interior
+        long long t = id - n0 - n1;
+        fam = 2; b = 1 + (int)(t / ip); a = 1 + (int)(t % ip);
+    } else {
+        fam = -1; a = b = 0;
+    }
+}
+__host__ __device__ inline long long bc_items(int nx, int ny, int nz) {
+    return (long long)(ny + 2) * (nz + 2) + (long long)nx * (nz + 2) + (long long)nx * ny;
+}
+
+}  // namespace les

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+The oracle replays the GPU's per-step SOR iteration counts, so both sides
+run the same iteration and differ only by float32 rounding (a
+free-running oracle is also checked to stop within one check interval).
+Bar: relative L2 per field <= 1e-5 after one step, <= 1e-4 after ten.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_02264_amd as les
+from les_inputs import (WORKLOADS, building_heights, building_mask, log_law_profile,
+                        make_workload_inputs, power_law_profile, random_fields, random_rhs)
+
+pytestmark = pytest.mark.gpu
+
+ALL_WALLS = (les.FREESLIP,) * 6
+
+
+def rel(a, b):
+    nb = np.linalg.norm(np.asarray(b, np.float64))
+    return np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / max(nb, 1e-300)
+
+
+def urban_case(nx, ny, nz, seed, cov=0.15, fmax=4, hmax=6):
+    h = building_heights(nx, ny, nz, cov, 2, fmax, 2, hmax, seed=seed, margin_x=4, margin_y=2)
+    return building_mask(h, nz), log_law_profile(nz, 2.0)
+
+
+def pair(nx, ny, nz, mask=None, dx=4.0, dy=4.0, dz=2.0, dt=0.05, **kw):
+    g = les.LES(nx, ny, nz, dx, dy, dz, dt, mask, **kw)
+    o = oracle.Oracle(nx, ny, nz, dx, dy, dz, dt, mask, **kw)
+    return g, o
+
+
+# ------------------------------------------------------------- pressure solve
+@pytest.mark.parametrize("shape", [(5, 7, 4), (33, 17, 9), (64, 48, 16)])
+@pytest.mark.parametrize("bc", [les.URBAN_BC, ALL_WALLS])
+def test_pressure_solve_parity(shape, bc):
+    nx, ny, nz = shape
+    print(f"[pressure_solve_parity] shape={shape} bc={bc}", flush=True)
+    g, o = pair(nx, ny, nz, dx=2.0, dy=2.0, dz=1.0, bc=bc)
+    rhs = random_rhs(nx, ny, nz, seed=nx * 7 + ny, smooth=2)
+    p0 = random_rhs(nx, ny, nz, seed=3, smooth=1) * 0.1
+    p, st, rc = g.pressure_solve(rhs, p0, tol=1e-5, max_iter=20000)
+    assert rc == les.LES_OK and st["converged"] == 1
+    po, sto, _ = o.pressure_solve(rhs, p0, tol=1e-5, max_iter=20000, forced=st["iters"])
+    if bc == ALL_WALLS:
+        p = p - p.mean()
+        po = po - po.mean()
+    assert rel(p, po) <= 1e-5
+    # the GPU's float64 residual agrees with the oracle's residual of the GPU answer
+    r_of_gpu = o.residual(rhs - (rhs.mean() if bc == ALL_WALLS else 0.0), p)
+    assert st["resid"] <= 1e-5
+    assert r_of_gpu <= 1.05e-5
+    # a free-running oracle stops within one check interval of the GPU
+    _, stf, _ = o.pressure_solve(rhs, p0, tol=1e-5, max_iter=20000)
+    assert abs(stf["iters"] - st["iters"]) <= 4
+
+
+def test_pressure_solve_edge_cases():
+    g, o = pair(6, 5, 4, dx=1.0, dy=1.0, dz=1.0)
+    z = np.zeros((4, 5, 6), np.float32)
+    p, st, rc = g.pressure_solve(z, z, tol=1e-5)
+    assert rc == les.LES_OK and st["iters"] == 0 and np.all(p == 0)
+    rhs = random_rhs(6, 5, 4, seed=1)
+    p0 = np.full_like(rhs, 0.5)
+    p, st, rc = g.pressure_solve(rhs, p0, tol=1e-5, max_iter=0)
+    assert rc == les.LES_NOT_CONVERGED and st["iters"] == 0 and np.array_equal(p, p0)
+    p, st, rc = g.pressure_solve(rhs, None, tol=1e-5, max_iter=6)
+    assert rc == les.LES_NOT_CONVERGED and st["iters"] == 6
+    po, _, _ = o.pressure_solve(rhs, None, forced=6)
+    assert rel(p, po) <= 1e-6
+
+
+def test_pressure_solve_dev_matches_host():
+    import torch
+    nx, ny, nz = 33, 17, 9
+    g = les.LES(nx, ny, nz, 2.0, 2.0, 1.0, 0.05)
+    rhs = random_rhs(nx, ny, nz, seed=5, smooth=2)
+    p_host, st_h, _ = g.pressure_solve(rhs, None)
+    d_rhs = torch.from_numpy(rhs).cuda()
+    d_p = torch.zeros_like(d_rhs)
+    st_d, _ = g.pressure_solve_dev(d_rhs, d_p, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st_d["iters"] == st_h["iters"]
+    assert np.array_equal(d_p.cpu().numpy(), p_host)
+
+
+# ----------------------------------------------------------------- one step
+@pytest.mark.parametrize("case", ["urban24", "odd33", "C1"])
+def test_one_step_parity(case):
+    print(f"[one_step_parity] case={case}", flush=True)
+    if case == "C1":
+        w = WORKLOADS["C1"]
+        mask, prof = make_workload_inputs(w)
+        nx, ny, nz, seed = w.nx, w.ny, w.nz, w.seed
+    elif case == "odd33":
+        nx, ny, nz, seed = 33, 17, 9, 4
+        mask, prof = urban_case(nx, ny, nz, seed, hmax=5)
+    else:
+        nx, ny, nz, seed = 24, 20, 12, 1
+        mask, prof = urban_case(nx, ny, nz, seed)
+    g, o = pair(nx, ny, nz, mask)
+    g.set_inflow(prof, 0.01, seed)
+    o.set_inflow(prof, 0.01, seed)
+    rc, st, iters = g.step(1)
+    assert rc == les.LES_OK
+    o.step(1, forced=iters)
+    for name, a, b in zip("uvwp", g.get_fields(), o.get_fields()):
+        e = rel(a, b)
+        print(f"  {name}: rel L2 {e:.3e}", flush=True)
+        assert e <= 1e-5, name
+    assert rel(g.get_nut(), o.get_nut()) <= 1e-5
+    assert rel(g.get_rhs(), o.get_rhs()) <= 1e-5
+    for a, b in zip(g.get_force(), o.get_force()):
+        assert rel(a, b) <= 1e-5
+    for a, b in zip(g.get_usum(), o.get_usum()):
+        if np.linalg.norm(b) > 0:
+            assert rel(a, b) <= 1e-5
+    # projection identity (P5) on the GPU: ||div u^{n+1}|| / ||div u*|| = R
+    assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
+
+
+@pytest.mark.slow
+def test_ten_step_parity_C1():
+    w = WORKLOADS["C1"]
+    print("[ten_step_parity_C1]", flush=True)
+    mask, prof = make_workload_inputs(w)
+    g, o = pair(w.nx, w.ny, w.nz, mask, w.dx, w.dy, w.dz, w.dt)
+    g.set_inflow(prof, w.noise_amp, w.seed)
+    o.set_inflow(prof, w.noise_amp, w.seed)
+    rc, st, iters = g.step(w.steps)
+    assert rc == les.LES_OK and st["not_converged"] == 0
+    o.step(w.steps, forced=iters)
+    for name, a, b in zip("uvwp", g.get_fields(), o.get_fields()):
+        e = rel(a, b)
+        print(f"  {name}: rel L2 {e:.3e} iters {list(iters)}", flush=True)
+        assert e <= 1e-4, name
+
+
+# ------------------------------------------------------------- boundaries
+@pytest.mark.parametrize("bc", [les.URBAN_BC, ALL_WALLS,
+                                (les.INFLOW, les.NOSLIP, les.NOSLIP, les.FREESLIP,
+                                 les.FREESLIP, les.NOSLIP)])
+def test_ghosts_match_oracle(bc):
+    nx, ny, nz = 9, 6, 5
+    g, o = pair(nx, ny, nz, bc=bc)
+    u, v, w, p = random_fields(nx, ny, nz, seed=2)
+    g.set_fields(u, v, w, p)
+    o.set_fields(u, v, w, p)
+    for a, b in zip(g.get_ghosted(), o.get_ghosted()):
+        assert np.array_equal(a.astype(np.float64), b)
+
+
+def test_uniform_flow_preserved():
+    """P6 on the GPU: constant inflow, no buildings, free-slip ground."""
+    nx, ny, nz = 32, 24, 16
+    bc = (les.INFLOW, les.OUTFLOW, les.FREESLIP, les.FREESLIP, les.FREESLIP, les.FREESLIP)
+    g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, bc=bc)
+    U = 3.25
+    g.set_inflow(np.full(nz, U, np.float32), 0.0, 1)
+    rc, st, iters = g.step(10)
+    u, v, w, p = g.get_fields()
+    assert np.abs(u - U).max() <= 1e-6 * U
+    assert np.abs(v).max() <= 1e-6 and np.abs(w).max() <= 1e-6 and np.abs(p).max() <= 1e-6
+    assert st["sor_iters_total"] == 0
+
+
+def test_taylor_green_decay_gpu():
+    """P7 on the GPU: the free-slip Taylor-Green mode follows the AB2 recursion."""
+    nx, ny, nz, dt, nu = 4, 16, 16, 0.1, 1.0
+    g = les.LES(nx, ny, nz, 1.0, 1.0, 1.0, dt, bc=ALL_WALLS, cs=0.0, nu=nu)
+    A = 1e-3
+    Ly = Lz = 16.0
+    ky, kz = math.pi / Ly, math.pi / Lz
+    B = A * math.sin(ky / 2) / math.sin(kz / 2)
+    yf, yc = np.arange(ny + 1), np.arange(ny) + 0.5
+    zf, zc = np.arange(nz + 1), np.arange(nz) + 0.5
+    v0 = (A * np.sin(ky * yf)[None, :, None] * np.cos(kz * zc)[:, None, None] * np.ones((1, 1, nx)))
+    w0 = (-B * np.cos(ky * yc)[None, :, None] * np.sin(kz * zf)[:, None, None] * np.ones((1, 1, nx)))
+    g.set_fields(np.zeros((nz, ny, nx + 1)), v0, w0, np.zeros((nz, ny, nx)))
+    lam = -4 * math.sin(ky / 2) ** 2 - 4 * math.sin(kz / 2) ** 2
+    mu = nu * lam * dt
+    a = [1.0, 1.0 + mu]
+    for n in range(1, 8):
+        a.append(a[n] + mu * (1.5 * a[n] - 0.5 * a[n - 1]))
+    for n in range(1, 9):
+        g.step(1)
+        _, v, w, _ = g.get_fields()
+        amp = np.vdot(v.astype(np.float64), v0) / np.vdot(v0, v0)
+        assert amp == pytest.approx(a[n], rel=1e-5)
+
+
+# ------------------------------------------------------ state, determinism
+def test_checkpoint_resume_bitwise():
+    nx, ny, nz = 24, 20, 12
+    mask, prof = urban_case(nx, ny, nz, 3)
+    a = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+    a.set_inflow(prof, 0.01, 3)
+    a.step(6)
+    ref = a.get_fields()
+    b = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+    b.set_inflow(prof, 0.01, 3)
+    b.step(3)
+    blob = b.get_state()
+    b.close()
+    c = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+    c.set_state(blob)
+    assert c.get_step() == 3
+    c.step(3)
+    for x, y in zip(ref, c.get_fields()):
+        assert np.array_equal(x, y)
+
+
+def test_runs_are_bitwise_deterministic():
+    nx, ny, nz = 33, 17, 9
+    mask, prof = urban_case(nx, ny, nz, 4, hmax=5)
+    out = []
+    for _ in range(2):
+        g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+        g.set_inflow(prof, 0.01, 4)
+        _, _, iters = g.step(3)
+        out.append((g.get_fields(), tuple(iters)))
+        g.close()
+    assert out[0][1] == out[1][1]
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------- error paths
+def test_error_statuses():
+    g = les.LES(8, 8, 8, 1.0, 1.0, 1.0, 0.05)
+    with pytest.raises(les.LesError) as e:
+        g.step(1)
+    assert e.value.code == les.LES_ESTATE
+    g.set_inflow(np.linspace(1, 2, 8).astype(np.float32), 0.01, 1)
+    g2 = les.LES(16, 12, 8, 1.0, 1.0, 1.0, 0.05, max_iter=1)
+    g2.set_inflow(np.linspace(1, 2, 8).astype(np.float32), 0.01, 1)
+    rc, st, iters = g2.step(1)
+    assert rc == les.LES_NOT_CONVERGED and iters[0] == 1 and st["not_converged"] == 1
+    u, v, w, p = g.get_fields()
+    u[3, 3, 3] = np.nan
+    g.set_fields(u, v, w, p)
+    with pytest.raises(les.LesError) as e:
+        g.step(1)
+    assert e.value.code == les.LES_ENONFINITE
+
+
+# ------------------------------------------------- full-size properties
+@pytest.mark.parametrize("name", ["C2"])
+def test_full_size_stage_parity(name):
+    """At the benchmark grid: nu_t, tendency and rhs of one step against the
+    oracle over the whole field, and the projection identity."""
+    w = WORKLOADS[name]
+    print(f"[full_size_stage_parity] {name}", flush=True)
+    mask, prof = make_workload_inputs(w)
+    g, o = pair(w.nx, w.ny, w.nz, mask, w.dx, w.dy, w.dz, w.dt)
+    g.set_inflow(prof, w.noise_amp, w.seed)
+    o.set_inflow(prof, w.noise_amp, w.seed)
+    u0, v0, w0, p0 = g.get_fields()
+    rc, st, iters = g.step(1)
+    assert st["resid_last"] <= 1e-5 or rc == les.LES_NOT_CONVERGED
+    nut_o = o.nut_of(u0, v0, w0)
+    assert rel(g.get_nut(), nut_o) <= 1e-5
+    o.step(1, forced=[0])   # tendency, inflow and rhs are independent of the solve
+    for a, b in zip(g.get_force(), o.get_force()):
+        assert rel(a, b) <= 1e-5
+    assert rel(g.get_rhs(), o.get_rhs()) <= 1e-5
+    if rc == les.LES_OK:
+        assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)

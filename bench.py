@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X urban-LES time step.
+
+One benchmark step is one full LES time step (nu_t, tendency + feedback +
+AB2, inflow, rhs, red-black SOR to relative residual 1e-5, projection,
+ghost refresh) on the 300 x 300 x 90 urban workload (30% building cover,
+power-law inflow), inputs resident in HBM before the timed region.
+
+Prints ONE JSON line:
+  value      LES cell-updates/s = cells * steps / wall time of les_step(steps)
+  roofline   the dominant kernel (SOR half-sweep): algorithmic bytes per launch
+             (8 B per cell: 4 B of the other colour, 4 B own p, 4 B own rhs
+             read for half the cells... see the design doc) over its mean HIP-event
+             duration on the library's stream
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, mask, prof, gpu_iters_per_step, sample_iters):
+    """Time the FP64 oracle on this host: one step's non-SOR work plus a
+    bounded number of SOR iterations, combined at the GPU's mean iteration
+    count into a per-step time."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask)
+    o.set_inflow(prof, w.noise_amp, w.seed)
+    t0 = time.perf_counter()
+    o.step(1, forced=[0])          # all of the step except the SOR iterations
+    t_fixed = time.perf_counter() - t0
+    rhs = o.get_rhs()
+    p0 = o.get_fields()[3]
+    t0 = time.perf_counter()
+    o.sor_iterations(rhs, p0, sample_iters)
+    t_iter = (time.perf_counter() - t0) / sample_iters
+    t_step = t_fixed + gpu_iters_per_step * t_iter
+    cells = w.nx * w.ny * w.nz
+    return {
+        "value": cells / t_step,
+        "unit": "cell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{w.name} {w.nx}x{w.ny}x{w.nz}: 1 step without SOR ({t_fixed:.2f} s) + "
+                   f"{sample_iters} SOR iterations ({t_iter * 1e3:.1f} ms each), combined at the "
+                   f"GPU's mean {gpu_iters_per_step:.0f} iterations/step -> {t_step:.2f} s/step "
+                   f"(extrapolated)"),
+        "s_per_step": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=100)
+    ap.add_argument("--no-timing", action="store_true",
+                    help="do not bracket kernels with HIP events (no roofline object)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1504_02264_amd as les
+    from les_inputs import WORKLOADS, make_workload_inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    cells = w.nx * w.ny * w.nz
+    mask, prof = make_workload_inputs(w)
+    g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask,
+                timing=0 if args.no_timing else 1)
+    g.set_inflow(prof, w.noise_amp, w.seed)
+    log(f"workload {w.name} {w.nx}x{w.ny}x{w.nz} ({cells} cells); warmup {args.warmup} steps")
+    if args.warmup:
+        g.step(args.warmup)
+    g.get_timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, iters = g.step(args.steps)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {dt_s:.3f} s; SOR iterations/step mean {iters.mean():.0f}")
+    timing = g.get_timing(reset=True)
+
+    value = cells * args.steps / dt_s
+    out = {
+        "metric": "LES cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: urban LES {w.nx}x{w.ny}x{w.nz}, dx=dy={w.dx} m dz={w.dz} m, "
+                         f"dt={w.dt} s, {int(w.coverage * 100)}% building cover (heights "
+                         f"{w.h_min}-{w.h_max} cells), {w.profile}-law inflow + {w.noise_amp:.0%} "
+                         f"noise, red-black SOR omega=1.8 to relative residual 1e-5"),
+            "cells": cells,
+            "sor_iters_per_step": float(iters.mean()),
+            "steps_per_s": args.steps / dt_s,
+            "not_converged_steps": int(st["not_converged"]),
+            "resid_last": st["resid_last"],
+        },
+    }
+    sor_ms, sor_n = timing["sor"]
+    if sor_n > 0:
+        t_launch = sor_ms / sor_n * 1e-3
+        bytes_per_launch = 8.0 * cells      # per half-sweep, see the design doc
+        achieved = bytes_per_launch / t_launch / 1e9
+        out["roofline"] = {
+            "bound": "hbm",
+            "kernel": "k_sor (red-black SOR half-sweep)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launch_us": t_launch * 1e6,
+            "timed_launches": int(sor_n),
+        }
+        out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in timing.items()
+                                     if v[1] > 0 and k != "sor"}
+        # the SOR sweeps are sampled (one check interval in 8): scale to all
+        out["kernel_ms_per_step"]["sor"] = (sor_ms / sor_n) * 2 * float(iters.mean())
+        out["time_to_resid_1e-5_ms"] = (out["kernel_ms_per_step"]["sor"]
+                                         + out["kernel_ms_per_step"].get("check", 0.0)
+                                         + out["kernel_ms_per_step"].get("rebase", 0.0))
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(w, mask, prof, float(iters.mean()), args.cpu_sample_iters)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,7 +83,9 @@ typedef struct {
                                 R residual checks (4); see les_pressure_solve */
     int32_t diagnostics;     /* 1: compute ||div u^{n+1}|| and max CFL on the last
                                 step of each les_step call (default 1) */
-    int32_t pad_;
+    int32_t timing;          /* 1: time kernels with HIP events on the handle's stream
+                                (every launch of the per-step kernels, the SOR sweeps
+                                of one check interval in 8); read by les_get_timing */
 } les_params;
 
 /* Per-call statistics of les_step.  Scalars describe the last step of the
@@ -209,6 +211,18 @@ int les_get_aux(les_handle* h, int32_t which, float* a, float* b, float* c);
 /* Full ghosted velocity boxes, float32 [nz+2][ny+2][nx+2] each (index 0 and
  * n+1 are ghosts / boundary faces), for boundary-condition checks. */
 int les_get_ghosted(les_handle* h, float* u, float* v, float* w);
+
+/* Kernel timing collected while les_params.timing = 1: for each kernel
+ * family, the summed event-bracketed device time and the number of timed
+ * launches.  Families: 0 nu_t, 1 tendency, 2 inflow, 3 rhs, 4 SOR
+ * half-sweep, 5 residual check, 6 rebase, 7 projection, 8 boundary
+ * refresh.  reset = 1 clears the counters after reading. */
+#define LES_NUM_KERNELS 9
+typedef struct {
+    double ms[LES_NUM_KERNELS];
+    int64_t launches[LES_NUM_KERNELS];
+} les_timing;
+int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
 
 /* Step counter (completed steps). */
 int les_get_step(const les_handle* h, int64_t* step);

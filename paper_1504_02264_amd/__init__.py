@@ -29,8 +29,13 @@ EXPORTS = (
     "les_set_inflow", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
-    "les_bc_map",
+    "les_bc_map", "les_get_timing",
 )
+KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * len(KERNEL_NAMES)), ("launches", C.c_int64 * len(KERNEL_NAMES))]
 
 
 class LesError(RuntimeError):
@@ -53,7 +58,7 @@ class Params(C.Structure):
         ("check_every", C.c_int32), ("max_iter", C.c_int32),
         ("cs", C.c_double), ("nu", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
         ("bc", C.c_int32 * 6), ("zero_guess", C.c_int32), ("rebase_every", C.c_int32),
-        ("diagnostics", C.c_int32), ("pad_", C.c_int32),
+        ("diagnostics", C.c_int32), ("timing", C.c_int32),
     ]
 
 
@@ -89,6 +94,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1504_02264_amd.build` (no CPU fallback exists)")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes this library bind to that one runtime, so device pointers
+    # and streams from torch are valid here
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     L.les_default_params.argtypes = [C.POINTER(Params)]
@@ -112,6 +124,7 @@ def lib():
     L.les_state_size.argtypes = [P, C.POINTER(C.c_int64)]
     L.les_get_state.argtypes = [P, P, C.c_int64]
     L.les_set_state.argtypes = [P, P, C.c_int64]
+    L.les_get_timing.argtypes = [P, C.POINTER(Timing), C.c_int32]
     L.les_bc_range.argtypes = [C.POINTER(Grid)]
     L.les_bc_range.restype = C.c_int64
     L.les_bc_map.argtypes = [C.POINTER(Grid), C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -261,6 +274,12 @@ class LES:
         u, v, w = (np.zeros(s, np.float32) for _ in range(3))
         self._check(lib().les_get_ghosted(self.h, _ptr(u), _ptr(v), _ptr(w)))
         return u, v, w
+
+    def get_timing(self, reset=True):
+        """{kernel: (total ms, timed launches)} collected with params.timing = 1."""
+        t = Timing()
+        self._check(lib().les_get_timing(self.h, C.byref(t), int(bool(reset))))
+        return {n: (t.ms[q], t.launches[q]) for q, n in enumerate(KERNEL_NAMES)}
 
     def get_step(self):
         s = C.c_int64()

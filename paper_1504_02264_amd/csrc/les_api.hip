@@ -200,6 +200,50 @@ int download(les_handle* h, const float* dev, std::vector<float>& host) {
     return LES_OK;
 }
 
+// ------------------------------------------------------------- timing
+enum Kind { KN_NUT = 0, KN_TEND, KN_INFLOW, KN_RHS, KN_SOR, KN_CHECK, KN_REBASE, KN_PROJECT, KN_BC };
+constexpr long long kNoTag = -1;
+
+// Record one pooled event on the handle's stream; returns its index.
+size_t tmark(les_handle* h) {
+    if (h->tev_used == h->tev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+        h->tev.push_back(e);
+    }
+    if (hipEventRecord(h->tev[h->tev_used], h->stream) != hipSuccess) return (size_t)-1;
+    return h->tev_used++;
+}
+
+// Launch through f(), bracketed by two events when timing is on.  tag >= 0
+// names the SOR check interval the launch belongs to (launches after the
+// solve stopped return at once and are not counted).
+template <class F>
+hipError_t timed(les_handle* h, int kind, long long tag, F&& f) {
+    if (!h->prm.timing) return f();
+    const size_t a = tmark(h);
+    const hipError_t e = f();
+    const size_t b = tmark(h);
+    if (a != (size_t)-1 && b != (size_t)-1) h->tpending.push_back({kind, a, b, tag});
+    return e;
+}
+
+// After a stream synchronisation: fold the pending brackets into the
+// counters.  SOR-family launches tagged with a check interval beyond the
+// last one executed (last_check) are dropped.
+void tresolve(les_handle* h, long long last_check) {
+    for (const auto& br : h->tpending) {
+        if (br.tag != kNoTag && br.tag > last_check) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->tev[br.a], h->tev[br.b]) == hipSuccess) {
+            h->tms[br.kind] += ms;
+            h->tcount[br.kind] += 1;
+        }
+    }
+    h->tpending.clear();
+    h->tev_used = 0;
+}
+
 // ------------------------------------------------------------- SOR driver
 // Preconditions: ctl initialised, P.rhs filled, ctl->rhs2 computed.
 // Runs the set-up rebase, then check intervals of K iterations (two
@@ -220,7 +264,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     double* rel1 = h->f.part[2];
 
     CK(launch_fold(g, st, P, ctl));
-    CK(launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0));
+    CK(timed(h, KN_REBASE, 0, [&] { return launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0); }));
     const long long n_checks = max_iter > 0 ? ((long long)max_iter + K - 1) / K : 0;
     long long c = 0;
     int batch = 2;
@@ -229,16 +273,22 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     while (c < n_checks) {
         const long long nb = std::min<long long>(batch, n_checks - c);
         for (long long q = 0; q < nb; ++q) {
-            for (int it = 0; it < K; ++it) {
-                CK(launch_sor(g, st, P, 0, omega, it, rel0, ctl));
-                CK(launch_sor(g, st, P, 1, omega, it, rel1, ctl));
-            }
             const long long cidx = c + q + 1;
+            const bool sample = h->prm.timing && (cidx % 8 == 1);
+            for (int it = 0; it < K; ++it) {
+                if (sample) {
+                    CK(timed(h, KN_SOR, cidx, [&] { return launch_sor(g, st, P, 0, omega, it, rel0, ctl); }));
+                    CK(timed(h, KN_SOR, cidx, [&] { return launch_sor(g, st, P, 1, omega, it, rel1, ctl); }));
+                } else {
+                    CK(launch_sor(g, st, P, 0, omega, it, rel0, ctl));
+                    CK(launch_sor(g, st, P, 1, omega, it, rel1, ctl));
+                }
+            }
             if (cidx % R == 0) {
                 CK(launch_fold(g, st, P, ctl));
-                CK(launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1));
+                CK(timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); }));
             } else {
-                CK(launch_check(g, st, P, part, rel0, rel1, nrel, ctl));
+                CK(timed(h, KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); }));
             }
         }
         c += nb;
@@ -255,6 +305,8 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     CK(hipMemcpyAsync(h->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     const Ctl& hc = *h->h_ctl;
+    // the check that stopped the solve is interval ceil(m / K)
+    if (h->prm.timing) tresolve(h, ((long long)hc.m + K - 1) / K);
     if (out) {
         out->iters = hc.m;
         out->resid = hc.resid;
@@ -312,6 +364,7 @@ int les_default_params(les_params* p) {
     p->zero_guess = 0;
     p->rebase_every = 4;
     p->diagnostics = 1;
+    p->timing = 0;
     return LES_OK;
 }
 
@@ -409,6 +462,7 @@ void les_destroy(les_handle* h) {
     if (h->h_flag) (void)hipHostFree(h->h_flag);
     for (int q = 0; q < 2; ++q)
         if (h->ev[q]) (void)hipEventDestroy(h->ev[q]);
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
 }
@@ -470,16 +524,24 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
     int worst = LES_OK;
     for (int q = 0; q < n; ++q) {
         const int a = h->cur, b = 1 - h->cur;
-        CK(launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2));
-        CK(launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu, h->f.fv,
-                           h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags, h->f.u[b], h->f.v[b],
-                           h->f.w[b], (float)p.nu, (float)p.alpha, (float)p.beta,
-                           h->have_old ? 0 : 1));
+        CK(timed(h, KN_NUT, kNoTag, [&] { return launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2); }));
+        const int first = h->have_old ? 0 : 1;
+        CK(timed(h, KN_TEND, kNoTag, [&] {
+            return launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
+                                   h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
+                                   h->f.u[b], h->f.v[b], h->f.w[b], (float)p.nu, (float)p.alpha,
+                                   (float)p.beta, first);
+        }));
         h->have_old = true;
-        if (g.inflow) CK(launch_inflow(g, s, h->f.u[b], h->f.prof, h->f.flags, h->amp, h->seed, h->step + 1));
+        if (g.inflow)
+            CK(timed(h, KN_INFLOW, kNoTag, [&] {
+                return launch_inflow(g, s, h->f.u[b], h->f.prof, h->f.flags, h->amp, h->seed, h->step + 1);
+            }));
         CK(launch_ctl_init(s, h->f.ctl, p.tol, p.max_iter, p.check_every));
-        CK(launch_rhs(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P.rhs, h->f.part[0], h->f.ctl,
-                      singular(h) ? 1 : 0));
+        CK(timed(h, KN_RHS, kNoTag, [&] {
+            return launch_rhs(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P.rhs, h->f.part[0],
+                              h->f.ctl, singular(h) ? 1 : 0);
+        }));
         if (singular(h)) CK(launch_remove_mean_rhs(g, s, h->f.P.rhs, h->f.part[0], h->f.ctl));
         if (p.zero_guess)
             for (int c = 0; c < 2; ++c) {
@@ -494,8 +556,8 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
             worst = LES_NOT_CONVERGED;
         }
         if (singular(h)) CK(launch_remove_mean_p(g, s, h->f.P, h->f.part[0], h->f.ctl));
-        CK(launch_project(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P));
-        CK(launch_bc(g, s, h->f.u[b], h->f.v[b], h->f.w[b]));
+        CK(timed(h, KN_PROJECT, kNoTag, [&] { return launch_project(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P); }));
+        CK(timed(h, KN_BC, kNoTag, [&] { return launch_bc(g, s, h->f.u[b], h->f.v[b], h->f.w[b]); }));
         h->cur = b;
         h->step += 1;
         acc.steps += 1;
@@ -519,6 +581,7 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
         }
     }
     CK(hipStreamSynchronize(s));
+    if (p.timing) tresolve(h, kNoTag);
     acc.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = acc;
     return worst;
@@ -718,6 +781,19 @@ int les_get_ghosted(les_handle* h, float* u, float* v, float* w) {
             for (int j = 0; j < g.ny + 2; ++j)
                 for (int i = 0; i < g.nx + 2; ++i)
                     dst[q][((size_t)k * (g.ny + 2) + j) * (g.nx + 2) + i] = box[g.nat(i, j, k)];
+    }
+    return LES_OK;
+}
+
+int les_get_timing(les_handle* h, les_timing* out, int32_t reset) {
+    if (!h || !out) return LES_EINVAL;
+    for (int q = 0; q < LES_NUM_KERNELS; ++q) {
+        out->ms[q] = h->tms[q];
+        out->launches[q] = h->tcount[q];
+        if (reset) {
+            h->tms[q] = 0.0;
+            h->tcount[q] = 0;
+        }
     }
     return LES_OK;
 }

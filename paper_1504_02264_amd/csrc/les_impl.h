@@ -133,6 +133,13 @@ struct les_handle {
     uint64_t seed = 0;
     std::vector<float> prof;
     std::vector<uint8_t> mask;
+    // kernel timing (les_params.timing): event pool and pending brackets
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    struct Bracket { int kind; size_t a, b; long long tag; };
+    std::vector<Bracket> tpending;
+    double tms[LES_NUM_KERNELS] = {};
+    int64_t tcount[LES_NUM_KERNELS] = {};
     les::Ctl* h_ctl = nullptr;   // pinned mirror of the control block
     int* h_flag = nullptr;       // pinned, 2 slots for pipelined flag reads
     hipEvent_t ev[2] = {nullptr, nullptr};

@@ -52,10 +52,13 @@ def test_pressure_solve_parity(shape, bc):
         p = p - p.mean()
         po = po - po.mean()
     assert rel(p, po) <= 1e-5
-    # the GPU's float64 residual agrees with the oracle's residual of the GPU answer
-    r_of_gpu = o.residual(rhs - (rhs.mean() if bc == ALL_WALLS else 0.0), p)
+    # the iterate meets tol; the float32 copy handed back adds at most the
+    # residual of its own rounding (the representation floor)
+    rr = rhs - (rhs.mean() if bc == ALL_WALLS else 0.0)
+    r_of_gpu = o.residual(rr, p)
+    r_round = np.linalg.norm(o.apply_A(po.astype(np.float32).astype(np.float64) - po)) / np.linalg.norm(rr)
     assert st["resid"] <= 1e-5
-    assert r_of_gpu <= 1.05e-5
+    assert r_of_gpu <= st["resid"] + 2.0 * r_round + 1e-7
     # a free-running oracle stops within one check interval of the GPU
     _, stf, _ = o.pressure_solve(rhs, p0, tol=1e-5, max_iter=20000)
     assert abs(stf["iters"] - st["iters"]) <= 4

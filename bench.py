@@ -94,6 +94,8 @@ def main():
     g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask,
                 timing=0 if args.no_timing else 1)
     g.set_inflow(prof, w.noise_amp, w.seed)
+    variant, us = g.autotune(reps=20)
+    log(f"autotune: SOR sweep variant {variant}; us per half-sweep {[round(x, 2) for x in us]}")
     log(f"workload {w.name} {w.nx}x{w.ny}x{w.nz} ({cells} cells); warmup {args.warmup} steps")
     if args.warmup:
         g.step(args.warmup)
@@ -130,6 +132,8 @@ def main():
             "steps_per_s": args.steps / dt_s,
             "not_converged_steps": int(st["not_converged"]),
             "resid_last": st["resid_last"],
+            "sor_variant": int(variant),
+            "autotune_us_per_sweep": [round(float(x), 3) for x in us],
         },
     }
     sor_ms, sor_n = timing["sor"]

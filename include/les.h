@@ -80,12 +80,13 @@ typedef struct {
                                 INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP) */
     int32_t zero_guess;      /* 1: each solve starts from p = 0 (default 0: previous p) */
     int32_t rebase_every;    /* fold the correction into the base pressure every
-                                R residual checks (4); see les_pressure_solve */
+                                R residual checks (16); see les_pressure_solve */
     int32_t diagnostics;     /* 1: compute ||div u^{n+1}|| and max CFL on the last
                                 step of each les_step call (default 1) */
     int32_t timing;          /* 1: time kernels with HIP events on the handle's stream
-                                (every launch of the per-step kernels, the SOR sweeps
-                                of one check interval in 8); read by les_get_timing */
+                                (every launch of the per-step kernels; for the SOR
+                                sweeps, one check interval in 8, its 2K back-to-back
+                                half-sweeps between one event pair); les_get_timing */
 } les_params;
 
 /* Per-call statistics of les_step.  Scalars describe the last step of the
@@ -223,6 +224,23 @@ typedef struct {
     int64_t launches[LES_NUM_KERNELS];
 } les_timing;
 int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
+
+/*
+ * Autotuner: times every SOR half-sweep tile variant (row width of 64 or 32
+ * half-cells per wavefront x 1, 2, 4 or 8 planes per block) for reps
+ * back-to-back red/black pairs on this handle's grid, keeps the fastest
+ * for all later sweeps of the handle and reports its index in *chosen
+ * (nullable) and the per-variant microseconds per half-sweep in
+ * us_per_sweep[LES_NUM_SOR_VARIANTS] (nullable).  Runs on a scratch
+ * pressure system: the time-stepping state is unchanged.  Every variant
+ * computes the same per-cell arithmetic, so results are bitwise
+ * independent of the choice.  LES_EINVAL unless 1 <= reps <= 1000.
+ */
+#define LES_NUM_SOR_VARIANTS 8
+int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sweep);
+
+/* Select a sweep variant by index (0 .. LES_NUM_SOR_VARIANTS-1). */
+int les_set_sor_variant(les_handle* h, int32_t variant);
 
 /* Step counter (completed steps). */
 int les_get_step(const les_handle* h, int64_t* step);

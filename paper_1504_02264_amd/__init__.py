@@ -29,8 +29,9 @@ EXPORTS = (
     "les_set_inflow", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
-    "les_bc_map", "les_get_timing",
+    "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
 )
+NUM_SOR_VARIANTS = 8
 KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
 
 
@@ -125,6 +126,8 @@ def lib():
     L.les_get_state.argtypes = [P, P, C.c_int64]
     L.les_set_state.argtypes = [P, P, C.c_int64]
     L.les_get_timing.argtypes = [P, C.POINTER(Timing), C.c_int32]
+    L.les_autotune.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), P]
+    L.les_set_sor_variant.argtypes = [P, C.c_int32]
     L.les_bc_range.argtypes = [C.POINTER(Grid)]
     L.les_bc_range.restype = C.c_int64
     L.les_bc_map.argtypes = [C.POINTER(Grid), C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -280,6 +283,16 @@ class LES:
         t = Timing()
         self._check(lib().les_get_timing(self.h, C.byref(t), int(bool(reset))))
         return {n: (t.ms[q], t.launches[q]) for q, n in enumerate(KERNEL_NAMES)}
+
+    def autotune(self, reps=20):
+        """Pick the fastest SOR sweep variant; returns (index, us per sweep per variant)."""
+        ch = C.c_int32()
+        us = np.zeros(NUM_SOR_VARIANTS, np.float64)
+        self._check(lib().les_autotune(self.h, int(reps), C.byref(ch), _ptr(us)))
+        return ch.value, us
+
+    def set_sor_variant(self, v):
+        return self._check(lib().les_set_sor_variant(self.h, int(v)))
 
     def get_step(self):
         s = C.c_int64()

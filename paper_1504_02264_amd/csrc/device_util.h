@@ -1,5 +1,7 @@
-// Device helpers: XCD-aware block numbering, wavefront/block reductions in
-// float64 and the "last block finishes the reduction" pattern.
+// Device helpers: XCD-aware block numbering and wavefront/block reductions
+// in float64.  Reductions are two-kernel: every block stores one partial,
+// then a single-block finalize kernel sums them in a fixed order (no
+// atomics, no cross-block fences, deterministic).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,36 +63,47 @@ __device__ __forceinline__ double block_max(double v) {
     return t;
 }
 
-// Called by every thread after thread 0 stored this block's partial.
-// Returns true in exactly one block: the last to arrive, which then sees
-// every other block's partial.  The counter is reset for the next use.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
-    __shared__ int is_last;
+// Block-wide reductions of the single-block finalize kernel (kFinBlock
+// threads, fixed order: deterministic for a given partial count).
+constexpr int kFinBlock = 1024;
+
+__device__ __forceinline__ double fin_sum(double v) {
+    __shared__ double red[kFinBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == nblocks - 1) ? 1 : 0;
-        if (is_last) {
-            __threadfence();
-            *counter = 0u;
-        }
-    }
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kFinBlock / 64; ++i) t += red[i];
     __syncthreads();
-    return is_last != 0;
+    return t;
 }
 
-// Fixed-order sum of n partials by one block (result valid in thread 0).
-__device__ __forceinline__ double sum_partials(const double* part, int n) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
-    return block_sum(s);
+__device__ __forceinline__ double fin_max(double v) {
+    __shared__ double redm[kFinBlock / 64];
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) redm[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kFinBlock / 64; ++i) t = fmax(t, redm[i]);
+    __syncthreads();
+    return t;
 }
 
-__device__ __forceinline__ double max_partials(const double* part, int n) {
+// Sum of n partials with stride (result valid in thread 0).
+__device__ __forceinline__ double sum_partials(const double* part, int n, int stride = 1) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, part[i]);
-    return block_max(s);
+    for (int i = threadIdx.x; i < n; i += kFinBlock) s += part[(long long)i * stride];
+    return fin_sum(s);
+}
+
+__device__ __forceinline__ double max_partials(const double* part, int n, int stride = 1) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kFinBlock) s = fmax(s, part[(long long)i * stride]);
+    return fin_max(s);
 }
 
 }  // namespace les

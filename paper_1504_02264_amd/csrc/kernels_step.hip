@@ -16,12 +16,14 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 // Decompose a linear interior-cell index (0-based, x fastest) into 1-based
 // cell coordinates.
 __device__ __forceinline__ void cell_of(const Geo& g, long long t, int& i, int& j, int& k) {
-    const long long nxy = (long long)g.nx * g.ny;
-    k = (int)(t / nxy);
-    long long r = t - (long long)k * nxy;
-    j = (int)(r / g.nx);
-    i = (int)(r - (long long)j * g.nx);
-    ++i; ++j; ++k;
+    const unsigned tt = (unsigned)t;   // cells < 2^31 (checked at create)
+    const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+    const unsigned kk = tt / nxy;
+    const unsigned r = tt - kk * nxy;
+    const unsigned jj = r / (unsigned)g.nx;
+    i = (int)(r - jj * (unsigned)g.nx) + 1;
+    j = (int)jj + 1;
+    k = (int)kk + 1;
 }
 
 // ------------------------------------------------------------------ les
@@ -38,11 +40,12 @@ __global__ __launch_bounds__(kBlock) void k_nut(Geo g, const float* __restrict__
     const long long nbox = (long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
     const long long t = (long long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (t >= nbox) return;
-    const long long pxy = (long long)(g.nx + 2) * (g.ny + 2);
-    int k = (int)(t / pxy);
-    long long r = t - (long long)k * pxy;
-    int j = (int)(r / (g.nx + 2));
-    int i = (int)(r - (long long)j * (g.nx + 2));
+    const unsigned pxy = (unsigned)(g.nx + 2) * (unsigned)(g.ny + 2);
+    const unsigned tt = (unsigned)t;
+    const int k = (int)(tt / pxy);
+    const unsigned r = tt - (unsigned)k * pxy;
+    const int j = (int)(r / (unsigned)(g.nx + 2));
+    const int i = (int)(r - (unsigned)j * (unsigned)(g.nx + 2));
     const int ic = min(max(i, 1), g.nx), jc = min(max(j, 1), g.ny), kc = min(max(k, 1), g.nz);
     auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
     auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
@@ -219,7 +222,6 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, int max_iter, int K) {
         ctl->rhs_sum = 0.0;
         ctl->resid = 0.0;
         ctl->reltmp2 = 0.0;
-        for (int i = 0; i < 4; ++i) ctl->cnt[i] = 0u;
     }
 }
 
@@ -230,7 +232,7 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, int max_iter, int K) {
 __global__ __launch_bounds__(kBlock) void k_rhs(Geo g, const float* __restrict__ us,
                                                 const float* __restrict__ vs,
                                                 const float* __restrict__ ws, float* rhs0,
-                                                float* rhs1, double* __restrict__ part, Ctl* ctl,
+                                                float* rhs1, double* __restrict__ part,
                                                 int singular) {
     const long long n = (long long)g.nx * g.ny * g.nz;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
@@ -250,13 +252,6 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Geo g, const float* __restrict__
     }
     const double bs = block_sum(acc);
     if (threadIdx.x == 0) part[lb] = bs;
-    if (last_block(&ctl->cnt[0], gridDim.x)) {
-        const double s = sum_partials(part, gridDim.x);
-        if (threadIdx.x == 0) {
-            if (singular) ctl->rhs_sum = s;
-            else ctl->rhs2 = s;
-        }
-    }
 }
 
 // Singular operator: subtract the mean of rhs, then sum rhs^2.
@@ -279,10 +274,6 @@ __global__ __launch_bounds__(kBlock) void k_rhs_mean(Geo g, float* rhs0, float* 
     }
     const double bs = block_sum(acc);
     if (threadIdx.x == 0) part[lb] = bs;
-    if (last_block(&ctl->cnt[0], gridDim.x)) {
-        const double s = sum_partials(part, gridDim.x);
-        if (threadIdx.x == 0) ctl->rhs2 = s;
-    }
 }
 
 // ------------------------------------------------------- velnw: projection
@@ -407,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(Geo g, float* u, float* v, float*
 __global__ __launch_bounds__(kBlock) void k_diag(Geo g, const float* __restrict__ u,
                                                  const float* __restrict__ v,
                                                  const float* __restrict__ w,
-                                                 double* __restrict__ part, Ctl* ctl) {
+                                                 double* __restrict__ part) {
     const long long n = (long long)g.nx * g.ny * g.nz;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const long long t = (long long)lb * kBlock + threadIdx.x;
@@ -428,19 +419,6 @@ __global__ __launch_bounds__(kBlock) void k_diag(Geo g, const float* __restrict_
     if (threadIdx.x == 0) {
         part[2 * lb] = s;
         part[2 * lb + 1] = mx;
-    }
-    if (last_block(&ctl->cnt[3], gridDim.x)) {
-        double a = 0.0, b = 0.0;
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += kBlock) {
-            a += part[2 * q];
-            b = fmax(b, part[2 * q + 1]);
-        }
-        a = block_sum(a);
-        b = block_max(b);
-        if (threadIdx.x == 0) {
-            ctl->div2 = a;
-            ctl->cfl = b;
-        }
     }
 }
 
@@ -517,8 +495,11 @@ hipError_t launch_rhs(const Geo& g, hipStream_t st, const float* us, const float
                       int singular) {
     const long long n = (long long)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_rhs, dim3(nblocks(n)), dim3(kBlock), 0, st, g, us, vs, ws, rhs[0],
-                       rhs[1], part, ctl, singular);
-    return hipGetLastError();
+                       rhs[1], part, singular);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(st, singular ? FIN_RHS_SUM : FIN_RHS2, part, (int)nblocks(n), nullptr,
+                           nullptr, 0, ctl);
 }
 
 hipError_t launch_remove_mean_rhs(const Geo& g, hipStream_t st, float* const rhs[2],
@@ -526,7 +507,9 @@ hipError_t launch_remove_mean_rhs(const Geo& g, hipStream_t st, float* const rhs
     const long long n = (long long)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_rhs_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, g, rhs[0], rhs[1],
                        part, ctl);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(st, FIN_RHS2, part, (int)nblocks(n), nullptr, nullptr, 0, ctl);
 }
 
 hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
@@ -546,8 +529,10 @@ hipError_t launch_bc(const Geo& g, hipStream_t st, float* u, float* v, float* w)
 hipError_t launch_diag(const Geo& g, hipStream_t st, const float* u, const float* v,
                        const float* w, double* part, Ctl* ctl) {
     const long long n = (long long)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(kBlock), 0, st, g, u, v, w, part, ctl);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(kBlock), 0, st, g, u, v, w, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(st, FIN_DIAG, part, (int)nblocks(n), nullptr, nullptr, 0, ctl);
 }
 
 hipError_t launch_cells_to_colour(const Geo& g, hipStream_t st, const float* src,

@@ -219,12 +219,12 @@ size_t tmark(les_handle* h) {
 // names the SOR check interval the launch belongs to (launches after the
 // solve stopped return at once and are not counted).
 template <class F>
-hipError_t timed(les_handle* h, int kind, long long tag, F&& f) {
+hipError_t timed(les_handle* h, int kind, long long tag, F&& f, int count = 1) {
     if (!h->prm.timing) return f();
     const size_t a = tmark(h);
     const hipError_t e = f();
     const size_t b = tmark(h);
-    if (a != (size_t)-1 && b != (size_t)-1) h->tpending.push_back({kind, a, b, tag});
+    if (a != (size_t)-1 && b != (size_t)-1) h->tpending.push_back({kind, a, b, tag, count});
     return e;
 }
 
@@ -237,7 +237,7 @@ void tresolve(les_handle* h, long long last_check) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, h->tev[br.a], h->tev[br.b]) == hipSuccess) {
             h->tms[br.kind] += ms;
-            h->tcount[br.kind] += 1;
+            h->tcount[br.kind] += br.count;
         }
     }
     h->tpending.clear();
@@ -258,7 +258,8 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     const int K = h->prm.check_every;
     const int R = h->prm.rebase_every;
     const float omega = (float)h->prm.omega;
-    const int nrel = sor_blocks(g);
+    const int var = h->sor_variant;
+    const int nrel = (int)sor_sweep_blocks(g, var);
     double* part = h->f.part[0];
     double* rel0 = h->f.part[1];
     double* rel1 = h->f.part[2];
@@ -274,16 +275,20 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
         const long long nb = std::min<long long>(batch, n_checks - c);
         for (long long q = 0; q < nb; ++q) {
             const long long cidx = c + q + 1;
+            // one check interval in 8 is timed as a whole: 2K back-to-back
+            // half-sweeps between one pair of events
             const bool sample = h->prm.timing && (cidx % 8 == 1);
-            for (int it = 0; it < K; ++it) {
-                if (sample) {
-                    CK(timed(h, KN_SOR, cidx, [&] { return launch_sor(g, st, P, 0, omega, it, rel0, ctl); }));
-                    CK(timed(h, KN_SOR, cidx, [&] { return launch_sor(g, st, P, 1, omega, it, rel1, ctl); }));
-                } else {
-                    CK(launch_sor(g, st, P, 0, omega, it, rel0, ctl));
-                    CK(launch_sor(g, st, P, 1, omega, it, rel1, ctl));
+            auto sweeps = [&]() -> hipError_t {
+                for (int it = 0; it < K; ++it) {
+                    hipError_t e = launch_sor(g, st, P, 0, omega, it, rel0, ctl, var);
+                    if (e != hipSuccess) return e;
+                    e = launch_sor(g, st, P, 1, omega, it, rel1, ctl, var);
+                    if (e != hipSuccess) return e;
                 }
-            }
+                return hipSuccess;
+            };
+            if (sample) CK(timed(h, KN_SOR, cidx, sweeps, 2 * K));
+            else CK(sweeps());
             if (cidx % R == 0) {
                 CK(launch_fold(g, st, P, ctl));
                 CK(timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); }));
@@ -362,7 +367,7 @@ int les_default_params(les_params* p) {
     p->bc[LES_ZM] = LES_BC_NOSLIP;
     p->bc[LES_ZP] = LES_BC_FREESLIP;
     p->zero_guess = 0;
-    p->rebase_every = 4;
+    p->rebase_every = 16;
     p->diagnostics = 1;
     p->timing = 0;
     return LES_OK;
@@ -403,7 +408,9 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     const size_t cb = align256((size_t)g.ctot * sizeof(float));
     const size_t fb = align256((size_t)g.ntot);
     const size_t ncells = align256((size_t)ncell * sizeof(float));
-    const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * sor_blocks(g)) + 64;
+    long long maxsweep = 0;
+    for (int v = 0; v < kNumSorVariants; ++v) maxsweep = std::max<long long>(maxsweep, sor_sweep_blocks(g, v));
+    const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), maxsweep) + 64;
     const size_t pb = align256(nparts * sizeof(double));
     const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 8 * cb +
                          3 * pb + align256(sizeof(Ctl));
@@ -449,6 +456,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
             return fail(LES_EDEVICE);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(LES_EDEVICE);
     h->prof.assign((size_t)g.nz, 0.f);
+    h->sor_variant = sor_default_variant(g);
     *out = h;
     return LES_OK;
 }
@@ -782,6 +790,54 @@ int les_get_ghosted(les_handle* h, float* u, float* v, float* w) {
                 for (int i = 0; i < g.nx + 2; ++i)
                     dst[q][((size_t)k * (g.ny + 2) + j) * (g.nx + 2) + i] = box[g.nat(i, j, k)];
     }
+    return LES_OK;
+}
+
+int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sweep) {
+    if (!h || reps < 1 || reps > 1000) return LES_EINVAL;
+    int rc = ensure_solve_arena(h);
+    if (rc != LES_OK) return rc;
+    const Geo& g = h->g;
+    hipStream_t s = h->stream;
+    // time the sweep variants on the stand-alone solve workspace (the
+    // time-stepping state is not touched); the control block is set so that
+    // no sweep is skipped
+    CK(launch_ctl_init(s, h->f.ctl, 1e-30, 1 << 30, 1 << 20));
+    hipEvent_t a = nullptr, b = nullptr;
+    CK(hipEventCreate(&a));
+    CK(hipEventCreate(&b));
+    double best = 1e300;
+    int best_v = h->sor_variant;
+    for (int v = 0; v < kNumSorVariants; ++v) {
+        for (int w = 0; w < 2; ++w) CK(launch_sor(g, s, h->S, w & 1, 1.0f, 0, nullptr, h->f.ctl, v));
+        CK(hipEventRecord(a, s));
+        for (int r = 0; r < reps; ++r) {
+            CK(launch_sor(g, s, h->S, 0, 1.0f, 0, nullptr, h->f.ctl, v));
+            CK(launch_sor(g, s, h->S, 1, 1.0f, 0, nullptr, h->f.ctl, v));
+        }
+        CK(hipEventRecord(b, s));
+        CK(hipEventSynchronize(b));
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, a, b));
+        const double us = 1e3 * ms / (2.0 * reps);
+        if (us_per_sweep) us_per_sweep[v] = us;
+        if (us < best) {
+            best = us;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->S.pd[c], g.ctot, 0.f));
+    CK(hipStreamSynchronize(s));
+    h->sor_variant = best_v;
+    if (chosen) *chosen = best_v;
+    return LES_OK;
+}
+
+int les_set_sor_variant(les_handle* h, int32_t variant) {
+    if (!h || variant < 0 || variant >= kNumSorVariants) return LES_EINVAL;
+    h->sor_variant = variant;
     return LES_OK;
 }
 

@@ -66,7 +66,7 @@ struct Ctl {
     int m;              // SOR iterations completed
     int K;              // check interval
     int max_iter;
-    unsigned cnt[4];    // last-block counters of the reductions
+    unsigned pad_u[4];
     double tol;
     double rhs2;        // sum rhs^2 (after mean removal)
     double rhs_sum;     // sum rhs (singular case)
@@ -126,6 +126,7 @@ struct les_handle {
     void* solve_arena = nullptr;
     les::PBufs S{};
     int cur = 0;               // index of u^n in f.u/v/w
+    int sor_variant = 0;       // SOR sweep tile variant (les_autotune)
     bool have_inflow = false;
     bool have_old = false;
     int64_t step = 0;
@@ -136,7 +137,7 @@ struct les_handle {
     // kernel timing (les_params.timing): event pool and pending brackets
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
-    struct Bracket { int kind; size_t a, b; long long tag; };
+    struct Bracket { int kind; size_t a, b; long long tag; int count; };
     std::vector<Bracket> tpending;
     double tms[LES_NUM_KERNELS] = {};
     int64_t tcount[LES_NUM_KERNELS] = {};
@@ -147,7 +148,12 @@ struct les_handle {
 
 namespace les {
 
+// Finalize operations of the single-block reduction kernel.
+enum FinOp { FIN_RHS2 = 0, FIN_RHS_SUM, FIN_PSUM, FIN_SETUP, FIN_CHECK, FIN_DIAG };
+
 // ---- kernel launchers (kernels_*.hip) ----
+hipError_t launch_finalize(hipStream_t st, int op, const double* part, int n, const double* rel0,
+                           const double* rel1, int nrel, Ctl* ctl);
 hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
                       const float* w, float* nut, float c2);
 hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const float* v,
@@ -169,9 +175,13 @@ hipError_t launch_rebase(const Geo& g, hipStream_t st, const PBufs& P, double* p
                          const double* rel0, const double* rel1, int nrel, Ctl* ctl, int decide);
 hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                         const double* rel0, const double* rel1, int nrel, Ctl* ctl);
+struct SorVariant { int tx, kt; };
+constexpr int kNumSorVariants = 8;
+extern const SorVariant kSorVariants[kNumSorVariants];
+int sor_default_variant(const Geo& g);
+unsigned sor_sweep_blocks(const Geo& g, int variant);
 hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, float omega,
-                      int local_iter, double* rel_part, const Ctl* ctl);
-int sor_blocks(const Geo& g);
+                      int local_iter, double* rel_part, const Ctl* ctl, int variant);
 hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
                           const PBufs& P);
 hipError_t launch_bc(const Geo& g, hipStream_t st, float* u, float* v, float* w);

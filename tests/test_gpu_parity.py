@@ -275,3 +275,38 @@ def test_full_size_stage_parity(name):
     assert rel(g.get_rhs(), o.get_rhs()) <= 1e-5
     if rc == les.LES_OK:
         assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
+
+
+# ------------------------------------------- autotuner / tile independence
+def test_sor_variants_bitwise_identical():
+    """Every sweep tile variant does the same per-cell arithmetic, so the
+    answer and the iteration count do not depend on the tile (a race or a
+    colour-order slip in one variant would show here)."""
+    nx, ny, nz = 45, 37, 19
+    g = les.LES(nx, ny, nz, 2.0, 2.0, 1.0, 0.05)
+    rhs = random_rhs(nx, ny, nz, seed=8, smooth=2)
+    ref = None
+    for v in range(les.NUM_SOR_VARIANTS):
+        g.set_sor_variant(v)
+        p, st, rc = g.pressure_solve(rhs, None, tol=1e-5)
+        if ref is None:
+            ref = (p, st["iters"])
+        else:
+            assert st["iters"] == ref[1], v
+            assert np.array_equal(p, ref[0]), v
+    chosen, us = g.autotune(reps=5)
+    assert 0 <= chosen < les.NUM_SOR_VARIANTS and np.all(us > 0)
+
+
+def test_step_independent_of_sor_variant():
+    nx, ny, nz = 33, 17, 9
+    mask, prof = urban_case(nx, ny, nz, 4, hmax=5)
+    out = []
+    for v in (0, 7):
+        g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+        g.set_sor_variant(v)
+        g.set_inflow(prof, 0.01, 4)
+        g.step(2)
+        out.append(g.get_fields())
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict_
     long long e = col_ok ? g.col(ii, j0, k_begin) : 0;
     float pb = col_ok ? poth[e - g.SP] : 0.f;
     float pc = col_ok ? poth[e] : 0.f;
-    double r2 = 0.0;
+    double r2 = 0.0, dr2 = 0.0;
     for (int k0 = k_begin; k0 < k_end; ++k0) {
         const float pt = col_ok ? poth[e + g.SP] : 0.f;
         // neighbours along the row from the adjacent lanes
@@ -131,19 +131,31 @@ __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict_
             const float nb = cx * (west + east) + cy * (ps + pn) + cz * (pb + pt);
             const float dxx = (i0 > 0 ? cx : 0.f) + (i0 < g.nx - 1 ? cx : (g.outflow ? 2.f * cx : 0.f));
             const float dzz = (k0 > 0 ? cz : 0.f) + (k0 < g.nz - 1 ? cz : 0.f);
-            const float inv = 1.0f / (dxx + dyy + dzz);
+            const float diag = dxx + dyy + dzz;
+            const float inv = 1.0f / diag;
             const float p = pself[e];
             const float reltmp = omega * (inv * (nb - rself[e]) - p);
             pself[e] = p + reltmp;
-            r2 += (double)reltmp * (double)reltmp;
+            if (acc) {
+                const double rt = (double)reltmp;
+                r2 += rt * rt;
+                dr2 += ((double)diag * rt) * ((double)diag * rt);
+            }
         }
         pb = pc;
         pc = pt;
         e += g.SP;
     }
     if (acc) {
+        // [sum reltmp^2, sum (diag reltmp)^2] per block; after the colour-1
+        // half-sweep, diag (omega-1)/omega reltmp is exactly the residual of
+        // the colour-1 cells, so the second sum bounds ||r|| from below
         const double bs = block_sum(r2);
-        if (threadIdx.x == 0) rel_part[lb] = bs;
+        const double bd = block_sum(dr2);
+        if (threadIdx.x == 0) {
+            rel_part[2 * lb] = bs;
+            rel_part[2 * lb + 1] = bd;
+        }
     }
 }
 
@@ -198,13 +210,13 @@ __device__ __forceinline__ double apply_A64(const Geo& g, const float* xo, const
 }
 
 // Shared decision of a residual check, run by the last block.
-__device__ void decide(Ctl* ctl, double sum_r2, double rel) {
+__device__ void decide(Ctl* ctl, double sum_r2) {
     if (ctl->done) return;
     const int m = min(ctl->m + ctl->K, ctl->max_iter);
     ctl->m = m;
+    ctl->skip = 0;
     const double R = sqrt(sum_r2) / sqrt(ctl->rhs2);
     ctl->resid = R;
-    ctl->reltmp2 = rel;
     if (!isfinite(R)) ctl->done = 3;
     else if (R <= ctl->tol) ctl->done = 1;
     else if (m >= ctl->max_iter) ctl->done = 2;
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_check(Geo g, const float* __restrict
                                                   const float* __restrict__ r00,
                                                   const float* __restrict__ r01,
                                                   double* __restrict__ part, const Ctl* ctl) {
-    if (ctl->done) return;
+    if (ctl->done || ctl->skip) return;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     long long t0, t1;
     red_chunk(g, lb, gridDim.x, t0, t1);
@@ -364,11 +376,19 @@ __global__ __launch_bounds__(kBlock) void k_colour_norm(Geo g, const float* __re
 
 // One block of kFinBlock threads: fixed-order sums of the partials of the
 // preceding reduction kernel, then the bookkeeping of op.
+//   FIN_BOUND  after the sweeps of a check interval: sum reltmp^2 for the
+//              report, and the colour-1 residual lower bound
+//              |omega-1|/omega sqrt(sum (diag reltmp)^2) <= ||r||; if it
+//              exceeds 1.5 tol the coming check cannot succeed and is
+//              skipped (never the last check before max_iter)
+//   FIN_CHECK  decide on the residual (or just count a skipped check)
+//   FIN_CHECK_FULL  decide on the residual (rebase checks never skip)
 __global__ __launch_bounds__(kFinBlock) void k_finalize(int op, const double* __restrict__ part,
                                                         int n, const double* __restrict__ rel0,
                                                         const double* __restrict__ rel1, int nrel,
-                                                        Ctl* ctl) {
-    if ((op == FIN_CHECK || op == FIN_SETUP) && ctl->done) return;
+                                                        Ctl* ctl, double omega) {
+    const bool sor_op = op == FIN_CHECK || op == FIN_CHECK_FULL || op == FIN_SETUP || op == FIN_BOUND;
+    if (sor_op && ctl->done) return;
     if (op == FIN_DIAG) {
         const double a = sum_partials(part, n, 2);
         const double b = max_partials(part + 1, n, 2);
@@ -378,9 +398,26 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int op, const double* __
         }
         return;
     }
+    if (op == FIN_BOUND) {
+        const double r0s = sum_partials(rel0, nrel, 2);
+        const double r1s = sum_partials(rel1, nrel, 2);
+        const double d1s = sum_partials(rel1 + 1, nrel, 2);
+        if (threadIdx.x == 0) {
+            ctl->reltmp2 = r0s + r1s;
+            const double lb = fabs(omega - 1.0) / omega * sqrt(d1s) / sqrt(ctl->rhs2);
+            const int m_next = min(ctl->m + ctl->K, ctl->max_iter);
+            ctl->skip = (m_next < ctl->max_iter && lb > 1.5 * ctl->tol) ? 1 : 0;
+        }
+        return;
+    }
+    if (op == FIN_CHECK && ctl->skip) {
+        if (threadIdx.x == 0) {
+            ctl->m = min(ctl->m + ctl->K, ctl->max_iter);
+            ctl->skip = 0;
+        }
+        return;
+    }
     const double s = sum_partials(part, n);
-    double rel = 0.0;
-    if (op == FIN_CHECK && rel0) rel = sum_partials(rel0, nrel) + sum_partials(rel1, nrel);
     if (threadIdx.x != 0) return;
     switch (op) {
         case FIN_RHS2: ctl->rhs2 = s; break;
@@ -397,7 +434,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int op, const double* __
                 if (!isfinite(ctl->resid)) ctl->done = 3;
             }
             break;
-        case FIN_CHECK: decide(ctl, s, rel); break;
+        case FIN_CHECK:
+        case FIN_CHECK_FULL: decide(ctl, s); break;
         default: break;
     }
 }
@@ -405,9 +443,9 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int op, const double* __
 }  // namespace
 
 hipError_t launch_finalize(hipStream_t st, int op, const double* part, int n, const double* rel0,
-                           const double* rel1, int nrel, Ctl* ctl) {
+                           const double* rel1, int nrel, Ctl* ctl, double omega) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, st, op, part, n, rel0, rel1,
-                       nrel, ctl);
+                       nrel, ctl, omega);
     return hipGetLastError();
 }
 
@@ -450,7 +488,7 @@ hipError_t launch_rebase(const Geo& g, hipStream_t st, const PBufs& P, double* p
                        (const Ctl*)ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(st, decide ? FIN_CHECK : FIN_SETUP, part, (int)red_blocks(g), rel0,
+    return launch_finalize(st, decide ? FIN_CHECK_FULL : FIN_SETUP, part, (int)red_blocks(g), rel0,
                            rel1, nrel, ctl);
 }
 

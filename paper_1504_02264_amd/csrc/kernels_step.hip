@@ -222,6 +222,7 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, int max_iter, int K) {
         ctl->rhs_sum = 0.0;
         ctl->resid = 0.0;
         ctl->reltmp2 = 0.0;
+        ctl->skip = 0;
     }
 }
 

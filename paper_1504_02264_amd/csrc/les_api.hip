@@ -289,6 +289,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
             };
             if (sample) CK(timed(h, KN_SOR, cidx, sweeps, 2 * K));
             else CK(sweeps());
+            CK(launch_finalize(st, FIN_BOUND, nullptr, 0, rel0, rel1, nrel, ctl, h->prm.omega));
             if (cidx % R == 0) {
                 CK(launch_fold(g, st, P, ctl));
                 CK(timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); }));
@@ -410,7 +411,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     const size_t ncells = align256((size_t)ncell * sizeof(float));
     long long maxsweep = 0;
     for (int v = 0; v < kNumSorVariants; ++v) maxsweep = std::max<long long>(maxsweep, sor_sweep_blocks(g, v));
-    const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), maxsweep) + 64;
+    const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * maxsweep) + 64;
     const size_t pb = align256(nparts * sizeof(double));
     const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 8 * cb +
                          3 * pb + align256(sizeof(Ctl));

@@ -66,7 +66,8 @@ struct Ctl {
     int m;              // SOR iterations completed
     int K;              // check interval
     int max_iter;
-    unsigned pad_u[4];
+    int skip;           // 1: the coming residual check is provably unsuccessful
+    unsigned pad_u[3];
     double tol;
     double rhs2;        // sum rhs^2 (after mean removal)
     double rhs_sum;     // sum rhs (singular case)
@@ -149,11 +150,12 @@ struct les_handle {
 namespace les {
 
 // Finalize operations of the single-block reduction kernel.
-enum FinOp { FIN_RHS2 = 0, FIN_RHS_SUM, FIN_PSUM, FIN_SETUP, FIN_CHECK, FIN_DIAG };
+enum FinOp { FIN_RHS2 = 0, FIN_RHS_SUM, FIN_PSUM, FIN_SETUP, FIN_CHECK, FIN_CHECK_FULL, FIN_DIAG,
+             FIN_BOUND };
 
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_finalize(hipStream_t st, int op, const double* part, int n, const double* rel0,
-                           const double* rel1, int nrel, Ctl* ctl);
+                           const double* rel1, int nrel, Ctl* ctl, double omega = 1.0);
 hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
                       const float* w, float* nut, float c2);
 hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const float* v,

@@ -75,6 +75,11 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events (no roofline object)")
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="cap SOR iterations per step (profiling runs only; not the benchmark)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run 5 plain torch copies of MB megabytes (the known-size kernel "
+                         "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -91,8 +96,17 @@ def main():
     w = WORKLOADS[args.workload]
     cells = w.nx * w.ny * w.nz
     mask, prof = make_workload_inputs(w)
+    extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
     g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask,
-                timing=0 if args.no_timing else 1)
+                timing=0 if args.no_timing else 1, **extra)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     g.set_inflow(prof, w.noise_amp, w.seed)
     variant, us = g.autotune(reps=20)
     log(f"autotune: SOR sweep variant {variant}; us per half-sweep {[round(x, 2) for x in us]}")

@@ -257,6 +257,40 @@ int les_get_state(les_handle* h, void* buf, int64_t bytes);
 int les_set_state(les_handle* h, const void* buf, int64_t bytes);
 
 /*
+ * Ensemble (batched, uneven grids).  An ensemble borrows 1..64 existing
+ * handles on one device (not owned: destroy the ensemble before them) with
+ * the same check_every and zero_guess = 0; each keeps its own grid,
+ * buildings, inflow and parameters.  les_ensemble_step advances every
+ * member by nsteps: per step each stage is one launch over an
+ * (instance, block) work list, the stage sequences before and after the
+ * pressure solve are replayed from HIP graphs, and the pressure solves of
+ * all members run in ONE persistent cooperative launch with per-member
+ * stopping tests on the device.  Results are bitwise identical to stepping
+ * each member alone with les_step.  Members' step counters and buffers
+ * are updated, so single steps and ensemble steps can be mixed.
+ * iters_out (nullable, caller-owned) receives nsteps x n iteration counts
+ * (step-major).  Host-synchronous.  Returns LES_NOT_CONVERGED if any solve
+ * hit max_iter, LES_ESTATE if a member has no inflow yet.
+ */
+typedef struct les_ensemble les_ensemble;
+typedef struct {
+    int32_t members;
+    int32_t steps;
+    int64_t cells_total;      /* sum of the members' cells */
+    int64_t sor_iters_total;  /* over members and steps */
+    int32_t not_converged;    /* member-steps that hit max_iter */
+    int32_t pad_;
+    double ms_total;          /* host wall time of the call */
+} les_ensemble_stats;
+int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** out);
+int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out);
+/* les_autotune on every member (reps as there), then use the chosen sweep
+ * variants in the ensemble's persistent solve. */
+int les_ensemble_autotune(les_ensemble* e, int32_t reps);
+const char* les_ensemble_last_error(const les_ensemble* e);
+void les_ensemble_destroy(les_ensemble* e);
+
+/*
  * Boundary-range mapping of the ghost-refresh launch (section 2.4),
  * exposed for host-side tests; no device work.  les_bc_range gives the
  * launch size for grid g: (ny+2)(nz+2) x-face items + nx(nz+2) y-face items

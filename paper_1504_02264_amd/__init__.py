@@ -30,6 +30,8 @@ EXPORTS = (
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
+    "les_ensemble_create", "les_ensemble_step", "les_ensemble_autotune",
+    "les_ensemble_last_error", "les_ensemble_destroy",
 )
 NUM_SOR_VARIANTS = 8
 KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
@@ -84,6 +86,15 @@ class SolveStats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class EnsembleStats(C.Structure):
+    _fields_ = [("members", C.c_int32), ("steps", C.c_int32), ("cells_total", C.c_int64),
+                ("sor_iters_total", C.c_int64), ("not_converged", C.c_int32), ("pad_", C.c_int32),
+                ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
 _lib = None
 
 
@@ -128,6 +139,13 @@ def lib():
     L.les_get_timing.argtypes = [P, C.POINTER(Timing), C.c_int32]
     L.les_autotune.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), P]
     L.les_set_sor_variant.argtypes = [P, C.c_int32]
+    L.les_ensemble_create.argtypes = [C.c_int32, C.POINTER(P), C.POINTER(P)]
+    L.les_ensemble_step.argtypes = [P, C.c_int32, C.POINTER(EnsembleStats), P]
+    L.les_ensemble_autotune.argtypes = [P, C.c_int32]
+    L.les_ensemble_last_error.argtypes = [P]
+    L.les_ensemble_last_error.restype = C.c_char_p
+    L.les_ensemble_destroy.argtypes = [P]
+    L.les_ensemble_destroy.restype = None
     L.les_bc_range.argtypes = [C.POINTER(Grid)]
     L.les_bc_range.restype = C.c_int64
     L.les_bc_map.argtypes = [C.POINTER(Grid), C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -324,3 +342,38 @@ def bc_map(nx: int, ny: int, nz: int, item: int):
     if rc != LES_OK:
         raise LesError(rc, "les_bc_map")
     return f.value, a.value, b.value
+
+
+class Ensemble:
+    """Several LES instances advanced together (les_ensemble_*).  Borrows the
+    members: keep them alive and close the ensemble first."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        arr = (C.c_void_p * len(self.members))(*[m.h for m in self.members])
+        h = C.c_void_p()
+        rc = lib().les_ensemble_create(len(self.members), arr, C.byref(h))
+        if rc != LES_OK:
+            raise LesError(rc, "les_ensemble_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().les_ensemble_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def step(self, n=1):
+        """Advance every member n steps: (status, stats, iterations[n, members])."""
+        st = EnsembleStats()
+        iters = np.zeros((max(int(n), 1), len(self.members)), np.int32)
+        rc = lib().les_ensemble_step(self.h, int(n), C.byref(st), _ptr(iters))
+        if rc not in (LES_OK, LES_NOT_CONVERGED):
+            raise LesError(rc, lib().les_ensemble_last_error(self.h).decode())
+        return rc, st.as_dict(), iters[:n].copy()
+
+    def autotune(self, reps=10):
+        rc = lib().les_ensemble_autotune(self.h, int(reps))
+        if rc != LES_OK:
+            raise LesError(rc, lib().les_ensemble_last_error(self.h).decode())

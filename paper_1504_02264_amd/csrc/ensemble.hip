@@ -1,0 +1,650 @@
+// Batched ensemble: several LES instances of uneven grids advanced together.
+//
+// Per step, every stage is ONE launch over an (instance, block) work list
+// (XCD-aware numbering, then a lookup of the owning instance), and the
+// whole pressure solve of all instances is ONE persistent cooperative
+// launch: its blocks walk the sweep work list of all unfinished instances,
+// meet at grid barriers between half-sweeps, evaluate each instance's
+// stopping test on the device and leave instances as they converge.  The
+// per-step stage sequences before and after the solve are captured once in
+// HIP graphs and replayed (two pairs, for the two velocity-buffer parities).
+// The per-cell arithmetic is the single-instance one (les_bodies.h), so an
+// ensemble step is bitwise identical to stepping each member alone.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "les_bodies.h"
+
+namespace cg = cooperative_groups;
+
+namespace les {
+
+// Device descriptor of one member.
+struct EnsInst {
+    Geo g;
+    float* u[2];
+    float* v[2];
+    float* w[2];
+    float* nut;
+    float* fu; float* fv; float* fw;
+    float* su; float* sv; float* sw;
+    uint8_t* flags;
+    float* prof;
+    PBufs P;
+    double* part;       // rhs / check / rebase partials
+    double* rel0;       // sweep partials, colour 0 and 1
+    double* rel1;
+    Ctl* ctl;
+    float c2, nu, alpha, beta, omega, amp;
+    uint64_t seed;
+    double tol;
+    int max_iter, K, R, variant, singular, inflow;
+    unsigned nsweep, nred;
+};
+
+// Per-member state that changes from step to step (device memory).
+struct EnsDyn {
+    int cur;            // index of u^n
+    int first;          // next step is the first (forward Euler)
+    long long step;     // completed steps
+    int last_iters;
+    int done;
+    double resid;
+    double reltmp2;
+    double rhs2;
+};
+
+// Offsets of each member's blocks in a stage's work list.
+struct EnsOffsets {
+    unsigned box[kMaxEnsemble + 1];
+    unsigned cell[kMaxEnsemble + 1];
+    unsigned half[kMaxEnsemble + 1];
+    unsigned red[kMaxEnsemble + 1];
+    unsigned bc[kMaxEnsemble + 1];
+    unsigned inflow[kMaxEnsemble + 1];
+    unsigned sweep[kMaxEnsemble + 1];
+    unsigned fold[kMaxEnsemble + 1];
+};
+
+namespace {
+
+// Control-block fields that steer the persistent solve are written by one
+// block and read by all after a grid barrier: read them coherently.
+__device__ __forceinline__ int ld(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool member_active(const Ctl* c, int it, bool& acc) {
+    const int done = ld(&c->done), m = ld(&c->m), K = ld(&c->K), mx = ld(&c->max_iter);
+    acc = (m + it + 1 == min(m + K, mx));
+    return !(done || m + it >= mx);
+}
+
+__device__ __forceinline__ int owner(const unsigned* off, int n, unsigned L) {
+    int lo = 0, hi = n - 1;   // largest q with off[q] <= L
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------- batched stages
+__global__ __launch_bounds__(kBlock) void k_ens_nut(const EnsInst* I, const EnsDyn* D, int n,
+                                                    const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->box, n, L);
+    const EnsInst& d = I[q];
+    const int a = D[q].cur;
+    nut_body(d.g, d.u[a], d.v[a], d.w[a], d.nut, d.c2, L - O->box[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_tendency(const EnsInst* I, const EnsDyn* D, int n,
+                                                         const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->cell, n, L);
+    const EnsInst& d = I[q];
+    const int a = D[q].cur, b = 1 - a;
+    TendArgs A{d.u[a], d.v[a], d.w[a], d.nut, d.fu, d.fv, d.fw, d.su, d.sv, d.sw, d.flags,
+               d.u[b], d.v[b], d.w[b], d.nu, d.alpha, d.beta, D[q].first};
+    tendency_body(d.g, A, L - O->cell[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_inflow(const EnsInst* I, const EnsDyn* D, int n,
+                                                       const EnsOffsets* O) {
+    const unsigned L = blockIdx.x;
+    const int q = owner(O->inflow, n, L);
+    const EnsInst& d = I[q];
+    if (!d.inflow) return;
+    inflow_body(d.g, d.u[1 - D[q].cur], d.prof, d.flags, d.amp, d.seed, D[q].step + 1,
+                L - O->inflow[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_rhs(const EnsInst* I, const EnsDyn* D, int n,
+                                                    const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->cell, n, L);
+    const EnsInst& d = I[q];
+    const int b = 1 - D[q].cur;
+    rhs_body(d.g, d.u[b], d.v[b], d.w[b], d.P.rhs[0], d.P.rhs[1], d.part, d.singular,
+             L - O->cell[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_rhs_mean(const EnsInst* I, int n,
+                                                         const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->cell, n, L);
+    const EnsInst& d = I[q];
+    if (!d.singular) return;
+    rhs_mean_body(d.g, d.P.rhs[0], d.P.rhs[1], d.part, d.ctl, L - O->cell[q]);
+}
+
+// One block per member: initialise the control block, then (op) finalize.
+__global__ __launch_bounds__(kBlock) void k_ens_ctl_init(const EnsInst* I) {
+    const EnsInst& d = I[blockIdx.x];
+    ctl_init_body(d.ctl, d.tol, d.max_iter, d.K);
+}
+
+// After k_ens_rhs: rhs2 (or the rhs sum of a singular member).
+__global__ __launch_bounds__(kBlock) void k_ens_fin_rhs(const EnsInst* I, const EnsOffsets* O) {
+    const int q = blockIdx.x;
+    const EnsInst& d = I[q];
+    finalize_body<kBlock>(d.singular ? FIN_RHS_SUM : FIN_RHS2, d.part, (int)(O->cell[q + 1] - O->cell[q]),
+                          nullptr, nullptr, 0, d.ctl, d.omega);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_fin_rhs_mean(const EnsInst* I, const EnsOffsets* O) {
+    const int q = blockIdx.x;
+    const EnsInst& d = I[q];
+    if (!d.singular) return;
+    finalize_body<kBlock>(FIN_RHS2, d.part, (int)(O->cell[q + 1] - O->cell[q]), nullptr, nullptr, 0,
+                          d.ctl, d.omega);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_p_sum(const EnsInst* I, int n, const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->red, n, L);
+    const EnsInst& d = I[q];
+    if (!d.singular) return;
+    colour_sum_body(d.g, d.P.ph[0], d.P.ph[1], d.P.pd[0], d.P.pd[1], 1, d.part, L - O->red[q], d.nred);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_fin_p_sum(const EnsInst* I) {
+    const EnsInst& d = I[blockIdx.x];
+    if (!d.singular) return;
+    finalize_body<kBlock>(FIN_PSUM, d.part, (int)d.nred, nullptr, nullptr, 0, d.ctl, d.omega);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_p_sub(const EnsInst* I, int n, const EnsOffsets* O) {
+    const unsigned L = blockIdx.x;
+    const int q = owner(O->half, n, L);
+    const EnsInst& d = I[q];
+    if (!d.singular) return;
+    p_sub_body(d.g, d.P, d.ctl, L - O->half[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_project(const EnsInst* I, const EnsDyn* D, int n,
+                                                        const EnsOffsets* O) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->cell, n, L);
+    const EnsInst& d = I[q];
+    const int b = 1 - D[q].cur;
+    project_body(d.g, d.u[b], d.v[b], d.w[b], d.P, L - O->cell[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_bc(const EnsInst* I, const EnsDyn* D, int n,
+                                                   const EnsOffsets* O) {
+    const unsigned L = blockIdx.x;
+    const int q = owner(O->bc, n, L);
+    const EnsInst& d = I[q];
+    const int b = 1 - D[q].cur;
+    bc_body(d.g, d.u[b], d.v[b], d.w[b], L - O->bc[q]);
+}
+
+// End of a step: flip the buffers, count the step, record the solve.
+__global__ void k_ens_advance(const EnsInst* I, EnsDyn* D, int n) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const Ctl* c = I[q].ctl;
+    EnsDyn& s = D[q];
+    s.cur = 1 - s.cur;
+    s.first = 0;
+    s.step += 1;
+    s.last_iters = c->m;
+    s.done = c->done;
+    s.resid = c->resid;
+    s.reltmp2 = c->reltmp2;
+    s.rhs2 = c->rhs2;
+}
+
+// Outside the graphs: copy this step's [iterations, status] per member.
+__global__ void k_ens_record(const EnsDyn* D, int n, int* out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    out[2 * q] = D[q].last_iters;
+    out[2 * q + 1] = D[q].done;
+}
+
+// ------------------------------------------------- persistent SOR solve
+template <int TX, int KT>
+__device__ __forceinline__ void sweep_one(const EnsInst& d, int c, bool acc, unsigned lb) {
+    sor_body<TX, KT>(d.g, c, d.P.pd[c], d.P.pd[1 - c], d.P.r0[c], d.omega, acc,
+                     c ? d.rel1 : d.rel0, lb);
+}
+
+__device__ __forceinline__ void sweep_variant(const EnsInst& d, int c, bool acc, unsigned lb) {
+    switch (d.variant) {
+        case 0: sweep_one<64, 1>(d, c, acc, lb); break;
+        case 1: sweep_one<32, 1>(d, c, acc, lb); break;
+        case 2: sweep_one<64, 2>(d, c, acc, lb); break;
+        case 3: sweep_one<32, 2>(d, c, acc, lb); break;
+        case 4: sweep_one<64, 4>(d, c, acc, lb); break;
+        case 5: sweep_one<32, 4>(d, c, acc, lb); break;
+        case 6: sweep_one<64, 8>(d, c, acc, lb); break;
+        default: sweep_one<32, 8>(d, c, acc, lb); break;
+    }
+}
+
+// The whole solve of every member in one cooperative launch.  Check
+// interval c (K iterations) is the same for all members; every loop trip
+// count depends only on data read after a grid barrier, so all blocks meet
+// every barrier, and the trip count of the outer loop is bounded by
+// max_checks.  A member leaves the work (its blocks return at once) when
+// its stopping test succeeds or it reaches its max_iter.
+__global__ __launch_bounds__(kBlock) void k_ens_solve(const EnsInst* I, int n, const EnsOffsets* O,
+                                                      int K, int max_checks) {
+    cg::grid_group grid = cg::this_grid();
+    const unsigned nb = gridDim.x;
+    // set-up: fold, sync, rebase (r0 and the initial residual), sync, finalize
+    for (unsigned L = blockIdx.x; L < O->fold[n]; L += nb) {
+        const int q = owner(O->fold, n, L);
+        const EnsInst& d = I[q];
+        if (ld(&d.ctl->done)) continue;
+        fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
+                  (long long)(L - O->fold[q]) * kBlock + threadIdx.x);
+    }
+    grid.sync();
+    for (unsigned L = blockIdx.x; L < O->red[n]; L += nb) {
+        const int q = owner(O->red, n, L);
+        const EnsInst& d = I[q];
+        if (ld(&d.ctl->done)) continue;
+        rebase_body(d.g, d.P, d.part, L - O->red[q], d.nred);
+    }
+    grid.sync();
+    for (int q = blockIdx.x; q < n; q += nb)
+        finalize_body<kBlock>(FIN_SETUP, I[q].part, (int)I[q].nred, nullptr, nullptr, 0, I[q].ctl, I[q].omega);
+    grid.sync();
+
+    for (int c = 0; c < max_checks; ++c) {
+        bool all_done = true;
+        for (int q = 0; q < n; ++q) all_done = all_done && (ld(&I[q].ctl->done) != 0);
+        if (all_done) break;   // uniform: every block read the same flags after the barrier
+        for (int it = 0; it < K; ++it) {
+            for (int colour = 0; colour < 2; ++colour) {
+                for (unsigned L = blockIdx.x; L < O->sweep[n]; L += nb) {
+                    const int q = owner(O->sweep, n, L);
+                    const EnsInst& d = I[q];
+                    bool acc;
+                    if (!member_active(d.ctl, it, acc)) continue;
+                    sweep_variant(d, colour, acc, L - O->sweep[q]);
+                }
+                grid.sync();
+            }
+        }
+        for (int q = blockIdx.x; q < n; q += nb)
+            finalize_body<kBlock>(FIN_BOUND, nullptr, 0, I[q].rel0, I[q].rel1, (int)I[q].nsweep,
+                                  I[q].ctl, I[q].omega);
+        grid.sync();
+        // members whose check interval ends with a rebase fold first
+        bool any_rebase = false;
+        for (int q = 0; q < n; ++q) any_rebase = any_rebase || ((c + 1) % I[q].R == 0);
+        if (any_rebase) {
+            for (unsigned L = blockIdx.x; L < O->fold[n]; L += nb) {
+                const int q = owner(O->fold, n, L);
+                const EnsInst& d = I[q];
+                if ((c + 1) % d.R != 0 || ld(&d.ctl->done)) continue;
+                fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
+                          (long long)(L - O->fold[q]) * kBlock + threadIdx.x);
+            }
+            grid.sync();
+        }
+        for (unsigned L = blockIdx.x; L < O->red[n]; L += nb) {
+            const int q = owner(O->red, n, L);
+            const EnsInst& d = I[q];
+            if (ld(&d.ctl->done)) continue;
+            if ((c + 1) % d.R == 0) rebase_body(d.g, d.P, d.part, L - O->red[q], d.nred);
+            else if (!ld(&d.ctl->skip)) check_body(d.g, d.P, d.part, L - O->red[q], d.nred);
+        }
+        grid.sync();
+        for (int q = blockIdx.x; q < n; q += nb) {
+            const EnsInst& d = I[q];
+            finalize_body<kBlock>(((c + 1) % d.R == 0) ? FIN_CHECK_FULL : FIN_CHECK, d.part,
+                                  (int)d.nred, d.rel0, d.rel1, (int)d.nsweep, d.ctl, d.omega);
+        }
+        grid.sync();
+    }
+}
+
+}  // namespace
+}  // namespace les
+
+using namespace les;
+
+struct les_ensemble {
+    int n = 0;
+    std::vector<les_handle*> members;
+    std::string err;
+    hipStream_t stream = nullptr;
+    EnsInst* d_inst = nullptr;
+    EnsDyn* d_dyn = nullptr;
+    EnsOffsets* d_off = nullptr;
+    EnsOffsets h_off{};
+    int* d_iters = nullptr;        // [capacity][n][iterations, status]
+    int iters_cap = 0;             // steps the [step][member][2] buffers hold
+    EnsDyn* h_dyn = nullptr;       // pinned
+    int* h_iters = nullptr;        // pinned
+    int K = 4;
+    int max_checks = 0;
+    int solve_grid = 0;
+    bool graphs_ready = false;
+    hipGraphExec_t pre[2] = {nullptr, nullptr};
+    hipGraphExec_t post[2] = {nullptr, nullptr};
+    int64_t cells_total = 0;
+    std::vector<EnsInst> h_inst;
+};
+
+namespace {
+
+int ens_err(les_ensemble* e, int code, const char* what, hipError_t he = hipSuccess) {
+    if (e) {
+        e->err = what;
+        if (he != hipSuccess) e->err += std::string(": ") + hipGetErrorString(he);
+    }
+    return code;
+}
+
+#define ECK(expr)                                                          \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) return ens_err(e, LES_EDEVICE, #expr, e_);   \
+    } while (0)
+
+unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Host copies of the member descriptors and work-list offsets, from the
+// members' current settings (inflow, sweep variant, parameters).
+void build_descriptors(les_ensemble* e) {
+    const int n = e->n;
+    e->h_inst.assign(n, EnsInst{});
+    EnsOffsets& o = e->h_off;
+    std::memset(&o, 0, sizeof o);
+    int max_iter_all = 0;
+    e->cells_total = 0;
+    for (int q = 0; q < n; ++q) {
+        les_handle* h = e->members[q];
+        EnsInst& d = e->h_inst[q];
+        std::memset(&d, 0, sizeof d);
+        d.g = h->g;
+        for (int b = 0; b < 2; ++b) {
+            d.u[b] = h->f.u[b];
+            d.v[b] = h->f.v[b];
+            d.w[b] = h->f.w[b];
+        }
+        d.nut = h->f.nut;
+        d.fu = h->f.fu; d.fv = h->f.fv; d.fw = h->f.fw;
+        d.su = h->f.su; d.sv = h->f.sv; d.sw = h->f.sw;
+        d.flags = h->f.flags;
+        d.prof = h->f.prof;
+        d.P = h->f.P;
+        d.part = h->f.part[0];
+        d.rel0 = h->f.part[1];
+        d.rel1 = h->f.part[2];
+        d.ctl = h->f.ctl;
+        const double delta = std::cbrt((double)h->g.dx * h->g.dy * h->g.dz);
+        d.c2 = (float)((h->prm.cs * delta) * (h->prm.cs * delta));
+        d.nu = (float)h->prm.nu;
+        d.alpha = (float)h->prm.alpha;
+        d.beta = (float)h->prm.beta;
+        d.omega = (float)h->prm.omega;
+        d.amp = h->amp;
+        d.seed = h->seed;
+        d.tol = h->prm.tol;
+        d.max_iter = h->prm.max_iter;
+        d.K = h->prm.check_every;
+        d.R = h->prm.rebase_every;
+        d.variant = h->sor_variant;
+        d.singular = h->g.outflow ? 0 : 1;
+        d.inflow = h->g.inflow;
+        d.nsweep = sor_sweep_blocks(h->g, h->sor_variant);
+        d.nred = red_blocks(h->g);
+        max_iter_all = std::max(max_iter_all, h->prm.max_iter);
+        o.box[q + 1] = o.box[q] + box_blocks(h->g);
+        o.cell[q + 1] = o.cell[q] + cell_blocks(h->g);
+        o.half[q + 1] = o.half[q] + half_blocks(h->g);
+        o.red[q + 1] = o.red[q] + d.nred;
+        o.bc[q + 1] = o.bc[q] + bc_blocks(h->g);
+        o.inflow[q + 1] = o.inflow[q] + nblk((long long)h->g.ny * h->g.nz);
+        o.sweep[q + 1] = o.sweep[q] + d.nsweep;
+        o.fold[q + 1] = o.fold[q] + nblk(2 * h->g.ctot);
+        e->cells_total += (int64_t)h->g.nx * h->g.ny * h->g.nz;
+    }
+    e->max_checks = (max_iter_all + e->K - 1) / e->K;
+}
+
+// The stage sequence before the solve (nu_t .. rhs, mean removal) and the
+// one after it (p mean, projection, boundary refresh, advance).
+int enqueue_pre(les_ensemble* e, hipStream_t s) {
+    const int n = e->n;
+    const EnsOffsets& o = e->h_off;
+    hipLaunchKernelGGL(k_ens_nut, dim3(o.box[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_tendency, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_inflow, dim3(o.inflow[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_ctl_init, dim3(n), dim3(kBlock), 0, s, e->d_inst);
+    hipLaunchKernelGGL(k_ens_rhs, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_fin_rhs, dim3(n), dim3(kBlock), 0, s, e->d_inst, e->d_off);
+    hipLaunchKernelGGL(k_ens_rhs_mean, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_fin_rhs_mean, dim3(n), dim3(kBlock), 0, s, e->d_inst, e->d_off);
+    ECK(hipGetLastError());
+    return LES_OK;
+}
+
+int enqueue_post(les_ensemble* e, hipStream_t s) {
+    const int n = e->n;
+    const EnsOffsets& o = e->h_off;
+    hipLaunchKernelGGL(k_ens_p_sum, dim3(o.red[n]), dim3(kBlock), 0, s, e->d_inst, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_fin_p_sum, dim3(n), dim3(kBlock), 0, s, e->d_inst);
+    hipLaunchKernelGGL(k_ens_p_sub, dim3(o.half[n]), dim3(kBlock), 0, s, e->d_inst, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_project, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_bc, dim3(o.bc[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_advance, dim3((n + 63) / 64), dim3(64), 0, s, e->d_inst, e->d_dyn, n);
+    ECK(hipGetLastError());
+    return LES_OK;
+}
+
+int launch_solve(les_ensemble* e, hipStream_t s) {
+    const EnsInst* I = e->d_inst;
+    int n = e->n;
+    const EnsOffsets* O = e->d_off;
+    int K = e->K, mc = e->max_checks;
+    void* args[] = {(void*)&I, (void*)&n, (void*)&O, (void*)&K, (void*)&mc};
+    ECK(hipLaunchCooperativeKernel((const void*)k_ens_solve, dim3(e->solve_grid), dim3(kBlock), args,
+                                   0, s));
+    return LES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** out) {
+    if (!out || !members || n < 1 || n > kMaxEnsemble) return LES_EINVAL;
+    *out = nullptr;
+    for (int q = 0; q < n; ++q) {
+        if (!members[q]) return LES_EINVAL;
+        for (int r = 0; r < q; ++r)
+            if (members[r] == members[q]) return LES_EINVAL;
+        if (members[q]->prm.check_every != members[0]->prm.check_every) return LES_EINVAL;
+        if (members[q]->device != members[0]->device) return LES_EINVAL;
+        if (members[q]->prm.zero_guess) return LES_EINVAL;
+    }
+    les_ensemble* e = new (std::nothrow) les_ensemble();
+    if (!e) return LES_ENOMEM;
+    e->n = n;
+    e->members.assign(members, members + n);
+    e->K = members[0]->prm.check_every;
+    auto fail = [&](int code) {
+        les_ensemble_destroy(e);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) return fail(LES_EDEVICE);
+    build_descriptors(e);
+    if (hipMalloc(&e->d_inst, sizeof(EnsInst) * n) != hipSuccess) return fail(LES_ENOMEM);
+    if (hipMalloc(&e->d_dyn, sizeof(EnsDyn) * n) != hipSuccess) return fail(LES_ENOMEM);
+    if (hipMalloc(&e->d_off, sizeof(EnsOffsets)) != hipSuccess) return fail(LES_ENOMEM);
+    if (hipHostMalloc((void**)&e->h_dyn, sizeof(EnsDyn) * n, hipHostMallocDefault) != hipSuccess)
+        return fail(LES_ENOMEM);
+    if (hipMemcpy(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LES_EDEVICE);
+    if (hipMemcpy(e->d_off, &e->h_off, sizeof(EnsOffsets), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LES_EDEVICE);
+    // cooperative grid: as many blocks as can be co-resident
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LES_EDEVICE);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(LES_EDEVICE);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_ens_solve, kBlock, 0) !=
+            hipSuccess || per_cu < 1)
+        return fail(LES_EDEVICE);
+    e->solve_grid = cus * std::min(per_cu, 4);
+    *out = e;
+    return LES_OK;
+}
+
+void les_ensemble_destroy(les_ensemble* e) {
+    if (!e) return;
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (int p = 0; p < 2; ++p) {
+        if (e->pre[p]) (void)hipGraphExecDestroy(e->pre[p]);
+        if (e->post[p]) (void)hipGraphExecDestroy(e->post[p]);
+    }
+    if (e->d_inst) (void)hipFree(e->d_inst);
+    if (e->d_dyn) (void)hipFree(e->d_dyn);
+    if (e->d_off) (void)hipFree(e->d_off);
+    if (e->d_iters) (void)hipFree(e->d_iters);
+    if (e->h_dyn) (void)hipHostFree(e->h_dyn);
+    if (e->h_iters) (void)hipHostFree(e->h_iters);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+const char* les_ensemble_last_error(const les_ensemble* e) { return e ? e->err.c_str() : ""; }
+
+int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
+    if (!e || reps < 1 || reps > 1000) return LES_EINVAL;
+    for (int q = 0; q < e->n; ++q) {
+        int rc = les_autotune(e->members[q], reps, nullptr, nullptr);
+        if (rc != LES_OK) return ens_err(e, rc, "les_autotune of a member");
+    }
+    return LES_OK;   // the chosen variants are picked up at the next step
+}
+
+int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out) {
+    if (!e || nsteps < 0) return LES_EINVAL;
+    const int n = e->n;
+    for (int q = 0; q < n; ++q)
+        if (!e->members[q]->have_inflow) return ens_err(e, LES_ESTATE, "member without inflow");
+    auto t0 = std::chrono::steady_clock::now();
+    // members' own streams finish first; the ensemble works on its stream
+    for (int q = 0; q < n; ++q) ECK(hipStreamSynchronize(e->members[q]->stream));
+    // current per-member state
+    for (int q = 0; q < n; ++q) {
+        les_handle* h = e->members[q];
+        EnsDyn& s = e->h_dyn[q];
+        std::memset(&s, 0, sizeof s);
+        s.cur = h->cur;
+        s.first = h->have_old ? 0 : 1;
+        s.step = h->step;
+    }
+    ECK(hipMemcpyAsync(e->d_dyn, e->h_dyn, sizeof(EnsDyn) * n, hipMemcpyHostToDevice, e->stream));
+    build_descriptors(e);
+    ECK(hipMemcpyAsync(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice, e->stream));
+    ECK(hipMemcpyAsync(e->d_off, &e->h_off, sizeof(EnsOffsets), hipMemcpyHostToDevice, e->stream));
+    if (nsteps > e->iters_cap) {
+        if (e->d_iters) ECK(hipFree(e->d_iters));
+        if (e->h_iters) ECK(hipHostFree(e->h_iters));
+        e->d_iters = nullptr;
+        e->h_iters = nullptr;
+        ECK(hipMalloc(&e->d_iters, 2 * sizeof(int) * (size_t)n * nsteps));
+        ECK(hipHostMalloc((void**)&e->h_iters, 2 * sizeof(int) * (size_t)n * nsteps, hipHostMallocDefault));
+        e->iters_cap = nsteps;
+    }
+    if (!e->graphs_ready && nsteps > 0) {
+        for (int p = 0; p < 2; ++p) {
+            for (int which = 0; which < 2; ++which) {
+                hipGraph_t gph = nullptr;
+                ECK(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+                int rc = which == 0 ? enqueue_pre(e, e->stream) : enqueue_post(e, e->stream);
+                hipError_t ce = hipStreamEndCapture(e->stream, &gph);
+                if (rc != LES_OK) return rc;
+                ECK(ce);
+                hipGraphExec_t& ex = which == 0 ? e->pre[p] : e->post[p];
+                if (ex) ECK(hipGraphExecDestroy(ex));
+                ex = nullptr;
+                ECK(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
+                ECK(hipGraphDestroy(gph));
+            }
+        }
+        e->graphs_ready = true;
+    }
+    for (int s = 0; s < nsteps; ++s) {
+        ECK(hipGraphLaunch(e->pre[s & 1], e->stream));
+        int rc = launch_solve(e, e->stream);
+        if (rc != LES_OK) return rc;
+        ECK(hipGraphLaunch(e->post[s & 1], e->stream));
+        hipLaunchKernelGGL(k_ens_record, dim3((n + 63) / 64), dim3(64), 0, e->stream, e->d_dyn, n,
+                           e->d_iters + 2 * (size_t)s * n);
+        ECK(hipGetLastError());
+    }
+    ECK(hipMemcpyAsync(e->h_dyn, e->d_dyn, sizeof(EnsDyn) * n, hipMemcpyDeviceToHost, e->stream));
+    if (nsteps > 0)
+        ECK(hipMemcpyAsync(e->h_iters, e->d_iters, 2 * sizeof(int) * (size_t)n * nsteps,
+                           hipMemcpyDeviceToHost, e->stream));
+    ECK(hipStreamSynchronize(e->stream));
+    int worst = LES_OK;
+    les_ensemble_stats acc{};
+    acc.members = n;
+    acc.steps = nsteps;
+    acc.cells_total = e->cells_total;
+    for (int q = 0; q < n; ++q) {
+        les_handle* h = e->members[q];
+        const EnsDyn& s = e->h_dyn[q];
+        h->cur = s.cur;
+        h->step = s.step;
+        if (nsteps > 0) h->have_old = true;
+        if (nsteps > 0 && (s.done == 3 || !std::isfinite(s.rhs2)))
+            return ens_err(e, LES_ENONFINITE, "non-finite residual norm in a member");
+    }
+    for (int s = 0; s < nsteps; ++s)
+        for (int q = 0; q < n; ++q) {
+            const int it = e->h_iters[2 * ((size_t)s * n + q)];
+            const int done = e->h_iters[2 * ((size_t)s * n + q) + 1];
+            acc.sor_iters_total += it;
+            if (iters_out) iters_out[(size_t)s * n + q] = it;
+            if (done == 2) {
+                acc.not_converged += 1;
+                worst = LES_NOT_CONVERGED;
+            }
+        }
+    acc.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = acc;
+    return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,835 @@
+// Device bodies of every LES kernel, parameterized by the logical block
+// index so that the same per-cell arithmetic runs in the single-instance
+// launches (kernels_step.hip, kernels_sor.hip) and in the batched and
+// persistent ensemble launches (ensemble.hip).
+//
+// Staggered (MAC) grid: u on x-faces, v on y-faces, w on z-faces, scalars
+// at cell centres; layouts in les_impl.h.  All fields float32, all norms
+// float64.
+#pragma once
+
+#include "device_util.h"
+#include "les_impl.h"
+
+namespace les {
+
+// Reductions over the H * ny * nz half-cells use at most kRedBlocks blocks;
+// block L owns one contiguous chunk of half-cells, walked by its threads
+// with unit stride, so finalizing sums few partials.
+constexpr unsigned kRedBlocks = 2048;
+inline unsigned red_blocks(const Geo& g) {
+    const long long n = (long long)g.H * g.ny * g.nz;
+    const long long b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < (long long)kRedBlocks ? b : (long long)kRedBlocks);
+}
+inline unsigned cell_blocks(const Geo& g) {
+    return (unsigned)(((long long)g.nx * g.ny * g.nz + kBlock - 1) / kBlock);
+}
+inline unsigned half_blocks(const Geo& g) {
+    return (unsigned)(((long long)g.H * g.ny * g.nz + kBlock - 1) / kBlock);
+}
+inline unsigned box_blocks(const Geo& g) {
+    return (unsigned)(((long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2) + kBlock - 1) / kBlock);
+}
+inline unsigned bc_blocks(const Geo& g) {
+    return (unsigned)((bc_items(g.nx, g.ny, g.nz) + kBlock - 1) / kBlock);
+}
+
+__device__ __forceinline__ void red_chunk(const Geo& g, unsigned lb, unsigned nb, long long& t0,
+                                          long long& t1) {
+    const long long n = (long long)g.H * g.ny * g.nz;
+    const long long chunk = ((n + nb - 1) / nb + kBlock - 1) / kBlock * kBlock;
+    t0 = (long long)lb * chunk;
+    t1 = (t0 + chunk < n) ? t0 + chunk : n;
+}
+
+// Linear interior-cell index (0-based, x fastest) -> 1-based cell coordinates.
+__device__ __forceinline__ void cell_of(const Geo& g, long long t, int& i, int& j, int& k) {
+    const unsigned tt = (unsigned)t;   // cells < 2^31 (checked at create)
+    const unsigned nxy = (unsigned)g.nx * (unsigned)g.ny;
+    const unsigned kk = tt / nxy;
+    const unsigned r = tt - kk * nxy;
+    const unsigned jj = r / (unsigned)g.nx;
+    i = (int)(r - jj * (unsigned)g.nx) + 1;
+    j = (int)jj + 1;
+    k = (int)kk + 1;
+}
+
+// Linear half-cell index -> colour-array coordinates (ii, j0, k0).
+__device__ __forceinline__ bool half_cell(const Geo& g, long long t, int& ii, int& j0, int& k0) {
+    const unsigned hy = (unsigned)g.H * (unsigned)g.ny;   // H ny nz < 2^31
+    if (t >= (long long)hy * g.nz) return false;
+    const unsigned tt = (unsigned)t;
+    const unsigned kk = tt / hy;
+    const unsigned r = tt - kk * hy;
+    const unsigned jj = r / (unsigned)g.H;
+    ii = (int)(r - jj * (unsigned)g.H);
+    j0 = (int)jj;
+    k0 = (int)kk;
+    return true;
+}
+
+// Diagonal of A at 0-based cell (i0, j0, k0): 1/h^2 per interior neighbour,
+// nothing across a wall or the inflow face (Neumann), 2/h^2 across the
+// outflow face (p = 0 on the face).
+__device__ __forceinline__ float diag_of(const Geo& g, int i0, int j0, int k0) {
+    const float dxx = (i0 > 0 ? g.cx : 0.f) + (i0 < g.nx - 1 ? g.cx : (g.outflow ? 2.f * g.cx : 0.f));
+    const float dyy = (j0 > 0 ? g.cy : 0.f) + (j0 < g.ny - 1 ? g.cy : 0.f);
+    const float dzz = (k0 > 0 ? g.cz : 0.f) + (k0 < g.nz - 1 ? g.cz : 0.f);
+    return dxx + dyy + dzz;
+}
+
+// ------------------------------------------------------------------ les
+// Smagorinsky eddy viscosity nu_t = (Cs Delta)^2 |S|, |S| = sqrt(2 S_ij S_ij)
+// (section 2.1, les).  S_ii from the two faces of the cell; S_ij (i != j)
+// is the mean of the four edge values around the cell, each edge value
+// being 1/2 (du_i/dx_j + du_j/dx_i) from the adjacent faces.  Covers the
+// whole ghosted box: a ghost cell takes the value of the nearest interior
+// cell (mirrored ghost ring).
+__device__ __forceinline__ void nut_body(const Geo& g, const float* __restrict__ u,
+                                         const float* __restrict__ v, const float* __restrict__ w,
+                                         float* __restrict__ nut, float c2, unsigned lb) {
+    const long long nbox = (long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= nbox) return;
+    const unsigned pxy = (unsigned)(g.nx + 2) * (unsigned)(g.ny + 2);
+    const unsigned tt = (unsigned)t;
+    const int k = (int)(tt / pxy);
+    const unsigned r = tt - (unsigned)k * pxy;
+    const int j = (int)(r / (unsigned)(g.nx + 2));
+    const int i = (int)(r - (unsigned)j * (unsigned)(g.nx + 2));
+    const int ic = min(max(i, 1), g.nx), jc = min(max(j, 1), g.ny), kc = min(max(k, 1), g.nz);
+    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
+    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
+    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
+    const float s11 = (U(ic, jc, kc) - U(ic - 1, jc, kc)) * g.idx;
+    const float s22 = (V(ic, jc, kc) - V(ic, jc - 1, kc)) * g.idy;
+    const float s33 = (W(ic, jc, kc) - W(ic, jc, kc - 1)) * g.idz;
+    float s12 = 0.f, s13 = 0.f, s23 = 0.f;
+#pragma unroll
+    for (int da = -1; da <= 0; ++da)
+#pragma unroll
+        for (int db = -1; db <= 0; ++db) {
+            const int a = ic + da, b = jc + db;   // x-y edge (face a, face b)
+            s12 += (U(a, b + 1, kc) - U(a, b, kc)) * g.idy + (V(a + 1, b, kc) - V(a, b, kc)) * g.idx;
+            const int c = kc + db;                // x-z edge (face a, face c)
+            s13 += (U(a, jc, c + 1) - U(a, jc, c)) * g.idz + (W(a + 1, jc, c) - W(a, jc, c)) * g.idx;
+            const int b2 = jc + da;               // y-z edge (face b2, face c)
+            s23 += (V(ic, b2, c + 1) - V(ic, b2, c)) * g.idz + (W(ic, b2 + 1, c) - W(ic, b2, c)) * g.idy;
+        }
+    s12 *= 0.125f;   // 1/4 (mean of 4 edges) * 1/2 (symmetric part)
+    s13 *= 0.125f;
+    s23 *= 0.125f;
+    const float ss = 2.f * (s11 * s11 + s22 * s22 + s33 * s33) + 4.f * (s12 * s12 + s13 * s13 + s23 * s23);
+    nut[g.nat(i, j, k)] = c2 * sqrtf(ss);
+}
+
+// ------------------------------------------- velfg + feedbf + adam (fused)
+// Per cell (i,j,k) the tendencies of its east u-face, north v-face and top
+// w-face:  F = -(covx + covy + covz) + nu lap + div(2 nu_t S).
+// The cov pieces are the paper's velfg assembly (section 2.5.3): products
+// of an averaged advecting velocity and a one-sided difference on the two
+// half-points around the face, averaged onto the face; the diffusive part
+// is the difference of the one-sided (diu) fluxes, i.e. the 7-point
+// Laplacian.  The subgrid stress uses nu_t at centres for the normal
+// component and the 4-cell edge mean for the shear components.
+// Then building feedback forcing on solid faces (feedbf):
+//   usum += dt u;  F += alpha usum + beta u
+// and the Adams-Bashforth update (adam):
+//   u* = u + dt (3/2 F - 1/2 F_old)  (F_old := F on the first step);  F_old <- F.
+struct TendArgs {
+    const float* u; const float* v; const float* w; const float* nut;
+    float* fu; float* fv; float* fw;
+    float* su; float* sv; float* sw;
+    const uint8_t* flags;
+    float* us; float* vs; float* ws;
+    float nu, alpha, beta;
+    int first;
+};
+
+__device__ __forceinline__ void tendency_body(const Geo& g, const TendArgs& A, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= n) return;
+    int i, j, k;
+    cell_of(g, t, i, j, k);
+    const float* __restrict__ u = A.u;
+    const float* __restrict__ v = A.v;
+    const float* __restrict__ w = A.w;
+    const float* __restrict__ nut = A.nut;
+    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
+    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
+    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
+    auto N = [&](int a, int b, int c) { return nut[g.nat(a, b, c)]; };
+    // edge viscosities and strain rates
+    auto n12 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b + 1, c) + N(a + 1, b + 1, c)); };
+    auto n13 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b, c + 1) + N(a + 1, b, c + 1)); };
+    auto n23 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a, b + 1, c) + N(a, b, c + 1) + N(a, b + 1, c + 1)); };
+    auto e12 = [&](int a, int b, int c) { return 0.5f * ((U(a, b + 1, c) - U(a, b, c)) * g.idy + (V(a + 1, b, c) - V(a, b, c)) * g.idx); };
+    auto e13 = [&](int a, int b, int c) { return 0.5f * ((U(a, b, c + 1) - U(a, b, c)) * g.idz + (W(a + 1, b, c) - W(a, b, c)) * g.idx); };
+    auto e23 = [&](int a, int b, int c) { return 0.5f * ((V(a, b, c + 1) - V(a, b, c)) * g.idz + (W(a, b + 1, c) - W(a, b, c)) * g.idy); };
+
+    const long long e = g.nat(i, j, k);
+    const uint8_t fl = A.flags[e];
+    const float dt = g.dt;
+    const float nu = A.nu, alpha = A.alpha, beta = A.beta;
+
+    if (i <= g.u_last) {
+        const float uc = U(i, j, k);
+        const float um = U(i - 1, j, k), up = U(i + 1, j, k);
+        const float covx = 0.5f * (0.5f * (um + uc) * (uc - um) + 0.5f * (uc + up) * (up - uc)) * g.idx;
+        const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i + 1, j - 1, k)) * (uc - U(i, j - 1, k)) +
+                                   0.5f * (V(i, j, k) + V(i + 1, j, k)) * (U(i, j + 1, k) - uc)) * g.idy;
+        const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i + 1, j, k - 1)) * (uc - U(i, j, k - 1)) +
+                                   0.5f * (W(i, j, k) + W(i + 1, j, k)) * (U(i, j, k + 1) - uc)) * g.idz;
+        const float lap = (up - 2.f * uc + um) * g.cx + (U(i, j + 1, k) - 2.f * uc + U(i, j - 1, k)) * g.cy +
+                          (U(i, j, k + 1) - 2.f * uc + U(i, j, k - 1)) * g.cz;
+        const float sgs = 2.f * (N(i + 1, j, k) * (up - uc) * g.idx - N(i, j, k) * (uc - um) * g.idx) * g.idx +
+                          2.f * (n12(i, j, k) * e12(i, j, k) - n12(i, j - 1, k) * e12(i, j - 1, k)) * g.idy +
+                          2.f * (n13(i, j, k) * e13(i, j, k) - n13(i, j, k - 1) * e13(i, j, k - 1)) * g.idz;
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_USOLID) {
+            const float s = A.su[e] + dt * uc;
+            A.su[e] = s;
+            F += alpha * s + beta * uc;
+        }
+        const float fo = A.first ? F : A.fu[e];
+        A.us[e] = uc + dt * (1.5f * F - 0.5f * fo);
+        A.fu[e] = F;
+    }
+    if (j <= g.ny - 1) {
+        const float vc = V(i, j, k);
+        const float vm = V(i, j - 1, k), vp = V(i, j + 1, k);
+        const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j + 1, k)) * (vc - V(i - 1, j, k)) +
+                                   0.5f * (U(i, j, k) + U(i, j + 1, k)) * (V(i + 1, j, k) - vc)) * g.idx;
+        const float covy = 0.5f * (0.5f * (vm + vc) * (vc - vm) + 0.5f * (vc + vp) * (vp - vc)) * g.idy;
+        const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i, j + 1, k - 1)) * (vc - V(i, j, k - 1)) +
+                                   0.5f * (W(i, j, k) + W(i, j + 1, k)) * (V(i, j, k + 1) - vc)) * g.idz;
+        const float lap = (V(i + 1, j, k) - 2.f * vc + V(i - 1, j, k)) * g.cx + (vp - 2.f * vc + vm) * g.cy +
+                          (V(i, j, k + 1) - 2.f * vc + V(i, j, k - 1)) * g.cz;
+        const float sgs = 2.f * (n12(i, j, k) * e12(i, j, k) - n12(i - 1, j, k) * e12(i - 1, j, k)) * g.idx +
+                          2.f * (N(i, j + 1, k) * (vp - vc) * g.idy - N(i, j, k) * (vc - vm) * g.idy) * g.idy +
+                          2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j, k - 1) * e23(i, j, k - 1)) * g.idz;
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_VSOLID) {
+            const float s = A.sv[e] + dt * vc;
+            A.sv[e] = s;
+            F += alpha * s + beta * vc;
+        }
+        const float fo = A.first ? F : A.fv[e];
+        A.vs[e] = vc + dt * (1.5f * F - 0.5f * fo);
+        A.fv[e] = F;
+    }
+    if (k <= g.nz - 1) {
+        const float wc = W(i, j, k);
+        const float wm = W(i, j, k - 1), wp = W(i, j, k + 1);
+        const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j, k + 1)) * (wc - W(i - 1, j, k)) +
+                                   0.5f * (U(i, j, k) + U(i, j, k + 1)) * (W(i + 1, j, k) - wc)) * g.idx;
+        const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i, j - 1, k + 1)) * (wc - W(i, j - 1, k)) +
+                                   0.5f * (V(i, j, k) + V(i, j, k + 1)) * (W(i, j + 1, k) - wc)) * g.idy;
+        const float covz = 0.5f * (0.5f * (wm + wc) * (wc - wm) + 0.5f * (wc + wp) * (wp - wc)) * g.idz;
+        const float lap = (W(i + 1, j, k) - 2.f * wc + W(i - 1, j, k)) * g.cx +
+                          (W(i, j + 1, k) - 2.f * wc + W(i, j - 1, k)) * g.cy + (wp - 2.f * wc + wm) * g.cz;
+        const float sgs = 2.f * (n13(i, j, k) * e13(i, j, k) - n13(i - 1, j, k) * e13(i - 1, j, k)) * g.idx +
+                          2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j - 1, k) * e23(i, j - 1, k)) * g.idy +
+                          2.f * (N(i, j, k + 1) * (wp - wc) * g.idz - N(i, j, k) * (wc - wm) * g.idz) * g.idz;
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_WSOLID) {
+            const float s = A.sw[e] + dt * wc;
+            A.sw[e] = s;
+            F += alpha * s + beta * wc;
+        }
+        const float fo = A.first ? F : A.fw[e];
+        A.ws[e] = wc + dt * (1.5f * F - 0.5f * fo);
+        A.fw[e] = F;
+    }
+}
+
+// --------------------------------------------------------- bondv1: inflow
+// splitmix64 (Steele, Lea & Flood 2014): output of the generator whose
+// state is x.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// u*(0, j, k) = U(k) (1 + a (2 xi - 1)) on fluid inflow faces, 0 on solid
+// ones; xi = top 24 bits of splitmix64(seed ^ (step 2^40 + k0 2^20 + j0)).
+__device__ __forceinline__ void inflow_body(const Geo& g, float* __restrict__ us,
+                                            const float* __restrict__ prof,
+                                            const uint8_t* __restrict__ flags, float amp,
+                                            uint64_t seed, long long step, unsigned lb) {
+    const int t = (int)(lb * kBlock + threadIdx.x);
+    if (t >= g.ny * g.nz) return;
+    const int k0 = t / g.ny, j0 = t - k0 * g.ny;
+    const uint64_t ctr = ((uint64_t)step << 40) + ((uint64_t)k0 << 20) + (uint64_t)j0;
+    const uint64_t r = splitmix64(seed ^ ctr);
+    const float xi = (float)(r >> 40) * (1.0f / 16777216.0f);
+    const bool solid = (flags[g.nat(1, j0 + 1, k0 + 1)] & F_CSOLID) != 0;
+    us[g.nat(0, j0 + 1, k0 + 1)] = solid ? 0.f : prof[k0] * (1.f + amp * (2.f * xi - 1.f));
+}
+
+__device__ __forceinline__ void ctl_init_body(Ctl* ctl, double tol, int max_iter, int K) {
+    if (threadIdx.x == 0) {
+        ctl->done = 0;
+        ctl->m = 0;
+        ctl->K = K;
+        ctl->max_iter = max_iter;
+        ctl->tol = tol;
+        ctl->rhs2 = 0.0;
+        ctl->rhs_sum = 0.0;
+        ctl->resid = 0.0;
+        ctl->reltmp2 = 0.0;
+        ctl->skip = 0;
+    }
+}
+
+// -------------------------------------------------------- press: the rhs
+// rhs = div(u*) / dt at every cell, stored in the colour layout; one
+// float64 partial per block of sum rhs^2 (or of rhs when the operator is
+// singular and the mean has to go first).
+__device__ __forceinline__ void rhs_body(const Geo& g, const float* __restrict__ us,
+                                         const float* __restrict__ vs, const float* __restrict__ ws,
+                                         float* rhs0, float* rhs1, double* __restrict__ part,
+                                         int singular, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    double acc = 0.0;
+    if (t < n) {
+        int i, j, k;
+        cell_of(g, t, i, j, k);
+        const float div = (us[g.nat(i, j, k)] - us[g.nat(i - 1, j, k)]) * g.idx +
+                          (vs[g.nat(i, j, k)] - vs[g.nat(i, j - 1, k)]) * g.idy +
+                          (ws[g.nat(i, j, k)] - ws[g.nat(i, j, k - 1)]) * g.idz;
+        const float r = div * g.idt;
+        const int i0 = i - 1, j0 = j - 1, k0 = k - 1;
+        float* dst = ((i0 + j0 + k0) & 1) ? rhs1 : rhs0;
+        dst[g.col(i0 >> 1, j0, k0)] = r;
+        acc = singular ? (double)r : (double)r * (double)r;
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// Singular operator: subtract the mean of rhs (from ctl->rhs_sum), then
+// leave partials of sum rhs^2.
+__device__ __forceinline__ void rhs_mean_body(const Geo& g, float* rhs0, float* rhs1,
+                                              double* __restrict__ part, const Ctl* ctl,
+                                              unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    const float mean = (float)(ctl->rhs_sum / (double)n);
+    double acc = 0.0;
+    if (t < n) {
+        int i, j, k;
+        cell_of(g, t, i, j, k);
+        const int i0 = i - 1, j0 = j - 1, k0 = k - 1;
+        float* dst = ((i0 + j0 + k0) & 1) ? rhs1 : rhs0;
+        const long long e = g.col(i0 >> 1, j0, k0);
+        const float r = dst[e] - mean;
+        dst[e] = r;
+        acc = (double)r * (double)r;
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// ------------------------------------------------------- velnw: projection
+// u = u* - dt grad p on faces between two cells and on the outflow face,
+// where p = 0 on the face (ghost -p).  p is the pair base + correction of
+// the pressure solve; differences are taken pairwise before the sum so
+// the gradient keeps the correction's precision.
+__device__ __forceinline__ void project_body(const Geo& g, float* __restrict__ us,
+                                             float* __restrict__ vs, float* __restrict__ ws,
+                                             const PBufs& P, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= n) return;
+    int i, j, k;
+    cell_of(g, t, i, j, k);
+    const int i0 = i - 1, j0 = j - 1, k0 = k - 1;
+    const int c = (i0 + j0 + k0) & 1;
+    const float* __restrict__ phc = P.ph[c];
+    const float* __restrict__ pdc = P.pd[c];
+    const float* __restrict__ pho = P.ph[1 - c];   // neighbours have the other colour
+    const float* __restrict__ pdo = P.pd[1 - c];
+    const long long ec = g.col(i0 >> 1, j0, k0);
+    const float hc = phc[ec], dc = pdc[ec];
+    const float dt = g.dt;
+    const long long e = g.nat(i, j, k);
+    if (i0 + 1 < g.nx) {
+        const long long en = g.col((i0 + 1) >> 1, j0, k0);
+        us[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * g.idx);
+    } else if (g.outflow) {
+        us[e] -= dt * ((-2.f * hc - 2.f * dc) * g.idx);
+    }
+    if (j0 + 1 < g.ny) {
+        const long long en = ec + g.S;
+        vs[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * g.idy);
+    }
+    if (k0 + 1 < g.nz) {
+        const long long en = ec + g.SP;
+        ws[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * g.idz);
+    }
+}
+
+// ------------------------------------------------ bondv1: ghost refresh
+// One item of the boundary range of section 2.4: (ny+2)(nz+2) items for
+// the x faces, nx(nz+2) for the y faces and nx ny for the z faces, split by
+// the item id; each item fills the low and the high ghost of its family
+// for u, v and w.  Every ghost value is composed directly from an owned
+// value (per axis: copy, negate or zero), so items never read what another
+// item writes and edges/corners need no ordering.
+struct AxisMap {
+    int src;
+    float sgn;
+    bool ghost;
+    bool zero;
+};
+
+__device__ __forceinline__ AxisMap map_x(const Geo& g, int comp, int i) {
+    if (comp == 0) {   // u: owned faces 0..nx, ghost nx+1
+        if (i == g.nx + 1) return {g.nx, 1.f, true, !g.outflow};
+        return {i, 1.f, false, false};
+    }
+    if (i == 0) return {1, g.s_xm, true, false};
+    if (i == g.nx + 1) return {g.nx, g.s_xp, true, false};
+    return {i, 1.f, false, false};
+}
+__device__ __forceinline__ AxisMap map_y(const Geo& g, int comp, int j) {
+    if (comp == 1) {   // v: owned faces 0..ny (0, ny walls), ny+1 unused
+        if (j == g.ny + 1) return {j, 0.f, true, true};
+        return {j, 1.f, false, false};
+    }
+    if (j == 0) return {1, g.s_ym, true, false};
+    if (j == g.ny + 1) return {g.ny, g.s_yp, true, false};
+    return {j, 1.f, false, false};
+}
+__device__ __forceinline__ AxisMap map_z(const Geo& g, int comp, int k) {
+    if (comp == 2) {   // w: owned faces 0..nz (0, nz walls), nz+1 unused
+        if (k == g.nz + 1) return {k, 0.f, true, true};
+        return {k, 1.f, false, false};
+    }
+    if (k == 0) return {1, g.s_zm, true, false};
+    if (k == g.nz + 1) return {g.nz, g.s_zp, true, false};
+    return {k, 1.f, false, false};
+}
+
+__device__ __forceinline__ void fill_ghost(const Geo& g, float* f, int comp, int i, int j, int k) {
+    const AxisMap ax = map_x(g, comp, i), ay = map_y(g, comp, j), az = map_z(g, comp, k);
+    if (!(ax.ghost || ay.ghost || az.ghost)) return;   // owned value: untouched
+    float val = 0.f;
+    if (!(ax.zero || ay.zero || az.zero)) val = ax.sgn * ay.sgn * az.sgn * f[g.nat(ax.src, ay.src, az.src)];
+    f[g.nat(i, j, k)] = val;
+}
+
+__device__ __forceinline__ void bc_body(const Geo& g, float* u, float* v, float* w, unsigned lb) {
+    const long long id = (long long)lb * kBlock + threadIdx.x;
+    int fam, a, b;
+    bc_item(g.nx, g.ny, g.nz, id, fam, a, b);
+    if (fam < 0) return;   // guarded padding of the launch
+    int p0[3], p1[3];
+    if (fam == 0) {        // (j, k) = (a, b); i = 0 and nx+1
+        p0[0] = 0; p0[1] = a; p0[2] = b;
+        p1[0] = g.nx + 1; p1[1] = a; p1[2] = b;
+    } else if (fam == 1) { // (i, k) = (a, b); j = 0 and ny+1
+        p0[0] = a; p0[1] = 0; p0[2] = b;
+        p1[0] = a; p1[1] = g.ny + 1; p1[2] = b;
+    } else {               // (i, j) = (a, b); k = 0 and nz+1
+        p0[0] = a; p0[1] = b; p0[2] = 0;
+        p1[0] = a; p1[1] = b; p1[2] = g.nz + 1;
+    }
+    fill_ghost(g, u, 0, p0[0], p0[1], p0[2]);
+    fill_ghost(g, v, 1, p0[0], p0[1], p0[2]);
+    fill_ghost(g, w, 2, p0[0], p0[1], p0[2]);
+    fill_ghost(g, u, 0, p1[0], p1[1], p1[2]);
+    fill_ghost(g, v, 1, p1[0], p1[1], p1[2]);
+    fill_ghost(g, w, 2, p1[0], p1[1], p1[2]);
+}
+
+// --------------------------------------------------- diagnostics (norms)
+// Partials [sum div(u)^2, max CFL]: CFL = dt (|u|/dx + |v|/dy + |w|/dz) with
+// cell-centred speeds; float64.
+__device__ __forceinline__ void diag_body(const Geo& g, const float* __restrict__ u,
+                                          const float* __restrict__ v, const float* __restrict__ w,
+                                          double* __restrict__ part, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    double d2 = 0.0, cf = 0.0;
+    if (t < n) {
+        int i, j, k;
+        cell_of(g, t, i, j, k);
+        const float u1 = u[g.nat(i, j, k)], u0 = u[g.nat(i - 1, j, k)];
+        const float v1 = v[g.nat(i, j, k)], v0 = v[g.nat(i, j - 1, k)];
+        const float w1 = w[g.nat(i, j, k)], w0 = w[g.nat(i, j, k - 1)];
+        const double div = ((double)u1 - u0) / g.dx + ((double)v1 - v0) / g.dy + ((double)w1 - w0) / g.dz;
+        d2 = div * div;
+        cf = (double)g.dt * (0.5 * fabs((double)u1 + u0) / g.dx + 0.5 * fabs((double)v1 + v0) / g.dy +
+                             0.5 * fabs((double)w1 + w0) / g.dz);
+    }
+    const double s = block_sum(d2);
+    const double mx = block_max(cf);
+    if (threadIdx.x == 0) {
+        part[2 * lb] = s;
+        part[2 * lb + 1] = mx;
+    }
+}
+
+// ================================================================= SOR
+// Red-black SOR for the pressure Poisson equation (section 2.6).
+//
+// The cells of one colour are stored contiguously (colour-split layout), so
+// a half-sweep reads the other colour's array and its own arrays with unit
+// stride and writes its own: 8 bytes per cell per half-sweep.  Within a
+// colour every update only reads the other colour, so the parallel
+// half-sweep equals the sequential one of the paper exactly.
+//
+// Precision.  p is held as a float32 base ph plus a float32 correction pd.
+// The sweeps relax pd against r0 = rhs - A ph (evaluated in float64,
+// stored in float32): SOR is affine, so the iterates ph + pd are those of
+// plain SOR on p, but each update rounds relative to |pd| instead of |p|.
+// Every few checks the correction is folded into the base (TwoSum, no
+// loss) and r0 recomputed.  Residuals ||rhs - A p|| are float64.
+
+// ---------------------------------------------------------- half-sweep
+// Colour c: for every cell of colour c,
+//   reltmp = omega (cn1 (sum_nb cn_nb p_nb - rhs) - p);  p += reltmp
+// with cn1 = 1/diag.  Outside the domain the other colour's array holds
+// zeros, so the neighbour sum needs no boundary branches.  On the last
+// iteration of a check interval (acc) the block also leaves the float64
+// partials [sum reltmp^2, sum (diag reltmp)^2]: after the colour-1
+// half-sweep, diag (omega-1)/omega reltmp is exactly the residual of a
+// colour-1 cell, so the second sum bounds ||r|| from below.
+//
+// Tiling: a block is 4 wavefronts; a wavefront covers TX consecutive
+// half-cells of 64/TX rows, and the block marches up KT planes (KT = 1:
+// one cell per thread, the most memory-level parallelism).  The other
+// colour's values at (ii, j0) stay in registers across k (the top
+// neighbour of plane k is the in-row value of plane k+1 and the bottom one
+// of plane k+2); east/west neighbours come from the adjacent lanes by
+// cross-lane shuffles, north/south ones from the cache.  Within a row the
+// cell parity is uniform.
+template <int TX, int KT>
+__device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict__ pself,
+                                         const float* __restrict__ poth,
+                                         const float* __restrict__ rself, float omega, bool acc,
+                                         double* __restrict__ rel_part, unsigned lb) {
+    constexpr int RPW = 64 / TX;            // rows per wavefront
+    constexpr int TY = RPW * (kBlock / 64); // rows per block
+    const unsigned nbx = (unsigned)(g.H + TX - 1) / TX;
+    const unsigned nby = (unsigned)(g.ny + TY - 1) / TY;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int tx = lane % TX;
+    const int ii = (int)bx * TX + tx;
+    const int j0 = (int)by * TY + (threadIdx.x >> 6) * RPW + lane / TX;
+    const int k_begin = (int)bk * KT;
+    const int k_end = min(g.nz, k_begin + KT);
+    const bool col_ok = ii < g.H && j0 < g.ny;
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    const float dyy = (j0 > 0 ? cy : 0.f) + (j0 < g.ny - 1 ? cy : 0.f);
+    long long e = col_ok ? g.col(ii, j0, k_begin) : 0;
+    float pb = col_ok ? poth[e - g.SP] : 0.f;
+    float pc = col_ok ? poth[e] : 0.f;
+    double r2 = 0.0, dr2 = 0.0;
+    for (int k0 = k_begin; k0 < k_end; ++k0) {
+        const float pt = col_ok ? poth[e + g.SP] : 0.f;
+        float pe = __shfl_down(pc, 1, TX);
+        float pw = __shfl_up(pc, 1, TX);
+        if (tx == TX - 1 && col_ok) pe = poth[e + 1];
+        if (tx == 0 && col_ok) pw = poth[e - 1];
+        const int s = (c + j0 + k0) & 1;
+        const int i0 = 2 * ii + s;
+        if (col_ok && i0 < g.nx) {
+            // cell i0 = 2 ii + s: west neighbour at half-index ii - 1 + s,
+            // east at ii + s
+            const float west = s ? pc : pw;
+            const float east = s ? pe : pc;
+            const float ps = poth[e - g.S], pn = poth[e + g.S];
+            const float nb = cx * (west + east) + cy * (ps + pn) + cz * (pb + pt);
+            const float dxx = (i0 > 0 ? cx : 0.f) + (i0 < g.nx - 1 ? cx : (g.outflow ? 2.f * cx : 0.f));
+            const float dzz = (k0 > 0 ? cz : 0.f) + (k0 < g.nz - 1 ? cz : 0.f);
+            const float diag = dxx + dyy + dzz;
+            const float inv = 1.0f / diag;
+            const float p = pself[e];
+            const float reltmp = omega * (inv * (nb - rself[e]) - p);
+            pself[e] = p + reltmp;
+            if (acc) {
+                const double rt = (double)reltmp;
+                r2 += rt * rt;
+                dr2 += ((double)diag * rt) * ((double)diag * rt);
+            }
+        }
+        pb = pc;
+        pc = pt;
+        e += g.SP;
+    }
+    if (acc) {
+        const double bs = block_sum(r2);
+        const double bd = block_sum(dr2);
+        if (threadIdx.x == 0) {
+            rel_part[2 * lb] = bs;
+            rel_part[2 * lb + 1] = bd;
+        }
+    }
+}
+
+// Whether the half-sweeps of local iteration it run, and whether they
+// accumulate the reltmp partials (last iteration of the check interval).
+__device__ __forceinline__ bool sweep_active(const Ctl* ctl, int it, bool& acc) {
+    const int m = ctl->m, K = ctl->K, mx = ctl->max_iter;
+    acc = (m + it + 1 == min(m + K, mx));
+    return !(ctl->done || m + it >= mx);
+}
+
+// ------------------------------------------------------------- fold
+// ph <- fl(ph + pd), pd <- exact remainder (Knuth's TwoSum), pointwise over
+// the whole colour arrays (padding stays 0 + 0 = 0).
+__device__ __forceinline__ void fold_body(long long n, float* __restrict__ ph0,
+                                          float* __restrict__ pd0, float* __restrict__ ph1,
+                                          float* __restrict__ pd1, long long t) {
+    if (t >= 2 * n) return;
+    float* ph = t < n ? ph0 : ph1;
+    float* pd = t < n ? pd0 : pd1;
+    const long long e = t < n ? t : t - n;
+    const float a = ph[e], b = pd[e];
+    const float s = a + b;
+    const float bb = s - a;
+    const float err = (a - (s - bb)) + (b - bb);
+    ph[e] = s;
+    pd[e] = err;
+}
+
+// (A x) at a cell in float64 from the float32 colour arrays x_own/x_oth.
+__device__ __forceinline__ double apply_A64(const Geo& g, const float* xo, const float* xn,
+                                            long long e, int s, double d) {
+    const double nb = (double)g.cx * ((double)xn[e - 1 + s] + (double)xn[e + s]) +
+                      (double)g.cy * ((double)xn[e - g.S] + (double)xn[e + g.S]) +
+                      (double)g.cz * ((double)xn[e - g.SP] + (double)xn[e + g.SP]);
+    return nb - d * (double)xo[e];
+}
+
+// ------------------------------------------------------------ rebase
+// After a fold: r0 = rhs - A ph in float64, stored in float32, and partials
+// of the float64 residual of the iterate, rhs - A (ph + pd).  Each thread
+// handles the two cells (one per colour) of its half-cells.
+__device__ __forceinline__ void rebase_body(const Geo& g, const PBufs& P, double* __restrict__ part,
+                                            unsigned lb, unsigned nb) {
+    long long t0, t1;
+    red_chunk(g, lb, nb, t0, t1);
+    double acc = 0.0;
+    for (long long t = t0 + threadIdx.x; t < t1; t += kBlock) {
+        int ii, j0, k0;
+        half_cell(g, t, ii, j0, k0);
+        const long long e = g.col(ii, j0, k0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int s = (c + j0 + k0) & 1;
+            const int i0 = 2 * ii + s;
+            if (i0 < g.nx) {
+                const double d = (double)diag_of(g, i0, j0, k0);
+                const double rb = (double)P.rhs[c][e] - apply_A64(g, P.ph[c], P.ph[1 - c], e, s, d);
+                P.r0[c][e] = (float)rb;
+                const double rt = rb - apply_A64(g, P.pd[c], P.pd[1 - c], e, s, d);
+                acc += rt * rt;
+            }
+        }
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// ------------------------------------------------------------- check
+// Partials of the residual of the iterate from the correction:
+// r = r0 - A pd (float64).
+__device__ __forceinline__ void check_body(const Geo& g, const PBufs& P, double* __restrict__ part,
+                                           unsigned lb, unsigned nb) {
+    long long t0, t1;
+    red_chunk(g, lb, nb, t0, t1);
+    double acc = 0.0;
+    for (long long t = t0 + threadIdx.x; t < t1; t += kBlock) {
+        int ii, j0, k0;
+        half_cell(g, t, ii, j0, k0);
+        const long long e = g.col(ii, j0, k0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int s = (c + j0 + k0) & 1;
+            const int i0 = 2 * ii + s;
+            if (i0 < g.nx) {
+                const double d = (double)diag_of(g, i0, j0, k0);
+                const double rt = (double)P.r0[c][e] - apply_A64(g, P.pd[c], P.pd[1 - c], e, s, d);
+                acc += rt * rt;
+            }
+        }
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// Partials over the cells of a colour-array pair (or the pair a + b when
+// b0 is given): mode 0 sum x^2, mode 1 sum x.
+__device__ __forceinline__ void colour_sum_body(const Geo& g, const float* a0, const float* a1,
+                                                const float* b0, const float* b1, int mode,
+                                                double* __restrict__ part, unsigned lb,
+                                                unsigned nb) {
+    long long t0, t1;
+    red_chunk(g, lb, nb, t0, t1);
+    double acc = 0.0;
+    for (long long t = t0 + threadIdx.x; t < t1; t += kBlock) {
+        int ii, j0, k0;
+        half_cell(g, t, ii, j0, k0);
+        const long long e = g.col(ii, j0, k0);
+        for (int c = 0; c < 2; ++c) {
+            const int i0 = 2 * ii + ((c + j0 + k0) & 1);
+            if (i0 < g.nx) {
+                double x = (double)(c ? a1 : a0)[e];
+                if (b0) x += (double)(c ? b1 : b0)[e];
+                acc += mode ? x : x * x;
+            }
+        }
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// Subtract the mean (ctl->rhs_sum / cells) from the (base + correction)
+// pair, keeping the correction's precision: the float32-rounded mean goes
+// out of the base, its rounding error out of the correction.
+__device__ __forceinline__ void p_sub_body(const Geo& g, const PBufs& P, const Ctl* ctl,
+                                           unsigned lb) {
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    int ii, j0, k0;
+    if (!half_cell(g, t, ii, j0, k0)) return;
+    const double mean = ctl->rhs_sum / ((double)g.nx * g.ny * g.nz);
+    const long long e = g.col(ii, j0, k0);
+    const float mh = (float)mean;
+    const float ml = (float)(mean - (double)mh);
+    for (int c = 0; c < 2; ++c) {
+        const int i0 = 2 * ii + ((c + j0 + k0) & 1);
+        if (i0 < g.nx) {
+            P.ph[c][e] = P.ph[c][e] - mh;
+            P.pd[c][e] = P.pd[c][e] - ml;
+        }
+    }
+}
+
+// ------------------------------------------------------------ finalize
+// Block-wide fixed-order reductions for a block of NT threads.
+template <int NT>
+__device__ __forceinline__ double nt_sum(const double* part, int n, int stride = 1) {
+    __shared__ double red[NT / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) v += part[(long long)i * stride];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+    __syncthreads();
+    return t;   // valid in every thread
+}
+
+template <int NT>
+__device__ __forceinline__ double nt_max(const double* part, int n, int stride = 1) {
+    __shared__ double redm[NT / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) v = fmax(v, part[(long long)i * stride]);
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) redm[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < NT / 64; ++i) t = fmax(t, redm[i]);
+    __syncthreads();
+    return t;
+}
+
+// Decision after a residual check.
+__device__ __forceinline__ void decide(Ctl* ctl, double sum_r2) {
+    if (ctl->done) return;
+    const int m = min(ctl->m + ctl->K, ctl->max_iter);
+    ctl->m = m;
+    ctl->skip = 0;
+    const double R = sqrt(sum_r2) / sqrt(ctl->rhs2);
+    ctl->resid = R;
+    if (!isfinite(R)) ctl->done = 3;
+    else if (R <= ctl->tol) ctl->done = 1;
+    else if (m >= ctl->max_iter) ctl->done = 2;
+}
+
+// Fixed-order sums of the partials of a preceding reduction, then the
+// bookkeeping of op (one block of NT threads):
+//   FIN_BOUND  after the sweeps of a check interval: sum reltmp^2 for the
+//              report, and the colour-1 residual lower bound
+//              |omega-1|/omega sqrt(sum (diag reltmp)^2) <= ||r||; if it
+//              exceeds 1.5 tol the coming check cannot succeed and is
+//              skipped (never the last check before max_iter)
+//   FIN_CHECK  decide on the residual (or just count a skipped check)
+//   FIN_CHECK_FULL  decide on the residual (rebase checks never skip)
+template <int NT>
+__device__ __forceinline__ void finalize_body(int op, const double* __restrict__ part, int n,
+                                              const double* __restrict__ rel0,
+                                              const double* __restrict__ rel1, int nrel, Ctl* ctl,
+                                              double omega) {
+    const bool sor_op = op == FIN_CHECK || op == FIN_CHECK_FULL || op == FIN_SETUP || op == FIN_BOUND;
+    if (sor_op && ctl->done) return;
+    if (op == FIN_DIAG) {
+        const double a = nt_sum<NT>(part, n, 2);
+        const double b = nt_max<NT>(part + 1, n, 2);
+        if (threadIdx.x == 0) {
+            ctl->div2 = a;
+            ctl->cfl = b;
+        }
+        return;
+    }
+    if (op == FIN_BOUND) {
+        const double r0s = nt_sum<NT>(rel0, nrel, 2);
+        const double r1s = nt_sum<NT>(rel1, nrel, 2);
+        const double d1s = nt_sum<NT>(rel1 + 1, nrel, 2);
+        if (threadIdx.x == 0) {
+            ctl->reltmp2 = r0s + r1s;
+            const double lbd = fabs(omega - 1.0) / omega * sqrt(d1s) / sqrt(ctl->rhs2);
+            const int m_next = min(ctl->m + ctl->K, ctl->max_iter);
+            ctl->skip = (m_next < ctl->max_iter && lbd > 1.5 * ctl->tol) ? 1 : 0;
+        }
+        return;
+    }
+    if (op == FIN_CHECK && ctl->skip) {
+        if (threadIdx.x == 0) {
+            ctl->m = min(ctl->m + ctl->K, ctl->max_iter);
+            ctl->skip = 0;
+        }
+        return;
+    }
+    const double s = nt_sum<NT>(part, n);
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case FIN_RHS2: ctl->rhs2 = s; break;
+        case FIN_RHS_SUM: ctl->rhs_sum = s; break;
+        case FIN_PSUM: ctl->rhs_sum = s; break;   // reused slot: sum of p
+        case FIN_SETUP:
+            if (!isfinite(ctl->rhs2)) {
+                ctl->done = 3;
+            } else if (ctl->rhs2 == 0.0) {
+                ctl->done = 1;
+                ctl->resid = 0.0;
+            } else {
+                ctl->resid = sqrt(s) / sqrt(ctl->rhs2);
+                if (!isfinite(ctl->resid)) ctl->done = 3;
+            }
+            break;
+        case FIN_CHECK:
+        case FIN_CHECK_FULL: decide(ctl, s); break;
+        default: break;
+    }
+}
+
+}  // namespace les

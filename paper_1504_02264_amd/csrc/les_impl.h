@@ -16,6 +16,7 @@ namespace les {
 constexpr int kBlock = 256;     // threads per block for the 1-D launches
 constexpr int kNumXcd = 8;      // MI355X: 8 XCDs, blocks dispatched round-robin
 constexpr int kMaxPartials = 1 << 20;
+constexpr int kMaxEnsemble = 64;   // members of one ensemble
 
 // Geometry, passed by value to every kernel.
 //

@@ -310,3 +310,70 @@ def test_step_independent_of_sor_variant():
         out.append(g.get_fields())
     for x, y in zip(*out):
         assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------- ensemble
+def _member(nx, ny, nz, seed, alpha_pl=None, **kw):
+    h = building_heights(nx, ny, nz, 0.2, 2, 5, 2, max(3, nz // 2), seed=seed, margin_x=4,
+                         margin_y=2)
+    mask = building_mask(h, nz)
+    prof = (power_law_profile(nz, 2.0, 3.0 + seed % 5, alpha_pl) if alpha_pl
+            else log_law_profile(nz, 2.0))
+    return mask, prof
+
+
+def test_ensemble_bitwise_equals_single_steps():
+    """An ensemble step of uneven members equals stepping each member alone
+    (same per-cell arithmetic, same per-member stopping decisions)."""
+    shapes = [(24, 20, 12), (33, 17, 9), (40, 24, 16), (17, 31, 10)]
+    ins = [_member(*s, seed=50 + q, alpha_pl=(0.1 + 0.05 * q) if q % 2 else None)
+           for q, s in enumerate(shapes)]
+    ens_members, singles = [], []
+    for (nx, ny, nz), (mask, prof), q in zip(shapes, ins, range(len(shapes))):
+        a = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+        b = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
+        for x in (a, b):
+            x.set_inflow(prof, 0.01, 70 + q)
+        ens_members.append(a)
+        singles.append(b)
+    ens = les.Ensemble(ens_members)
+    rc, st, iters = ens.step(3)
+    assert st["members"] == 4 and st["steps"] == 3
+    for q, b in enumerate(singles):
+        _, _, it_b = b.step(3)
+        assert list(iters[:, q]) == list(it_b), q
+        for x, y in zip(ens_members[q].get_fields(), b.get_fields()):
+            assert np.array_equal(x, y), q
+        assert ens_members[q].get_step() == 3
+    # single steps continue from the ensemble's state
+    for q in range(2):
+        ens_members[q].step(1)
+        singles[q].step(1)
+        for x, y in zip(ens_members[q].get_fields(), singles[q].get_fields()):
+            assert np.array_equal(x, y)
+    ens.close()
+
+
+def test_ensemble_with_singular_member_and_autotune():
+    shapes = [(24, 20, 12), (16, 16, 16)]
+    mask, prof = _member(24, 20, 12, seed=3)
+    a1 = les.LES(24, 20, 12, 4.0, 4.0, 2.0, 0.05, mask)
+    b1 = les.LES(24, 20, 12, 4.0, 4.0, 2.0, 0.05, mask)
+    for x in (a1, b1):
+        x.set_inflow(prof, 0.01, 5)
+    a2 = les.LES(16, 16, 16, 1.0, 1.0, 1.0, 0.05, bc=ALL_WALLS, nu=0.01)
+    b2 = les.LES(16, 16, 16, 1.0, 1.0, 1.0, 0.05, bc=ALL_WALLS, nu=0.01)
+    u, v, w, p = random_fields(16, 16, 16, seed=9, scale=0.1)
+    for x in (a2, b2):
+        x.set_fields(u, v, w, p)
+    ens = les.Ensemble([a1, a2])
+    ens.autotune(reps=3)
+    rc, st, iters = ens.step(2)
+    ens.close()
+    # the singles keep the default variant: variants do not change results
+    _, _, it1 = b1.step(2)
+    _, _, it2 = b2.step(2)
+    assert list(iters[:, 0]) == list(it1) and list(iters[:, 1]) == list(it2)
+    for a, b in ((a1, b1), (a2, b2)):
+        for x, y in zip(a.get_fields(), b.get_fields()):
+            assert np.array_equal(x, y)

@@ -65,12 +65,68 @@ def cpu_baseline(w, mask, prof, gpu_iters_per_step, sample_iters):
     }
 
 
+def bench_ensemble(args, les, torch):
+    """Aggregate cell-updates/s of an uneven ensemble in one persistent solve per step."""
+    from les_inputs import ensemble_members, make_workload_inputs
+    ws = ensemble_members(args.ensemble)
+    members = []
+    for w in ws:
+        mask, prof = make_workload_inputs(w)
+        extra = {} if args.max_iter is None else {"max_iter": args.max_iter}
+        g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask, **extra)
+        g.set_inflow(prof, w.noise_amp, w.seed)
+        members.append(g)
+    ens = les.Ensemble(members)
+    ens.autotune(reps=3)
+    cells = sum(w.nx * w.ny * w.nz for w in ws)
+    log(f"ensemble of {len(ws)} members, {cells} cells; warmup {args.warmup}")
+    if args.warmup:
+        ens.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, iters = ens.step(args.steps)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {dt_s:.3f} s; mean SOR iterations {iters.mean():.0f}")
+    out = {
+        "metric": "LES cell-updates/s (ensemble aggregate)",
+        "value": cells * args.steps / dt_s,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"ensemble of {len(ws)} urban LES members, nx, ny in 96-256, nz in 64-90, "
+                         "power-law inflow (alpha 0.1-0.35, 2-12 m/s), 15-35% building cover, "
+                         "one persistent cooperative SOR launch per step"),
+            "cells_total": cells,
+            "sor_iters_mean": float(iters.mean()),
+            "sor_iters_min": int(iters.min()),
+            "sor_iters_max": int(iters.max()),
+            "not_converged_member_steps": int(st["not_converged"]),
+        },
+    }
+    ens.close()
+    for g in members:
+        g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--ensemble", type=int, default=0, metavar="N",
+                    help="instead: an ensemble of N uneven members (sizes 96-256 x 96-256 x "
+                         "64-90, seeds 1000+i) advanced together; aggregate cell-updates/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-timing", action="store_true",
@@ -93,6 +149,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.ensemble:
+        return bench_ensemble(args, les, torch)
     w = WORKLOADS[args.workload]
     cells = w.nx * w.ny * w.nz
     mask, prof = make_workload_inputs(w)
@@ -155,14 +213,24 @@ def main():
         t_launch = sor_ms / sor_n * 1e-3
         bytes_per_launch = 8.0 * cells      # per half-sweep, see the design doc
         achieved = bytes_per_launch / t_launch / 1e9
+        from paper_1504_02264_amd import profsum
+        tx, kt = les.SOR_VARIANTS[variant]
+        kname = f"k_sor<{tx}, {kt}>"
+        pmc_file = os.path.join(ROOT, "profiles", f"k_sor_traffic_{w.nx}x{w.ny}x{w.nz}.txt")
+        tr = profsum.read_traffic(pmc_file, kname)
         out["roofline"] = {
             "bound": "hbm",
-            "kernel": "k_sor (red-black SOR half-sweep)",
+            "kernel": f"{kname} (red-black SOR half-sweep)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE +
+            # WRITE_SIZE, copy-calibrated) over the same launch time; null if
+            # the kernel changed since the counters were taken
+            "traffic": None if tr is None else (tr[0] + tr[1]) / t_launch / 1e9,
+            "traffic_bytes_per_launch": None if tr is None else tr[0] + tr[1],
+            "algorithmic_bytes_per_launch": bytes_per_launch,
             "launch_us": t_launch * 1e6,
             "timed_launches": int(sor_n),
         }

@@ -34,6 +34,8 @@ EXPORTS = (
     "les_ensemble_last_error", "les_ensemble_destroy",
 )
 NUM_SOR_VARIANTS = 8
+# (row width TX, planes per block KT) of each sweep variant, as in the library
+SOR_VARIANTS = ((64, 1), (32, 1), (64, 2), (32, 2), (64, 4), (32, 4), (64, 8), (32, 8))
 KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
 
 

@@ -233,50 +233,81 @@ __global__ void k_ens_record(const EnsDyn* D, int n, int* out) {
 }
 
 // ------------------------------------------------- persistent SOR solve
+// Half-sweeps of items [a, b) of one member, the tile variant resolved once.
 template <int TX, int KT>
-__device__ __forceinline__ void sweep_one(const EnsInst& d, int c, bool acc, unsigned lb) {
-    sor_body<TX, KT>(d.g, c, d.P.pd[c], d.P.pd[1 - c], d.P.r0[c], d.omega, acc,
-                     c ? d.rel1 : d.rel0, lb);
+__device__ __forceinline__ void sweep_items(const EnsInst& d, int c, bool acc, unsigned a, unsigned b) {
+    float* ps = d.P.pd[c];
+    const float* po = d.P.pd[1 - c];
+    const float* rs = d.P.r0[c];
+    double* rel = c ? d.rel1 : d.rel0;
+    for (unsigned lb = a; lb < b; ++lb) sor_body<TX, KT>(d.g, c, ps, po, rs, d.omega, acc, rel, lb);
 }
 
-__device__ __forceinline__ void sweep_variant(const EnsInst& d, int c, bool acc, unsigned lb) {
+__device__ __forceinline__ void sweep_range(const EnsInst& d, int c, bool acc, unsigned a, unsigned b) {
     switch (d.variant) {
-        case 0: sweep_one<64, 1>(d, c, acc, lb); break;
-        case 1: sweep_one<32, 1>(d, c, acc, lb); break;
-        case 2: sweep_one<64, 2>(d, c, acc, lb); break;
-        case 3: sweep_one<32, 2>(d, c, acc, lb); break;
-        case 4: sweep_one<64, 4>(d, c, acc, lb); break;
-        case 5: sweep_one<32, 4>(d, c, acc, lb); break;
-        case 6: sweep_one<64, 8>(d, c, acc, lb); break;
-        default: sweep_one<32, 8>(d, c, acc, lb); break;
+        case 0: sweep_items<64, 1>(d, c, acc, a, b); break;
+        case 1: sweep_items<32, 1>(d, c, acc, a, b); break;
+        case 2: sweep_items<64, 2>(d, c, acc, a, b); break;
+        case 3: sweep_items<32, 2>(d, c, acc, a, b); break;
+        case 4: sweep_items<64, 4>(d, c, acc, a, b); break;
+        case 5: sweep_items<32, 4>(d, c, acc, a, b); break;
+        case 6: sweep_items<64, 8>(d, c, acc, a, b); break;
+        default: sweep_items<32, 8>(d, c, acc, a, b); break;
+    }
+}
+
+// Block b owns the contiguous items [b chunk, (b+1) chunk) of a work list
+// (offsets in LDS) and visits them member by member: f(q, a, b) for the
+// member-local item range [a, b).
+template <class F>
+__device__ __forceinline__ void walk_items(const unsigned* s_off, int n, F&& f) {
+    const unsigned total = s_off[n];
+    const unsigned chunk = (total + gridDim.x - 1) / gridDim.x;
+    const unsigned L0 = blockIdx.x * chunk;
+    const unsigned L1 = min(total, L0 + chunk);
+    if (L0 >= L1) return;
+    int q = owner(s_off, n, L0);
+    unsigned L = L0;
+    while (L < L1 && q < n) {
+        const unsigned end = min(L1, s_off[q + 1]);
+        if (end > L) f(q, L - s_off[q], end - s_off[q]);
+        L = end;
+        ++q;
     }
 }
 
 // The whole solve of every member in one cooperative launch.  Check
 // interval c (K iterations) is the same for all members; every loop trip
-// count depends only on data read after a grid barrier, so all blocks meet
-// every barrier, and the trip count of the outer loop is bounded by
-// max_checks.  A member leaves the work (its blocks return at once) when
-// its stopping test succeeds or it reaches its max_iter.
-__global__ __launch_bounds__(kBlock) void k_ens_solve(const EnsInst* I, int n, const EnsOffsets* O,
-                                                      int K, int max_checks) {
+// count between grid barriers depends only on kernel arguments or on data
+// read after a barrier, so all blocks meet every barrier, and the outer
+// loop is bounded by max_checks.  A member leaves the work once its
+// stopping test succeeds or it reaches its max_iter.
+__global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restrict__ I, int n,
+                                                      const EnsOffsets* __restrict__ O, int K,
+                                                      int max_checks) {
     cg::grid_group grid = cg::this_grid();
+    __shared__ unsigned s_sweep[kMaxEnsemble + 1], s_red[kMaxEnsemble + 1], s_fold[kMaxEnsemble + 1];
+    for (int q = threadIdx.x; q <= n; q += kBlock) {
+        s_sweep[q] = O->sweep[q];
+        s_red[q] = O->red[q];
+        s_fold[q] = O->fold[q];
+    }
+    __syncthreads();
     const unsigned nb = gridDim.x;
     // set-up: fold, sync, rebase (r0 and the initial residual), sync, finalize
-    for (unsigned L = blockIdx.x; L < O->fold[n]; L += nb) {
-        const int q = owner(O->fold, n, L);
+    walk_items(s_fold, n, [&](int q, unsigned a, unsigned b) {
         const EnsInst& d = I[q];
-        if (ld(&d.ctl->done)) continue;
-        fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
-                  (long long)(L - O->fold[q]) * kBlock + threadIdx.x);
-    }
+        if (ld(&d.ctl->done)) return;
+        for (unsigned L = a; L < b; ++L)
+            fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
+                      (long long)L * kBlock + threadIdx.x);
+    });
     grid.sync();
-    for (unsigned L = blockIdx.x; L < O->red[n]; L += nb) {
-        const int q = owner(O->red, n, L);
+    walk_items(s_red, n, [&](int q, unsigned a, unsigned b) {
         const EnsInst& d = I[q];
-        if (ld(&d.ctl->done)) continue;
-        rebase_body(d.g, d.P, d.part, L - O->red[q], d.nred);
-    }
+        if (ld(&d.ctl->done)) return;
+        for (unsigned L = a; L < b; ++L) rebase_body(d.g, d.P, d.part, L, d.nred);
+    });
     grid.sync();
     for (int q = blockIdx.x; q < n; q += nb)
         finalize_body<kBlock>(FIN_SETUP, I[q].part, (int)I[q].nred, nullptr, nullptr, 0, I[q].ctl, I[q].omega);
@@ -288,13 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_ens_solve(const EnsInst* I, int n, c
         if (all_done) break;   // uniform: every block read the same flags after the barrier
         for (int it = 0; it < K; ++it) {
             for (int colour = 0; colour < 2; ++colour) {
-                for (unsigned L = blockIdx.x; L < O->sweep[n]; L += nb) {
-                    const int q = owner(O->sweep, n, L);
+                walk_items(s_sweep, n, [&](int q, unsigned a, unsigned b) {
                     const EnsInst& d = I[q];
                     bool acc;
-                    if (!member_active(d.ctl, it, acc)) continue;
-                    sweep_variant(d, colour, acc, L - O->sweep[q]);
-                }
+                    if (!member_active(d.ctl, it, acc)) return;
+                    sweep_range(d, colour, acc, a, b);
+                });
                 grid.sync();
             }
         }
@@ -306,22 +336,24 @@ __global__ __launch_bounds__(kBlock) void k_ens_solve(const EnsInst* I, int n, c
         bool any_rebase = false;
         for (int q = 0; q < n; ++q) any_rebase = any_rebase || ((c + 1) % I[q].R == 0);
         if (any_rebase) {
-            for (unsigned L = blockIdx.x; L < O->fold[n]; L += nb) {
-                const int q = owner(O->fold, n, L);
+            walk_items(s_fold, n, [&](int q, unsigned a, unsigned b) {
                 const EnsInst& d = I[q];
-                if ((c + 1) % d.R != 0 || ld(&d.ctl->done)) continue;
-                fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
-                          (long long)(L - O->fold[q]) * kBlock + threadIdx.x);
-            }
+                if ((c + 1) % d.R != 0 || ld(&d.ctl->done)) return;
+                for (unsigned L = a; L < b; ++L)
+                    fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
+                              (long long)L * kBlock + threadIdx.x);
+            });
             grid.sync();
         }
-        for (unsigned L = blockIdx.x; L < O->red[n]; L += nb) {
-            const int q = owner(O->red, n, L);
+        walk_items(s_red, n, [&](int q, unsigned a, unsigned b) {
             const EnsInst& d = I[q];
-            if (ld(&d.ctl->done)) continue;
-            if ((c + 1) % d.R == 0) rebase_body(d.g, d.P, d.part, L - O->red[q], d.nred);
-            else if (!ld(&d.ctl->skip)) check_body(d.g, d.P, d.part, L - O->red[q], d.nred);
-        }
+            if (ld(&d.ctl->done)) return;
+            if ((c + 1) % d.R == 0) {
+                for (unsigned L = a; L < b; ++L) rebase_body(d.g, d.P, d.part, L, d.nred);
+            } else if (!ld(&d.ctl->skip)) {
+                for (unsigned L = a; L < b; ++L) check_body(d.g, d.P, d.part, L, d.nred);
+            }
+        });
         grid.sync();
         for (int q = blockIdx.x; q < n; q += nb) {
             const EnsInst& d = I[q];
@@ -353,6 +385,7 @@ struct les_ensemble {
     int K = 4;
     int max_checks = 0;
     int solve_grid = 0;
+    int solve_per_cu = 0;
     bool graphs_ready = false;
     hipGraphExec_t pre[2] = {nullptr, nullptr};
     hipGraphExec_t post[2] = {nullptr, nullptr};
@@ -522,7 +555,8 @@ int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** ou
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_ens_solve, kBlock, 0) !=
             hipSuccess || per_cu < 1)
         return fail(LES_EDEVICE);
-    e->solve_grid = cus * std::min(per_cu, 4);
+    e->solve_grid = cus * std::min(per_cu, 8);
+    e->solve_per_cu = per_cu;
     *out = e;
     return LES_OK;
 }

@@ -77,7 +77,9 @@ def bench_ensemble(args, les, torch):
         g.set_inflow(prof, w.noise_amp, w.seed)
         members.append(g)
     ens = les.Ensemble(members)
-    ens.autotune(reps=3)
+    ens.set_mode(les.ENSEMBLE_BATCHED if args.ensemble_mode == "batched" else les.ENSEMBLE_PERSISTENT)
+    variant, us = ens.autotune(reps=3)
+    log(f"ensemble autotune: variant {variant}, us per half-sweep {[round(float(x), 1) for x in us]}")
     cells = sum(w.nx * w.ny * w.nz for w in ws)
     log(f"ensemble of {len(ws)} members, {cells} cells; warmup {args.warmup}")
     if args.warmup:
@@ -104,12 +106,14 @@ def bench_ensemble(args, les, torch):
         "config": {
             "workload": (f"ensemble of {len(ws)} urban LES members, nx, ny in 96-256, nz in 64-90, "
                          "power-law inflow (alpha 0.1-0.35, 2-12 m/s), 15-35% building cover, "
-                         "one persistent cooperative SOR launch per step"),
+                         f"{args.ensemble_mode} solve of all members"),
             "cells_total": cells,
             "sor_iters_mean": float(iters.mean()),
             "sor_iters_min": int(iters.min()),
             "sor_iters_max": int(iters.max()),
             "not_converged_member_steps": int(st["not_converged"]),
+            "sor_variant": int(variant),
+            "autotune_us_per_sweep": [round(float(x), 2) for x in us],
         },
     }
     ens.close()
@@ -124,6 +128,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--ensemble-mode", choices=["batched", "persistent"], default="batched")
     ap.add_argument("--ensemble", type=int, default=0, metavar="N",
                     help="instead: an ensemble of N uneven members (sizes 96-256 x 96-256 x "
                          "64-90, seeds 1000+i) advanced together; aggregate cell-updates/s")

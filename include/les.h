@@ -264,8 +264,9 @@ int les_set_state(les_handle* h, const void* buf, int64_t bytes);
  * member by nsteps: per step each stage is one launch over an
  * (instance, block) work list, the stage sequences before and after the
  * pressure solve are replayed from HIP graphs, and the pressure solves of
- * all members run in ONE persistent cooperative launch with per-member
- * stopping tests on the device.  Results are bitwise identical to stepping
+ * all members run together with per-member stopping tests on the device
+ * (see les_ensemble_set_mode: batched launches or one persistent
+ * cooperative launch).  Results are bitwise identical to stepping
  * each member alone with les_step.  Members' step counters and buffers
  * are updated, so single steps and ensemble steps can be mixed.
  * iters_out (nullable, caller-owned) receives nsteps x n iteration counts
@@ -284,11 +285,26 @@ typedef struct {
 } les_ensemble_stats;
 int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** out);
 int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out);
-/* les_autotune on every member (reps as there), then use the chosen sweep
- * variants in the ensemble's persistent solve. */
+/* Autotuner for the ensemble: times the batched half-sweep over all
+ * members for each tile variant (all members on one variant: with the
+ * members' working sets together the cache behaviour differs from each one
+ * alone) on the members' scratch pressure systems (the state is not
+ * touched), reps red/black pairs each, and uses the fastest from the next
+ * step on.  les_ensemble_tuning reports the choice and the microseconds
+ * per half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]). */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);
+int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep);
 const char* les_ensemble_last_error(const les_ensemble* e);
 void les_ensemble_destroy(les_ensemble* e);
+
+/* How the members' pressure solves run (same arithmetic, same results):
+ * LES_ENSEMBLE_BATCHED (default): one launch per half-sweep (and per check
+ * phase) over all members' work, check intervals replayed from a HIP graph
+ * in batches of 8, per-member stop flags on the device.
+ * LES_ENSEMBLE_PERSISTENT: the whole solve of all members in one
+ * cooperative launch with grid barriers between phases. */
+enum { LES_ENSEMBLE_BATCHED = 0, LES_ENSEMBLE_PERSISTENT = 1 };
+int les_ensemble_set_mode(les_ensemble* e, int32_t mode);
 
 /*
  * Boundary-range mapping of the ghost-refresh launch (section 2.4),

@@ -31,8 +31,10 @@ EXPORTS = (
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
     "les_ensemble_create", "les_ensemble_step", "les_ensemble_autotune",
-    "les_ensemble_last_error", "les_ensemble_destroy",
+    "les_ensemble_last_error", "les_ensemble_destroy", "les_ensemble_set_mode",
+    "les_ensemble_tuning",
 )
+ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
 NUM_SOR_VARIANTS = 8
 # (row width TX, planes per block KT) of each sweep variant, as in the library
 SOR_VARIANTS = ((64, 1), (32, 1), (64, 2), (32, 2), (64, 4), (32, 4), (64, 8), (32, 8))
@@ -146,6 +148,8 @@ def lib():
     L.les_ensemble_autotune.argtypes = [P, C.c_int32]
     L.les_ensemble_last_error.argtypes = [P]
     L.les_ensemble_last_error.restype = C.c_char_p
+    L.les_ensemble_set_mode.argtypes = [P, C.c_int32]
+    L.les_ensemble_tuning.argtypes = [P, C.POINTER(C.c_int32), P]
     L.les_ensemble_destroy.argtypes = [P]
     L.les_ensemble_destroy.restype = None
     L.les_bc_range.argtypes = [C.POINTER(Grid)]
@@ -375,7 +379,18 @@ class Ensemble:
             raise LesError(rc, lib().les_ensemble_last_error(self.h).decode())
         return rc, st.as_dict(), iters[:n].copy()
 
+    def set_mode(self, mode):
+        rc = lib().les_ensemble_set_mode(self.h, int(mode))
+        if rc != LES_OK:
+            raise LesError(rc, "les_ensemble_set_mode")
+
     def autotune(self, reps=10):
+        """Pick the fastest sweep variant for the whole ensemble:
+        returns (index, us per half-sweep per variant)."""
         rc = lib().les_ensemble_autotune(self.h, int(reps))
         if rc != LES_OK:
             raise LesError(rc, lib().les_ensemble_last_error(self.h).decode())
+        v = C.c_int32()
+        us = np.zeros(NUM_SOR_VARIANTS, np.float64)
+        lib().les_ensemble_tuning(self.h, C.byref(v), _ptr(us))
+        return v.value, us

@@ -364,6 +364,93 @@ __global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restri
     }
 }
 
+// ----------------------------------------------- batched (non-persistent) solve
+// The same solve as k_ens_solve, one launch per phase over all members.
+// Every decision lives on the device (each member's control block), so a
+// batch of check intervals is a fixed launch sequence, replayed from a HIP
+// graph; launches after a member's convergence return at once.
+// In these separate launches the control blocks were written by earlier
+// kernels, so plain loads are coherent (kernel boundaries order them).
+__device__ __forceinline__ bool rebase_due(const EnsInst& d) {
+    // the check that ends the current interval is number m/K + 1
+    return ((d.ctl->m / d.K) + 1) % d.R == 0;
+}
+
+constexpr unsigned kAuxBlocks = 4096;   // grid of the fold / check phases
+
+__global__ __launch_bounds__(kBlock) void k_ens_sweep(const EnsInst* __restrict__ I,
+                                                      const unsigned char* __restrict__ owner_of,
+                                                      const EnsOffsets* __restrict__ O, int colour,
+                                                      int it) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner_of[L];
+    const EnsInst& d = I[q];
+    bool acc;
+    if (!sweep_active(d.ctl, it, acc)) return;
+    sweep_range(d, colour, acc, L - O->sweep[q], L - O->sweep[q] + 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_bound(const EnsInst* __restrict__ I) {
+    const EnsInst& d = I[blockIdx.x];
+    finalize_body<kBlock>(FIN_BOUND, nullptr, 0, d.rel0, d.rel1, (int)d.nsweep, d.ctl, d.omega);
+}
+
+// setup = 1: fold every unfinished member (start of the solve); else only
+// those whose current interval ends with a rebase.
+// Capped grids walking the item lists member by member (walk_items):
+// members with nothing to do cost one test per block, not one block per item.
+__global__ __launch_bounds__(kBlock) void k_ens_fold(const EnsInst* __restrict__ I, int n,
+                                                     const EnsOffsets* __restrict__ O, int setup) {
+    __shared__ unsigned s_off[kMaxEnsemble + 1];
+    for (int q = threadIdx.x; q <= n; q += kBlock) s_off[q] = O->fold[q];
+    __syncthreads();
+    walk_items(s_off, n, [&](int q, unsigned a, unsigned b) {
+        const EnsInst& d = I[q];
+        if (d.ctl->done || !(setup || rebase_due(d))) return;
+        for (unsigned L = a; L < b; ++L)
+            fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
+                      (long long)L * kBlock + threadIdx.x);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_check(const EnsInst* __restrict__ I, int n,
+                                                      const EnsOffsets* __restrict__ O, int setup) {
+    __shared__ unsigned s_off[kMaxEnsemble + 1];
+    for (int q = threadIdx.x; q <= n; q += kBlock) s_off[q] = O->red[q];
+    __syncthreads();
+    walk_items(s_off, n, [&](int q, unsigned a, unsigned b) {
+        const EnsInst& d = I[q];
+        if (d.ctl->done) return;
+        if (setup || rebase_due(d)) {
+            for (unsigned L = a; L < b; ++L) rebase_body(d.g, d.P, d.part, L, d.nred);
+        } else if (!d.ctl->skip) {
+            for (unsigned L = a; L < b; ++L) check_body(d.g, d.P, d.part, L, d.nred);
+        }
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void k_ens_fin_check(const EnsInst* __restrict__ I, int setup) {
+    const EnsInst& d = I[blockIdx.x];
+    const int op = setup ? FIN_SETUP : (rebase_due(d) ? FIN_CHECK_FULL : FIN_CHECK);
+    finalize_body<kBlock>(op, d.part, (int)d.nred, d.rel0, d.rel1, (int)d.nsweep, d.ctl, d.omega);
+}
+
+// Control block that lets every sweep run (autotuning only).
+__global__ void k_ctl_probe_init(Ctl* ctl) { ctl_init_body(ctl, 1e-30, 1 << 30, 1 << 20); }
+
+__global__ __launch_bounds__(kBlock) void k_zero(float* p, long long n) {
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) p[t] = 0.f;
+}
+
+// 1 when every member is done (read by the host one batch behind).
+__global__ void k_ens_all_done(const EnsInst* __restrict__ I, int n, int* flag) {
+    if (threadIdx.x != 0) return;
+    int all = 1;
+    for (int q = 0; q < n; ++q) all &= (I[q].ctl->done != 0) ? 1 : 0;
+    *flag = all;
+}
+
 }  // namespace
 }  // namespace les
 
@@ -386,6 +473,17 @@ struct les_ensemble {
     int max_checks = 0;
     int solve_grid = 0;
     int solve_per_cu = 0;
+    int mode = LES_ENSEMBLE_BATCHED;
+    unsigned char* d_owner = nullptr;   // sweep block -> member (batched mode)
+    int* d_flag = nullptr;
+    int* h_flag = nullptr;              // pinned, 2 slots
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipGraphExec_t chunk_graph = nullptr;
+    int chunk_graph_checks = 0;
+    unsigned owner_blocks = 0;
+    int variant = -1;                   // -1: each member's own sweep variant
+    double tune_us[kNumSorVariants] = {};
+    bool descriptors_dirty = false;
     bool graphs_ready = false;
     hipGraphExec_t pre[2] = {nullptr, nullptr};
     hipGraphExec_t post[2] = {nullptr, nullptr};
@@ -452,10 +550,10 @@ void build_descriptors(les_ensemble* e) {
         d.max_iter = h->prm.max_iter;
         d.K = h->prm.check_every;
         d.R = h->prm.rebase_every;
-        d.variant = h->sor_variant;
+        d.variant = e->variant >= 0 ? e->variant : h->sor_variant;
         d.singular = h->g.outflow ? 0 : 1;
         d.inflow = h->g.inflow;
-        d.nsweep = sor_sweep_blocks(h->g, h->sor_variant);
+        d.nsweep = sor_sweep_blocks(h->g, d.variant);
         d.nred = red_blocks(h->g);
         max_iter_all = std::max(max_iter_all, h->prm.max_iter);
         o.box[q + 1] = o.box[q] + box_blocks(h->g);
@@ -501,7 +599,86 @@ int enqueue_post(les_ensemble* e, hipStream_t s) {
     return LES_OK;
 }
 
+// Sweep-block -> member map for the batched sweeps (rebuilt with the
+// descriptors: the members' sweep variants may change).
+int upload_owner_map(les_ensemble* e) {
+    const EnsOffsets& o = e->h_off;
+    const unsigned total = o.sweep[e->n];
+    std::vector<unsigned char> map(total);
+    for (int q = 0; q < e->n; ++q)
+        for (unsigned L = o.sweep[q]; L < o.sweep[q + 1]; ++L) map[L] = (unsigned char)q;
+    if (total > e->owner_blocks) {
+        if (e->d_owner) ECK(hipFree(e->d_owner));
+        e->d_owner = nullptr;
+        ECK(hipMalloc(&e->d_owner, total));
+        e->owner_blocks = total;
+    }
+    ECK(hipMemcpy(e->d_owner, map.data(), total, hipMemcpyHostToDevice));
+    return LES_OK;
+}
+
+// One check interval of every member: 2K half-sweeps, the residual bound,
+// the fold of members due for a rebase, the check (or rebase), the decision.
+int enqueue_chunk(les_ensemble* e, hipStream_t s) {
+    const int n = e->n;
+    const EnsOffsets& o = e->h_off;
+    for (int it = 0; it < e->K; ++it)
+        for (int c = 0; c < 2; ++c)
+            hipLaunchKernelGGL(k_ens_sweep, dim3(o.sweep[n]), dim3(kBlock), 0, s, e->d_inst,
+                               e->d_owner, e->d_off, c, it);
+    hipLaunchKernelGGL(k_ens_bound, dim3(n), dim3(kBlock), 0, s, e->d_inst);
+    hipLaunchKernelGGL(k_ens_fold, dim3(std::min(o.fold[n], kAuxBlocks)), dim3(kBlock), 0, s,
+                       e->d_inst, n, e->d_off, 0);
+    hipLaunchKernelGGL(k_ens_check, dim3(std::min(o.red[n], kAuxBlocks)), dim3(kBlock), 0, s,
+                       e->d_inst, n, e->d_off, 0);
+    hipLaunchKernelGGL(k_ens_fin_check, dim3(n), dim3(kBlock), 0, s, e->d_inst, 0);
+    ECK(hipGetLastError());
+    return LES_OK;
+}
+
+int run_batched_solve(les_ensemble* e, hipStream_t s) {
+    const int n = e->n;
+    const EnsOffsets& o = e->h_off;
+    constexpr int kGraphChecks = 8;   // check intervals per graph replay
+    hipLaunchKernelGGL(k_ens_fold, dim3(std::min(o.fold[n], kAuxBlocks)), dim3(kBlock), 0, s,
+                       e->d_inst, n, e->d_off, 1);
+    hipLaunchKernelGGL(k_ens_check, dim3(std::min(o.red[n], kAuxBlocks)), dim3(kBlock), 0, s,
+                       e->d_inst, n, e->d_off, 1);
+    hipLaunchKernelGGL(k_ens_fin_check, dim3(n), dim3(kBlock), 0, s, e->d_inst, 1);
+    ECK(hipGetLastError());
+    if (!e->chunk_graph) {
+        hipGraph_t gph = nullptr;
+        ECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = LES_OK;
+        for (int q = 0; q < kGraphChecks && rc == LES_OK; ++q) rc = enqueue_chunk(e, s);
+        hipError_t ce = hipStreamEndCapture(s, &gph);
+        if (rc != LES_OK) return rc;
+        ECK(ce);
+        ECK(hipGraphInstantiate(&e->chunk_graph, gph, nullptr, nullptr, 0));
+        ECK(hipGraphDestroy(gph));
+        e->chunk_graph_checks = kGraphChecks;
+    }
+    const long long n_batches = (e->max_checks + kGraphChecks - 1) / kGraphChecks;
+    int slot = 0;
+    bool pending = false;
+    for (long long b = 0; b < n_batches; ++b) {
+        ECK(hipGraphLaunch(e->chunk_graph, s));
+        hipLaunchKernelGGL(k_ens_all_done, dim3(1), dim3(64), 0, s, e->d_inst, n, e->d_flag + slot);
+        ECK(hipGetLastError());
+        ECK(hipMemcpyAsync(&e->h_flag[slot], e->d_flag + slot, sizeof(int), hipMemcpyDeviceToHost, s));
+        ECK(hipEventRecord(e->ev[slot], s));
+        if (pending) {
+            ECK(hipEventSynchronize(e->ev[1 - slot]));
+            if (e->h_flag[1 - slot]) break;
+        }
+        pending = true;
+        slot = 1 - slot;
+    }
+    return LES_OK;
+}
+
 int launch_solve(les_ensemble* e, hipStream_t s) {
+    if (e->mode == LES_ENSEMBLE_BATCHED) return run_batched_solve(e, s);
     const EnsInst* I = e->d_inst;
     int n = e->n;
     const EnsOffsets* O = e->d_off;
@@ -557,6 +734,12 @@ int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** ou
         return fail(LES_EDEVICE);
     e->solve_grid = cus * std::min(per_cu, 8);
     e->solve_per_cu = per_cu;
+    if (hipMalloc(&e->d_flag, 2 * sizeof(int)) != hipSuccess) return fail(LES_ENOMEM);
+    if (hipHostMalloc((void**)&e->h_flag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return fail(LES_ENOMEM);
+    for (int q = 0; q < 2; ++q)
+        if (hipEventCreateWithFlags(&e->ev[q], hipEventDisableTiming) != hipSuccess) return fail(LES_EDEVICE);
+    if (upload_owner_map(e) != LES_OK) return fail(LES_EDEVICE);
     *out = e;
     return LES_OK;
 }
@@ -568,6 +751,12 @@ void les_ensemble_destroy(les_ensemble* e) {
         if (e->pre[p]) (void)hipGraphExecDestroy(e->pre[p]);
         if (e->post[p]) (void)hipGraphExecDestroy(e->post[p]);
     }
+    if (e->chunk_graph) (void)hipGraphExecDestroy(e->chunk_graph);
+    if (e->d_owner) (void)hipFree(e->d_owner);
+    if (e->d_flag) (void)hipFree(e->d_flag);
+    if (e->h_flag) (void)hipHostFree(e->h_flag);
+    for (int q = 0; q < 2; ++q)
+        if (e->ev[q]) (void)hipEventDestroy(e->ev[q]);
     if (e->d_inst) (void)hipFree(e->d_inst);
     if (e->d_dyn) (void)hipFree(e->d_dyn);
     if (e->d_off) (void)hipFree(e->d_off);
@@ -580,13 +769,84 @@ void les_ensemble_destroy(les_ensemble* e) {
 
 const char* les_ensemble_last_error(const les_ensemble* e) { return e ? e->err.c_str() : ""; }
 
+int les_ensemble_set_mode(les_ensemble* e, int32_t mode) {
+    if (!e || (mode != LES_ENSEMBLE_BATCHED && mode != LES_ENSEMBLE_PERSISTENT)) return LES_EINVAL;
+    e->mode = mode;
+    return LES_OK;
+}
+
 int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     if (!e || reps < 1 || reps > 1000) return LES_EINVAL;
-    for (int q = 0; q < e->n; ++q) {
-        int rc = les_autotune(e->members[q], reps, nullptr, nullptr);
-        if (rc != LES_OK) return ens_err(e, rc, "les_autotune of a member");
+    const int n = e->n;
+    // time the batched half-sweep of all members for each tile variant,
+    // used by every member, on the members' scratch pressure systems (the
+    // time-stepping state is not touched); keep the fastest
+    for (int q = 0; q < n; ++q) {
+        les_handle* h = e->members[q];
+        if (!h->solve_arena) {
+            les_solve_stats st{};
+            (void)st;
+            int rc = les_autotune(h, 1, nullptr, nullptr);   // allocates the scratch system
+            if (rc != LES_OK) return ens_err(e, rc, "member scratch allocation");
+        }
     }
-    return LES_OK;   // the chosen variants are picked up at the next step
+    hipEvent_t a = nullptr, b = nullptr;
+    ECK(hipEventCreate(&a));
+    ECK(hipEventCreate(&b));
+    double best = 1e300;
+    int best_v = 0;
+    const int saved = e->variant;
+    for (int v = 0; v < kNumSorVariants; ++v) {
+        e->variant = v;
+        build_descriptors(e);
+        for (int q = 0; q < n; ++q) e->h_inst[q].P = e->members[q]->S;
+        ECK(hipMemcpy(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice));
+        ECK(hipMemcpy(e->d_off, &e->h_off, sizeof(EnsOffsets), hipMemcpyHostToDevice));
+        int rc = upload_owner_map(e);
+        if (rc != LES_OK) return rc;
+        for (int q = 0; q < n; ++q)
+            hipLaunchKernelGGL(k_ctl_probe_init, dim3(1), dim3(64), 0, e->stream, e->h_inst[q].ctl);
+        const unsigned grid = e->h_off.sweep[n];
+        for (int w = 0; w < 2; ++w)
+            hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
+                               e->d_owner, e->d_off, w & 1, 0);
+        ECK(hipEventRecord(a, e->stream));
+        for (int r = 0; r < reps; ++r)
+            for (int c = 0; c < 2; ++c)
+                hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
+                                   e->d_owner, e->d_off, c, 0);
+        ECK(hipEventRecord(b, e->stream));
+        ECK(hipEventSynchronize(b));
+        float ms = 0.f;
+        ECK(hipEventElapsedTime(&ms, a, b));
+        const double us = 1e3 * ms / (2.0 * reps);
+        e->tune_us[v] = us;
+        if (us < best) {
+            best = us;
+            best_v = v;
+        }
+    }
+    (void)saved;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    for (int q = 0; q < n; ++q)
+        for (int c = 0; c < 2; ++c) {
+            les_handle* h = e->members[q];
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)((h->g.ctot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               e->stream, h->S.pd[c], h->g.ctot);
+        }
+    ECK(hipStreamSynchronize(e->stream));
+    e->variant = best_v;
+    e->descriptors_dirty = true;
+    return LES_OK;
+}
+
+int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep) {
+    if (!e) return LES_EINVAL;
+    if (variant) *variant = e->variant;
+    if (us_per_sweep)
+        for (int v = 0; v < kNumSorVariants; ++v) us_per_sweep[v] = e->tune_us[v];
+    return LES_OK;
 }
 
 int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out) {
@@ -607,9 +867,24 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
         s.step = h->step;
     }
     ECK(hipMemcpyAsync(e->d_dyn, e->h_dyn, sizeof(EnsDyn) * n, hipMemcpyHostToDevice, e->stream));
-    build_descriptors(e);
-    ECK(hipMemcpyAsync(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice, e->stream));
-    ECK(hipMemcpyAsync(e->d_off, &e->h_off, sizeof(EnsOffsets), hipMemcpyHostToDevice, e->stream));
+    {
+        const unsigned old_sweep = e->h_off.sweep[n];
+        std::vector<int> old_var(n);
+        for (int q = 0; q < n; ++q) old_var[q] = e->h_inst.empty() ? -1 : e->h_inst[q].variant;
+        build_descriptors(e);
+        bool changed = e->h_off.sweep[n] != old_sweep || e->descriptors_dirty;
+        e->descriptors_dirty = false;
+        for (int q = 0; q < n; ++q) changed = changed || old_var[q] != e->h_inst[q].variant;
+        ECK(hipMemcpyAsync(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice, e->stream));
+        ECK(hipMemcpyAsync(e->d_off, &e->h_off, sizeof(EnsOffsets), hipMemcpyHostToDevice, e->stream));
+        if (changed) {
+            ECK(hipStreamSynchronize(e->stream));
+            int rc = upload_owner_map(e);
+            if (rc != LES_OK) return rc;
+            if (e->chunk_graph) ECK(hipGraphExecDestroy(e->chunk_graph));
+            e->chunk_graph = nullptr;   // sweep grid size changed
+        }
+    }
     if (nsteps > e->iters_cap) {
         if (e->d_iters) ECK(hipFree(e->d_iters));
         if (e->h_iters) ECK(hipHostFree(e->h_iters));

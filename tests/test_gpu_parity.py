@@ -322,9 +322,11 @@ def _member(nx, ny, nz, seed, alpha_pl=None, **kw):
     return mask, prof
 
 
-def test_ensemble_bitwise_equals_single_steps():
+@pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
+def test_ensemble_bitwise_equals_single_steps(mode):
     """An ensemble step of uneven members equals stepping each member alone
-    (same per-cell arithmetic, same per-member stopping decisions)."""
+    (same per-cell arithmetic, same per-member stopping decisions), in both
+    solve modes."""
     shapes = [(24, 20, 12), (33, 17, 9), (40, 24, 16), (17, 31, 10)]
     ins = [_member(*s, seed=50 + q, alpha_pl=(0.1 + 0.05 * q) if q % 2 else None)
            for q, s in enumerate(shapes)]
@@ -337,6 +339,7 @@ def test_ensemble_bitwise_equals_single_steps():
         ens_members.append(a)
         singles.append(b)
     ens = les.Ensemble(ens_members)
+    ens.set_mode(mode)
     rc, st, iters = ens.step(3)
     assert st["members"] == 4 and st["steps"] == 3
     for q, b in enumerate(singles):

@@ -105,6 +105,12 @@ typedef struct {
     double cfl_last;         /* max CFL of u^{n+1} (diagnostics on), else -1 */
     double ms_total;         /* host wall time of the call */
     int32_t* iters_out;      /* optional, caller-owned: n per-step iteration counts */
+    /* learned warm start (lesnet.h, les_set_warm_start); -1 when off */
+    int32_t warm_taken;      /* steps of the call whose solve started from the network */
+    int32_t pad2_;
+    double warm_r_prev_last; /* relative residual of p_prev at the last step (after the
+                                trial iterations under the trial rule) */
+    double warm_r_net_last;  /* the same for the network's start */
 } les_step_stats;
 
 typedef struct {

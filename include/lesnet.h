@@ -1,0 +1,130 @@
+/*
+ * lesnet.h -- C ABI of the learned warm start of the pressure solve.
+ *
+ * Not part of the paper's method: the paper starts each SOR solve from the
+ * previous step's pressure (section 2.6, press).  This library adds a small
+ * 3-D U-Net that predicts the change of pressure over a step from the
+ * residual of that start, and hands SOR whichever start has the smaller
+ * residual, so the solve still stops at the same tolerance and the result
+ * keeps the paper's accuracy.
+ *
+ * Network (channels c1, c2, c3; default 16, 32, 64):
+ *   e1 = relu(conv3(relu(conv3(x))))                  c1, full grid (skip)
+ *   e2 = relu(conv3(relu(conv3(pool(e1)))))           c2, 1/2 grid (skip)
+ *   b  = relu(conv3(relu(conv3(pool(e2)))))           c3, 1/4 grid
+ *   d2 = relu(conv3(relu(conv3(cat(up(b), e2)))))     c2
+ *   d1 = relu(conv3(relu(conv3(cat(up(d2), e1)))))    c1
+ *   y  = head(d1)                                     1 channel, float32
+ * conv3: 3x3x3, zero padding; pool: 2x2x2 max; up: 2x2x2 stride-2
+ * transposed convolution; head: 1x1x1.  Activations and weights are
+ * bfloat16 on the matrix cores with float32 accumulation; the master
+ * weights, their gradients and the Adam moments are float32.
+ *
+ * Tensors: x [B][D][H][W][3] float32 (channels last), y and targets
+ * [B][D][H][W] float32, all device pointers.  D, H, W are multiples of 4
+ * (two poolings), >= 4.  Calls are ordered on `stream` (NULL: the default
+ * stream) and do not synchronise unless stated.
+ *
+ * Flat parameter vector (float32), layer by layer in the order e1a, e1b,
+ * e2a, e2b, b1, b2, u2, d2a, d2b, u1, d1a, d1b, head; per layer the weight
+ * then the bias.  Weight layouts (C order): conv3 [27][Cin][Cout] with tap
+ * t = 9 (dz+1) + 3 (dy+1) + (dx+1) reading x[z+dz][y+dy][x+dx];
+ * up [8][Cin][Cout] with child s = 4 dz + 2 dy + dx written at
+ * (2z+dz, 2y+dy, 2x+dx); head [c1][1].  Cin of e1a is 3, of d2a 2 c2,
+ * of d1a 2 c1 (upsampled channels first, then the skip).
+ *
+ * Statuses are the LES_* codes of les.h.
+ */
+#ifndef LESNET_H_
+#define LESNET_H_
+
+#include <stdint.h>
+
+#include "les.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lesnet lesnet;
+
+typedef struct {
+    int32_t c1, c2, c3;   /* channels per level: c1, c2 in {16, 32}; c3 in {16, 32, 64} */
+    int32_t pad_;
+    uint64_t seed;        /* initial weights: He-normal, zero biases */
+    double lr;            /* Adam step size (default 1e-3) */
+    double beta1, beta2;  /* Adam moment decays (0.9, 0.999) */
+    double eps;           /* Adam denominator guard (1e-8) */
+} lesnet_config;
+
+int lesnet_default_config(lesnet_config* cfg);
+/* cfg NULL: defaults.  LES_EINVAL on channel counts outside the sets above
+ * or non-positive lr/eps, LES_ENOMEM if the parameter buffers fail. */
+int lesnet_create(const lesnet_config* cfg, lesnet** out);
+void lesnet_destroy(lesnet* n);
+const char* lesnet_last_error(const lesnet* n);
+
+/* Parameter access: host float32 arrays of exactly lesnet_num_params
+ * entries (else LES_EINVAL); synchronous.  lesnet_get_grads returns the
+ * gradients of the last lesnet_gradients / lesnet_train_step call. */
+int lesnet_num_params(const lesnet* n, int64_t* count);
+int lesnet_get_params(lesnet* n, float* host, int64_t count);
+int lesnet_set_params(lesnet* n, const float* host, int64_t count);
+int lesnet_get_grads(lesnet* n, float* host, int64_t count);
+
+/* y = net(x).  Activations live in a workspace sized for the last (B, D,
+ * H, W) seen and kept by the handle. */
+int lesnet_forward(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
+                   float* d_y, void* stream);
+/* Gradients of sum(y * dy) with respect to every parameter for the given
+ * output gradient dy (a forward pass runs first); read them with
+ * lesnet_get_grads. */
+int lesnet_gradients(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
+                     const float* d_dy, void* stream);
+/* One Adam step on the mean squared error between net(x) and t over all
+ * B D H W voxels.  *loss (optional) receives the loss before the step;
+ * asking for it synchronises the stream. */
+int lesnet_train_step(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
+                      const float* d_t, double* loss, void* stream);
+
+/*
+ * Coupling to an LES handle.  The network grid of a handle is (D, H, W) =
+ * (nz, ny, nx) each rounded up to a multiple of 4; voxel (z, y, x) is cell
+ * (i, j, k) = (x+1, y+1, z+1), the padding voxels are zero.  With
+ * r = rhs - A p_prev the residual of the previous pressure and N the cell
+ * count, the three input channels are
+ *   r / RMS(r),  1 for a building cell else 0,  p_prev / RMS(p_prev)
+ * (a channel whose RMS is 0 is zero), and the network's output y gives the
+ * candidate start
+ *   p0 = p_prev + y * RMS(r) / dbar * target_scale,  dbar = 2 (1/dx^2 + 1/dy^2 + 1/dz^2).
+ * The training target of a step is (p* - p_prev) dbar / RMS(r), p* the
+ * converged pressure.
+ */
+int les_warm_grid(const les_handle* h, int32_t* D, int32_t* H, int32_t* W);
+/* Use n (NULL: switch off) in every following les_step.  After the
+ * right-hand side is built the network proposes p0 and SOR starts from
+ * p0 or from p_prev, chosen by trial_iters:
+ *   0   residual rule: the float64 residual norms of the two starts are
+ *       compared on the device; p0 only if strictly smaller
+ *   > 0 trial rule: SOR runs trial_iters iterations (rounded up to whole
+ *       check intervals) from each start in a scratch copy and the start
+ *       whose residual is then strictly smaller is taken; the trial
+ *       iterations are extra work, not counted in sor_iters
+ *   -1  always p0 (for measurements)
+ * Either way the solve itself runs to the handle's tolerance, and when
+ * p_prev is kept the step is bit for bit the plain one.  The handle
+ * borrows n; keep it alive while set.  les_step_stats reports the choice
+ * and the two residuals compared.  LES_EINVAL for target_scale not
+ * positive and finite or trial_iters < -1. */
+int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t trial_iters);
+/* Training-pair capture (NULL, NULL: off): every following les_step writes
+ * the network input of the step to d_x [D][H][W][3] and, after the solve,
+ * its training target to d_t [D][H][W] (device buffers owned by the
+ * caller, overwritten by each step). */
+int les_set_capture(les_handle* h, float* d_x, float* d_t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LESNET_H_ */

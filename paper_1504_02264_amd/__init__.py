@@ -23,7 +23,7 @@ LES_EINVAL, LES_ENOMEM, LES_EDEVICE, LES_ENONFINITE, LES_ESTATE = -1, -2, -3, -4
 FREESLIP, NOSLIP, INFLOW, OUTFLOW = 0, 1, 2, 3
 URBAN_BC = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP)
 
-# every function include/les.h declares
+# every function include/les.h and include/lesnet.h declare
 EXPORTS = (
     "les_default_params", "les_create", "les_destroy", "les_last_error", "les_set_stream",
     "les_set_inflow", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
@@ -33,6 +33,11 @@ EXPORTS = (
     "les_ensemble_create", "les_ensemble_step", "les_ensemble_autotune",
     "les_ensemble_last_error", "les_ensemble_destroy", "les_ensemble_set_mode",
     "les_ensemble_tuning",
+    # include/lesnet.h
+    "lesnet_default_config", "lesnet_create", "lesnet_destroy", "lesnet_last_error",
+    "lesnet_num_params", "lesnet_get_params", "lesnet_set_params", "lesnet_get_grads",
+    "lesnet_forward", "lesnet_gradients", "lesnet_train_step", "les_warm_grid",
+    "les_set_warm_start", "les_set_capture",
 )
 ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
 NUM_SOR_VARIANTS = 8
@@ -76,10 +81,19 @@ class StepStats(C.Structure):
         ("resid_last", C.c_double), ("reltmp2_last", C.c_double), ("rhs_norm_last", C.c_double),
         ("div_star_last", C.c_double), ("div_new_last", C.c_double), ("cfl_last", C.c_double),
         ("ms_total", C.c_double), ("iters_out", C.POINTER(C.c_int32)),
+        ("warm_taken", C.c_int32), ("pad2_", C.c_int32),
+        ("warm_r_prev_last", C.c_double), ("warm_r_net_last", C.c_double),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("pad_", "iters_out")}
+        return {f: getattr(self, f) for f, _ in self._fields_
+                if f not in ("pad_", "pad2_", "iters_out")}
+
+
+class NetConfig(C.Structure):
+    _fields_ = [("c1", C.c_int32), ("c2", C.c_int32), ("c3", C.c_int32), ("pad_", C.c_int32),
+                ("seed", C.c_uint64), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -156,6 +170,22 @@ def lib():
     L.les_bc_range.restype = C.c_int64
     L.les_bc_map.argtypes = [C.POINTER(Grid), C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32)]
+    L.lesnet_default_config.argtypes = [C.POINTER(NetConfig)]
+    L.lesnet_create.argtypes = [C.POINTER(NetConfig), C.POINTER(P)]
+    L.lesnet_destroy.argtypes = [P]
+    L.lesnet_destroy.restype = None
+    L.lesnet_last_error.argtypes = [P]
+    L.lesnet_last_error.restype = C.c_char_p
+    L.lesnet_num_params.argtypes = [P, C.POINTER(C.c_int64)]
+    for f in ("lesnet_get_params", "lesnet_set_params", "lesnet_get_grads"):
+        getattr(L, f).argtypes = [P, P, C.c_int64]
+    I = C.c_int32
+    L.lesnet_forward.argtypes = [P, I, I, I, I, P, P, P]
+    L.lesnet_gradients.argtypes = [P, I, I, I, I, P, P, P]
+    L.lesnet_train_step.argtypes = [P, I, I, I, I, P, P, C.POINTER(C.c_double), P]
+    L.les_warm_grid.argtypes = [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
+    L.les_set_warm_start.argtypes = [P, P, C.c_double, C.c_int32]
+    L.les_set_capture.argtypes = [P, P, P]
     _lib = L
     return L
 
@@ -334,6 +364,104 @@ class LES:
         buf = C.create_string_buffer(blob, len(blob))
         return self._check(lib().les_set_state(self.h, buf, len(blob)))
 
+
+
+class Net:
+    """The warm-start network (``lesnet_create``).  Device tensors are torch
+    tensors (float32, contiguous, on the current device); work is ordered on
+    torch's current stream."""
+
+    def __init__(self, c1=16, c2=32, c3=64, seed=0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        cfg = NetConfig()
+        lib().lesnet_default_config(C.byref(cfg))
+        cfg.c1, cfg.c2, cfg.c3, cfg.seed = c1, c2, c3, seed
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
+        h = C.c_void_p()
+        rc = lib().lesnet_create(C.byref(cfg), C.byref(h))
+        if rc != LES_OK:
+            raise LesError(rc, "lesnet_create failed")
+        self.h = h
+        self.channels = (c1, c2, c3)
+        n = C.c_int64()
+        lib().lesnet_num_params(self.h, C.byref(n))
+        self.num_params = n.value
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lesnet_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, rc):
+        if rc != LES_OK:
+            raise LesError(rc, lib().lesnet_last_error(self.h).decode())
+
+    def get_params(self):
+        out = np.zeros(self.num_params, np.float32)
+        self._check(lib().lesnet_get_params(self.h, _ptr(out), self.num_params))
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32).reshape(-1)
+        self._check(lib().lesnet_set_params(self.h, _ptr(a), a.size))
+
+    def get_grads(self):
+        out = np.zeros(self.num_params, np.float32)
+        self._check(lib().lesnet_get_grads(self.h, _ptr(out), self.num_params))
+        return out
+
+    @staticmethod
+    def _dims(x):
+        if x.dim() != 5 or x.shape[4] != 3:
+            raise ValueError("x must be [B, D, H, W, 3]")
+        return tuple(int(d) for d in x.shape[:4])
+
+    @staticmethod
+    def _stream():
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def forward(self, x):
+        import torch
+        B, D, H, W = self._dims(x)
+        y = torch.empty((B, D, H, W), dtype=torch.float32, device=x.device)
+        self._check(lib().lesnet_forward(self.h, B, D, H, W, C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), self._stream()))
+        return y
+
+    def gradients(self, x, dy):
+        B, D, H, W = self._dims(x)
+        self._check(lib().lesnet_gradients(self.h, B, D, H, W, C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(dy.data_ptr()), self._stream()))
+        return self.get_grads()
+
+    def train_step(self, x, t, want_loss=True):
+        B, D, H, W = self._dims(x)
+        loss = C.c_double(float("nan"))
+        self._check(lib().lesnet_train_step(self.h, B, D, H, W, C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(t.data_ptr()),
+                                            C.byref(loss) if want_loss else None, self._stream()))
+        return loss.value
+
+
+def warm_grid(les: "LES"):
+    D, H, W = C.c_int32(), C.c_int32(), C.c_int32()
+    les._check(lib().les_warm_grid(les.h, C.byref(D), C.byref(H), C.byref(W)))
+    return D.value, H.value, W.value
+
+
+def set_warm_start(les: "LES", net: Optional[Net], target_scale: float = 1.0, trial_iters: int = 0):
+    """trial_iters: 0 residual rule, > 0 trial rule, -1 always the network."""
+    les._check(lib().les_set_warm_start(les.h, net.h if net is not None else None,
+                                        float(target_scale), int(trial_iters)))
+
+
+def set_capture(les: "LES", d_x=None, d_t=None):
+    """Capture each step's network input / training target into the torch
+    tensors d_x [D, H, W, 3] and d_t [D, H, W] (None, None: off)."""
+    les._check(lib().les_set_capture(les.h, C.c_void_p(d_x.data_ptr()) if d_x is not None else None,
+                                     C.c_void_p(d_t.data_ptr()) if d_t is not None else None))
 
 
 def bc_range(nx: int, ny: int, nz: int) -> int:

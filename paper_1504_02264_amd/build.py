@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libles.so")
-SOURCES = ["kernels_step.hip", "kernels_sor.hip", "ensemble.hip", "les_api.hip"]
+SOURCES = ["kernels_step.hip", "kernels_sor.hip", "ensemble.hip", "les_api.hip", "lesnet.hip",
+           "warm.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -328,7 +328,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
 int ensure_solve_arena(les_handle* h) {
     if (h->solve_arena) return LES_OK;
     const size_t cb = align256((size_t)h->g.ctot * sizeof(float));
-    const size_t total = 8 * cb;
+    const size_t total = 8 * cb + align256(sizeof(Ctl));
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) return set_err(h, LES_ENOMEM, "hipMalloc(solve workspace)", e);
@@ -341,8 +341,49 @@ int ensure_solve_arena(les_handle* h) {
         h->S.r0[c] = (float*)(b + (4 + c) * cb);
         h->S.rhs[c] = (float*)(b + (6 + c) * cb);
     }
+    h->ctl_save = (Ctl*)(b + 8 * cb);
     CK(hipStreamSynchronize(h->stream));
     return LES_OK;
+}
+
+// Residual after `iters` SOR iterations from the pair `start` against the
+// step's right-hand side, run in the solve workspace (start and the step's
+// pressure are not touched; the step's control block must be saved by the
+// caller).
+int trial_resid(les_handle* h, const PBufs& start, int iters, double* resid) {
+    const Geo& g = h->g;
+    hipStream_t s = h->stream;
+    const size_t cb = (size_t)g.ctot * sizeof(float);
+    for (int c = 0; c < 2; ++c) {
+        CK(hipMemcpyAsync(h->S.ph[c], start.ph[c], cb, hipMemcpyDeviceToDevice, s));
+        CK(hipMemcpyAsync(h->S.pd[c], start.pd[c], cb, hipMemcpyDeviceToDevice, s));
+    }
+    PBufs T = h->S;
+    T.rhs[0] = h->f.P.rhs[0];
+    T.rhs[1] = h->f.P.rhs[1];
+    CK(launch_ctl_init(s, h->f.ctl, 0.0, iters, h->prm.check_every));
+    CK(hipMemcpyAsync(&h->f.ctl->rhs2, &h->ctl_save->rhs2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    les_solve_stats st{};
+    const int rc = run_solve(h, T, 0.0, iters, &st);
+    if (rc < 0) return rc;
+    *resid = st.resid;
+    return LES_OK;
+}
+
+// Trial and forced modes of the warm start: choose between the previous
+// pressure and the network's candidate on the host.
+int warm_choose(les_handle* h) {
+    if (!h->warm_net || h->warm_trial == 0) return LES_OK;
+    if (h->warm_trial < 0) return warm_take(h, 1, -1.0, -1.0);
+    int rc = ensure_solve_arena(h);
+    if (rc != LES_OK) return rc;
+    hipStream_t s = h->stream;
+    CK(hipMemcpyAsync(h->ctl_save, h->f.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, s));
+    double ra = 0.0, rb = 0.0;
+    if ((rc = trial_resid(h, h->f.P, h->warm_trial, &ra)) != LES_OK) return rc;
+    if ((rc = trial_resid(h, warm_candidate(h), h->warm_trial, &rb)) != LES_OK) return rc;
+    CK(hipMemcpyAsync(h->f.ctl, h->ctl_save, sizeof(Ctl), hipMemcpyDeviceToDevice, s));
+    return warm_take(h, rb < ra ? 1 : 0, ra, rb);
 }
 
 }  // namespace
@@ -467,6 +508,7 @@ void les_destroy(les_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->arena) (void)hipFree(h->arena);
     if (h->solve_arena) (void)hipFree(h->solve_arena);
+    warm_free(h);
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
     if (h->h_flag) (void)hipHostFree(h->h_flag);
     for (int q = 0; q < 2; ++q)
@@ -530,6 +572,8 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
     if (st) acc.iters_out = st->iters_out;
     acc.div_new_last = -1.0;
     acc.cfl_last = -1.0;
+    acc.warm_r_prev_last = -1.0;
+    acc.warm_r_net_last = -1.0;
     int worst = LES_OK;
     for (int q = 0; q < n; ++q) {
         const int a = h->cur, b = 1 - h->cur;
@@ -557,6 +601,9 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
                 CK(launch_fill(s, h->f.P.ph[c], g.ctot, 0.f));
                 CK(launch_fill(s, h->f.P.pd[c], g.ctot, 0.f));
             }
+        int wrc = warm_pre(h);
+        if (wrc == LES_OK) wrc = warm_choose(h);
+        if (wrc != LES_OK) return wrc;
         les_solve_stats ss{};
         int rc = run_solve(h, h->f.P, p.tol, p.max_iter, &ss);
         if (rc < 0) return rc;
@@ -565,6 +612,12 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
             worst = LES_NOT_CONVERGED;
         }
         if (singular(h)) CK(launch_remove_mean_p(g, s, h->f.P, h->f.part[0], h->f.ctl));
+        if ((wrc = warm_post(h)) != LES_OK) return wrc;
+        if (h->warm_net) {
+            int taken = 0;
+            if ((wrc = warm_result(h, &taken, &acc.warm_r_prev_last, &acc.warm_r_net_last)) != LES_OK) return wrc;
+            acc.warm_taken += taken;
+        }
         CK(timed(h, KN_PROJECT, kNoTag, [&] { return launch_project(g, s, h->f.u[b], h->f.v[b], h->f.w[b], h->f.P); }));
         CK(timed(h, KN_BC, kNoTag, [&] { return launch_bc(g, s, h->f.u[b], h->f.v[b], h->f.w[b]); }));
         h->cur = b;

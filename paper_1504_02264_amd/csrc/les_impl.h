@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/les.h"
+#include "../../include/lesnet.h"
 
 namespace les {
 
@@ -127,6 +128,7 @@ struct les_handle {
     // lazily allocated workspace of les_pressure_solve
     void* solve_arena = nullptr;
     les::PBufs S{};
+    les::Ctl* ctl_save = nullptr;   // in solve_arena: the step's control block during warm-start trials
     int cur = 0;               // index of u^n in f.u/v/w
     int sor_variant = 0;       // SOR sweep tile variant (les_autotune)
     bool have_inflow = false;
@@ -146,6 +148,14 @@ struct les_handle {
     les::Ctl* h_ctl = nullptr;   // pinned mirror of the control block
     int* h_flag = nullptr;       // pinned, 2 slots for pipelined flag reads
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // learned warm start and training-pair capture (warm.hip)
+    lesnet* warm_net = nullptr;
+    double warm_scale = 1.0;
+    int warm_trial = 0;          // 0 residual rule, > 0 trial iterations, -1 always take
+    float* cap_x = nullptr;
+    float* cap_t = nullptr;
+    void* warm_arena = nullptr;
+    struct WarmView* warm = nullptr;
 };
 
 namespace les {
@@ -192,6 +202,18 @@ hipError_t launch_diag(const Geo& g, hipStream_t st, const float* u, const float
                        const float* w, double* part, Ctl* ctl);
 hipError_t launch_remove_mean_p(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                                 Ctl* ctl);
+// learned warm start (warm.hip): warm_pre after the right-hand side is
+// built (inputs, network, candidate start, and the choice under the
+// residual rule), warm_take records a choice made on the host (trial and
+// forced modes), warm_post after the solve (capture target); warm_result
+// reads the choice of the last step.
+int warm_pre(les_handle* h);
+PBufs warm_candidate(les_handle* h);   // the candidate pair (ph, pd only)
+int warm_take(les_handle* h, int take, double r_prev, double r_net);
+int warm_post(les_handle* h);
+int warm_result(les_handle* h, int* taken, double* r_prev, double* r_net);
+void warm_free(les_handle* h);
+
 // natural-order [nz][ny][nx] <-> colour layout
 hipError_t launch_cells_to_colour(const Geo& g, hipStream_t st, const float* src, float* const dst[2]);
 hipError_t launch_pair_to_cells(const Geo& g, hipStream_t st, const PBufs& P, float* dst);

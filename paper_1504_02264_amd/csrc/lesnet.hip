@@ -1,0 +1,1007 @@
+// Warm-start network for the SOR solve: a small 3-D U-Net (3 levels,
+// 16/32/64 channels, two 3x3x3 convolutions per level, 2x2x2 max pooling,
+// 2x2x2 stride-2 transposed convolutions, skip concatenation, ReLU, a
+// 1x1x1 head), trained on pairs the LES itself produces.  BF16 activations
+// and weights, FP32 accumulation on the matrix cores, FP32 master weights
+// updated by Adam (Kingma & Ba 2015).
+//
+// Forward and backward run on the same implicit-GEMM kernel:
+//   conv forward     gather 27 neighbours,            W[co][(t, ci)]
+//   conv dgrad       gather 27 neighbours of dY*relu', W flipped in t, [ci][(t, co)]
+//   up forward       same voxel, output scattered to child s (grid y), U_s[co][ci]
+//   up dgrad         gather the 8 children of dY,     U[ci][(s, co)]
+// and weight gradients on a second matrix-core kernel with a fixed-order
+// split over voxels (deterministic).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device_util.h"
+#include "les_impl.h"
+#include "lesnet_kernels.h"
+
+namespace les {
+namespace net {
+namespace {
+
+__device__ __forceinline__ void vox_of(long long v, int D, int H, int W, int& b, int& z, int& y,
+                                       int& x) {
+    x = (int)(v % W);
+    long long r = v / W;
+    y = (int)(r % H);
+    r /= H;
+    z = (int)(r % D);
+    b = (int)(r / D);
+}
+
+__device__ __forceinline__ long long vox_id(int b, int z, int y, int x, int D, int H, int W) {
+    return (((long long)b * D + z) * H + y) * W + x;
+}
+
+// ------------------------------------------------------ implicit GEMM
+template <int NT>
+__global__ __launch_bounds__(kNetBlock) void k_gemm(GemmArgs a) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const long long M = (long long)a.B * a.D * a.H * a.W;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    if (m0 >= M) return;   // whole wavefront past the end (no block-wide sync below)
+    const int slice = a.scatter_child ? (int)blockIdx.y : 0;
+    const bf16* wt = a.wt + (size_t)slice * a.cout * a.kp;
+    const long long mv = m0 + (l & 15);
+    const bool mv_ok = mv < M;
+    int b = 0, z = 0, y = 0, x = 0;
+    if (mv_ok) vox_of(mv, a.D, a.H, a.W, b, z, y, x);
+    const int ntaps = a.gather == G_TAP27 ? 27 : (a.gather == G_CHILD8 ? 8 : 1);
+    const int K = ntaps * a.cin_p;
+    const int kgrp = (l >> 4) * 8;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < a.kp; k0 += 32) {
+        const int k = k0 + kgrp;
+        bf16x8 av;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = (bf16)0.f;
+        if (mv_ok && k < K) {
+            const int t = k >> a.cin_shift;
+            const int ci = k - (t << a.cin_shift);
+            long long iv = -1;
+            if (a.gather == G_TAP27) {
+                const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                if (zz >= 0 && zz < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    iv = vox_id(b, zz, yy, xx, a.D, a.H, a.W);
+            } else if (a.gather == G_CHILD8) {
+                iv = vox_id(b, 2 * z + (t >> 2), 2 * y + ((t >> 1) & 1), 2 * x + (t & 1), 2 * a.D,
+                            2 * a.H, 2 * a.W);
+            } else {
+                iv = mv;
+            }
+            if (iv >= 0) {
+                av = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ci);
+                if (a.mask) {
+                    const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ci);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((float)mk[i] > 0.f)) av[i] = (bf16)0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wt + (size_t)(16 * nt + (l & 15)) * a.kp + k);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int ch = 16 * nt + (l & 15);
+        const float bias = a.bias ? a.bias[ch] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long ov = m0 + 4 * (l >> 4) + i;
+            if (ov >= M) continue;
+            float val = acc[nt][i] + bias;
+            if (a.relu) val = fmaxf(val, 0.f);
+            long long dst = ov;
+            if (a.scatter_child) {
+                int ob, oz, oy, ox;
+                vox_of(ov, a.D, a.H, a.W, ob, oz, oy, ox);
+                dst = vox_id(ob, 2 * oz + (slice >> 2), 2 * oy + ((slice >> 1) & 1), 2 * ox + (slice & 1),
+                             2 * a.D, 2 * a.H, 2 * a.W);
+            }
+            a.out[dst * a.out_cs + a.out_coff + ch] = (bf16)val;
+        }
+    }
+}
+
+// ------------------------------------------------------ weight gradients
+// Block = 4 wavefronts over one chunk of voxels and one tap (grid y); each
+// wavefront walks 32-voxel steps (the MFMA K), the block sums its four
+// wavefronts in LDS in a fixed order and stores one partial per chunk.
+template <int MT, int NT>
+__global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
+    __shared__ float red[MT * 16][NT * 16];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int t = blockIdx.y;
+    const long long M = (long long)a.B * a.D * a.H * a.W;
+    const long long c0 = (long long)blockIdx.x * a.chunk;
+    const long long c1 = c0 + a.chunk < M ? c0 + a.chunk : M;
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kgrp = (l >> 4) * 8;
+    for (long long v0 = c0 + (long long)wave * 32; v0 < c1; v0 += 4 * 32) {
+        bf16x8 av[MT], bv[NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) av[mt][i] = (bf16)0.f;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bv[nt][i] = (bf16)0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const long long v = v0 + kgrp + i;
+            if (v >= c1) break;
+            int b, z, y, x;
+            vox_of(v, a.D, a.H, a.W, b, z, y, x);
+            long long ia = -1, ib = -1;
+            if (!a.up) {
+                const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                if (zz >= 0 && zz < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    ia = vox_id(b, zz, yy, xx, a.D, a.H, a.W);
+                ib = v;
+            } else {
+                ia = v;
+                ib = vox_id(b, 2 * z + (t >> 2), 2 * y + ((t >> 1) & 1), 2 * x + (t & 1), 2 * a.D,
+                            2 * a.H, 2 * a.W);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int ci = 16 * mt + (l & 15);
+                if (ia >= 0 && ci < a.cin) av[mt][i] = a.in[ia * a.in_cs + ci];
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + (l & 15);
+                bf16 g = a.dout[ib * a.dout_cs + co];
+                if (a.mask && !((float)a.mask[ib * a.mask_cs + co] > 0.f)) g = (bf16)0.f;
+                bv[nt][i] = g;
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+    }
+    // wavefronts add their tiles in turn (fixed order 0, 1, 2, 3)
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float& r = red[16 * mt + 4 * (l >> 4) + i][16 * nt + (l & 15)];
+                        r = (w == 0 ? 0.f : r) + acc[mt][nt][i];
+                    }
+        }
+        __syncthreads();
+    }
+    const int taps = a.up ? 8 : 27;
+    float* dst = a.part + ((size_t)blockIdx.x * taps + t) * (MT * 16) * (NT * 16);
+    for (int e = threadIdx.x; e < MT * 16 * NT * 16; e += kNetBlock) dst[e] = red[e / (NT * 16)][e % (NT * 16)];
+}
+
+// dW[t][ci][co] (the oracle layout, ci < cin) = sum over chunks, fixed order.
+__global__ void k_wgrad_reduce(const float* part, int chunks, int taps, int cin, int cin_t, int cout,
+                               float* dw) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)taps * cin * cout;
+    if (e >= n) return;
+    const int co = (int)(e % cout);
+    const long long r = e / cout;
+    const int ci = (int)(r % cin);
+    const int t = (int)(r / cin);
+    const size_t stride = (size_t)taps * cin_t * cout;
+    const size_t off = ((size_t)t * cin_t + ci) * cout + co;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[c * stride + off];
+    dw[e] = s;
+}
+
+// Per-block channel sums of dout * relu'(mask): bias gradients (partials).
+__global__ __launch_bounds__(kNetBlock) void k_bias_part(const bf16* dout, int dout_cs, const bf16* mask,
+                                                         int mask_cs, int C, long long M, long long chunk,
+                                                         float* part) {
+    __shared__ float red[kNetBlock];
+    const long long c0 = (long long)blockIdx.x * chunk;
+    const long long c1 = c0 + chunk < M ? c0 + chunk : M;
+    const int lanes_per_c = kNetBlock / C;   // C divides 256
+    const int c = threadIdx.x % C, q = threadIdx.x / C;
+    float s = 0.f;
+    for (long long v = c0 + q; v < c1; v += lanes_per_c) {
+        float g = (float)dout[v * dout_cs + c];
+        if (mask && !((float)mask[v * mask_cs + c] > 0.f)) g = 0.f;
+        s += g;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.f;
+        for (int r = 0; r < lanes_per_c; ++r) t += red[r * C + threadIdx.x];
+        part[(size_t)blockIdx.x * C + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_bias_reduce(const float* part, int chunks, int C, float* db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float s = 0.f;
+    for (int k = 0; k < chunks; ++k) s += part[(size_t)k * C + c];
+    db[c] = s;
+}
+
+// ------------------------------------------------------ pooling
+// 2x2x2 max over the children of coarse voxel v; idx = child of the max
+// (first in child order on ties).
+__global__ __launch_bounds__(kNetBlock) void k_pool(const bf16* in, int in_cs, bf16* out, int out_cs,
+                                                    uint8_t* idx, int C, int B, int D, int H, int W) {
+    const long long e = (long long)blockIdx.x * kNetBlock + threadIdx.x;
+    const long long Mc = (long long)B * D * H * W;
+    if (e >= Mc * C) return;
+    const int c = (int)(e % C);
+    const long long v = e / C;
+    int b, z, y, x;
+    vox_of(v, D, H, W, b, z, y, x);
+    float best = -INFINITY;
+    int bi = 0;
+    for (int s = 0; s < 8; ++s) {
+        const long long f = vox_id(b, 2 * z + (s >> 2), 2 * y + ((s >> 1) & 1), 2 * x + (s & 1), 2 * D, 2 * H, 2 * W);
+        const float val = (float)in[f * in_cs + c];
+        if (val > best) {
+            best = val;
+            bi = s;
+        }
+    }
+    out[v * out_cs + c] = (bf16)best;
+    idx[e] = (uint8_t)bi;
+}
+
+// dfine[child s of v][c] = (idx == s ? dcoarse[v][c] : 0) + skip[child][c].
+__global__ __launch_bounds__(kNetBlock) void k_unpool_add(const bf16* dcoarse, int dc_cs, const uint8_t* idx,
+                                                          const bf16* skip, int skip_cs, bf16* dfine, int df_cs,
+                                                          int C, int B, int D, int H, int W) {
+    const long long e = (long long)blockIdx.x * kNetBlock + threadIdx.x;
+    const long long Mf = (long long)B * D * H * W * 8;
+    if (e >= Mf * C) return;
+    const int c = (int)(e % C);
+    const long long f = e / C;
+    int b, z, y, x;
+    vox_of(f, 2 * D, 2 * H, 2 * W, b, z, y, x);
+    const int s = ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+    const long long v = vox_id(b, z >> 1, y >> 1, x >> 1, D, H, W);
+    float g = (idx[v * C + c] == s) ? (float)dcoarse[v * dc_cs + c] : 0.f;
+    g += (float)skip[f * skip_cs + c];
+    dfine[f * df_cs + c] = (bf16)g;
+}
+
+// ------------------------------------------------------ head, loss
+__global__ __launch_bounds__(kNetBlock) void k_head(const bf16* in, int cs, int C, const float* w,
+                                                    const float* bias, long long M, float* y) {
+    const long long v = (long long)blockIdx.x * kNetBlock + threadIdx.x;
+    if (v >= M) return;
+    float s = bias[0];
+    for (int c = 0; c < C; ++c) s += (float)in[v * cs + c] * w[c];
+    y[v] = s;
+}
+
+// dy = 2 (y - t) / n; partial float64 sums of (y - t)^2 per block.
+__global__ __launch_bounds__(kNetBlock) void k_mse(const float* y, const float* t, long long n, float* dy,
+                                                   double* part) {
+    const long long v = (long long)blockIdx.x * kNetBlock + threadIdx.x;
+    double r2 = 0.0;
+    if (v < n) {
+        const float r = y[v] - t[v];
+        dy[v] = 2.f * r / (float)n;
+        r2 = (double)r * (double)r;
+    }
+    const double s = block_sum(r2);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Head backward: dd[v][c] = dy[v] w[c] (bf16); partial dW/db per block.
+__global__ __launch_bounds__(kNetBlock) void k_head_back(const bf16* in, int cs, int C, const float* w,
+                                                         const float* dy, long long M, bf16* dd, int dd_cs,
+                                                         float* part) {
+    __shared__ float red[kNetBlock][33];   // C <= 32
+    const long long v = (long long)blockIdx.x * kNetBlock + threadIdx.x;
+    float g = 0.f;
+    for (int c = 0; c <= C; ++c) red[threadIdx.x][c] = 0.f;
+    if (v < M) {
+        g = dy[v];
+        for (int c = 0; c < C; ++c) {
+            dd[v * dd_cs + c] = (bf16)(g * w[c]);
+            red[threadIdx.x][c] = (float)in[v * cs + c] * g;
+        }
+        red[threadIdx.x][C] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x <= C) {
+        float s = 0.f;
+        for (int r = 0; r < kNetBlock; ++r) s += red[r][threadIdx.x];
+        part[(size_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_sum_cols(const float* part, int rows, int cols, float* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[(size_t)r * cols + c];
+    out[c] = s;
+}
+
+__global__ void k_sum_f64(const double* part, int n, double* out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kNetBlock) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ------------------------------------------------------ weights, Adam
+// Forward layout of a conv3 (taps 27) or up (taps 8, per-child slices):
+//   conv: wt[co][t cin_p + ci] = W[t][ci][co]
+//   up:   wt[s][co][ci]         = U[s][ci][co]
+// Dgrad layout:
+//   conv: wd[ci][t' cout + co] = W[26 - t'][ci][co]
+//   up:   wd[ci][s cout + co]  = U[s][ci][co]
+// Zero where ci >= cin or k >= the filled K.
+__global__ void k_layout_fwd(const float* W, int taps, int cin, int cout, int cin_p, int kp, int up,
+                             bf16* wt) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int slices = up ? taps : 1;
+    const long long n = (long long)slices * cout * kp;
+    if (e >= n) return;
+    const int k = (int)(e % kp);
+    const long long r = e / kp;
+    const int co = (int)(r % cout);
+    const int sl = (int)(r / cout);
+    float val = 0.f;
+    if (up) {
+        if (k < cin) val = W[((size_t)sl * cin + k) * cout + co];
+    } else {
+        const int t = k / cin_p, ci = k % cin_p;
+        if (t < taps && ci < cin) val = W[((size_t)t * cin + ci) * cout + co];
+    }
+    wt[e] = (bf16)val;
+}
+
+__global__ void k_layout_dgrad(const float* W, int taps, int cin, int cout, int kp, int up, bf16* wd) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)cin * kp;
+    if (e >= n) return;
+    const int k = (int)(e % kp);
+    const int ci = (int)(e / kp);
+    const int t = k / cout, co = k % cout;
+    float val = 0.f;
+    if (t < taps) {
+        const int src = up ? t : (taps - 1 - t);
+        val = W[((size_t)src * cin + ci) * cout + co];
+    }
+    wd[e] = (bf16)val;
+}
+
+__global__ void k_adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// float [v][3] -> bf16 [v][8] (channels 3..7 zero)
+__global__ void k_pack_input(const float* x, long long M, bf16* out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * 8) return;
+    const int c = (int)(e & 7);
+    const long long v = e >> 3;
+    out[e] = (bf16)(c < 3 ? x[v * 3 + c] : 0.f);
+}
+
+inline unsigned nb(long long n, int b = kNetBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace net
+}  // namespace les
+
+using namespace les;
+using namespace les::net;
+
+// ============================================================ host side
+namespace {
+
+struct Layer {
+    const char* name;
+    int up;          // 0: conv3 (27 taps), 1: up (8 children)
+    int cin, cout;
+    int cin_p;       // input channel padding (conv) / K padding base (up)
+    long long w_off, b_off;   // offsets in the flat float parameter array
+    long long wt_off, wd_off; // offsets in the bf16 layout arena
+    int kp_f, kp_d;           // padded K of the forward / dgrad layouts
+};
+
+int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct lesnet {
+    std::string err;
+    int c1 = 16, c2 = 32, c3 = 64;
+    uint64_t seed = 0;
+    double lr = 1e-3, beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
+    int64_t t = 0;
+    std::vector<Layer> L;
+    long long nparam = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // device, fp32
+    bf16* lay = nullptr;                                           // device, bf16 layouts
+    long long nlay = 0;
+    bool layout_fresh = false;
+    // activation workspace for (B, D, H, W)
+    int B = 0, D = 0, H = 0, W = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    struct Act {
+        bf16 *x, *e1a, *C1, *p1, *e2a, *C2, *p2, *b1, *b2, *d2a, *d2b, *d1a, *d1b;
+        uint8_t *i1, *i2;
+        float *y, *dy;
+        bf16 *g_d1b, *g_d1a, *gC1, *g_d2b, *g_d2a, *gC2, *g_b2, *g_b1, *g_p2, *g_e2b, *g_e2a, *g_p1, *g_e1b, *g_e1a;
+        float* part;
+        double* dpart;
+        double* dsum;
+        long long part_n;
+    } a{};
+    double target_scale = 1.0;
+};
+
+namespace {
+
+int net_err(lesnet* n, int code, const char* what, hipError_t he = hipSuccess) {
+    if (n) {
+        n->err = what;
+        if (he != hipSuccess) n->err += std::string(": ") + hipGetErrorString(he);
+    }
+    return code;
+}
+
+#define NCK(expr)                                                        \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) return net_err(n, LES_EDEVICE, #expr, e_); \
+    } while (0)
+
+void build_layers(lesnet* n) {
+    const int c1 = n->c1, c2 = n->c2, c3 = n->c3;
+    struct Spec { const char* nm; int up, cin, cout; };
+    const Spec spec[] = {{"e1a", 0, 3, c1},      {"e1b", 0, c1, c1},      {"e2a", 0, c1, c2},
+                         {"e2b", 0, c2, c2},     {"b1", 0, c2, c3},       {"b2", 0, c3, c3},
+                         {"u2", 1, c3, c2},      {"d2a", 0, 2 * c2, c2},  {"d2b", 0, c2, c2},
+                         {"u1", 1, c2, c1},      {"d1a", 0, 2 * c1, c1},  {"d1b", 0, c1, c1}};
+    n->L.clear();
+    long long off = 0, loff = 0;
+    for (const Spec& s : spec) {
+        Layer l{};
+        l.name = s.nm;
+        l.up = s.up;
+        l.cin = s.cin;
+        l.cout = s.cout;
+        l.cin_p = s.cin < 8 ? 8 : s.cin;
+        const int taps = s.up ? 8 : 27;
+        l.w_off = off;
+        off += (long long)taps * s.cin * s.cout;
+        l.b_off = off;
+        off += s.cout;
+        l.kp_f = s.up ? rup(s.cin, 32) : rup(27 * l.cin_p, 32);
+        l.kp_d = rup(taps * s.cout, 32);
+        l.wt_off = loff;
+        loff += (long long)(s.up ? 8 : 1) * s.cout * l.kp_f;
+        l.wd_off = loff;
+        loff += (long long)s.cin * l.kp_d;
+        n->L.push_back(l);
+    }
+    // head: W [c1][1], b [1]
+    Layer h{};
+    h.name = "head";
+    h.up = -1;
+    h.cin = c1;
+    h.cout = 1;
+    h.w_off = off;
+    off += c1;
+    h.b_off = off;
+    off += 1;
+    n->L.push_back(h);
+    n->nparam = off;
+    n->nlay = loff;
+}
+
+Layer& layer(lesnet* n, const char* nm) {
+    for (Layer& l : n->L)
+        if (std::strcmp(l.name, nm) == 0) return l;
+    return n->L.back();
+}
+
+int refresh_layouts(lesnet* n, hipStream_t s) {
+    if (n->layout_fresh) return LES_OK;
+    for (const Layer& l : n->L) {
+        if (l.up < 0) continue;
+        const int taps = l.up ? 8 : 27;
+        const long long nf = (long long)(l.up ? 8 : 1) * l.cout * l.kp_f;
+        hipLaunchKernelGGL(k_layout_fwd, dim3(nb(nf)), dim3(kNetBlock), 0, s, n->w + l.w_off, taps, l.cin,
+                           l.cout, l.cin_p, l.kp_f, l.up, n->lay + l.wt_off);
+        const long long nd = (long long)l.cin * l.kp_d;
+        hipLaunchKernelGGL(k_layout_dgrad, dim3(nb(nd)), dim3(kNetBlock), 0, s, n->w + l.w_off, taps, l.cin,
+                           l.cout, l.kp_d, l.up, n->lay + l.wd_off);
+    }
+    NCK(hipGetLastError());
+    n->layout_fresh = true;
+    return LES_OK;
+}
+
+int ensure_ws(lesnet* n, int B, int D, int H, int W) {
+    if (n->ws && n->B == B && n->D == D && n->H == H && n->W == W) return LES_OK;
+    if (n->ws) NCK(hipFree(n->ws));
+    n->ws = nullptr;
+    const long long V1 = (long long)B * D * H * W, V2 = V1 / 8, V3 = V2 / 8;
+    const int c1 = n->c1, c2 = n->c2, c3 = n->c3;
+    std::vector<std::pair<void**, size_t>> req;
+    auto bf = [&](bf16** p, long long elems) { req.push_back({(void**)p, (size_t)elems * sizeof(bf16)}); };
+    lesnet::Act& a = n->a;
+    bf(&a.x, V1 * 8);
+    bf(&a.e1a, V1 * c1);
+    bf(&a.C1, V1 * 2 * c1);
+    bf(&a.p1, V2 * c1);
+    bf(&a.e2a, V2 * c2);
+    bf(&a.C2, V2 * 2 * c2);
+    bf(&a.p2, V3 * c2);
+    bf(&a.b1, V3 * c3);
+    bf(&a.b2, V3 * c3);
+    bf(&a.d2a, V2 * c2);
+    bf(&a.d2b, V2 * c2);
+    bf(&a.d1a, V1 * c1);
+    bf(&a.d1b, V1 * c1);
+    req.push_back({(void**)&a.i1, (size_t)V2 * c1});
+    req.push_back({(void**)&a.i2, (size_t)V3 * c2});
+    req.push_back({(void**)&a.y, (size_t)V1 * 4});
+    req.push_back({(void**)&a.dy, (size_t)V1 * 4});
+    bf(&a.g_d1b, V1 * c1);
+    bf(&a.g_d1a, V1 * c1);
+    bf(&a.gC1, V1 * 2 * c1);
+    bf(&a.g_d2b, V2 * c2);
+    bf(&a.g_d2a, V2 * c2);
+    bf(&a.gC2, V2 * 2 * c2);
+    bf(&a.g_b2, V3 * c3);
+    bf(&a.g_b1, V3 * c3);
+    bf(&a.g_p2, V3 * c2);
+    bf(&a.g_e2b, V2 * c2);
+    bf(&a.g_e2a, V2 * c2);
+    bf(&a.g_p1, V2 * c1);
+    bf(&a.g_e1b, V1 * c1);
+    bf(&a.g_e1a, V1 * c1);
+    // partials: weight gradients (at most 256 voxel chunks x 27 taps x 64 x
+    // 64), bias gradients (at most 1024 chunks x 64), head (blocks x 33)
+    a.part_n = std::max(256LL * 27 * 64 * 64 + 1024LL * 64, (V1 / kNetBlock + 1) * 33);
+    req.push_back({(void**)&a.part, (size_t)a.part_n * 4});
+    req.push_back({(void**)&a.dpart, (size_t)(V1 / kNetBlock + 16) * 8});
+    req.push_back({(void**)&a.dsum, 64});
+    size_t total = 0;
+    for (auto& r : req) total += (r.second + 255) & ~(size_t)255;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) return net_err(n, LES_ENOMEM, "hipMalloc(network workspace)", e);
+    n->ws = p;
+    n->ws_bytes = total;
+    char* c = (char*)p;
+    for (auto& r : req) {
+        *r.first = c;
+        c += (r.second + 255) & ~(size_t)255;
+    }
+    NCK(hipMemset(p, 0, total));
+    n->B = B;
+    n->D = D;
+    n->H = H;
+    n->W = W;
+    return LES_OK;
+}
+
+// One GEMM launch (NT = cout / 16 in {1, 2, 4}).
+hipError_t gemm(hipStream_t s, const GemmArgs& a) {
+    const long long M = (long long)a.B * a.D * a.H * a.W;
+    const dim3 grid(nb(M, 64), a.scatter_child ? 8 : 1);
+    switch (a.cout / 16) {
+        case 1: hipLaunchKernelGGL(k_gemm<1>, grid, dim3(kNetBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_gemm<2>, grid, dim3(kNetBlock), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_gemm<4>, grid, dim3(kNetBlock), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int log2i(int x) {
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+}
+
+// conv3 / up forward of layer l: in (cs) -> out (cs, coff)
+int fwd_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in_cs, bf16* out, int out_cs,
+              int out_coff, int B, int D, int H, int W) {
+    GemmArgs a{};
+    a.in = in;
+    a.in_cs = in_cs;
+    a.cin_p = l.up ? l.cin : l.cin_p;   // up: K = cin, padded to kp_f by zero weights
+    a.cin_shift = log2i(a.cin_p);
+    a.wt = n->lay + l.wt_off;
+    a.kp = l.kp_f;
+    a.bias = n->w + l.b_off;
+    a.out = out;
+    a.out_cs = out_cs;
+    a.out_coff = out_coff;
+    a.cout = l.cout;
+    a.relu = l.up ? 0 : 1;
+    a.gather = l.up ? G_TAP1 : G_TAP27;
+    a.scatter_child = l.up ? 1 : 0;
+    a.B = B; a.D = D; a.H = H; a.W = W;   // grid of the GEMM rows (coarse grid for up)
+    NCK(gemm(s, a));
+    return LES_OK;
+}
+
+// input gradient of layer l: dout (cs) masked by the layer output (mask, cs)
+// -> din (cs, coff); the GEMM rows are the layer's input grid
+int dgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* dout, int dout_cs, const bf16* mask,
+                int mask_cs, bf16* din, int din_cs, int B, int D, int H, int W) {
+    GemmArgs a{};
+    a.in = dout;
+    a.in_cs = dout_cs;
+    a.cin_p = l.cout;
+    a.cin_shift = log2i(l.cout);
+    a.mask = mask;
+    a.mask_cs = mask_cs;
+    a.wt = n->lay + l.wd_off;
+    a.kp = l.kp_d;
+    a.out = din;
+    a.out_cs = din_cs;
+    a.out_coff = 0;
+    a.cout = l.cin;
+    a.gather = l.up ? G_CHILD8 : G_TAP27;
+    a.B = B; a.D = D; a.H = H; a.W = W;
+    NCK(gemm(s, a));
+    return LES_OK;
+}
+
+// weight and bias gradients of layer l into n->g
+int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in_cs, const bf16* dout,
+                int dout_cs, const bf16* mask, int mask_cs, int B, int D, int H, int W) {
+    const long long M = (long long)B * D * H * W;
+    const int taps = l.up ? 8 : 27;
+    const int cin_t = rup(l.cin, 16);
+    long long chunk = std::max<long long>(4 * 32 * 4, (M + 255) / 256);
+    chunk = (chunk + 127) / 128 * 128;
+    const int chunks = (int)((M + chunk - 1) / chunk);
+    const long long Mo = l.up ? M * 8 : M;   // the layer's output grid
+    const long long bchunk = std::max<long long>(1024, (Mo + 1023) / 1024);
+    const int bchunks = (int)((Mo + bchunk - 1) / bchunk);
+    const long long wparts = (long long)chunks * taps * cin_t * l.cout;
+    if (wparts + (long long)bchunks * l.cout > n->a.part_n) return net_err(n, LES_ENOMEM, "wgrad partials");
+    WgradArgs a{};
+    a.in = in; a.in_cs = in_cs; a.cin = l.cin;
+    a.dout = dout; a.dout_cs = dout_cs; a.cout = l.cout;
+    a.mask = mask; a.mask_cs = mask_cs;
+    a.up = l.up;
+    a.B = B; a.D = D; a.H = H; a.W = W;
+    a.chunk = chunk;
+    a.part = n->a.part;
+    const dim3 grid(chunks, taps);
+    const int MT = cin_t / 16, NT = l.cout / 16;
+#define WG(mt, nt) \
+    if (MT == mt && NT == nt) hipLaunchKernelGGL((k_wgrad<mt, nt>), grid, dim3(kNetBlock), 0, s, a)
+    WG(1, 1); else WG(1, 2); else WG(1, 4); else WG(2, 1); else WG(2, 2); else WG(2, 4);
+    else WG(4, 1); else WG(4, 2); else WG(4, 4);
+    else return net_err(n, LES_EINVAL, "wgrad tile");
+#undef WG
+    NCK(hipGetLastError());
+    const long long nw = (long long)taps * l.cin * l.cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps, l.cin,
+                       cin_t, l.cout, n->g + l.w_off);
+    // bias: sum of dout * relu' over the layer's output grid
+    hipLaunchKernelGGL(k_bias_part, dim3(bchunks), dim3(kNetBlock), 0, s, dout, dout_cs, mask, mask_cs, l.cout,
+                       Mo, bchunk, n->a.part + wparts);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, s, n->a.part + wparts, bchunks, l.cout,
+                       n->g + l.b_off);
+    NCK(hipGetLastError());
+    return LES_OK;
+}
+
+int forward(lesnet* n, hipStream_t s, int B, int D, int H, int W) {
+    lesnet::Act& a = n->a;
+    const int c1 = n->c1, c2 = n->c2, c3 = n->c3;
+    const int D2 = D / 2, H2 = H / 2, W2 = W / 2, D3 = D / 4, H3 = H / 4, W3 = W / 4;
+    int rc;
+    if ((rc = refresh_layouts(n, s)) != LES_OK) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "e1a"), a.x, 8, a.e1a, c1, 0, B, D, H, W))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "e1b"), a.e1a, c1, a.C1, 2 * c1, c1, B, D, H, W))) return rc;
+    hipLaunchKernelGGL(k_pool, dim3(nb((long long)B * D2 * H2 * W2 * c1)), dim3(kNetBlock), 0, s, a.C1 + c1,
+                       2 * c1, a.p1, c1, a.i1, c1, B, D2, H2, W2);
+    if ((rc = fwd_layer(n, s, layer(n, "e2a"), a.p1, c1, a.e2a, c2, 0, B, D2, H2, W2))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "e2b"), a.e2a, c2, a.C2, 2 * c2, c2, B, D2, H2, W2))) return rc;
+    hipLaunchKernelGGL(k_pool, dim3(nb((long long)B * D3 * H3 * W3 * c2)), dim3(kNetBlock), 0, s, a.C2 + c2,
+                       2 * c2, a.p2, c2, a.i2, c2, B, D3, H3, W3);
+    if ((rc = fwd_layer(n, s, layer(n, "b1"), a.p2, c2, a.b1, c3, 0, B, D3, H3, W3))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "b2"), a.b1, c3, a.b2, c3, 0, B, D3, H3, W3))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "u2"), a.b2, c3, a.C2, 2 * c2, 0, B, D3, H3, W3))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "d2a"), a.C2, 2 * c2, a.d2a, c2, 0, B, D2, H2, W2))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "d2b"), a.d2a, c2, a.d2b, c2, 0, B, D2, H2, W2))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "u1"), a.d2b, c2, a.C1, 2 * c1, 0, B, D2, H2, W2))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "d1a"), a.C1, 2 * c1, a.d1a, c1, 0, B, D, H, W))) return rc;
+    if ((rc = fwd_layer(n, s, layer(n, "d1b"), a.d1a, c1, a.d1b, c1, 0, B, D, H, W))) return rc;
+    const Layer& hd = layer(n, "head");
+    const long long V1 = (long long)B * D * H * W;
+    hipLaunchKernelGGL(k_head, dim3(nb(V1)), dim3(kNetBlock), 0, s, a.d1b, c1, c1, n->w + hd.w_off,
+                       n->w + hd.b_off, V1, a.y);
+    NCK(hipGetLastError());
+    return LES_OK;
+}
+
+// Backward from a.dy: every gradient into n->g.
+int backward(lesnet* n, hipStream_t s, int B, int D, int H, int W) {
+    lesnet::Act& a = n->a;
+    const int c1 = n->c1, c2 = n->c2, c3 = n->c3;
+    const int D2 = D / 2, H2 = H / 2, W2 = W / 2, D3 = D / 4, H3 = H / 4, W3 = W / 4;
+    const long long V1 = (long long)B * D * H * W;
+    int rc;
+    // head
+    const Layer& hd = layer(n, "head");
+    const unsigned hb = nb(V1);
+    hipLaunchKernelGGL(k_head_back, dim3(hb), dim3(kNetBlock), 0, s, a.d1b, c1, c1, n->w + hd.w_off, a.dy, V1,
+                       a.g_d1b, c1, a.part);
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(64), 0, s, a.part, (int)hb, c1 + 1, n->g + hd.w_off);
+    NCK(hipGetLastError());
+    // d1b (output d1b, input d1a)
+    const Layer &d1b = layer(n, "d1b"), &d1a = layer(n, "d1a"), &u1 = layer(n, "u1");
+    const Layer &d2b = layer(n, "d2b"), &d2a = layer(n, "d2a"), &u2 = layer(n, "u2");
+    const Layer &b2 = layer(n, "b2"), &b1 = layer(n, "b1"), &e2b = layer(n, "e2b"), &e2a = layer(n, "e2a");
+    const Layer &e1b = layer(n, "e1b"), &e1a = layer(n, "e1a");
+    if ((rc = wgrad_layer(n, s, d1b, a.d1a, c1, a.g_d1b, c1, a.d1b, c1, B, D, H, W))) return rc;
+    if ((rc = dgrad_layer(n, s, d1b, a.g_d1b, c1, a.d1b, c1, a.g_d1a, c1, B, D, H, W))) return rc;
+    if ((rc = wgrad_layer(n, s, d1a, a.C1, 2 * c1, a.g_d1a, c1, a.d1a, c1, B, D, H, W))) return rc;
+    if ((rc = dgrad_layer(n, s, d1a, a.g_d1a, c1, a.d1a, c1, a.gC1, 2 * c1, B, D, H, W))) return rc;
+    // u1: output = gC1[..., 0:c1] (no relu), input d2b on the coarse grid
+    if ((rc = wgrad_layer(n, s, u1, a.d2b, c2, a.gC1, 2 * c1, nullptr, 0, B, D2, H2, W2))) return rc;
+    if ((rc = dgrad_layer(n, s, u1, a.gC1, 2 * c1, nullptr, 0, a.g_d2b, c2, B, D2, H2, W2))) return rc;
+    if ((rc = wgrad_layer(n, s, d2b, a.d2a, c2, a.g_d2b, c2, a.d2b, c2, B, D2, H2, W2))) return rc;
+    if ((rc = dgrad_layer(n, s, d2b, a.g_d2b, c2, a.d2b, c2, a.g_d2a, c2, B, D2, H2, W2))) return rc;
+    if ((rc = wgrad_layer(n, s, d2a, a.C2, 2 * c2, a.g_d2a, c2, a.d2a, c2, B, D2, H2, W2))) return rc;
+    if ((rc = dgrad_layer(n, s, d2a, a.g_d2a, c2, a.d2a, c2, a.gC2, 2 * c2, B, D2, H2, W2))) return rc;
+    if ((rc = wgrad_layer(n, s, u2, a.b2, c3, a.gC2, 2 * c2, nullptr, 0, B, D3, H3, W3))) return rc;
+    if ((rc = dgrad_layer(n, s, u2, a.gC2, 2 * c2, nullptr, 0, a.g_b2, c3, B, D3, H3, W3))) return rc;
+    if ((rc = wgrad_layer(n, s, b2, a.b1, c3, a.g_b2, c3, a.b2, c3, B, D3, H3, W3))) return rc;
+    if ((rc = dgrad_layer(n, s, b2, a.g_b2, c3, a.b2, c3, a.g_b1, c3, B, D3, H3, W3))) return rc;
+    if ((rc = wgrad_layer(n, s, b1, a.p2, c2, a.g_b1, c3, a.b1, c3, B, D3, H3, W3))) return rc;
+    if ((rc = dgrad_layer(n, s, b1, a.g_b1, c3, a.b1, c3, a.g_p2, c2, B, D3, H3, W3))) return rc;
+    hipLaunchKernelGGL(k_unpool_add, dim3(nb((long long)B * D2 * H2 * W2 * c2)), dim3(kNetBlock), 0, s, a.g_p2,
+                       c2, a.i2, a.gC2 + c2, 2 * c2, a.g_e2b, c2, c2, B, D3, H3, W3);
+    NCK(hipGetLastError());
+    if ((rc = wgrad_layer(n, s, e2b, a.e2a, c2, a.g_e2b, c2, a.C2 + c2, 2 * c2, B, D2, H2, W2))) return rc;
+    if ((rc = dgrad_layer(n, s, e2b, a.g_e2b, c2, a.C2 + c2, 2 * c2, a.g_e2a, c2, B, D2, H2, W2))) return rc;
+    if ((rc = wgrad_layer(n, s, e2a, a.p1, c1, a.g_e2a, c2, a.e2a, c2, B, D2, H2, W2))) return rc;
+    if ((rc = dgrad_layer(n, s, e2a, a.g_e2a, c2, a.e2a, c2, a.g_p1, c1, B, D2, H2, W2))) return rc;
+    hipLaunchKernelGGL(k_unpool_add, dim3(nb(V1 * c1)), dim3(kNetBlock), 0, s, a.g_p1, c1, a.i1, a.gC1 + c1,
+                       2 * c1, a.g_e1b, c1, c1, B, D2, H2, W2);
+    NCK(hipGetLastError());
+    if ((rc = wgrad_layer(n, s, e1b, a.e1a, c1, a.g_e1b, c1, a.C1 + c1, 2 * c1, B, D, H, W))) return rc;
+    if ((rc = dgrad_layer(n, s, e1b, a.g_e1b, c1, a.C1 + c1, 2 * c1, a.g_e1a, c1, B, D, H, W))) return rc;
+    if ((rc = wgrad_layer(n, s, e1a, a.x, 8, a.g_e1a, c1, a.e1a, c1, B, D, H, W))) return rc;
+    return LES_OK;
+}
+
+bool dims_ok(int B, int D, int H, int W) {
+    return B >= 1 && D >= 4 && H >= 4 && W >= 4 && D % 4 == 0 && H % 4 == 0 && W % 4 == 0 &&
+           (long long)B * D * H * W < (1LL << 31);
+}
+
+}  // namespace
+
+namespace les {
+namespace net {
+int ws_prepare(lesnet* n, int B, int D, int H, int W) {
+    if (!dims_ok(B, D, H, W)) return net_err(n, LES_EINVAL, "network grid");
+    return ensure_ws(n, B, D, H, W);
+}
+bf16* ws_input(lesnet* n) { return n->a.x; }
+const float* ws_output(const lesnet* n) { return n->a.y; }
+int ws_forward(lesnet* n, hipStream_t s, int B, int D, int H, int W) { return forward(n, s, B, D, H, W); }
+}  // namespace net
+}  // namespace les
+
+extern "C" {
+
+int lesnet_default_config(lesnet_config* cfg) {
+    if (!cfg) return LES_EINVAL;
+    *cfg = lesnet_config{};
+    cfg->c1 = 16;
+    cfg->c2 = 32;
+    cfg->c3 = 64;
+    cfg->seed = 0;
+    cfg->lr = 1e-3;
+    cfg->beta1 = 0.9;
+    cfg->beta2 = 0.999;
+    cfg->eps = 1e-8;
+    return LES_OK;
+}
+
+int lesnet_create(const lesnet_config* cfg, lesnet** out) {
+    if (!out) return LES_EINVAL;
+    *out = nullptr;
+    lesnet* n = new (std::nothrow) lesnet();
+    if (!n) return LES_ENOMEM;
+    if (cfg) {
+        // tile limits: channel counts are MFMA tiles of 16; the concatenated
+        // inputs (2 c1, 2 c2) and c3 are at most 64; the head reads <= 32
+        auto tile = [](int c, int hi) { return c == 16 || c == 32 || (c == 64 && hi >= 64); };
+        if (!tile(cfg->c1, 32) || !tile(cfg->c2, 32) || !tile(cfg->c3, 64) || !(cfg->lr > 0) ||
+            !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0)) {
+            delete n;
+            return LES_EINVAL;
+        }
+        n->c1 = cfg->c1; n->c2 = cfg->c2; n->c3 = cfg->c3;
+        n->seed = cfg->seed;
+        n->lr = cfg->lr; n->beta1 = cfg->beta1; n->beta2 = cfg->beta2; n->eps = cfg->eps;
+    }
+    build_layers(n);
+    const size_t pb = (size_t)n->nparam * 4;
+    if (hipMalloc(&n->w, pb) != hipSuccess || hipMalloc(&n->g, pb) != hipSuccess ||
+        hipMalloc(&n->m, pb) != hipSuccess || hipMalloc(&n->v, pb) != hipSuccess ||
+        hipMalloc(&n->lay, (size_t)n->nlay * sizeof(bf16)) != hipSuccess) {
+        lesnet_destroy(n);
+        return LES_ENOMEM;
+    }
+    (void)hipMemset(n->g, 0, pb);
+    (void)hipMemset(n->m, 0, pb);
+    (void)hipMemset(n->v, 0, pb);
+    (void)hipMemset(n->lay, 0, (size_t)n->nlay * sizeof(bf16));
+    // He-normal initial weights (Box-Muller on splitmix64 counters), zero biases
+    std::vector<float> w((size_t)n->nparam, 0.f);
+    uint64_t ctr = n->seed * 0x9E3779B97F4A7C15ULL;
+    auto u01 = [&]() {
+        uint64_t z = (ctr += 0x9E3779B97F4A7C15ULL);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    for (const Layer& l : n->L) {
+        const long long nw = l.up < 0 ? l.cin : (long long)(l.up ? 8 : 27) * l.cin * l.cout;
+        const double fan = l.up < 0 ? l.cin : (double)(l.up ? 8 : 27) * l.cin;
+        const double sd = std::sqrt(2.0 / fan);
+        for (long long q = 0; q < nw; ++q) {
+            const double r = std::sqrt(-2.0 * std::log(u01())) * std::cos(6.283185307179586 * u01());
+            w[(size_t)(l.w_off + q)] = (float)(sd * r);
+        }
+    }
+    if (hipMemcpy(n->w, w.data(), pb, hipMemcpyHostToDevice) != hipSuccess) {
+        lesnet_destroy(n);
+        return LES_EDEVICE;
+    }
+    *out = n;
+    return LES_OK;
+}
+
+void lesnet_destroy(lesnet* n) {
+    if (!n) return;
+    (void)hipDeviceSynchronize();
+    if (n->w) (void)hipFree(n->w);
+    if (n->g) (void)hipFree(n->g);
+    if (n->m) (void)hipFree(n->m);
+    if (n->v) (void)hipFree(n->v);
+    if (n->lay) (void)hipFree(n->lay);
+    if (n->ws) (void)hipFree(n->ws);
+    delete n;
+}
+
+const char* lesnet_last_error(const lesnet* n) { return n ? n->err.c_str() : ""; }
+
+int lesnet_num_params(const lesnet* n, int64_t* count) {
+    if (!n || !count) return LES_EINVAL;
+    *count = n->nparam;
+    return LES_OK;
+}
+
+int lesnet_get_params(lesnet* n, float* host, int64_t count) {
+    if (!n || !host || count != n->nparam) return LES_EINVAL;
+    NCK(hipMemcpy(host, n->w, (size_t)count * 4, hipMemcpyDeviceToHost));
+    return LES_OK;
+}
+
+int lesnet_set_params(lesnet* n, const float* host, int64_t count) {
+    if (!n || !host || count != n->nparam) return LES_EINVAL;
+    NCK(hipMemcpy(n->w, host, (size_t)count * 4, hipMemcpyHostToDevice));
+    n->layout_fresh = false;
+    return LES_OK;
+}
+
+int lesnet_get_grads(lesnet* n, float* host, int64_t count) {
+    if (!n || !host || count != n->nparam) return LES_EINVAL;
+    NCK(hipMemcpy(host, n->g, (size_t)count * 4, hipMemcpyDeviceToHost));
+    return LES_OK;
+}
+
+int lesnet_forward(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x, float* d_y,
+                   void* stream) {
+    if (!n || !d_x || !d_y || !dims_ok(B, D, H, W)) return LES_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_ws(n, B, D, H, W);
+    if (rc != LES_OK) return rc;
+    const long long V1 = (long long)B * D * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(nb(V1 * 8)), dim3(kNetBlock), 0, s, d_x, V1, n->a.x);
+    NCK(hipGetLastError());
+    if ((rc = forward(n, s, B, D, H, W)) != LES_OK) return rc;
+    NCK(hipMemcpyAsync(d_y, n->a.y, (size_t)V1 * 4, hipMemcpyDeviceToDevice, s));
+    return LES_OK;
+}
+
+int lesnet_gradients(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
+                     const float* d_dy, void* stream) {
+    if (!n || !d_x || !d_dy || !dims_ok(B, D, H, W)) return LES_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_ws(n, B, D, H, W);
+    if (rc != LES_OK) return rc;
+    const long long V1 = (long long)B * D * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(nb(V1 * 8)), dim3(kNetBlock), 0, s, d_x, V1, n->a.x);
+    NCK(hipGetLastError());
+    if ((rc = forward(n, s, B, D, H, W)) != LES_OK) return rc;
+    NCK(hipMemcpyAsync(n->a.dy, d_dy, (size_t)V1 * 4, hipMemcpyDeviceToDevice, s));
+    return backward(n, s, B, D, H, W);
+}
+
+int lesnet_train_step(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
+                      const float* d_t, double* loss, void* stream) {
+    if (!n || !d_x || !d_t || !dims_ok(B, D, H, W)) return LES_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_ws(n, B, D, H, W);
+    if (rc != LES_OK) return rc;
+    const long long V1 = (long long)B * D * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(nb(V1 * 8)), dim3(kNetBlock), 0, s, d_x, V1, n->a.x);
+    NCK(hipGetLastError());
+    if ((rc = forward(n, s, B, D, H, W)) != LES_OK) return rc;
+    const unsigned mb = nb(V1);
+    hipLaunchKernelGGL(k_mse, dim3(mb), dim3(kNetBlock), 0, s, n->a.y, d_t, V1, n->a.dy, n->a.dpart);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kNetBlock), 0, s, n->a.dpart, (int)mb, n->a.dsum);
+    NCK(hipGetLastError());
+    if ((rc = backward(n, s, B, D, H, W)) != LES_OK) return rc;
+    n->t += 1;
+    const double c1 = 1.0 - std::pow(n->beta1, (double)n->t), c2 = 1.0 - std::pow(n->beta2, (double)n->t);
+    hipLaunchKernelGGL(k_adam, dim3(nb(n->nparam)), dim3(kNetBlock), 0, s, n->w, n->g, n->m, n->v, n->nparam,
+                       (float)n->lr, (float)n->beta1, (float)n->beta2, (float)n->eps, (float)c1, (float)c2);
+    NCK(hipGetLastError());
+    n->layout_fresh = false;
+    if (loss) {
+        double h = 0.0;
+        NCK(hipMemcpyAsync(&h, n->a.dsum, 8, hipMemcpyDeviceToHost, s));
+        NCK(hipStreamSynchronize(s));
+        *loss = h / (double)V1;
+    }
+    return LES_OK;
+}
+
+}  // extern "C"

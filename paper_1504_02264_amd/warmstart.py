@@ -1,0 +1,111 @@
+"""Training and evaluation of the learned SOR warm start on LES runs.
+
+Pairs come from the LES itself: with capture on (``les_set_capture``) each
+step leaves its network input (residual of the previous pressure, building
+mask, previous pressure, normalised) and its target (the converged change
+of pressure, scaled by dbar / RMS(residual)) on the device.  Training runs
+the network's own kernels (``lesnet_train_step``); evaluation runs the
+same cases with and without the warm start and compares the SOR iteration
+counts, which stop at the same tolerance either way.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+import paper_1504_02264_amd as les
+
+
+def make_case(base: str, seed: int, **params):
+    """An LES handle for workload `base` with buildings and inflow noise
+    drawn from `seed`."""
+    from les_inputs import WORKLOADS, make_workload_inputs
+
+    w = dataclasses.replace(WORKLOADS[base], seed=seed)
+    mask, prof = make_workload_inputs(w)
+    g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask, **params)
+    g.set_inflow(prof, w.noise_amp, seed)
+    return g
+
+
+def collect(base: str, seed: int, steps: int, skip: int = 0):
+    """Run `skip` + `steps` steps; return the (inputs [n, D, H, W, 3],
+    targets [n, D, H, W]) of the last `steps` as device tensors, with the
+    per-step SOR iterations."""
+    import torch
+
+    g = make_case(base, seed)
+    try:
+        if skip:
+            g.step(skip)
+        D, H, W = les.warm_grid(g)
+        X = torch.empty((steps, D, H, W, 3), device="cuda")
+        T = torch.empty((steps, D, H, W), device="cuda")
+        its = []
+        for s in range(steps):
+            les.set_capture(g, X[s], T[s])
+            _, _, it = g.step(1)
+            its.append(int(it[0]))
+        les.set_capture(g, None, None)
+        torch.cuda.synchronize()
+        return X, T, np.array(its)
+    finally:
+        g.close()
+
+
+def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None):
+    """Adam on random mini-batches of the pairs; targets are divided by
+    their RMS over the set, which is returned as the warm start's
+    target_scale, with the loss history."""
+    import torch
+
+    scale = float(torch.sqrt(torch.mean(T.double() ** 2)).item())
+    Tn = (T / scale).contiguous()
+    rng = np.random.default_rng(seed)
+    losses = []
+    n = X.shape[0]
+    for it in range(iters):
+        idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).cuda()
+        xb = X.index_select(0, idx).contiguous()
+        tb = Tn.index_select(0, idx).contiguous()
+        want = (it % 50 == 0) or it == iters - 1
+        loss = net.train_step(xb, tb, want_loss=want)
+        if want:
+            losses.append((it, loss))
+            if log:
+                log(f"train iter {it}: loss {loss:.4f}")
+    return scale, losses
+
+
+def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float = 1.0,
+             skip: int = 0, trial_iters: int = 0):
+    """Iterations per step and wall ms per step of `steps` steps (after
+    `skip` plain steps), warm-started by `net` if given (choice rule
+    `trial_iters`, see les_set_warm_start)."""
+    import torch
+
+    g = make_case(base, seed)
+    try:
+        if skip:
+            g.step(skip)
+        if net is not None:
+            les.set_warm_start(g, net, scale, trial_iters)
+        torch.cuda.synchronize()
+        its, taken, rnet, rprev = [], 0, [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, it = g.step(1)
+            its.append(int(it[0]))
+            taken += st["warm_taken"]
+            rnet.append(st["warm_r_net_last"])
+            rprev.append(st["warm_r_prev_last"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if net is not None:
+            les.set_warm_start(g, None)
+        return {"iters": np.array(its), "ms_per_step": ms, "taken": taken,
+                "r_net": np.array(rnet), "r_prev": np.array(rprev)}
+    finally:
+        g.close()

@@ -14,9 +14,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "les.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(les_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in ("les.h", "lesnet.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b((?:les|lesnet)_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():

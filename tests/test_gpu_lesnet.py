@@ -1,0 +1,243 @@
+"""GPU parity of the warm-start network (matrix-core kernels through the C
+ABI) against the FP64 oracle of oracle/lesnet.py.
+
+Both sides get the same bfloat16-representable weights and inputs.  The
+GPU rounds every activation and activation gradient to bfloat16 (unit
+roundoff u = 2^-8) and accumulates in float32; the oracle keeps float64
+throughout.  Each rounding perturbs a tensor by at most u relative per
+element; independent perturbations through L rounding stages of unit gain
+add in quadrature, so the relative L2 error of the output is about
+u sqrt(L).  The forward pass has L = 13 rounded tensors on its longest
+path (u sqrt(13) = 1.4e-2), the backward pass another 13 plus the
+forward's (u sqrt(26) = 2.0e-2).  The bars below are those figures.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1504_02264_amd as les
+from oracle import lesnet as N
+
+pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -8
+TOL_FWD = U_BF16 * np.sqrt(13)
+TOL_GRAD = U_BF16 * np.sqrt(26)
+
+
+def bf16(a):
+    return torch.from_numpy(np.asarray(a, np.float64)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def make_params(seed, c=(16, 32, 64)):
+    p = N.init_params(seed=seed, c1=c[0], c2=c[1], c3=c[2])
+    rng = np.random.default_rng(seed + 100)
+    for k in list(p):
+        if k.endswith(".b"):
+            p[k] = (rng.standard_normal(p[k].shape) * 0.05).astype(np.float32).astype(np.float64)
+        elif k == "head":
+            p[k] = p[k].astype(np.float32).astype(np.float64)
+        else:
+            p[k] = bf16(p[k])
+    return p
+
+
+def flat(p):
+    return np.concatenate([np.concatenate([p[n].ravel(), p[n + ".b"].ravel()]) for n in N.LAYERS])
+
+
+def unflat(v, c=(16, 32, 64)):
+    out, o = {}, 0
+    for n, shp in N.shapes(*c).items():
+        k = int(np.prod(shp))
+        out[n] = v[o:o + k].reshape(shp)
+        o += k
+        out[n + ".b"] = v[o:o + shp[-1]]
+        o += shp[-1]
+    assert o == v.size
+    return out
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def net():
+    n = les.Net(seed=1)
+    yield n
+    n.close()
+
+
+def test_param_count_matches_oracle(net):
+    assert net.num_params == sum(int(np.prod(s)) + s[-1] for s in N.shapes().values())
+
+
+@pytest.mark.parametrize("B,D,H,W", [(1, 8, 12, 16), (2, 4, 8, 4), (1, 16, 8, 12)])
+def test_forward_parity(net, B, D, H, W):
+    print(f"[lesnet_forward] B={B} D={D} H={H} W={W}", flush=True)
+    p = make_params(7)
+    net.set_params(flat(p))
+    x = bf16(np.random.default_rng(B * 100 + D).standard_normal((B, D, H, W, 3)))
+    y = net.forward(dev(x)).cpu().numpy()
+    torch.cuda.synchronize()
+    for b in range(B):
+        yo, _ = N.forward(p, x[b])
+        e = rel(y[b], yo[..., 0])
+        print(f"  sample {b}: rel L2 {e:.3e} (bar {TOL_FWD:.3e})", flush=True)
+        assert e <= TOL_FWD
+
+
+def test_gradient_parity(net):
+    """Random weights: some ReLU signs and pooling argmaxes sit within the
+    GPU's forward error band of their threshold and may fall the other
+    way.  Each such decision moves one whole term of a gradient sum; with
+    terms of random sign a fraction f of moved terms changes the sum by
+    about sqrt(f) relative, so the bar is the rounding figure plus
+    sqrt(f), f counted on the oracle's own activations (the linear-regime
+    test below has no such decisions and holds the rounding bar alone)."""
+    B, D, H, W = 2, 8, 8, 12
+    print(f"[lesnet_gradients] B={B} D={D} H={H} W={W}", flush=True)
+    p = make_params(11)
+    net.set_params(flat(p))
+    rng = np.random.default_rng(5)
+    x = bf16(rng.standard_normal((B, D, H, W, 3)))
+    dy = rng.standard_normal((B, D, H, W)).astype(np.float32)
+    g = unflat(net.gradients(dev(x), dev(dy)).astype(np.float64))
+    go = None
+    for b in range(B):
+        _, c = N.forward(p, x[b])
+        gb = N.backward(p, c, dy[b][..., None].astype(np.float64))
+        go = gb if go is None else {k: go[k] + gb[k] for k in go}
+    worst = 0.0
+    errs = {}
+    for k in go:
+        errs[k] = rel(g[k], go[k])
+        worst = max(worst, errs[k])
+        print(f"  {k:7s} rel L2 {errs[k]:.3e}", flush=True)
+    f = ambiguous_fraction(p, x)
+    bar = TOL_GRAD + np.sqrt(f)
+    print(f"  worst {worst:.3e}; ambiguous fraction {f:.3e}; bar {bar:.3e}", flush=True)
+    for k, e in errs.items():
+        assert e <= bar, k
+
+
+def ambiguous_fraction(p, x):
+    """Fraction of the network's discrete decisions (ReLU signs, pooling
+    argmaxes) whose margin is within the forward error band of the GPU."""
+    band = 2 * TOL_FWD
+    tot = amb = 0
+    for b in range(x.shape[0]):
+        _, c = N.forward(p, x[b])
+        ins = {"e1a": c["x"], "e1b": c["e1a"], "e2a": c["p1"], "e2b": c["e2a"], "b1": c["p2"],
+               "b2": c["b1"], "d2a": c["c2"], "d2b": c["d2a"], "d1a": c["c1"], "d1b": c["d1a"]}
+        for k, xin in ins.items():
+            pre = N.conv3(xin, p[k], p[k + ".b"])
+            amb += np.count_nonzero(np.abs(pre) < band * np.sqrt(np.mean(pre ** 2)))
+            tot += pre.size
+        for k in ("e1b", "e2b"):
+            a = c[k]
+            blocks = np.sort(np.stack([a[dz::2, dy::2, dx::2] for dz, dy, dx in N.SUB]), axis=0)
+            amb += np.count_nonzero(blocks[-1] - blocks[-2] < band * np.sqrt(np.mean(a ** 2)))
+            tot += blocks[-1].size
+    return amb / tot
+
+
+def test_gradient_parity_linear_regime(net):
+    """Non-negative weights, inputs and positive biases keep every ReLU in
+    its linear branch on both sides, so only rounding separates them (and
+    the rare pooling near-tie)."""
+    B, D, H, W = 1, 8, 8, 12
+    rng = np.random.default_rng(17)
+    p = {}
+    for k, shp in N.shapes().items():
+        fan = int(np.prod(shp[:-1]))
+        w = rng.uniform(0, 2.0 / fan, shp)
+        p[k] = w.astype(np.float32).astype(np.float64) if k == "head" else bf16(w)
+        p[k + ".b"] = rng.uniform(0.01, 0.1, shp[-1]).astype(np.float32).astype(np.float64)
+    net.set_params(flat(p))
+    x = bf16(np.abs(rng.standard_normal((B, D, H, W, 3))))
+    dy = rng.standard_normal((B, D, H, W)).astype(np.float32)
+    g = unflat(net.gradients(dev(x), dev(dy)).astype(np.float64))
+    _, c = N.forward(p, x[0])
+    go = N.backward(p, c, dy[0][..., None].astype(np.float64))
+    errs = {k: rel(g[k], go[k]) for k in go}
+    for k, e in errs.items():
+        print(f"  {k:7s} rel L2 {e:.3e}", flush=True)
+    print(f"  ambiguous fraction {ambiguous_fraction(p, x):.3e}", flush=True)
+    for k, e in errs.items():
+        assert e <= TOL_GRAD, k
+
+
+def test_gradients_deterministic(net):
+    p = make_params(3)
+    net.set_params(flat(p))
+    rng = np.random.default_rng(9)
+    x = dev(bf16(rng.standard_normal((1, 8, 8, 8, 3))))
+    dy = dev(rng.standard_normal((1, 8, 8, 8)))
+    g1 = net.gradients(x, dy)
+    g2 = net.gradients(x, dy)
+    assert np.array_equal(g1, g2)
+
+
+def test_train_step_loss_and_adam_direction():
+    """The reported loss is the oracle's MSE of the forward pass; the first
+    Adam step moves every weight by lr * sign(g) (bias correction makes
+    m/sqrt(v) = g/|g|), checked where the oracle's gradient is clearly
+    away from zero."""
+    lr = 1e-3
+    n = les.Net(seed=2, lr=lr)
+    try:
+        p = make_params(13)
+        w0 = flat(p)
+        n.set_params(w0)
+        rng = np.random.default_rng(21)
+        x = bf16(rng.standard_normal((1, 8, 8, 8, 3)))
+        t = rng.standard_normal((1, 8, 8, 8)).astype(np.float32)
+        loss = n.train_step(dev(x), dev(t))
+        yo, c = N.forward(p, x[0])
+        lo, dyo = N.mse(yo, t[0][..., None].astype(np.float64))
+        assert abs(loss - lo) <= 2 * TOL_FWD * lo
+        go = flat(N.backward(p, c, dyo))
+        step = n.get_params().astype(np.float64) - w0.astype(np.float32).astype(np.float64)
+        big = np.abs(go) > 0.2 * np.abs(go).max()
+        assert big.sum() > 20
+        assert np.allclose(step[big], -lr * np.sign(go[big]), rtol=1e-3, atol=1e-7)
+    finally:
+        n.close()
+
+
+def test_training_lowers_loss():
+    n = les.Net(seed=4, lr=3e-3)
+    try:
+        rng = np.random.default_rng(8)
+        x = dev(rng.standard_normal((2, 8, 8, 8, 3)))
+        t = dev(np.tanh(rng.standard_normal((2, 8, 8, 8))))
+        losses = [n.train_step(x, t) for _ in range(30)]
+        print(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+        assert losses[-1] < 0.5 * losses[0]
+    finally:
+        n.close()
+
+
+def test_bad_arguments(net):
+    L = les.lib()
+    x = torch.zeros((1, 6, 8, 8, 3), device="cuda")
+    y = torch.zeros((1, 6, 8, 8), device="cuda")
+    # D not a multiple of 4
+    assert L.lesnet_forward(net.h, 1, 6, 8, 8, x.data_ptr(), y.data_ptr(), None) == les.LES_EINVAL
+    assert L.lesnet_forward(net.h, 0, 8, 8, 8, x.data_ptr(), y.data_ptr(), None) == les.LES_EINVAL
+    w = np.zeros(net.num_params - 1, np.float32)
+    assert L.lesnet_set_params(net.h, w.ctypes.data, w.size) == les.LES_EINVAL
+    cfg = les.NetConfig()
+    L.lesnet_default_config(cfg)
+    cfg.c1 = 24
+    import ctypes as C
+    h = C.c_void_p()
+    assert L.lesnet_create(cfg, C.byref(h)) == les.LES_EINVAL and not h.value

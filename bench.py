@@ -65,6 +65,123 @@ def cpu_baseline(w, mask, prof, gpu_iters_per_step, sample_iters):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak, vendor figure
+
+
+def net_flops(D, H, W, c=(16, 32, 64), cin=3):
+    """Algorithmic FLOPs (multiply-add = 2) of one forward pass and one
+    backward pass (input and weight gradients) of the warm-start U-Net on
+    a D x H x W grid, with the unpadded channel counts."""
+    c1, c2, c3 = c
+    m1, m2, m3 = D * H * W, D * H * W // 8, D * H * W // 64
+    convs = [(m1, cin, c1), (m1, c1, c1), (m2, c1, c2), (m2, c2, c2), (m3, c2, c3), (m3, c3, c3),
+             (m2, 2 * c2, c2), (m2, c2, c2), (m1, 2 * c1, c1), (m1, c1, c1)]
+    ups = [(m3, c3, c2), (m2, c2, c1)]
+    fwd = sum(2 * 27 * ci * co * m for m, ci, co in convs) + sum(2 * 8 * ci * co * m for m, ci, co in ups)
+    fwd += 2 * c1 * m1
+    # backward: weight gradients for every layer, input gradients for all but the first
+    bwd = 2 * fwd - 2 * 27 * cin * c1 * m1
+    return fwd, bwd
+
+
+def bench_net(les, torch, D=64, H=128, W=128, reps=10):
+    """Forward and training-step time of the warm-start network on one
+    D x H x W crop (HIP events on torch's stream, which the network's
+    kernels run on), against the dense BF16 matrix peak."""
+    net = les.Net(seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((1, D, H, W, 3), device="cuda", generator=g)
+    t = torch.randn((1, D, H, W), device="cuda", generator=g)
+    for _ in range(2):
+        net.forward(x)
+        net.train_step(x, t, want_loss=False)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(reps):
+        net.forward(x)
+    e1.record()
+    for _ in range(reps):
+        net.train_step(x, t, want_loss=False)
+    e2.record()
+    torch.cuda.synchronize()
+    f_ms = e0.elapsed_time(e1) / reps
+    t_ms = e1.elapsed_time(e2) / reps
+    fwd, bwd = net_flops(D, H, W)
+    nparams = net.num_params
+    net.close()
+    f_tf = fwd / (f_ms * 1e-3) / 1e12
+    t_tf = (fwd + bwd) / (t_ms * 1e-3) / 1e12
+    return {
+        "grid": [D, H, W],
+        "voxels": D * H * W,
+        "params": int(nparams),
+        "forward_ms": f_ms,
+        "train_step_ms": t_ms,
+        "forward_gflop": fwd / 1e9,
+        "train_step_gflop": (fwd + bwd) / 1e9,
+        "roofline": {"bound": "mfma", "achieved": f_tf, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": f_tf / MFMA_BF16_PEAK_TFLOPS, "scope": "whole forward pass"},
+        "train_step_tflops": t_tf,
+        "train_step_frac": t_tf / MFMA_BF16_PEAK_TFLOPS,
+    }
+
+
+def bench_warm_start(args, les, torch):
+    """Plain SOR from p_prev against the learned start on held-out C1
+    cases (train on seeds 11-14, evaluate on 21-22); network inference is
+    inside the timed steps."""
+    import numpy as np
+    from paper_1504_02264_amd import warmstart as ws
+    smooth = 16
+    Xs, Ts = [], []
+    for seed in (11, 12, 13, 14):
+        X, T, _ = ws.collect("C1", seed, steps=20, skip=2, smooth=smooth)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    net = les.Net(seed=0, lr=1e-3)
+    t0 = time.perf_counter()
+    scale, losses = ws.train(net, X, T, iters=4000, batch=8, lr=1e-3, lr_final=5e-5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, T
+    rows = []
+    for seed in (21, 22):
+        b = ws.evaluate("C1", seed, steps=args.steps, net=None, skip=2)
+        rows.append(("plain", seed, b))
+        for name, rule, param in (("residual rule", les.WARM_RESIDUAL, 0), ("trial rule 64", les.WARM_TRIAL, 64),
+                                  ("always", les.WARM_ALWAYS, 0)):
+            w = ws.evaluate("C1", seed, steps=args.steps, net=net, scale=scale, skip=2, rule=rule, param=param,
+                            smooth=smooth)
+            rows.append((name, seed, w))
+    res = {}
+    for name, seed, r in rows:
+        d = res.setdefault(name, {"iters": [], "ms": [], "taken": 0})
+        d["iters"].append(float(r["iters"].mean()))
+        d["ms"].append(r["ms_per_step"])
+        d["taken"] += int(r.get("taken", 0))
+    base_ms = float(np.mean(res["plain"]["ms"]))
+    out = {
+        "metric": "time to relative residual 1e-5 per step (learned start)",
+        "value": float(np.mean(res["always"]["ms"])),
+        "unit": "ms/step",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "dtype": "f32 LES, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": "C1 64x64x32 urban LES; network trained on building seeds 11-14 "
+                               "(80 captured pairs, 4000 Adam steps), evaluated on seeds 21-22",
+                   "train_s": train_s, "final_loss": losses[-1][1], "smooth_passes": smooth},
+        "rules": {k: {"sor_iters_per_step": float(np.mean(v["iters"])), "ms_per_step": float(np.mean(v["ms"])),
+                      "steps_from_network": v["taken"], "ms_vs_plain": float(np.mean(v["ms"])) / base_ms}
+                  for k, v in res.items()},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_ensemble(args, les, torch):
     """Aggregate cell-updates/s of an uneven ensemble in one persistent solve per step."""
     from les_inputs import ensemble_members, make_workload_inputs
@@ -133,6 +250,10 @@ def main():
                     help="instead: an ensemble of N uneven members (sizes 96-256 x 96-256 x "
                          "64-90, seeds 1000+i) advanced together; aggregate cell-updates/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-net", action="store_true",
+                    help="skip the warm-start network timing (forward / train step on a 64x128x128 crop)")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="instead of the LES line: plain SOR vs the learned start on held-out C1 cases")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events (no roofline object)")
@@ -154,6 +275,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.warm_start:
+        return bench_warm_start(args, les, torch)
     if args.ensemble:
         return bench_ensemble(args, les, torch)
     w = WORKLOADS[args.workload]
@@ -246,6 +369,9 @@ def main():
         out["time_to_resid_1e-5_ms"] = (out["kernel_ms_per_step"]["sor"]
                                          + out["kernel_ms_per_step"].get("check", 0.0)
                                          + out["kernel_ms_per_step"].get("rebase", 0.0))
+    if not args.no_net:
+        log("warm-start network: forward and train step on a 64x128x128 crop")
+        out["warm_start_net"] = bench_net(les, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(w, mask, prof, float(iters.mean()), args.cpu_sample_iters)

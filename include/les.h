@@ -108,8 +108,8 @@ typedef struct {
     /* learned warm start (lesnet.h, les_set_warm_start); -1 when off */
     int32_t warm_taken;      /* steps of the call whose solve started from the network */
     int32_t pad2_;
-    double warm_r_prev_last; /* relative residual of p_prev at the last step (after the
-                                trial iterations under the trial rule) */
+    double warm_r_prev_last; /* norm the rule compared for p_prev at the last step, over
+                                ||rhs|| (residual; after the trial iterations; smoothed) */
     double warm_r_net_last;  /* the same for the network's start */
 } les_step_stats;
 

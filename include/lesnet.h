@@ -86,6 +86,40 @@ int lesnet_gradients(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, cons
  * asking for it synchronises the stream. */
 int lesnet_train_step(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,
                       const float* d_t, double* loss, void* stream);
+/* Adam step size of the following train steps (a schedule); LES_EINVAL
+ * unless positive and finite. */
+int lesnet_set_lr(lesnet* n, double lr);
+
+/*
+ * One layer operation on the matrix cores, on its own (no handle): the
+ * float32 operands are rounded to bfloat16 on the device, products are
+ * accumulated in float32 and the result is returned in float32, so a
+ * caller can check each kernel of the network in isolation.  Grids as for
+ * the network (B, D, H, W; channels last); for the up operations (B, D, H,
+ * W) is the coarse grid and the fine grid is twice it per axis.
+ *   LESNET_OP_CONV3        a = x [B][D][H][W][cin], b = W [27][cin][cout],
+ *                          c = bias [cout] or NULL; out = y [..][cout] (no ReLU)
+ *   LESNET_OP_CONV3_DGRAD  a = dy [..][cout], b = W; out = dx [..][cin]
+ *   LESNET_OP_CONV3_WGRAD  a = x [..][cin], b = dy [..][cout]; out = dW [27][cin][cout]
+ *   LESNET_OP_UP           a = x coarse [..][cin], b = U [8][cin][cout], c = bias
+ *                          or NULL; out = y fine [B][2D][2H][2W][cout]
+ *   LESNET_OP_UP_DGRAD     a = dy fine [..][cout], b = U; out = dx coarse [..][cin]
+ *   LESNET_OP_UP_WGRAD     a = x coarse, b = dy fine; out = dU [8][cin][cout]
+ * cout in {16, 32, 64}; cin in {16, 32, 64}, or 1..8 for the forward and
+ * weight-gradient operations.  Device pointers; allocates its own
+ * workspace and synchronises `stream` before returning.  LES_EINVAL for
+ * other sizes or NULL operands, LES_ENOMEM, LES_EDEVICE.
+ */
+enum {
+    LESNET_OP_CONV3 = 0,
+    LESNET_OP_CONV3_DGRAD = 1,
+    LESNET_OP_CONV3_WGRAD = 2,
+    LESNET_OP_UP = 3,
+    LESNET_OP_UP_DGRAD = 4,
+    LESNET_OP_UP_WGRAD = 5
+};
+int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t cin, int32_t cout,
+              const float* d_a, const float* d_b, const float* d_c, float* d_out, void* stream);
 
 /*
  * Coupling to an LES handle.  The network grid of a handle is (D, H, W) =
@@ -101,27 +135,41 @@ int lesnet_train_step(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, con
  * converged pressure.
  */
 int les_warm_grid(const les_handle* h, int32_t* D, int32_t* H, int32_t* W);
-/* Use n (NULL: switch off) in every following les_step.  After the
- * right-hand side is built the network proposes p0 and SOR starts from
- * p0 or from p_prev, chosen by trial_iters:
- *   0   residual rule: the float64 residual norms of the two starts are
- *       compared on the device; p0 only if strictly smaller
- *   > 0 trial rule: SOR runs trial_iters iterations (rounded up to whole
- *       check intervals) from each start in a scratch copy and the start
- *       whose residual is then strictly smaller is taken; the trial
- *       iterations are extra work, not counted in sor_iters
- *   -1  always p0 (for measurements)
- * Either way the solve itself runs to the handle's tolerance, and when
- * p_prev is kept the step is bit for bit the plain one.  The handle
- * borrows n; keep it alive while set.  les_step_stats reports the choice
- * and the two residuals compared.  LES_EINVAL for target_scale not
- * positive and finite or trial_iters < -1. */
-int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t trial_iters);
+/* Choice between the two starts (les_set_warm_start).  Whichever start is
+ * taken, the solve itself runs to the handle's tolerance, and when p_prev
+ * is kept the step is bit for bit the plain one. */
+enum {
+    LES_WARM_RESIDUAL = 0,   /* p0 if its float64 residual norm is strictly smaller */
+    LES_WARM_TRIAL = 1,      /* SOR runs `param` iterations (whole check intervals)
+                                from each start in a scratch copy; p0 if its residual
+                                is then strictly smaller.  The trial iterations are
+                                extra work, not counted in sor_iters */
+    LES_WARM_SMOOTH = 2,     /* both residuals are smoothed by `param` passes (rounded
+                                up to even) of the 7-point mean over the cells, p0
+                                if the smoothed norm is strictly smaller: the rule
+                                weighs the smooth error that SOR removes slowly */
+    LES_WARM_ALWAYS = 3      /* always p0 (for measurements) */
+};
+/* Use n (NULL: switch off) in every following les_step: after the
+ * right-hand side is built the network proposes p0 and `rule` picks the
+ * start; param is the trial iterations or smoothing passes (1..100000,
+ * unused by the other rules).  `smooth` passes of the 7-point mean over
+ * the cells (0..100000) are applied to the network's output before it
+ * forms p0: a network trained on targets captured with the same
+ * smoothing proposes only the smooth part of the change, the part SOR is
+ * slow to find.  All rules but LES_WARM_TRIAL decide on the device
+ * without a host round trip.  The handle borrows n; keep it alive while
+ * set.  les_step_stats reports the choice and the two norms compared
+ * (relative to ||rhs||).  LES_EINVAL for target_scale not positive and
+ * finite, an unknown rule, param or smooth out of range. */
+int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t rule, int32_t param,
+                       int32_t smooth);
 /* Training-pair capture (NULL, NULL: off): every following les_step writes
  * the network input of the step to d_x [D][H][W][3] and, after the solve,
  * its training target to d_t [D][H][W] (device buffers owned by the
- * caller, overwritten by each step). */
-int les_set_capture(les_handle* h, float* d_x, float* d_t);
+ * caller, overwritten by each step), the target smoothed by `smooth`
+ * passes (rounded up to even) of the mean described above. */
+int les_set_capture(les_handle* h, float* d_x, float* d_t, int32_t smooth);
 
 #ifdef __cplusplus
 }

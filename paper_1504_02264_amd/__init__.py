@@ -36,7 +36,7 @@ EXPORTS = (
     # include/lesnet.h
     "lesnet_default_config", "lesnet_create", "lesnet_destroy", "lesnet_last_error",
     "lesnet_num_params", "lesnet_get_params", "lesnet_set_params", "lesnet_get_grads",
-    "lesnet_forward", "lesnet_gradients", "lesnet_train_step", "les_warm_grid",
+    "lesnet_forward", "lesnet_gradients", "lesnet_train_step", "lesnet_set_lr", "lesnet_op", "les_warm_grid",
     "les_set_warm_start", "les_set_capture",
 )
 ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
@@ -183,9 +183,11 @@ def lib():
     L.lesnet_forward.argtypes = [P, I, I, I, I, P, P, P]
     L.lesnet_gradients.argtypes = [P, I, I, I, I, P, P, P]
     L.lesnet_train_step.argtypes = [P, I, I, I, I, P, P, C.POINTER(C.c_double), P]
+    L.lesnet_set_lr.argtypes = [P, C.c_double]
+    L.lesnet_op.argtypes = [I, I, I, I, I, I, I, P, P, P, P, P]
     L.les_warm_grid.argtypes = [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
-    L.les_set_warm_start.argtypes = [P, P, C.c_double, C.c_int32]
-    L.les_set_capture.argtypes = [P, P, P]
+    L.les_set_warm_start.argtypes = [P, P, C.c_double, C.c_int32, C.c_int32, C.c_int32]
+    L.les_set_capture.argtypes = [P, P, P, C.c_int32]
     _lib = L
     return L
 
@@ -436,6 +438,9 @@ class Net:
                                            C.c_void_p(dy.data_ptr()), self._stream()))
         return self.get_grads()
 
+    def set_lr(self, lr):
+        self._check(lib().lesnet_set_lr(self.h, float(lr)))
+
     def train_step(self, x, t, want_loss=True):
         B, D, H, W = self._dims(x)
         loss = C.c_double(float("nan"))
@@ -445,23 +450,63 @@ class Net:
         return loss.value
 
 
+NET_OPS = {"conv3": 0, "conv3_dgrad": 1, "conv3_wgrad": 2, "up": 3, "up_dgrad": 4, "up_wgrad": 5}
+
+
+def net_op(op: str, a, b, c=None, cin=None, cout=None):
+    """One layer operation (``lesnet_op``) on torch device tensors; returns
+    the float32 result as a torch tensor."""
+    import torch
+
+    code = NET_OPS[op]
+    up = op.startswith("up")
+    if op in ("conv3", "up"):
+        B, D, H, W, cin = a.shape
+        cout = b.shape[2]
+        f = 2 if up else 1
+        out = torch.empty((B, f * D, f * H, f * W, cout), device=a.device)
+    elif op.endswith("dgrad"):
+        B, D, H, W, cout = a.shape
+        cin = b.shape[1]
+        if up:
+            D, H, W = D // 2, H // 2, W // 2
+        out = torch.empty((B, D, H, W, cin), device=a.device)
+    else:
+        B, D, H, W, cin = a.shape
+        cout = b.shape[4]
+        out = torch.empty((8 if up else 27, cin, cout), device=a.device)
+    ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+    rc = lib().lesnet_op(code, B, D, H, W, cin, cout, ptr(a), ptr(b), ptr(c), ptr(out),
+                         C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != LES_OK:
+        raise LesError(rc, f"lesnet_op({op})")
+    return out
+
+
 def warm_grid(les: "LES"):
     D, H, W = C.c_int32(), C.c_int32(), C.c_int32()
     les._check(lib().les_warm_grid(les.h, C.byref(D), C.byref(H), C.byref(W)))
     return D.value, H.value, W.value
 
 
-def set_warm_start(les: "LES", net: Optional[Net], target_scale: float = 1.0, trial_iters: int = 0):
-    """trial_iters: 0 residual rule, > 0 trial rule, -1 always the network."""
+WARM_RESIDUAL, WARM_TRIAL, WARM_SMOOTH, WARM_ALWAYS = 0, 1, 2, 3
+
+
+def set_warm_start(les: "LES", net: Optional[Net], target_scale: float = 1.0,
+                   rule: int = WARM_RESIDUAL, param: int = 0, smooth: int = 0):
+    """Warm-start the handle's solves with `net` (None: off); `rule`,
+    `param` and `smooth` as in les_set_warm_start (lesnet.h)."""
     les._check(lib().les_set_warm_start(les.h, net.h if net is not None else None,
-                                        float(target_scale), int(trial_iters)))
+                                        float(target_scale), int(rule), int(param), int(smooth)))
 
 
-def set_capture(les: "LES", d_x=None, d_t=None):
+def set_capture(les: "LES", d_x=None, d_t=None, smooth: int = 0):
     """Capture each step's network input / training target into the torch
-    tensors d_x [D, H, W, 3] and d_t [D, H, W] (None, None: off)."""
+    tensors d_x [D, H, W, 3] and d_t [D, H, W] (None, None: off), the
+    target smoothed by `smooth` passes."""
     les._check(lib().les_set_capture(les.h, C.c_void_p(d_x.data_ptr()) if d_x is not None else None,
-                                     C.c_void_p(d_t.data_ptr()) if d_t is not None else None))
+                                     C.c_void_p(d_t.data_ptr()) if d_t is not None else None,
+                                     int(smooth)))
 
 
 def bc_range(nx: int, ny: int, nz: int) -> int:

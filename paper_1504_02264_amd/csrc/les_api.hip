@@ -370,18 +370,17 @@ int trial_resid(les_handle* h, const PBufs& start, int iters, double* resid) {
     return LES_OK;
 }
 
-// Trial and forced modes of the warm start: choose between the previous
-// pressure and the network's candidate on the host.
+// Trial rule of the warm start: choose between the previous pressure and
+// the network's candidate on the host.
 int warm_choose(les_handle* h) {
-    if (!h->warm_net || h->warm_trial == 0) return LES_OK;
-    if (h->warm_trial < 0) return warm_take(h, 1, -1.0, -1.0);
+    if (!h->warm_net || h->warm_rule != LES_WARM_TRIAL) return LES_OK;
     int rc = ensure_solve_arena(h);
     if (rc != LES_OK) return rc;
     hipStream_t s = h->stream;
     CK(hipMemcpyAsync(h->ctl_save, h->f.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, s));
     double ra = 0.0, rb = 0.0;
-    if ((rc = trial_resid(h, h->f.P, h->warm_trial, &ra)) != LES_OK) return rc;
-    if ((rc = trial_resid(h, warm_candidate(h), h->warm_trial, &rb)) != LES_OK) return rc;
+    if ((rc = trial_resid(h, h->f.P, h->warm_param, &ra)) != LES_OK) return rc;
+    if ((rc = trial_resid(h, warm_candidate(h), h->warm_param, &rb)) != LES_OK) return rc;
     CK(hipMemcpyAsync(h->f.ctl, h->ctl_save, sizeof(Ctl), hipMemcpyDeviceToDevice, s));
     return warm_take(h, rb < ra ? 1 : 0, ra, rb);
 }

@@ -151,7 +151,10 @@ struct les_handle {
     // learned warm start and training-pair capture (warm.hip)
     lesnet* warm_net = nullptr;
     double warm_scale = 1.0;
-    int warm_trial = 0;          // 0 residual rule, > 0 trial iterations, -1 always take
+    int warm_rule = 0;           // LES_WARM_* (lesnet.h)
+    int warm_param = 0;          // trial iterations / smoothing passes of the rule
+    int warm_smooth = 0;         // smoothing passes on the network's output
+    int cap_smooth = 0;          // smoothing passes on captured targets
     float* cap_x = nullptr;
     float* cap_t = nullptr;
     void* warm_arena = nullptr;

@@ -112,7 +112,8 @@ __global__ __launch_bounds__(kNetBlock) void k_gemm(GemmArgs a) {
                 dst = vox_id(ob, 2 * oz + (slice >> 2), 2 * oy + ((slice >> 1) & 1), 2 * ox + (slice & 1),
                              2 * a.D, 2 * a.H, 2 * a.W);
             }
-            a.out[dst * a.out_cs + a.out_coff + ch] = (bf16)val;
+            if (a.out_f32) a.out_f32[dst * a.out_cs + a.out_coff + ch] = val;
+            else a.out[dst * a.out_cs + a.out_coff + ch] = (bf16)val;
         }
     }
 }
@@ -419,6 +420,21 @@ __global__ void k_pack_input(const float* x, long long M, bf16* out) {
     const int c = (int)(e & 7);
     const long long v = e >> 3;
     out[e] = (bf16)(c < 3 ? x[v * 3 + c] : 0.f);
+}
+
+// float [v][c] -> bf16 [v][cp] (channels c..cp-1 zero)
+__global__ void k_to_bf16(const float* x, long long M, int c, int cp, bf16* out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * cp) return;
+    const int q = (int)(e % cp);
+    const long long v = e / cp;
+    out[e] = (bf16)(q < c ? x[v * c + q] : 0.f);
+}
+
+// bf16-round a float array in place of a copy (weights of single ops)
+__global__ void k_round_bf16(const float* x, long long n, float* out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = (float)(bf16)x[e];
 }
 
 inline unsigned nb(long long n, int b = kNetBlock) { return (unsigned)((n + b - 1) / b); }
@@ -972,6 +988,103 @@ int lesnet_gradients(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, cons
     if ((rc = forward(n, s, B, D, H, W)) != LES_OK) return rc;
     NCK(hipMemcpyAsync(n->a.dy, d_dy, (size_t)V1 * 4, hipMemcpyDeviceToDevice, s));
     return backward(n, s, B, D, H, W);
+}
+
+// One layer operation on its own (see lesnet.h).  Allocates its own
+// workspace and synchronises the stream before returning.
+int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t cin, int32_t cout,
+              const float* d_a, const float* d_b, const float* d_c, float* d_out, void* stream) {
+    lesnet* n = nullptr;   // NCK needs the name; errors carry no handle here
+    const bool up = op == LESNET_OP_UP || op == LESNET_OP_UP_DGRAD || op == LESNET_OP_UP_WGRAD;
+    if (op < LESNET_OP_CONV3 || op > LESNET_OP_UP_WGRAD || !d_a || !d_b || !d_out) return LES_EINVAL;
+    if (B < 1 || D < 1 || H < 1 || W < 1 || (long long)B * D * H * W * 8 >= (1LL << 31)) return LES_EINVAL;
+    auto t16 = [](int c) { return c == 16 || c == 32 || c == 64; };
+    if (!t16(cout)) return LES_EINVAL;
+    const bool dgrad = op == LESNET_OP_CONV3_DGRAD || op == LESNET_OP_UP_DGRAD;
+    const bool wgrad = op == LESNET_OP_CONV3_WGRAD || op == LESNET_OP_UP_WGRAD;
+    if (dgrad ? !t16(cin) : !(t16(cin) || (cin >= 1 && cin <= 8))) return LES_EINVAL;
+    if (wgrad && !d_b) return LES_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int taps = up ? 8 : 27;
+    const long long M = (long long)B * D * H * W;          // GEMM grid (coarse grid for up)
+    const long long Mf = up ? M * 8 : M;                    // output grid of the layer
+    const int cin_p = cin <= 8 ? 8 : cin;
+    // workspace: bf16 copies of the activations, weight layouts, partials
+    const long long na = (dgrad ? Mf * cout : M * cin_p), nbw = Mf * cout;
+    const int kp_f = up ? rup(cin, 32) : rup(27 * cin_p, 32), kp_d = rup(taps * cout, 32);
+    const long long nlay = (long long)(up ? 8 : 1) * cout * kp_f + (long long)cin * kp_d;
+    long long chunk = std::max<long long>(4 * 32 * 4, (M + 255) / 256);
+    chunk = (chunk + 127) / 128 * 128;
+    const int chunks = (int)((M + chunk - 1) / chunk);
+    const int cin_t = rup(cin, 16);
+    const long long npart = (long long)chunks * taps * cin_t * cout;
+    const size_t bytes = ((size_t)na * 2 + 255) / 256 * 256 + ((size_t)nbw * 2 + 255) / 256 * 256 +
+                         ((size_t)nlay * 2 + 255) / 256 * 256 + (size_t)npart * 4 + 256;
+    void* ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) return LES_ENOMEM;
+    char* c = (char*)ws;
+    bf16* abuf = (bf16*)c;
+    c += ((size_t)na * 2 + 255) / 256 * 256;
+    bf16* bbuf = (bf16*)c;
+    c += ((size_t)nbw * 2 + 255) / 256 * 256;
+    bf16* lay = (bf16*)c;
+    c += ((size_t)nlay * 2 + 255) / 256 * 256;
+    float* part = (float*)c;
+    hipError_t e = hipSuccess;
+    GemmArgs g{};
+    g.B = B; g.D = D; g.H = H; g.W = W;
+    if (op == LESNET_OP_CONV3 || op == LESNET_OP_UP) {
+        hipLaunchKernelGGL(k_to_bf16, dim3(nb(M * cin_p)), dim3(kNetBlock), 0, s, d_a, M, cin, cin_p, abuf);
+        hipLaunchKernelGGL(k_layout_fwd, dim3(nb((long long)(up ? 8 : 1) * cout * kp_f)), dim3(kNetBlock), 0, s,
+                           d_b, taps, cin, cout, cin_p, kp_f, up ? 1 : 0, lay);
+        g.in = abuf; g.in_cs = cin_p;
+        g.cin_p = up ? cin_p : cin_p;
+        g.cin_shift = log2i(g.cin_p);
+        g.wt = lay; g.kp = kp_f; g.bias = d_c;
+        g.out_f32 = d_out; g.out_cs = cout; g.cout = cout;
+        g.gather = up ? G_TAP1 : G_TAP27;
+        g.scatter_child = up ? 1 : 0;
+        e = gemm(s, g);
+    } else if (dgrad) {
+        hipLaunchKernelGGL(k_to_bf16, dim3(nb(Mf * cout)), dim3(kNetBlock), 0, s, d_a, Mf, cout, cout, abuf);
+        hipLaunchKernelGGL(k_layout_dgrad, dim3(nb((long long)cin * kp_d)), dim3(kNetBlock), 0, s, d_b, taps, cin,
+                           cout, kp_d, up ? 1 : 0, lay);
+        g.in = abuf; g.in_cs = cout; g.cin_p = cout; g.cin_shift = log2i(cout);
+        g.wt = lay; g.kp = kp_d;
+        g.out_f32 = d_out; g.out_cs = cin; g.cout = cin;
+        g.gather = up ? G_CHILD8 : G_TAP27;
+        e = gemm(s, g);
+    } else {
+        hipLaunchKernelGGL(k_to_bf16, dim3(nb(M * cin_p)), dim3(kNetBlock), 0, s, d_a, M, cin, cin_p, abuf);
+        hipLaunchKernelGGL(k_to_bf16, dim3(nb(Mf * cout)), dim3(kNetBlock), 0, s, d_b, Mf, cout, cout, bbuf);
+        WgradArgs w{};
+        w.in = abuf; w.in_cs = cin_p; w.cin = cin;
+        w.dout = bbuf; w.dout_cs = cout; w.cout = cout;
+        w.up = up ? 1 : 0;
+        w.B = B; w.D = D; w.H = H; w.W = W;
+        w.chunk = chunk; w.part = part;
+        const dim3 grid(chunks, taps);
+        const int MT = cin_t / 16, NT = cout / 16;
+#define WG(mt, nt) \
+    if (MT == mt && NT == nt) hipLaunchKernelGGL((k_wgrad<mt, nt>), grid, dim3(kNetBlock), 0, s, w)
+        WG(1, 1); else WG(1, 2); else WG(1, 4); else WG(2, 1); else WG(2, 2); else WG(2, 4);
+        else WG(4, 1); else WG(4, 2); else WG(4, 4);
+#undef WG
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout)), dim3(kNetBlock), 0, s, part,
+                           chunks, taps, cin, cin_t, cout, d_out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    (void)n;
+    return e == hipSuccess ? LES_OK : LES_EDEVICE;
+}
+
+int lesnet_set_lr(lesnet* n, double lr) {
+    if (!n || !(std::isfinite(lr) && lr > 0.0)) return LES_EINVAL;
+    n->lr = lr;
+    return LES_OK;
 }
 
 int lesnet_train_step(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, const float* d_x,

@@ -37,6 +37,7 @@ struct GemmArgs {
     const bf16* wt; int kp;                                // [slices][cout][kp]
     const float* bias;
     bf16* out; int out_cs; int out_coff;
+    float* out_f32;       // non-null: float32 output here instead of out (same indexing)
     int cout;
     int relu;
     int gather;

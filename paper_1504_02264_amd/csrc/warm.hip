@@ -28,6 +28,8 @@ struct WarmCtl {
     double r2_net;    // sum (rhs - A p0)^2 (-1: no candidate this step)
     int taken;        // 1: the solve started from p0
     int pad_;
+    double s2_prev;   // smoothed-residual rule: sum of the smoothed r^2 of each start
+    double s2_net;
 };
 
 struct WarmPair {   // candidate start, colour layout, ghosts zero
@@ -39,6 +41,8 @@ struct WarmView {
     int D = 0, H = 0, W = 0;     // network grid
     float* tr = nullptr;         // r on the network grid
     float* tp = nullptr;         // p_prev on the network grid
+    float* tn = nullptr;         // residual of the candidate (smoothed-residual rule)
+    float* ts = nullptr;         // smoothing scratch
     WarmPair cand{};             // candidate p0
     double* part = nullptr;      // 2 * kRedBlocks partials
     WarmCtl* ctl = nullptr;
@@ -121,9 +125,14 @@ __global__ __launch_bounds__(kBlock) void k_w_fin(const double* part, int n, War
             wc->r2_prev = a;
             wc->p2 = b;
             wc->r2_net = -1.0;
+            wc->s2_prev = -1.0;
+            wc->s2_net = -1.0;
             wc->taken = 0;
-        } else {
+        } else if (which == 1) {
             wc->r2_net = a;
+        } else {
+            wc->s2_prev = a;
+            wc->s2_net = b;
         }
     }
 }
@@ -184,8 +193,9 @@ __global__ __launch_bounds__(kBlock) void k_w_cand(Geo g, PBufs P, int H, int W,
 }
 
 // Step 4b: partials of sum (rhs - A p0)^2 (second slot unused), formed as
-// for the previous pressure.
-__global__ __launch_bounds__(kBlock) void k_w_resid_cand(Geo g, PBufs P, WarmPair C, double* part) {
+// for the previous pressure; the residual itself to tn if given.
+__global__ __launch_bounds__(kBlock) void k_w_resid_cand(Geo g, PBufs P, WarmPair C, int H, int W, float* tn,
+                                                         double* part) {
     const unsigned lb = blockIdx.x, nb = gridDim.x;
     long long t0, t1;
     red_chunk(g, lb, nb, t0, t1);
@@ -202,6 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_w_resid_cand(Geo g, PBufs P, WarmPai
                 const double d = (double)diag_of(g, i0, j0, k0);
                 const double r = (double)P.rhs[c][e] - apply_A64(g, C.h[c], C.h[1 - c], e, s, d) -
                                  apply_A64(g, C.d[c], C.d[1 - c], e, s, d);
+                if (tn) tn[net_vox(g, W, H, i0, j0, k0)] = (float)r;
                 ar += r * r;
             }
         }
@@ -213,10 +224,59 @@ __global__ __launch_bounds__(kBlock) void k_w_resid_cand(Geo g, PBufs P, WarmPai
     }
 }
 
+// One pass of the 7-point mean over the cells: each cell becomes the mean
+// of itself and its neighbours inside the domain (constants are kept).
+// Repeated passes keep the smooth part of a field, the part SOR removes
+// slowly: used on residuals (smoothed-residual rule), on the network's
+// output and on captured targets.
+__global__ __launch_bounds__(kBlock) void k_w_smooth(Geo g, int H, int W, const float* in, float* out) {
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long long)g.nx * g.ny * g.nz) return;
+    const int x = (int)(t % g.nx);
+    const int y = (int)((t / g.nx) % g.ny);
+    const int z = (int)(t / ((long long)g.nx * g.ny));
+    const long long v = ((long long)z * H + y) * W + x;
+    const long long sy = W, sz = (long long)W * H;
+    float a = in[v];
+    int n = 1;
+    if (x > 0) a += in[v - 1], ++n;
+    if (x < g.nx - 1) a += in[v + 1], ++n;
+    if (y > 0) a += in[v - sy], ++n;
+    if (y < g.ny - 1) a += in[v + sy], ++n;
+    if (z > 0) a += in[v - sz], ++n;
+    if (z < g.nz - 1) a += in[v + sz], ++n;
+    out[v] = a / (float)n;
+}
+
+// Partials [2 lb] = sum a^2, [2 lb + 1] = sum b^2 over the cells.
+__global__ __launch_bounds__(kBlock) void k_w_sumsq2(Geo g, int H, int W, const float* a, const float* b,
+                                                     double* part) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long per = (n + gridDim.x - 1) / gridDim.x;
+    const long long t0 = (long long)blockIdx.x * per, t1 = t0 + per < n ? t0 + per : n;
+    double sa = 0.0, sb = 0.0;
+    for (long long t = t0 + threadIdx.x; t < t1; t += kBlock) {
+        const int x = (int)(t % g.nx);
+        const int y = (int)((t / g.nx) % g.ny);
+        const int z = (int)(t / ((long long)g.nx * g.ny));
+        const long long v = ((long long)z * H + y) * W + x;
+        sa += (double)a[v] * (double)a[v];
+        sb += (double)b[v] * (double)b[v];
+    }
+    sa = block_sum(sa);
+    sb = block_sum(sb);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa;
+        part[2 * blockIdx.x + 1] = sb;
+    }
+}
+
 // Step 5: take p0 if its residual is strictly smaller (every element of
 // the colour arrays, ghosts included: both are zero there).
-__global__ __launch_bounds__(kBlock) void k_w_select(long long n, PBufs P, WarmPair C, WarmCtl* wc, int force) {
-    const bool take = force || (wc->r2_net >= 0.0 && wc->r2_net < wc->r2_prev);
+__global__ __launch_bounds__(kBlock) void k_w_select(long long n, PBufs P, WarmPair C, WarmCtl* wc, int rule) {
+    const bool take = rule == LES_WARM_ALWAYS ||
+                      (rule == LES_WARM_RESIDUAL && wc->r2_net >= 0.0 && wc->r2_net < wc->r2_prev) ||
+                      (rule == LES_WARM_SMOOTH && wc->s2_net >= 0.0 && wc->s2_net < wc->s2_prev);
     const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (e == 0) wc->taken = take ? 1 : 0;
     if (!take || e >= n) return;
@@ -262,7 +322,7 @@ int ensure_warm(les_handle* h) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t bv = al((size_t)V * 4), bc = al((size_t)g.ctot * 4), bp = al(2 * (size_t)kRedBlocks * 8),
                  bw = al(sizeof(WarmCtl));
-    const size_t total = 2 * bv + 4 * bc + bp + bw;
+    const size_t total = 4 * bv + 4 * bc + bp + bw;
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) {
@@ -279,6 +339,10 @@ int ensure_warm(les_handle* h) {
     w->tr = (float*)c;
     c += bv;
     w->tp = (float*)c;
+    c += bv;
+    w->tn = (float*)c;
+    c += bv;
+    w->ts = (float*)c;
     c += bv;
     for (int q = 0; q < 2; ++q) {
         w->cand.h[q] = (float*)c;
@@ -328,15 +392,35 @@ int warm_pre(les_handle* h) {
     if ((rc = net::ws_forward(h->warm_net, s, 1, w->D, w->H, w->W)) != LES_OK)
         return werr(h, rc, lesnet_last_error(h->warm_net));
     const double scale = h->warm_scale / dbar_of(g);
-    hipLaunchKernelGGL(k_w_cand, dim3(half_blocks(g)), dim3(kBlock), 0, s, g, h->f.P, w->H, w->W,
-                       net::ws_output(h->warm_net), w->ctl, ncell, scale, w->cand);
-    hipLaunchKernelGGL(k_w_resid_cand, dim3(rb), dim3(kBlock), 0, s, g, h->f.P, w->cand, w->part);
+    const unsigned cb = nblk((long long)g.nx * g.ny * g.nz);
+    const float* y = net::ws_output(h->warm_net);
+    for (int q = 0; q < h->warm_smooth; ++q) {   // smoothed output: y -> ts -> tn -> ts ...
+        float* dst = q % 2 ? w->tn : w->ts;
+        hipLaunchKernelGGL(k_w_smooth, dim3(cb), dim3(kBlock), 0, s, g, w->H, w->W, y, dst);
+        y = dst;
+    }
+    hipLaunchKernelGGL(k_w_cand, dim3(half_blocks(g)), dim3(kBlock), 0, s, g, h->f.P, w->H, w->W, y, w->ctl,
+                       ncell, scale, w->cand);
+    const int rule = h->warm_rule;
+    hipLaunchKernelGGL(k_w_resid_cand, dim3(rb), dim3(kBlock), 0, s, g, h->f.P, w->cand, w->H, w->W,
+                       rule == LES_WARM_SMOOTH ? w->tn : nullptr, w->part);
     hipLaunchKernelGGL(k_w_fin, dim3(1), dim3(kBlock), 0, s, w->part, (int)rb, w->ctl, 1);
-    // residual rule: decided on the device; trial and forced modes decide
-    // on the host (warm_take)
-    if (h->warm_trial == 0)
+    if (rule == LES_WARM_SMOOTH) {
+        // the same passes over both residuals, ping-ponging through ts
+        // (an even count leaves the result in tr / tn)
+        const int passes = 2 * ((h->warm_param + 1) / 2);
+        for (float* f : {w->tr, w->tn})
+            for (int q = 0; q < passes; ++q)
+                hipLaunchKernelGGL(k_w_smooth, dim3(cb), dim3(kBlock), 0, s, g, w->H, w->W, q % 2 ? w->ts : f,
+                                   q % 2 ? f : w->ts);
+        hipLaunchKernelGGL(k_w_sumsq2, dim3(rb), dim3(kBlock), 0, s, g, w->H, w->W, w->tr, w->tn, w->part);
+        hipLaunchKernelGGL(k_w_fin, dim3(1), dim3(kBlock), 0, s, w->part, (int)rb, w->ctl, 2);
+    }
+    // residual, smoothed-residual and always rules decide on the device,
+    // the trial rule on the host (warm_take)
+    if (rule != LES_WARM_TRIAL)
         hipLaunchKernelGGL(k_w_select, dim3(nblk(g.ctot)), dim3(kBlock), 0, s, (long long)g.ctot, h->f.P,
-                           w->cand, w->ctl, 0);
+                           w->cand, w->ctl, rule);
     WCK(hipGetLastError());
     w->candidate = true;
     return LES_OK;
@@ -355,7 +439,7 @@ int warm_take(les_handle* h, int take, double r_prev, double r_net) {
     WarmView* w = h->warm;
     if (take)
         hipLaunchKernelGGL(k_w_select, dim3(nblk(h->g.ctot)), dim3(kBlock), 0, h->stream, (long long)h->g.ctot,
-                           h->f.P, w->cand, w->ctl, 1);
+                           h->f.P, w->cand, w->ctl, (int)LES_WARM_ALWAYS);
     WCK(hipGetLastError());
     w->host_choice = true;
     w->taken = take;
@@ -371,6 +455,11 @@ int warm_post(les_handle* h) {
     const long long V = (long long)w->D * w->H * w->W;
     hipLaunchKernelGGL(k_w_target, dim3(nblk(V)), dim3(kBlock), 0, h->stream, g, h->f.P, w->D, w->H, w->W, w->tp,
                        w->ctl, (double)g.nx * g.ny * g.nz, dbar_of(g), h->cap_t);
+    // smoothed target (an even number of passes ends in cap_t)
+    const unsigned cb = nblk((long long)g.nx * g.ny * g.nz);
+    for (int q = 0; q < 2 * ((h->cap_smooth + 1) / 2); ++q)
+        hipLaunchKernelGGL(k_w_smooth, dim3(cb), dim3(kBlock), 0, h->stream, g, w->H, w->W,
+                           q % 2 ? w->ts : h->cap_t, q % 2 ? h->cap_t : w->ts);
     WCK(hipGetLastError());
     return LES_OK;
 }
@@ -394,9 +483,11 @@ int warm_result(les_handle* h, int* taken, double* r_prev, double* r_net) {
     WCK(hipStreamSynchronize(h->stream));
     const double rn = std::sqrt(h->h_ctl->rhs2);
     *taken = c.taken;
+    const bool sm = h->warm_rule == LES_WARM_SMOOTH;
+    const double a = sm ? c.s2_prev : c.r2_prev, b = sm ? c.s2_net : c.r2_net;
     if (rn > 0.0) {
-        *r_prev = std::sqrt(c.r2_prev) / rn;
-        *r_net = c.r2_net >= 0.0 ? std::sqrt(c.r2_net) / rn : -1.0;
+        *r_prev = a >= 0.0 ? std::sqrt(a) / rn : -1.0;
+        *r_net = b >= 0.0 ? std::sqrt(b) / rn : -1.0;
     }
     return LES_OK;
 }
@@ -423,24 +514,32 @@ int les_warm_grid(const les_handle* h, int32_t* D, int32_t* H, int32_t* W) {
     return LES_OK;
 }
 
-int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t trial_iters) {
+int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t rule, int32_t param,
+                       int32_t smooth) {
     if (!h) return LES_EINVAL;
+    if (smooth < 0 || smooth > 100000) return werr(h, LES_EINVAL, "smoothing passes");
     if (n && !(std::isfinite(target_scale) && target_scale > 0.0)) return werr(h, LES_EINVAL, "target_scale");
-    if (trial_iters < -1) return werr(h, LES_EINVAL, "trial_iters");
+    if (rule < LES_WARM_RESIDUAL || rule > LES_WARM_ALWAYS) return werr(h, LES_EINVAL, "warm-start rule");
+    if ((rule == LES_WARM_TRIAL || rule == LES_WARM_SMOOTH) && (param < 1 || param > 100000))
+        return werr(h, LES_EINVAL, "warm-start rule parameter");
     WCK(hipStreamSynchronize(h->stream));
     h->warm_net = n;
     h->warm_scale = n ? target_scale : 1.0;
-    h->warm_trial = n ? trial_iters : 0;
+    h->warm_rule = n ? rule : LES_WARM_RESIDUAL;
+    h->warm_param = param;
+    h->warm_smooth = smooth;
     if (h->warm) h->warm->candidate = false;
     return LES_OK;
 }
 
-int les_set_capture(les_handle* h, float* d_x, float* d_t) {
+int les_set_capture(les_handle* h, float* d_x, float* d_t, int32_t smooth) {
     if (!h) return LES_EINVAL;
     if ((d_x == nullptr) != (d_t == nullptr)) return werr(h, LES_EINVAL, "capture buffers: both or neither");
+    if (smooth < 0 || smooth > 100000) return werr(h, LES_EINVAL, "smoothing passes");
     WCK(hipStreamSynchronize(h->stream));
     h->cap_x = d_x;
     h->cap_t = d_t;
+    h->cap_smooth = smooth;
     return LES_OK;
 }
 

@@ -30,7 +30,7 @@ def make_case(base: str, seed: int, **params):
     return g
 
 
-def collect(base: str, seed: int, steps: int, skip: int = 0):
+def collect(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0):
     """Run `skip` + `steps` steps; return the (inputs [n, D, H, W, 3],
     targets [n, D, H, W]) of the last `steps` as device tensors, with the
     per-step SOR iterations."""
@@ -45,7 +45,7 @@ def collect(base: str, seed: int, steps: int, skip: int = 0):
         T = torch.empty((steps, D, H, W), device="cuda")
         its = []
         for s in range(steps):
-            les.set_capture(g, X[s], T[s])
+            les.set_capture(g, X[s], T[s], smooth)
             _, _, it = g.step(1)
             its.append(int(it[0]))
         les.set_capture(g, None, None)
@@ -55,10 +55,12 @@ def collect(base: str, seed: int, steps: int, skip: int = 0):
         g.close()
 
 
-def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None):
+def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None,
+          lr: float | None = None, lr_final: float | None = None):
     """Adam on random mini-batches of the pairs; targets are divided by
     their RMS over the set, which is returned as the warm start's
-    target_scale, with the loss history."""
+    target_scale, with the loss history.  With lr given, the step size
+    decays geometrically from lr to lr_final (default lr / 10)."""
     import torch
 
     scale = float(torch.sqrt(torch.mean(T.double() ** 2)).item())
@@ -67,6 +69,9 @@ def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=Non
     losses = []
     n = X.shape[0]
     for it in range(iters):
+        if lr is not None:
+            lf = lr / 10 if lr_final is None else lr_final
+            net.set_lr(lr * (lf / lr) ** (it / max(iters - 1, 1)))
         idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).cuda()
         xb = X.index_select(0, idx).contiguous()
         tb = Tn.index_select(0, idx).contiguous()
@@ -80,10 +85,10 @@ def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=Non
 
 
 def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float = 1.0,
-             skip: int = 0, trial_iters: int = 0):
+             skip: int = 0, rule: int = les.WARM_RESIDUAL, param: int = 0, smooth: int = 0):
     """Iterations per step and wall ms per step of `steps` steps (after
-    `skip` plain steps), warm-started by `net` if given (choice rule
-    `trial_iters`, see les_set_warm_start)."""
+    `skip` plain steps), warm-started by `net` if given (choice `rule`,
+    `param`, see les_set_warm_start)."""
     import torch
 
     g = make_case(base, seed)
@@ -91,7 +96,7 @@ def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float
         if skip:
             g.step(skip)
         if net is not None:
-            les.set_warm_start(g, net, scale, trial_iters)
+            les.set_warm_start(g, net, scale, rule, param, smooth)
         torch.cuda.synchronize()
         its, taken, rnet, rprev = [], 0, [], []
         t0 = time.perf_counter()

@@ -241,3 +241,75 @@ def test_bad_arguments(net):
     import ctypes as C
     h = C.c_void_p()
     assert L.lesnet_create(cfg, C.byref(h)) == les.LES_EINVAL and not h.value
+
+
+# ------------------------------------------------------------ single ops
+# Each kernel on its own: bfloat16 operands, float32 accumulation and
+# float32 output.  The sums have at most K = 27 * 64 = 1728 products (conv)
+# or one per voxel (weight gradients, split over blocks); float32 rounding
+# of a K-term sum of random-sign products leaves a relative L2 error near
+# sqrt(K) 2^-24 = 2.5e-6, so 1e-5 is the bar.
+TOL_OP = 1e-5
+OP_CASES = [  # (B, D, H, W, cin, cout)
+    (1, 6, 5, 7, 3, 16), (2, 4, 6, 8, 16, 32), (1, 5, 4, 6, 32, 64), (1, 4, 4, 4, 64, 16),
+    (1, 3, 5, 4, 64, 64),
+]
+
+
+def _rnd(shape, seed):
+    return bf16(np.random.default_rng(seed).standard_normal(shape))
+
+
+@pytest.mark.parametrize("B,D,H,W,cin,cout", OP_CASES)
+def test_op_conv3_forward_dgrad_wgrad(B, D, H, W, cin, cout):
+    print(f"[lesnet_op conv3] B={B} D={D} H={H} W={W} cin={cin} cout={cout}", flush=True)
+    x = _rnd((B, D, H, W, cin), 1)
+    Wt = _rnd((27, cin, cout), 2) / np.sqrt(27 * cin)
+    Wt = bf16(Wt)
+    bias = np.random.default_rng(3).standard_normal(cout).astype(np.float32)
+    dy = _rnd((B, D, H, W, cout), 4)
+    y = les.net_op("conv3", dev(x), dev(Wt), dev(bias)).cpu().numpy()
+    yo = np.stack([N.conv3(x[b], Wt, bias.astype(np.float64)) for b in range(B)])
+    assert rel(y, yo) <= TOL_OP
+    wg = les.net_op("conv3_wgrad", dev(x), dev(dy)).cpu().numpy()
+    dxo, dWo = np.zeros_like(x), np.zeros_like(Wt)
+    for b in range(B):
+        dx_b, dW_b, _ = N.conv3_backward(x[b], Wt, dy[b])
+        dxo[b] = dx_b
+        dWo += dW_b
+    assert rel(wg, dWo) <= TOL_OP
+    if cin in (16, 32, 64):
+        dx = les.net_op("conv3_dgrad", dev(dy), dev(Wt)).cpu().numpy()
+        assert rel(dx, dxo) <= TOL_OP
+
+
+@pytest.mark.parametrize("B,D,H,W,cin,cout", OP_CASES)
+def test_op_up_forward_dgrad_wgrad(B, D, H, W, cin, cout):
+    print(f"[lesnet_op up] B={B} D={D} H={H} W={W} cin={cin} cout={cout}", flush=True)
+    x = _rnd((B, D, H, W, cin), 5)
+    U = bf16(_rnd((8, cin, cout), 6) / np.sqrt(cin))
+    bias = np.random.default_rng(7).standard_normal(cout).astype(np.float32)
+    dy = _rnd((B, 2 * D, 2 * H, 2 * W, cout), 8)
+    y = les.net_op("up", dev(x), dev(U), dev(bias)).cpu().numpy()
+    yo = np.stack([N.up(x[b], U, bias.astype(np.float64)) for b in range(B)])
+    assert rel(y, yo) <= TOL_OP
+    dxo, dUo = np.zeros_like(x), np.zeros_like(U)
+    for b in range(B):
+        dx_b, dU_b, _ = N.up_backward(x[b], U, dy[b])
+        dxo[b] = dx_b
+        dUo += dU_b
+    wg = les.net_op("up_wgrad", dev(x), dev(dy)).cpu().numpy()
+    assert rel(wg, dUo) <= TOL_OP
+    if cin in (16, 32, 64):
+        dx = les.net_op("up_dgrad", dev(dy), dev(U)).cpu().numpy()
+        assert rel(dx, dxo) <= TOL_OP
+
+
+def test_op_rejects_bad_sizes():
+    a = torch.zeros((1, 4, 4, 4, 16), device="cuda")
+    w = torch.zeros((27, 16, 24), device="cuda")
+    with pytest.raises(les.LesError):
+        les.net_op("conv3", a, w)              # cout 24 is not a tile size
+    L = les.lib()
+    assert L.lesnet_op(9, 1, 4, 4, 4, 16, 16, a.data_ptr(), w.data_ptr(), None, a.data_ptr(),
+                       None) == les.LES_EINVAL

@@ -82,7 +82,7 @@ def test_capture_channels_and_target():
         g.close()
 
 
-def _run(net_params, scale, steps=4, zero=False):
+def _run(net_params, scale, steps=4, zero=False, rule=les.WARM_RESIDUAL, param=0):
     g, _ = case()
     net = None
     try:
@@ -94,7 +94,7 @@ def _run(net_params, scale, steps=4, zero=False):
             else:
                 w *= net_params
             net.set_params(w)
-            les.set_warm_start(g, net, scale)
+            les.set_warm_start(g, net, scale, rule, param)
         stats = []
         for _ in range(steps):
             _, st, _ = g.step(1)
@@ -111,8 +111,13 @@ def test_unhelpful_network_is_never_taken():
     a wildly scaled one proposes a far worse start.  Either way the run is
     the plain run, bit for bit."""
     base, _ = _run(None, 1.0)
-    for mult, scale, zero in ((1.0, 1.0, True), (1.0, 1e4, False)):
-        f, stats = _run(mult, scale, zero=zero)
+    for mult, scale, zero, rule, param in ((1.0, 1.0, True, les.WARM_RESIDUAL, 0),
+                                           (1.0, 1.0, True, les.WARM_SMOOTH, 8),
+                                           (1.0, 1.0, True, les.WARM_TRIAL, 8),
+                                           (1.0, 1e4, False, les.WARM_RESIDUAL, 0),
+                                           (1.0, 1e4, False, les.WARM_SMOOTH, 8)):
+        print(f"  rule {rule} param {param} zero={zero}", flush=True)
+        f, stats = _run(mult, scale, zero=zero, rule=rule, param=param)
         assert all(s["warm_taken"] == 0 for s in stats)
         for a, b in zip(f, base):
             assert np.array_equal(a, b)
@@ -141,4 +146,38 @@ def test_choice_follows_the_residuals():
             assert st["resid_last"] <= 1e-5
     finally:
         g.close()
+        net.close()
+
+
+def test_learned_start_saves_iterations_on_held_out_cases():
+    """Train on pairs captured from C1-size runs with building seeds 11-14,
+    then run held-out seeds 21 and 22: starting each solve from the
+    network's (smoothed) proposal lowers the mean SOR iteration count at
+    the same tolerance.  Training and the runs are deterministic."""
+    from paper_1504_02264_amd import warmstart as ws
+
+    smooth = 16
+    Xs, Ts = [], []
+    for seed in (11, 12, 13, 14):
+        X, T, _ = ws.collect("C1", seed, steps=20, skip=2, smooth=smooth)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    print(f"  {X.shape[0]} training pairs", flush=True)
+    net = les.Net(seed=0, lr=1e-3)
+    try:
+        scale, losses = ws.train(net, X, T, iters=4000, batch=8, lr=1e-3, lr_final=5e-5)
+        print(f"  loss {losses[0][1]:.3f} -> {losses[-1][1]:.4f}", flush=True)
+        del X, T
+        base, warm = [], []
+        for seed in (21, 22):
+            b = ws.evaluate("C1", seed, steps=8, net=None, skip=2)
+            w = ws.evaluate("C1", seed, steps=8, net=net, scale=scale, skip=2,
+                            rule=les.WARM_ALWAYS, smooth=smooth)
+            print(f"  seed {seed}: plain {b['iters'].mean():.0f} it {b['ms_per_step']:.1f} ms/step; "
+                  f"learned {w['iters'].mean():.0f} it {w['ms_per_step']:.1f} ms/step", flush=True)
+            base.append(b["iters"].mean())
+            warm.append(w["iters"].mean())
+        assert np.mean(warm) <= 0.95 * np.mean(base)
+    finally:
         net.close()

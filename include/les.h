@@ -277,7 +277,8 @@ int les_set_state(les_handle* h, const void* buf, int64_t bytes);
  * are updated, so single steps and ensemble steps can be mixed.
  * iters_out (nullable, caller-owned) receives nsteps x n iteration counts
  * (step-major).  Host-synchronous.  Returns LES_NOT_CONVERGED if any solve
- * hit max_iter, LES_ESTATE if a member has no inflow yet.
+ * hit max_iter, LES_ESTATE if a member has no inflow yet or has a learned
+ * warm start or a capture set (lesnet.h; those run with les_step only).
  */
 typedef struct les_ensemble les_ensemble;
 typedef struct {

@@ -852,8 +852,11 @@ int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_
 int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out) {
     if (!e || nsteps < 0) return LES_EINVAL;
     const int n = e->n;
-    for (int q = 0; q < n; ++q)
+    for (int q = 0; q < n; ++q) {
         if (!e->members[q]->have_inflow) return ens_err(e, LES_ESTATE, "member without inflow");
+        if (e->members[q]->warm_net || e->members[q]->cap_x)
+            return ens_err(e, LES_ESTATE, "member with a warm start or capture set (single-handle only)");
+    }
     auto t0 = std::chrono::steady_clock::now();
     // members' own streams finish first; the ensemble works on its stream
     for (int q = 0; q < n; ++q) ECK(hipStreamSynchronize(e->members[q]->stream));

@@ -42,181 +42,278 @@ __device__ __forceinline__ long long vox_id(int b, int z, int y, int x, int D, i
 }
 
 // ------------------------------------------------------ implicit GEMM
-template <int NT>
+// A wavefront computes MW tiles of 16 voxels x NT tiles of 16 channels;
+// the weight fragment of each K step is loaded once and used for the MW
+// voxel tiles.  Voxel counts < 2^31 (checked on the host).
+template <int NT, int MW>
 __global__ __launch_bounds__(kNetBlock) void k_gemm(GemmArgs a) {
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const long long M = (long long)a.B * a.D * a.H * a.W;
-    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    const unsigned M = (unsigned)a.B * a.D * a.H * a.W;
+    const unsigned m0 = (blockIdx.x * 4u + wave) * 16u * MW;
     if (m0 >= M) return;   // whole wavefront past the end (no block-wide sync below)
     const int slice = a.scatter_child ? (int)blockIdx.y : 0;
     const bf16* wt = a.wt + (size_t)slice * a.cout * a.kp;
-    const long long mv = m0 + (l & 15);
-    const bool mv_ok = mv < M;
-    int b = 0, z = 0, y = 0, x = 0;
-    if (mv_ok) vox_of(mv, a.D, a.H, a.W, b, z, y, x);
+    const unsigned D = a.D, H = a.H, W = a.W;
+    int vb[MW], vz[MW], vy[MW], vx[MW];
+    bool vok[MW];
+#pragma unroll
+    for (int mw = 0; mw < MW; ++mw) {
+        const unsigned mv = m0 + 16u * mw + (l & 15);
+        vok[mw] = mv < M;
+        const unsigned vv = vok[mw] ? mv : 0u;
+        vx[mw] = (int)(vv % W);
+        const unsigned r = vv / W;
+        vy[mw] = (int)(r % H);
+        const unsigned r2 = r / H;
+        vz[mw] = (int)(r2 % D);
+        vb[mw] = (int)(r2 / D);
+    }
     const int ntaps = a.gather == G_TAP27 ? 27 : (a.gather == G_CHILD8 ? 8 : 1);
     const int K = ntaps * a.cin_p;
     const int kgrp = (l >> 4) * 8;
-    f32x4 acc[NT];
+    f32x4 acc[MW][NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < a.kp; k0 += 32) {
         const int k = k0 + kgrp;
-        bf16x8 av;
+        bf16x8 bv[NT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) av[i] = (bf16)0.f;
-        if (mv_ok && k < K) {
-            const int t = k >> a.cin_shift;
-            const int ci = k - (t << a.cin_shift);
-            long long iv = -1;
-            if (a.gather == G_TAP27) {
-                const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
-                if (zz >= 0 && zz < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    iv = vox_id(b, zz, yy, xx, a.D, a.H, a.W);
-            } else if (a.gather == G_CHILD8) {
-                iv = vox_id(b, 2 * z + (t >> 2), 2 * y + ((t >> 1) & 1), 2 * x + (t & 1), 2 * a.D,
-                            2 * a.H, 2 * a.W);
-            } else {
-                iv = mv;
+        for (int nt = 0; nt < NT; ++nt)
+            bv[nt] = *reinterpret_cast<const bf16x8*>(wt + (size_t)(16 * nt + (l & 15)) * a.kp + k);
+        const int t = k >> a.cin_shift;
+        const int ci = k - (t << a.cin_shift);
+#pragma unroll
+        for (int mw = 0; mw < MW; ++mw) {
+            bf16x8 av;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) av[i] = (bf16)0.f;
+            if (vok[mw] && k < K) {
+                const int b = vb[mw], z = vz[mw], y = vy[mw], x = vx[mw];
+                long long iv = -1;
+                if (a.gather == G_TAP27) {
+                    const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
+                    if (zz >= 0 && zz < (int)D && yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W)
+                        iv = (((long long)b * D + zz) * H + yy) * W + xx;
+                } else if (a.gather == G_CHILD8) {
+                    iv = (((long long)b * 2 * D + 2 * z + (t >> 2)) * 2 * H + 2 * y + ((t >> 1) & 1)) * 2 * W +
+                         2 * x + (t & 1);
+                } else {
+                    iv = m0 + 16u * mw + (l & 15);
+                }
+                if (iv >= 0) {
+                    av = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ci);
+                    if (a.mask) {
+                        const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ci);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (!((float)mk[i] > 0.f)) av[i] = (bf16)0.f;
+                    }
+                }
             }
-            if (iv >= 0) {
-                av = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ci);
-                if (a.mask) {
-                    const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ci);
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (!((float)mk[i] > 0.f)) av[i] = (bf16)0.f;
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mw][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[mw][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int ch = 16 * nt + (l & 15);
+            const float bias = a.bias ? a.bias[ch] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned ov = m0 + 16u * mw + 4 * (l >> 4) + i;
+                if (ov >= M) continue;
+                float val = acc[mw][nt][i] + bias;
+                if (a.relu) val = fmaxf(val, 0.f);
+                size_t dst = ov;
+                if (a.scatter_child) {
+                    const unsigned ox = ov % W, r = ov / W, oy = r % H, r2 = r / H, oz = r2 % D, ob = r2 / D;
+                    dst = (((size_t)ob * 2 * D + 2 * oz + (slice >> 2)) * 2 * H + 2 * oy + ((slice >> 1) & 1)) *
+                              2 * W + 2 * ox + (slice & 1);
+                }
+                if (a.out_f32) a.out_f32[dst * a.out_cs + a.out_coff + ch] = val;
+                else a.out[dst * a.out_cs + a.out_coff + ch] = (bf16)val;
+            }
+        }
+}
+
+// ------------------------------------------------------ weight gradients
+// Block = 4 wavefronts over one chunk of voxels and TPB consecutive taps
+// (tap group = grid y).  Each wavefront walks 32-voxel steps (the MFMA K);
+// the operand that does not depend on the tap (the output gradient of a
+// convolution, the input of an up layer) is loaded once per step and
+// reused for the TPB taps.  The block sums its four wavefronts in LDS in
+// a fixed order and stores one partial per chunk and tap.
+template <int MT, int NT, int TPB, bool ROW8>
+__global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
+    __shared__ float red[TPB][MT * 16][NT * 16];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int taps = a.up ? 8 : 27;
+    const int tb = blockIdx.y * TPB;
+    // voxel counts < 2^31 (checked on the host): 32-bit index arithmetic
+    const unsigned M = (unsigned)a.B * a.D * a.H * a.W;
+    const unsigned c0 = blockIdx.x * (unsigned)a.chunk;
+    const unsigned c1 = c0 + (unsigned)a.chunk < M ? c0 + (unsigned)a.chunk : M;
+    const unsigned D = a.D, H = a.H, W = a.W;
+    f32x4 acc[TPB][MT][NT];
+#pragma unroll
+    for (int tt = 0; tt < TPB; ++tt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[tt][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const unsigned kgrp = (l >> 4) * 8;
+    for (unsigned v0 = c0 + wave * 32; v0 < c1; v0 += 4 * 32) {
+        // coordinates of the lane's 8 voxels v0 + kgrp + i; with ROW8 (W a
+        // multiple of 8) they are one aligned run along x
+        int vb[ROW8 ? 1 : 8], vz[ROW8 ? 1 : 8], vy[ROW8 ? 1 : 8], vx[ROW8 ? 1 : 8];
+        bool ok[8];
+#pragma unroll
+        for (int i = 0; i < (ROW8 ? 1 : 8); ++i) {
+            const unsigned v = v0 + kgrp + i;
+            const unsigned vv = v < c1 ? v : c0;
+            vx[i] = (int)(vv % W);
+            const unsigned r = vv / W;
+            vy[i] = (int)(r % H);
+            const unsigned r2 = r / H;
+            vz[i] = (int)(r2 % D);
+            vb[i] = (int)(r2 / D);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ok[i] = v0 + kgrp + i < c1;
+        auto coord = [&](int i, int& b, int& z, int& y, int& x) {
+            if (ROW8) {
+                b = vb[0]; z = vz[0]; y = vy[0]; x = vx[0] + i;
+            } else {
+                b = vb[i]; z = vz[i]; y = vy[i]; x = vx[i];
+            }
+        };
+        auto vid = [&](int b, int z, int y, int x, unsigned d, unsigned h, unsigned w) {
+            return (((unsigned)b * d + (unsigned)z) * h + (unsigned)y) * w + (unsigned)x;
+        };
+        // the tap-independent operand
+        bf16x8 sh_a[MT], sh_b[NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sh_a[mt][i] = (bf16)0.f;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sh_b[nt][i] = (bf16)0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (!ok[i]) continue;
+            const size_t v = v0 + kgrp + i;
+            if (!a.up) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = 16 * nt + (l & 15);
+                    bf16 g = a.dout[v * a.dout_cs + co];
+                    if (a.mask && !((float)a.mask[v * a.mask_cs + co] > 0.f)) g = (bf16)0.f;
+                    sh_b[nt][i] = g;
+                }
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int ci = 16 * mt + (l & 15);
+                    if (ci < a.cin) sh_a[mt][i] = a.in[v * a.in_cs + ci];
                 }
             }
         }
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wt + (size_t)(16 * nt + (l & 15)) * a.kp + k);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+        for (int tt = 0; tt < TPB; ++tt) {
+            const int t = tb + tt;
+            if (t >= taps) break;   // uniform over the block
+            bf16x8 av[MT], bv[NT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) av[mt] = sh_a[mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bv[nt] = sh_b[nt];
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int b, z, y, x;
+                coord(i, b, z, y, x);
+                if (!a.up) {
+                    const int zz = z + dz, yy = y + dy, xx = x + dx;
+                    const bool in_grid = ok[i] && zz >= 0 && zz < (int)D && yy >= 0 && yy < (int)H && xx >= 0 &&
+                                         xx < (int)W;
+                    const size_t ia = in_grid ? vid(b, zz, yy, xx, D, H, W) : 0;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const int ci = 16 * mt + (l & 15);
+                        av[mt][i] = (in_grid && ci < a.cin) ? a.in[ia * a.in_cs + ci] : (bf16)0.f;
+                    }
+                } else {
+                    const size_t ib = vid(b, 2 * z + (t >> 2), 2 * y + ((t >> 1) & 1), 2 * x + (t & 1), 2 * D,
+                                          2 * H, 2 * W);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int co = 16 * nt + (l & 15);
+                        bv[nt][i] = ok[i] ? a.dout[ib * a.dout_cs + co] : (bf16)0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[tt][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[tt][mt][nt], 0, 0, 0);
         }
-    }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int ch = 16 * nt + (l & 15);
-        const float bias = a.bias ? a.bias[ch] : 0.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long ov = m0 + 4 * (l >> 4) + i;
-            if (ov >= M) continue;
-            float val = acc[nt][i] + bias;
-            if (a.relu) val = fmaxf(val, 0.f);
-            long long dst = ov;
-            if (a.scatter_child) {
-                int ob, oz, oy, ox;
-                vox_of(ov, a.D, a.H, a.W, ob, oz, oy, ox);
-                dst = vox_id(ob, 2 * oz + (slice >> 2), 2 * oy + ((slice >> 1) & 1), 2 * ox + (slice & 1),
-                             2 * a.D, 2 * a.H, 2 * a.W);
-            }
-            if (a.out_f32) a.out_f32[dst * a.out_cs + a.out_coff + ch] = val;
-            else a.out[dst * a.out_cs + a.out_coff + ch] = (bf16)val;
-        }
-    }
-}
-
-// ------------------------------------------------------ weight gradients
-// Block = 4 wavefronts over one chunk of voxels and one tap (grid y); each
-// wavefront walks 32-voxel steps (the MFMA K), the block sums its four
-// wavefronts in LDS in a fixed order and stores one partial per chunk.
-template <int MT, int NT>
-__global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
-    __shared__ float red[MT * 16][NT * 16];
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int t = blockIdx.y;
-    const long long M = (long long)a.B * a.D * a.H * a.W;
-    const long long c0 = (long long)blockIdx.x * a.chunk;
-    const long long c1 = c0 + a.chunk < M ? c0 + a.chunk : M;
-    f32x4 acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kgrp = (l >> 4) * 8;
-    for (long long v0 = c0 + (long long)wave * 32; v0 < c1; v0 += 4 * 32) {
-        bf16x8 av[MT], bv[NT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) av[mt][i] = (bf16)0.f;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) bv[nt][i] = (bf16)0.f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const long long v = v0 + kgrp + i;
-            if (v >= c1) break;
-            int b, z, y, x;
-            vox_of(v, a.D, a.H, a.W, b, z, y, x);
-            long long ia = -1, ib = -1;
-            if (!a.up) {
-                const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x + t % 3 - 1;
-                if (zz >= 0 && zz < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    ia = vox_id(b, zz, yy, xx, a.D, a.H, a.W);
-                ib = v;
-            } else {
-                ia = v;
-                ib = vox_id(b, 2 * z + (t >> 2), 2 * y + ((t >> 1) & 1), 2 * x + (t & 1), 2 * a.D,
-                            2 * a.H, 2 * a.W);
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const int ci = 16 * mt + (l & 15);
-                if (ia >= 0 && ci < a.cin) av[mt][i] = a.in[ia * a.in_cs + ci];
-            }
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = 16 * nt + (l & 15);
-                bf16 g = a.dout[ib * a.dout_cs + co];
-                if (a.mask && !((float)a.mask[ib * a.mask_cs + co] > 0.f)) g = (bf16)0.f;
-                bv[nt][i] = g;
-            }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
     }
     // wavefronts add their tiles in turn (fixed order 0, 1, 2, 3)
     for (int w = 0; w < 4; ++w) {
         if (wave == w) {
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int tt = 0; tt < TPB; ++tt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
+                for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float& r = red[16 * mt + 4 * (l >> 4) + i][16 * nt + (l & 15)];
-                        r = (w == 0 ? 0.f : r) + acc[mt][nt][i];
-                    }
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float& r = red[tt][16 * mt + 4 * (l >> 4) + i][16 * nt + (l & 15)];
+                            r = (w == 0 ? 0.f : r) + acc[tt][mt][nt][i];
+                        }
         }
         __syncthreads();
     }
-    const int taps = a.up ? 8 : 27;
-    float* dst = a.part + ((size_t)blockIdx.x * taps + t) * (MT * 16) * (NT * 16);
-    for (int e = threadIdx.x; e < MT * 16 * NT * 16; e += kNetBlock) dst[e] = red[e / (NT * 16)][e % (NT * 16)];
+    constexpr int tile = MT * 16 * NT * 16;
+    for (int tt = 0; tt < TPB; ++tt) {
+        const int t = tb + tt;
+        if (t >= taps) break;
+        float* dst = a.part + ((size_t)blockIdx.x * taps + t) * tile;
+        for (int e = threadIdx.x; e < tile; e += kNetBlock) dst[e] = red[tt][e / (NT * 16)][e % (NT * 16)];
+    }
 }
 
-// dW[t][ci][co] (the oracle layout, ci < cin) = sum over chunks, fixed order.
-__global__ void k_wgrad_reduce(const float* part, int chunks, int taps, int cin, int cin_t, int cout,
-                               float* dw) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// dW[t][ci][co] (the oracle layout, ci < cin) = sum over chunks in a fixed
+// order: 16 lanes per output element take every 16th chunk, then a fixed
+// shuffle tree adds the 16 lane sums.
+__global__ __launch_bounds__(kNetBlock) void k_wgrad_reduce(const float* part, int chunks, int taps, int cin,
+                                                            int cin_t, int cout, float* dw) {
+    const long long e = (long long)blockIdx.x * (kNetBlock / 16) + (threadIdx.x >> 4);
+    const int q = threadIdx.x & 15;
     const long long n = (long long)taps * cin * cout;
-    if (e >= n) return;
-    const int co = (int)(e % cout);
-    const long long r = e / cout;
+    const bool live = e < n;
+    const long long ee = live ? e : 0;
+    const int co = (int)(ee % cout);
+    const long long r = ee / cout;
     const int ci = (int)(r % cin);
     const int t = (int)(r / cin);
     const size_t stride = (size_t)taps * cin_t * cout;
     const size_t off = ((size_t)t * cin_t + ci) * cout + co;
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[c * stride + off];
-    dw[e] = s;
+    if (live)
+        for (int c = q; c < chunks; c += 16) s += part[c * stride + off];
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
+    if (live && q == 0) dw[e] = s;
 }
 
 // Per-block channel sums of dout * relu'(mask): bias gradients (partials).
@@ -243,12 +340,13 @@ __global__ __launch_bounds__(kNetBlock) void k_bias_part(const bf16* dout, int d
     }
 }
 
-__global__ void k_bias_reduce(const float* part, int chunks, int C, float* db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    float s = 0.f;
-    for (int k = 0; k < chunks; ++k) s += part[(size_t)k * C + c];
-    db[c] = s;
+// out[c] = sum over rows of part[row][c] (one block per column, fixed order)
+__global__ __launch_bounds__(kNetBlock) void k_col_sum(const float* part, int rows, int cols, float* out) {
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += kNetBlock) s += (double)part[(size_t)r * cols + c];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[c] = (float)s;
 }
 
 // ------------------------------------------------------ pooling
@@ -341,14 +439,6 @@ __global__ __launch_bounds__(kNetBlock) void k_head_back(const bf16* in, int cs,
         for (int r = 0; r < kNetBlock; ++r) s += red[r][threadIdx.x];
         part[(size_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
     }
-}
-
-__global__ void k_sum_cols(const float* part, int rows, int cols, float* out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[(size_t)r * cols + c];
-    out[c] = s;
 }
 
 __global__ void k_sum_f64(const double* part, int n, double* out) {
@@ -575,6 +665,8 @@ int refresh_layouts(lesnet* n, hipStream_t s) {
     return LES_OK;
 }
 
+long long wgrad_part_floats(long long M, int up, int cin, int cout);
+
 int ensure_ws(lesnet* n, int B, int D, int H, int W) {
     if (n->ws && n->B == B && n->D == D && n->H == H && n->W == W) return LES_OK;
     if (n->ws) NCK(hipFree(n->ws));
@@ -615,9 +707,18 @@ int ensure_ws(lesnet* n, int B, int D, int H, int W) {
     bf(&a.g_p1, V2 * c1);
     bf(&a.g_e1b, V1 * c1);
     bf(&a.g_e1a, V1 * c1);
-    // partials: weight gradients (at most 256 voxel chunks x 27 taps x 64 x
-    // 64), bias gradients (at most 1024 chunks x 64), head (blocks x 33)
-    a.part_n = std::max(256LL * 27 * 64 * 64 + 1024LL * 64, (V1 / kNetBlock + 1) * 33);
+    // partials: the largest weight-gradient need over the layers plus the
+    // bias partials (at most 1024 chunks x 64), or the head's (blocks x 33)
+    long long need = 0;
+    for (const Layer& l : n->L) {
+        if (l.up < 0) continue;
+        const bool lvl1 = !strcmp(l.name, "e1a") || !strcmp(l.name, "e1b") || !strcmp(l.name, "d1a") ||
+                          !strcmp(l.name, "d1b");
+        const bool lvl3 = !strcmp(l.name, "b1") || !strcmp(l.name, "b2") || !strcmp(l.name, "u2");
+        const long long M = lvl1 ? V1 : (lvl3 ? V3 : V2);   // u1 runs on level 2, u2 on level 3
+        need = std::max(need, wgrad_part_floats(M, l.up, l.cin, l.cout));
+    }
+    a.part_n = std::max(need + 1024LL * 64, (V1 / kNetBlock + 1) * 33);
     req.push_back({(void**)&a.part, (size_t)a.part_n * 4});
     req.push_back({(void**)&a.dpart, (size_t)(V1 / kNetBlock + 16) * 8});
     req.push_back({(void**)&a.dsum, 64});
@@ -641,16 +742,65 @@ int ensure_ws(lesnet* n, int B, int D, int H, int W) {
     return LES_OK;
 }
 
-// One GEMM launch (NT = cout / 16 in {1, 2, 4}).
+// Voxel chunking of the weight-gradient reduction: at most 512 chunks of
+// at least 512 voxels (multiples of 128: four wavefronts x 32).
+void wgrad_chunking(long long M, long long* chunk, int* chunks) {
+    long long c = std::max<long long>(512, (M + 511) / 512);
+    c = (c + 127) / 128 * 128;
+    *chunk = c;
+    *chunks = (int)((M + c - 1) / c);
+}
+
+// Taps per block of k_wgrad: as many as the accumulators allow.
+int wgrad_tpb(int MT, int NT, int up) {
+    const int t = MT * NT;
+    if (!up) return t <= 2 ? 9 : (t <= 8 ? 3 : 1);
+    return t <= 2 ? 8 : (t <= 4 ? 4 : (t <= 8 ? 2 : 1));
+}
+
+// Float partials the weight gradient of one layer needs.
+long long wgrad_part_floats(long long M, int up, int cin, int cout) {
+    long long chunk;
+    int chunks;
+    wgrad_chunking(M, &chunk, &chunks);
+    return (long long)chunks * (up ? 8 : 27) * rup(cin, 16) * cout;
+}
+
+template <bool ROW8>
+hipError_t launch_wgrad_t(hipStream_t s, const WgradArgs& a, int chunks) {
+    const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
+    const int taps = a.up ? 8 : 27;
+    const int tpb = wgrad_tpb(MT, NT, a.up);
+    const dim3 grid(chunks, (taps + tpb - 1) / tpb);
+#define WG(mt, nt, tp)                                                                                  \
+    if (MT == mt && NT == nt && tpb == tp)                                                              \
+    hipLaunchKernelGGL((k_wgrad<mt, nt, tp, ROW8>), grid, dim3(kNetBlock), 0, s, a)
+    WG(1, 1, 9); else WG(1, 1, 8); else WG(1, 2, 9); else WG(1, 2, 8); else WG(2, 1, 9); else WG(2, 1, 8);
+    else WG(1, 4, 3); else WG(1, 4, 4); else WG(2, 2, 3); else WG(2, 2, 4); else WG(4, 1, 3); else WG(4, 1, 4);
+    else WG(2, 4, 3); else WG(2, 4, 2); else WG(4, 2, 3); else WG(4, 2, 2);
+    else WG(4, 4, 1);
+    else return hipErrorInvalidValue;
+#undef WG
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad(hipStream_t s, const WgradArgs& a, int chunks) {
+    return a.W % 8 == 0 ? launch_wgrad_t<true>(s, a, chunks) : launch_wgrad_t<false>(s, a, chunks);
+}
+
+// One GEMM launch: NT = cout / 16 in {1, 2, 4}; voxel tiles per wavefront
+// MW = 4 / NT while the grid keeps at least 1024 blocks, else 1.
 hipError_t gemm(hipStream_t s, const GemmArgs& a) {
     const long long M = (long long)a.B * a.D * a.H * a.W;
-    const dim3 grid(nb(M, 64), a.scatter_child ? 8 : 1);
-    switch (a.cout / 16) {
-        case 1: hipLaunchKernelGGL(k_gemm<1>, grid, dim3(kNetBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_gemm<2>, grid, dim3(kNetBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_gemm<4>, grid, dim3(kNetBlock), 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    const int NT = a.cout / 16;
+    int MW = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+    if (nb(M, 64 * MW) < 1024) MW = 1;
+    const dim3 grid(nb(M, 64 * MW), a.scatter_child ? 8 : 1);
+#define GM(nt, mw) \
+    if (NT == nt && MW == mw) hipLaunchKernelGGL((k_gemm<nt, mw>), grid, dim3(kNetBlock), 0, s, a)
+    GM(1, 4); else GM(1, 1); else GM(2, 2); else GM(2, 1); else GM(4, 1);
+    else return hipErrorInvalidValue;
+#undef GM
     return hipGetLastError();
 }
 
@@ -712,9 +862,9 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     const long long M = (long long)B * D * H * W;
     const int taps = l.up ? 8 : 27;
     const int cin_t = rup(l.cin, 16);
-    long long chunk = std::max<long long>(4 * 32 * 4, (M + 255) / 256);
-    chunk = (chunk + 127) / 128 * 128;
-    const int chunks = (int)((M + chunk - 1) / chunk);
+    long long chunk;
+    int chunks;
+    wgrad_chunking(M, &chunk, &chunks);
     const long long Mo = l.up ? M * 8 : M;   // the layer's output grid
     const long long bchunk = std::max<long long>(1024, (Mo + 1023) / 1024);
     const int bchunks = (int)((Mo + bchunk - 1) / bchunk);
@@ -728,22 +878,14 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     a.B = B; a.D = D; a.H = H; a.W = W;
     a.chunk = chunk;
     a.part = n->a.part;
-    const dim3 grid(chunks, taps);
-    const int MT = cin_t / 16, NT = l.cout / 16;
-#define WG(mt, nt) \
-    if (MT == mt && NT == nt) hipLaunchKernelGGL((k_wgrad<mt, nt>), grid, dim3(kNetBlock), 0, s, a)
-    WG(1, 1); else WG(1, 2); else WG(1, 4); else WG(2, 1); else WG(2, 2); else WG(2, 4);
-    else WG(4, 1); else WG(4, 2); else WG(4, 4);
-    else return net_err(n, LES_EINVAL, "wgrad tile");
-#undef WG
-    NCK(hipGetLastError());
+    NCK(launch_wgrad(s, a, chunks));
     const long long nw = (long long)taps * l.cin * l.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps, l.cin,
-                       cin_t, l.cout, n->g + l.w_off);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw, kNetBlock / 16)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps,
+                       l.cin, cin_t, l.cout, n->g + l.w_off);
     // bias: sum of dout * relu' over the layer's output grid
     hipLaunchKernelGGL(k_bias_part, dim3(bchunks), dim3(kNetBlock), 0, s, dout, dout_cs, mask, mask_cs, l.cout,
                        Mo, bchunk, n->a.part + wparts);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, s, n->a.part + wparts, bchunks, l.cout,
+    hipLaunchKernelGGL(k_col_sum, dim3(l.cout), dim3(kNetBlock), 0, s, n->a.part + wparts, bchunks, l.cout,
                        n->g + l.b_off);
     NCK(hipGetLastError());
     return LES_OK;
@@ -791,7 +933,7 @@ int backward(lesnet* n, hipStream_t s, int B, int D, int H, int W) {
     const unsigned hb = nb(V1);
     hipLaunchKernelGGL(k_head_back, dim3(hb), dim3(kNetBlock), 0, s, a.d1b, c1, c1, n->w + hd.w_off, a.dy, V1,
                        a.g_d1b, c1, a.part);
-    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(64), 0, s, a.part, (int)hb, c1 + 1, n->g + hd.w_off);
+    hipLaunchKernelGGL(k_col_sum, dim3(c1 + 1), dim3(kNetBlock), 0, s, a.part, (int)hb, c1 + 1, n->g + hd.w_off);
     NCK(hipGetLastError());
     // d1b (output d1b, input d1a)
     const Layer &d1b = layer(n, "d1b"), &d1a = layer(n, "d1a"), &u1 = layer(n, "u1");
@@ -1013,9 +1155,9 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
     const long long na = (dgrad ? Mf * cout : M * cin_p), nbw = Mf * cout;
     const int kp_f = up ? rup(cin, 32) : rup(27 * cin_p, 32), kp_d = rup(taps * cout, 32);
     const long long nlay = (long long)(up ? 8 : 1) * cout * kp_f + (long long)cin * kp_d;
-    long long chunk = std::max<long long>(4 * 32 * 4, (M + 255) / 256);
-    chunk = (chunk + 127) / 128 * 128;
-    const int chunks = (int)((M + chunk - 1) / chunk);
+    long long chunk;
+    int chunks;
+    wgrad_chunking(M, &chunk, &chunks);
     const int cin_t = rup(cin, 16);
     const long long npart = (long long)chunks * taps * cin_t * cout;
     const size_t bytes = ((size_t)na * 2 + 255) / 256 * 256 + ((size_t)nbw * 2 + 255) / 256 * 256 +
@@ -1063,16 +1205,11 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         w.up = up ? 1 : 0;
         w.B = B; w.D = D; w.H = H; w.W = W;
         w.chunk = chunk; w.part = part;
-        const dim3 grid(chunks, taps);
-        const int MT = cin_t / 16, NT = cout / 16;
-#define WG(mt, nt) \
-    if (MT == mt && NT == nt) hipLaunchKernelGGL((k_wgrad<mt, nt>), grid, dim3(kNetBlock), 0, s, w)
-        WG(1, 1); else WG(1, 2); else WG(1, 4); else WG(2, 1); else WG(2, 2); else WG(2, 4);
-        else WG(4, 1); else WG(4, 2); else WG(4, 4);
-#undef WG
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout)), dim3(kNetBlock), 0, s, part,
-                           chunks, taps, cin, cin_t, cout, d_out);
-        e = hipGetLastError();
+        e = launch_wgrad(s, w, chunks);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, kNetBlock / 16)),
+                               dim3(kNetBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);
+        (void)cin_t;
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);

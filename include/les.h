@@ -206,6 +206,16 @@ int les_set_fields(les_handle* h, const float* u, const float* v, const float* w
                    int32_t reset_history);
 
 /*
+ * Start of the next pressure solve from a device array d_p [nz][ny][nx]
+ * (e.g. a caller's own predictor): the pressure becomes d_p (its
+ * correction part zero).  Borrowed for the call; ordered on stream (NULL:
+ * the handle's), no synchronisation; work on another stream must be
+ * ordered by the caller (or use les_set_stream).  The next les_step builds
+ * its right-hand side and starts SOR from this pressure.
+ */
+int les_set_initial_guess_dev(les_handle* h, const float* d_p, void* stream);
+
+/*
  * Intermediates of the most recent step, for inspection:
  *   which 0: nu_t at cell centres [nz][ny][nx]            -> a
  *   which 1: Poisson rhs = div(u*)/dt [nz][ny][nx]        -> a

@@ -32,7 +32,7 @@ EXPORTS = (
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
     "les_ensemble_create", "les_ensemble_step", "les_ensemble_autotune",
     "les_ensemble_last_error", "les_ensemble_destroy", "les_ensemble_set_mode",
-    "les_ensemble_tuning",
+    "les_ensemble_tuning", "les_set_initial_guess_dev",
     # include/lesnet.h
     "lesnet_default_config", "lesnet_create", "lesnet_destroy", "lesnet_last_error",
     "lesnet_num_params", "lesnet_get_params", "lesnet_set_params", "lesnet_get_grads",
@@ -149,6 +149,7 @@ def lib():
     L.les_get_fields_dev.argtypes = [P, P, P, P, P, P]
     L.les_set_fields.argtypes = [P, P, P, P, P, C.c_int32]
     L.les_get_aux.argtypes = [P, C.c_int32, P, P, P]
+    L.les_set_initial_guess_dev.argtypes = [P, P, P]
     L.les_get_ghosted.argtypes = [P, P, P, P]
     L.les_get_step.argtypes = [P, C.POINTER(C.c_int64)]
     L.les_state_size.argtypes = [P, C.POINTER(C.c_int64)]
@@ -305,6 +306,11 @@ class LES:
         a = [None if x is None else _f32(x, s) for x, s in zip((u, v, w, p), (su, sv, sw, sp))]
         return self._check(lib().les_set_fields(self.h, *[_ptr(x) for x in a],
                                                 int(bool(reset_history))))
+
+    def set_initial_guess_dev(self, d_p, stream=None):
+        """Start the next solve from the device tensor d_p [nz, ny, nx]."""
+        s = None if stream is None else C.c_void_p(stream)
+        return self._check(lib().les_set_initial_guess_dev(self.h, C.c_void_p(d_p.data_ptr()), s))
 
     def get_nut(self):
         a = np.zeros(self.shapes[3], np.float32)

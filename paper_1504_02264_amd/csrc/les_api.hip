@@ -787,6 +787,15 @@ int les_set_fields(les_handle* h, const float* u, const float* v, const float* w
     return LES_OK;
 }
 
+int les_set_initial_guess_dev(les_handle* h, const float* d_p, void* stream) {
+    if (!h || !d_p) return LES_EINVAL;
+    const Geo& g = h->g;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    CK(launch_cells_to_colour(g, s, d_p, h->f.P.ph));
+    for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->f.P.pd[c], g.ctot, 0.f));
+    return LES_OK;
+}
+
 int les_get_aux(les_handle* h, int32_t which, float* a, float* b, float* c) {
     if (!h) return LES_EINVAL;
     const Geo& g = h->g;

@@ -181,3 +181,25 @@ def test_learned_start_saves_iterations_on_held_out_cases():
         assert np.mean(warm) <= 0.95 * np.mean(base)
     finally:
         net.close()
+
+
+def test_initial_guess_dev_starts_the_next_solve():
+    """A solve started (les_set_initial_guess_dev) from the converged
+    pressure of the same step needs at most a couple of check intervals and
+    lands on the same solution."""
+    a, _ = case()
+    b, _ = case()
+    try:
+        _, _, it_a = a.step(1)
+        pa = a.get_fields()[3]
+        b.set_initial_guess_dev(torch.from_numpy(pa).cuda())
+        torch.cuda.synchronize()
+        _, st, it_b = b.step(1)
+        pb = b.get_fields()[3]
+        print(f"  iterations from p_prev {it_a[0]}, from the converged p {it_b[0]}", flush=True)
+        assert it_a[0] > 8 and it_b[0] <= 8
+        assert np.linalg.norm(pb - pa) / np.linalg.norm(pa) <= 1e-4
+        assert st["resid_last"] <= 1e-5
+    finally:
+        a.close()
+        b.close()

@@ -141,6 +141,104 @@ __global__ __launch_bounds__(kNetBlock) void k_gemm(GemmArgs a) {
         }
 }
 
+// ------------------------------------------------------ convolution, LDS brick
+// The 27-tap gather (convolution forward, and its input gradient from the
+// masked output gradient) with the input staged in LDS.  A block owns
+// BZ x 4 x 16 output voxels (z, y, x) of one sample and loads the
+// (BZ+2) x 6 x 18 input voxels around them once (16-byte chunks of 8
+// channels, zero outside the grid, the optional mask applied on load);
+// every A operand is then a 16-byte LDS read.  A tile (the MFMA's 16 M
+// rows) is one x-row of 16 voxels; wavefront w takes tiles w, w+4, ...;
+// each weight fragment is loaded once per K step for all of them.
+template <int NT, int CINP, int BZ>
+__global__ __launch_bounds__(kNetBlock) void k_conv_brick(GemmArgs a) {
+    constexpr int BX = 16, BY = 4;
+    constexpr int HZ = BZ + 2, HY = BY + 2, HX = BX + 2;
+    constexpr int CH = CINP / 8;       // 16-byte chunks per voxel
+    constexpr int TPW = BZ * BY / 4;   // tiles per wavefront
+    __shared__ bf16x8 brick[HZ * HY * HX * CH];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int D = a.D, H = a.H, W = a.W;
+    const int nbx = (W + BX - 1) / BX, nby = (H + BY - 1) / BY, nbz = (D + BZ - 1) / BZ;
+    int bid = blockIdx.x;
+    const int bx = bid % nbx;
+    bid /= nbx;
+    const int by = bid % nby;
+    bid /= nby;
+    const int bz = bid % nbz;
+    const int b = bid / nbz;
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
+    bf16x8 zero;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) zero[i] = (bf16)0.f;
+    for (int q = threadIdx.x; q < HZ * HY * HX * CH; q += kNetBlock) {
+        const int ch = q % CH;
+        const int v = q / CH;
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        const int gz = z0 - 1 + hz, gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        bf16x8 val = zero;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+            val = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ch * 8);
+            if (a.mask) {
+                const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ch * 8);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (!((float)mk[i] > 0.f)) val[i] = (bf16)0.f;
+            }
+        }
+        brick[q] = val;
+    }
+    __syncthreads();
+    const int kgrp = (l >> 4) * 8;
+    const int m = l & 15;
+    f32x4 acc[TPW][NT];
+#pragma unroll
+    for (int tw = 0; tw < TPW; ++tw)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[tw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < a.kp; k0 += 32) {
+        const int k = k0 + kgrp;
+        bf16x8 bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            bv[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + k);
+        const bool kok = k < 27 * CINP;
+        const int t = k / CINP, ci = k % CINP;
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // 0..2: the window is shifted by one
+#pragma unroll
+        for (int tw = 0; tw < TPW; ++tw) {
+            const int tile = wave + 4 * tw;
+            const int tz = tile / BY, ty = tile % BY;
+            const bf16x8 av = kok ? brick[(((tz + dz) * HY + (ty + dy)) * HX + (m + dx)) * CH + ci / 8] : zero;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[tw][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tw][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int tw = 0; tw < TPW; ++tw) {
+        const int tile = wave + 4 * tw;
+        const int z = z0 + tile / BY, y = y0 + tile % BY;
+        if (z >= D || y >= H) continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int chn = 16 * nt + (l & 15);
+            const float bias = a.bias ? a.bias[chn] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * (l >> 4) + i;
+                if (x >= W) continue;
+                float val = acc[tw][nt][i] + bias;
+                if (a.relu) val = fmaxf(val, 0.f);
+                const size_t dst = (((size_t)b * D + z) * H + y) * W + x;
+                if (a.out_f32) a.out_f32[dst * a.out_cs + a.out_coff + chn] = val;
+                else a.out[dst * a.out_cs + a.out_coff + chn] = (bf16)val;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------ weight gradients
 // Block = 4 wavefronts over one chunk of voxels and TPB consecutive taps
 // (tap group = grid y).  Each wavefront walks 32-voxel steps (the MFMA K);
@@ -788,9 +886,29 @@ hipError_t launch_wgrad(hipStream_t s, const WgradArgs& a, int chunks) {
     return a.W % 8 == 0 ? launch_wgrad_t<true>(s, a, chunks) : launch_wgrad_t<false>(s, a, chunks);
 }
 
-// One GEMM launch: NT = cout / 16 in {1, 2, 4}; voxel tiles per wavefront
-// MW = 4 / NT while the grid keeps at least 1024 blocks, else 1.
+// Convolutions (27-tap gathers) on the LDS-brick kernel.
+hipError_t conv_brick(hipStream_t s, const GemmArgs& a) {
+    const int NT = a.cout / 16, C = a.cin_p;
+    const int bz = C == 64 ? 2 : 4;
+    const long long blocks = (long long)a.B * ((a.D + bz - 1) / bz) * ((a.H + 3) / 4) * ((a.W + 15) / 16);
+    const dim3 grid((unsigned)blocks);
+#define CB(nt, c, z) \
+    if (NT == nt && C == c) hipLaunchKernelGGL((k_conv_brick<nt, c, z>), grid, dim3(kNetBlock), 0, s, a)
+    CB(1, 8, 4); else CB(1, 16, 4); else CB(1, 32, 4); else CB(1, 64, 2);
+    else CB(2, 8, 4); else CB(2, 16, 4); else CB(2, 32, 4); else CB(2, 64, 2);
+    else CB(4, 8, 4); else CB(4, 16, 4); else CB(4, 32, 4); else CB(4, 64, 2);
+    else return hipErrorInvalidValue;
+#undef CB
+    return hipGetLastError();
+}
+
+// One GEMM launch: 27-tap gathers on the LDS-brick kernel; the others on
+// k_gemm with NT = cout / 16 in {1, 2, 4} and MW = 4 / NT voxel tiles per
+// wavefront while the grid keeps at least 1024 blocks, else 1.
 hipError_t gemm(hipStream_t s, const GemmArgs& a) {
+    if (a.gather == G_TAP27 && !a.scatter_child &&
+        (a.cin_p == 8 || a.cin_p == 16 || a.cin_p == 32 || a.cin_p == 64))
+        return conv_brick(s, a);
     const long long M = (long long)a.B * a.D * a.H * a.W;
     const int NT = a.cout / 16;
     int MW = NT == 1 ? 4 : (NT == 2 ? 2 : 1);

@@ -133,16 +133,16 @@ def bench_warm_start(args, les, torch):
     inside the timed steps."""
     import numpy as np
     from paper_1504_02264_amd import warmstart as ws
-    smooth = 16
+    smooth = 32
     Xs, Ts = [], []
     for seed in (11, 12, 13, 14):
-        X, T, _ = ws.collect("C1", seed, steps=20, skip=2, smooth=smooth)
+        X, T, _ = ws.collect("C1", seed, steps=24, skip=2, smooth=smooth)
         Xs.append(X)
         Ts.append(T)
     X, T = torch.cat(Xs), torch.cat(Ts)
     net = les.Net(seed=0, lr=1e-3)
     t0 = time.perf_counter()
-    scale, losses = ws.train(net, X, T, iters=4000, batch=8, lr=1e-3, lr_final=5e-5)
+    scale, losses = ws.train(net, X, T, iters=6000, batch=8, lr=1e-3, lr_final=5e-5)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del X, T
@@ -172,7 +172,7 @@ def bench_warm_start(args, les, torch):
         "dtype": "f32 LES, bf16 network",
         "data": "synthetic",
         "config": {"workload": "C1 64x64x32 urban LES; network trained on building seeds 11-14 "
-                               "(80 captured pairs, 4000 Adam steps), evaluated on seeds 21-22",
+                               "(96 captured pairs, 6000 Adam steps), evaluated on seeds 21-22",
                    "train_s": train_s, "final_loss": losses[-1][1], "smooth_passes": smooth},
         "rules": {k: {"sor_iters_per_step": float(np.mean(v["iters"])), "ms_per_step": float(np.mean(v["ms"])),
                       "steps_from_network": v["taken"], "ms_vs_plain": float(np.mean(v["ms"])) / base_ms}

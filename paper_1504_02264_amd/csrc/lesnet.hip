@@ -5,13 +5,13 @@
 // and weights, FP32 accumulation on the matrix cores, FP32 master weights
 // updated by Adam (Kingma & Ba 2015).
 //
-// Forward and backward run on the same implicit-GEMM kernel:
-//   conv forward     gather 27 neighbours,            W[co][(t, ci)]
-//   conv dgrad       gather 27 neighbours of dY*relu', W flipped in t, [ci][(t, co)]
-//   up forward       same voxel, output scattered to child s (grid y), U_s[co][ci]
-//   up dgrad         gather the 8 children of dY,     U[ci][(s, co)]
-// and weight gradients on a second matrix-core kernel with a fixed-order
-// split over voxels (deterministic).
+// Forward and backward are implicit GEMMs (M = voxels, N = output channels):
+//   conv forward     gather 27 neighbours,            W[co][(t, ci)]           k_conv_brick
+//   conv dgrad       gather 27 neighbours of dY*relu', W flipped in t, [ci][(t, co)]  k_conv_brick
+//   up forward       same voxel, output scattered to child s (grid y), U_s[co][ci]    k_gemm
+//   up dgrad         gather the 8 children of dY,     U[ci][(s, co)]           k_gemm
+// and weight gradients (K = voxels) on k_wgrad with a fixed-order split over
+// voxels (deterministic).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -1254,7 +1254,6 @@ int lesnet_gradients(lesnet* n, int32_t B, int32_t D, int32_t H, int32_t W, cons
 // workspace and synchronises the stream before returning.
 int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t cin, int32_t cout,
               const float* d_a, const float* d_b, const float* d_c, float* d_out, void* stream) {
-    lesnet* n = nullptr;   // NCK needs the name; errors carry no handle here
     const bool up = op == LESNET_OP_UP || op == LESNET_OP_UP_DGRAD || op == LESNET_OP_UP_WGRAD;
     if (op < LESNET_OP_CONV3 || op > LESNET_OP_UP_WGRAD || !d_a || !d_b || !d_out) return LES_EINVAL;
     if (B < 1 || D < 1 || H < 1 || W < 1 || (long long)B * D * H * W * 8 >= (1LL << 31)) return LES_EINVAL;
@@ -1298,7 +1297,7 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         hipLaunchKernelGGL(k_layout_fwd, dim3(nb((long long)(up ? 8 : 1) * cout * kp_f)), dim3(kNetBlock), 0, s,
                            d_b, taps, cin, cout, cin_p, kp_f, up ? 1 : 0, lay);
         g.in = abuf; g.in_cs = cin_p;
-        g.cin_p = up ? cin_p : cin_p;
+        g.cin_p = cin_p;
         g.cin_shift = log2i(g.cin_p);
         g.wt = lay; g.kp = kp_f; g.bias = d_c;
         g.out_f32 = d_out; g.out_cs = cout; g.cout = cout;
@@ -1327,12 +1326,10 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         if (e == hipSuccess)
             hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, kNetBlock / 16)),
                                dim3(kNetBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);
-        (void)cin_t;
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(ws);
-    (void)n;
     return e == hipSuccess ? LES_OK : LES_EDEVICE;
 }
 

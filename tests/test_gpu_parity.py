@@ -254,14 +254,17 @@ def test_error_statuses():
 
 
 # ------------------------------------------------- full-size properties
-@pytest.mark.parametrize("name", ["C2"])
-def test_full_size_stage_parity(name):
-    """At the benchmark grid: nu_t, tendency and rhs of one step against the
-    oracle over the whole field, and the projection identity."""
+@pytest.mark.parametrize("name,max_iter", [("C2", 20000), ("C3", 400)])
+def test_full_size_stage_parity(name, max_iter):
+    """At the benchmark grids (300x300x90 as benchmarked; 1024x1024x96 with
+    the solve capped): nu_t, tendency and rhs of one step against the
+    oracle over the whole field, and the projection identity
+    ||div u^{n+1}|| = dt ||r|| = ||div u*|| R, which holds whether or not the
+    solve reached the tolerance."""
     w = WORKLOADS[name]
-    print(f"[full_size_stage_parity] {name}", flush=True)
+    print(f"[full_size_stage_parity] {name} max_iter={max_iter}", flush=True)
     mask, prof = make_workload_inputs(w)
-    g, o = pair(w.nx, w.ny, w.nz, mask, w.dx, w.dy, w.dz, w.dt)
+    g, o = pair(w.nx, w.ny, w.nz, mask, w.dx, w.dy, w.dz, w.dt, max_iter=max_iter)
     g.set_inflow(prof, w.noise_amp, w.seed)
     o.set_inflow(prof, w.noise_amp, w.seed)
     u0, v0, w0, p0 = g.get_fields()
@@ -273,8 +276,7 @@ def test_full_size_stage_parity(name):
     for a, b in zip(g.get_force(), o.get_force()):
         assert rel(a, b) <= 1e-5
     assert rel(g.get_rhs(), o.get_rhs()) <= 1e-5
-    if rc == les.LES_OK:
-        assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
+    assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
 
 
 # ------------------------------------------- autotuner / tile independence

@@ -156,17 +156,17 @@ def test_learned_start_saves_iterations_on_held_out_cases():
     the same tolerance.  Training and the runs are deterministic."""
     from paper_1504_02264_amd import warmstart as ws
 
-    smooth = 16
+    smooth = 32
     Xs, Ts = [], []
     for seed in (11, 12, 13, 14):
-        X, T, _ = ws.collect("C1", seed, steps=20, skip=2, smooth=smooth)
+        X, T, _ = ws.collect("C1", seed, steps=24, skip=2, smooth=smooth)
         Xs.append(X)
         Ts.append(T)
     X, T = torch.cat(Xs), torch.cat(Ts)
     print(f"  {X.shape[0]} training pairs", flush=True)
     net = les.Net(seed=0, lr=1e-3)
     try:
-        scale, losses = ws.train(net, X, T, iters=4000, batch=8, lr=1e-3, lr_final=5e-5)
+        scale, losses = ws.train(net, X, T, iters=6000, batch=8, lr=1e-3, lr_final=5e-5)
         print(f"  loss {losses[0][1]:.3f} -> {losses[-1][1]:.4f}", flush=True)
         del X, T
         base, warm = [], []

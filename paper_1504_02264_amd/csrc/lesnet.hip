@@ -390,6 +390,146 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
     }
 }
 
+// Convolution weight gradients with both operands staged in LDS.  The
+// output grid is cut into bricks of BZ x BY x 16 voxels; a block takes the
+// bricks of one chunk and TPB consecutive taps (tap group = grid y).  Per
+// brick it loads the (BZ+2) x (BY+2) x 18 input voxels around it and the
+// masked output gradient of the brick (16-byte chunks, channels last,
+// zero outside the grid), then every MFMA operand element is an LDS read:
+// K = 32 voxels (two x-rows of the brick), A[ci][voxel] = input at the
+// voxel shifted by the tap, B[voxel][co] = gradient.  Wavefront w takes the
+// K steps w, w+4, ... of each brick; the four wavefronts' tiles are summed
+// in a fixed order at the end and one partial per chunk and tap is stored.
+// Dynamic LDS: max of the operands ((BZ+2)(BY+2) 18 cinp + BZ BY 16 cout
+// bf16) and the reduction tiles (TPB x MT 16 x NT 16 float), which reuse
+// the operands' space at the end.
+template <int MT, int NT, int TPB, int BZ, int BY>
+__global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp, int bricks_per_chunk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int BX = 16, HZ = BZ + 2, HY = BY + 2, HX = BX + 2;
+    constexpr int NV = BZ * BY * BX;   // voxels per brick
+    constexpr int KS = NV / 32;        // K steps per brick
+    bf16* s_in = reinterpret_cast<bf16*>(smem);
+    bf16* s_g = s_in + HZ * HY * HX * cinp;
+    float(*red)[MT * 16][NT * 16] = reinterpret_cast<float(*)[MT * 16][NT * 16]>(smem);
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int D = a.D, H = a.H, W = a.W, cout = a.cout;
+    const int nbx = (W + BX - 1) / BX, nby = (H + BY - 1) / BY, nbz = (D + BZ - 1) / BZ;
+    const int nbricks = a.B * nbz * nby * nbx;
+    const int tb = blockIdx.y * TPB;
+    const int br0 = blockIdx.x * bricks_per_chunk;
+    const int br1 = min(nbricks, br0 + bricks_per_chunk);
+    bf16x8 zero;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) zero[i] = (bf16)0.f;
+    f32x4 acc[TPB][MT][NT];
+#pragma unroll
+    for (int tt = 0; tt < TPB; ++tt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[tt][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int gi = l >> 4;   // lane group: voxels 8 gi .. 8 gi + 7 of a K step
+    for (int br = br0; br < br1; ++br) {
+        int bid = br;
+        const int bx = bid % nbx;
+        bid /= nbx;
+        const int by = bid % nby;
+        bid /= nby;
+        const int bz = bid % nbz;
+        const int b = bid / nbz;
+        const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
+        __syncthreads();   // the previous brick's operands are no longer read
+        const int cchi = cinp / 8;
+        for (int q = threadIdx.x; q < HZ * HY * HX * cchi; q += kNetBlock) {
+            const int ch = q % cchi;
+            const int v = q / cchi;
+            const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+            const int gz = z0 - 1 + hz, gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            bf16x8 val = zero;
+            if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                val = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ch * 8);
+            }
+            *reinterpret_cast<bf16x8*>(s_in + (size_t)q * 8) = val;
+        }
+        const int ccho = cout / 8;
+        for (int q = threadIdx.x; q < NV * ccho; q += kNetBlock) {
+            const int ch = q % ccho;
+            const int v = q / ccho;
+            const int lx = v % BX, ly = (v / BX) % BY, lz = v / (BX * BY);
+            const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+            bf16x8 val = zero;
+            if (gz < D && gy < H && gx < W) {
+                const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + ch * 8);
+                if (a.mask) {
+                    const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ch * 8);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((float)mk[i] > 0.f)) val[i] = (bf16)0.f;
+                }
+            }
+            *reinterpret_cast<bf16x8*>(s_g + (size_t)q * 8) = val;
+        }
+        __syncthreads();
+        for (int ks = wave; ks < KS; ks += 4) {
+            // the lane's 8 voxels: brick row ks * 2 + gi / 2, x = 8 (gi % 2) + i
+            const int row = ks * 2 + (gi >> 1);
+            const int lz = row / BY, ly = row % BY, xb = 8 * (gi & 1);
+            bf16x8 bv[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = 16 * nt + (l & 15);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bv[nt][i] = s_g[((row * BX) + xb + i) * cout + co];
+            }
+#pragma unroll
+            for (int tt = 0; tt < TPB; ++tt) {
+                const int t = tb + tt;
+                if (t >= 27) break;   // uniform over the block
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // window offsets 0..2
+                const int hbase = ((lz + dz) * HY + (ly + dy)) * HX + xb + dx;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int ci = 16 * mt + (l & 15);
+                    bf16x8 av;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) av[i] = ci < cinp ? s_in[(hbase + i) * cinp + ci] : (bf16)0.f;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[tt][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tt][mt][nt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();   // operands done: the reduction tiles reuse their space
+    // wavefronts add their tiles in turn (fixed order 0, 1, 2, 3)
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int tt = 0; tt < TPB; ++tt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float& r = red[tt][16 * mt + 4 * (l >> 4) + i][16 * nt + (l & 15)];
+                            r = (w == 0 ? 0.f : r) + acc[tt][mt][nt][i];
+                        }
+        }
+        __syncthreads();
+    }
+    constexpr int tile = MT * 16 * NT * 16;
+    for (int tt = 0; tt < TPB; ++tt) {
+        const int t = tb + tt;
+        if (t >= 27) break;
+        float* dst = a.part + ((size_t)blockIdx.x * 27 + t) * tile;
+        for (int e = threadIdx.x; e < tile; e += kNetBlock) dst[e] = red[tt][e / (NT * 16)][e % (NT * 16)];
+    }
+}
+
 // dW[t][ci][co] (the oracle layout, ci < cin) = sum over chunks in a fixed
 // order: 16 lanes per output element take every 16th chunk, then a fixed
 // shuffle tree adds the 16 lane sums.
@@ -763,7 +903,7 @@ int refresh_layouts(lesnet* n, hipStream_t s) {
     return LES_OK;
 }
 
-long long wgrad_part_floats(long long M, int up, int cin, int cout);
+int layer_wgrad_chunks(int up, int cin, int cout, int B, int D, int H, int W, long long* chunk, int* bpc);
 
 int ensure_ws(lesnet* n, int B, int D, int H, int W) {
     if (n->ws && n->B == B && n->D == D && n->H == H && n->W == W) return LES_OK;
@@ -813,8 +953,11 @@ int ensure_ws(lesnet* n, int B, int D, int H, int W) {
         const bool lvl1 = !strcmp(l.name, "e1a") || !strcmp(l.name, "e1b") || !strcmp(l.name, "d1a") ||
                           !strcmp(l.name, "d1b");
         const bool lvl3 = !strcmp(l.name, "b1") || !strcmp(l.name, "b2") || !strcmp(l.name, "u2");
-        const long long M = lvl1 ? V1 : (lvl3 ? V3 : V2);   // u1 runs on level 2, u2 on level 3
-        need = std::max(need, wgrad_part_floats(M, l.up, l.cin, l.cout));
+        const int f = lvl1 ? 1 : (lvl3 ? 4 : 2);   // grid of the weight-gradient sum (u1: level 2, u2: level 3)
+        long long chunk;
+        int bpc;
+        const int chunks = layer_wgrad_chunks(l.up, l.cin, l.cout, B, D / f, H / f, W / f, &chunk, &bpc);
+        need = std::max(need, (long long)chunks * (l.up ? 8 : 27) * rup(l.cin, 16) * l.cout);
     }
     a.part_n = std::max(need + 1024LL * 64, (V1 / kNetBlock + 1) * 33);
     req.push_back({(void**)&a.part, (size_t)a.part_n * 4});
@@ -856,14 +999,6 @@ int wgrad_tpb(int MT, int NT, int up) {
     return t <= 2 ? 8 : (t <= 4 ? 4 : (t <= 8 ? 2 : 1));
 }
 
-// Float partials the weight gradient of one layer needs.
-long long wgrad_part_floats(long long M, int up, int cin, int cout) {
-    long long chunk;
-    int chunks;
-    wgrad_chunking(M, &chunk, &chunks);
-    return (long long)chunks * (up ? 8 : 27) * rup(cin, 16) * cout;
-}
-
 template <bool ROW8>
 hipError_t launch_wgrad_t(hipStream_t s, const WgradArgs& a, int chunks) {
     const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
@@ -884,6 +1019,66 @@ hipError_t launch_wgrad_t(hipStream_t s, const WgradArgs& a, int chunks) {
 
 hipError_t launch_wgrad(hipStream_t s, const WgradArgs& a, int chunks) {
     return a.W % 8 == 0 ? launch_wgrad_t<true>(s, a, chunks) : launch_wgrad_t<false>(s, a, chunks);
+}
+
+// Convolution weight gradients on the LDS-brick kernel: chunks of whole
+// bricks, at most 512 chunks.  Returns the chunk count
+// (partials [chunks][27][cin_t][cout]) or -1 for an unsupported shape.
+// LDS of a weight-gradient block with bricks of bz x bz x 16 voxels, and
+// the brick (4 x 4 x 16 voxels, else 2 x 2 x 16) that keeps it within 64 KB.
+size_t wgrad_brick_lds(const WgradArgs& a, int bz) {
+    const int cinp = a.cin <= 8 ? 8 : a.cin;
+    const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
+    const size_t red = (size_t)wgrad_tpb(MT, NT, 0) * MT * 16 * NT * 16 * sizeof(float);
+    const size_t ops = ((size_t)(bz + 2) * (bz + 2) * 18 * cinp + (size_t)bz * bz * 16 * a.cout) * sizeof(bf16);
+    return std::max(red, ops);
+}
+
+int wgrad_brick_bz(const WgradArgs& a) { return wgrad_brick_lds(a, 4) <= 64 * 1024 ? 4 : 2; }
+
+int wgrad_brick_chunks(const WgradArgs& a, int* bpc_out) {
+    const int bz = wgrad_brick_bz(a), by = bz;
+    const long long nbricks = (long long)a.B * ((a.D + bz - 1) / bz) * ((a.H + by - 1) / by) * ((a.W + 15) / 16);
+    const int bpc = (int)std::max<long long>(1, (nbricks + 511) / 512);
+    *bpc_out = bpc;
+    return (int)((nbricks + bpc - 1) / bpc);
+}
+
+hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int bpc) {
+    const int cinp = a.cin <= 8 ? 8 : a.cin;
+    const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
+    const int bz = wgrad_brick_bz(a);
+    const size_t lds = wgrad_brick_lds(a, bz);
+    const int tpb = wgrad_tpb(MT, NT, 0);
+    const dim3 grid(chunks, (27 + tpb - 1) / tpb);
+#define WB(mt, nt, tp, z, y)                                                                          \
+    if (MT == mt && NT == nt && tpb == tp && bz == z)                                                 \
+    hipLaunchKernelGGL((k_wgrad_brick<mt, nt, tp, z, y>), grid, dim3(kNetBlock), lds, s, a, cinp, bpc)
+    WB(1, 1, 9, 4, 4); else WB(1, 2, 9, 4, 4); else WB(2, 1, 9, 4, 4); else WB(2, 2, 3, 4, 4);
+    else WB(1, 4, 3, 4, 4); else WB(4, 1, 3, 4, 4); else WB(2, 4, 3, 4, 4); else WB(4, 2, 3, 4, 4);
+    else WB(4, 4, 1, 4, 4);
+    else WB(1, 1, 9, 2, 2); else WB(1, 2, 9, 2, 2); else WB(2, 1, 9, 2, 2); else WB(2, 2, 3, 2, 2);
+    else WB(1, 4, 3, 2, 2); else WB(4, 1, 3, 2, 2); else WB(2, 4, 3, 2, 2); else WB(4, 2, 3, 2, 2);
+    else WB(4, 4, 1, 2, 2);
+    else return hipErrorInvalidValue;
+#undef WB
+    return hipGetLastError();
+}
+
+// Chunks of the weight-gradient sum of a layer (and its chunk size in
+// voxels / bricks per chunk): the brick kernel for convolutions, the
+// voxel-chunked one for up layers.
+int layer_wgrad_chunks(int up, int cin, int cout, int B, int D, int H, int W, long long* chunk, int* bpc) {
+    const long long M = (long long)B * D * H * W;
+    int chunks;
+    wgrad_chunking(M, chunk, &chunks);
+    *bpc = 0;
+    if (up) return chunks;
+    WgradArgs a{};
+    a.cin = cin;
+    a.cout = cout;
+    a.B = B; a.D = D; a.H = H; a.W = W;
+    return wgrad_brick_chunks(a, bpc);
 }
 
 // Convolutions (27-tap gathers) on the LDS-brick kernel.
@@ -981,8 +1176,8 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     const int taps = l.up ? 8 : 27;
     const int cin_t = rup(l.cin, 16);
     long long chunk;
-    int chunks;
-    wgrad_chunking(M, &chunk, &chunks);
+    int bpc;
+    const int chunks = layer_wgrad_chunks(l.up, l.cin, l.cout, B, D, H, W, &chunk, &bpc);
     const long long Mo = l.up ? M * 8 : M;   // the layer's output grid
     const long long bchunk = std::max<long long>(1024, (Mo + 1023) / 1024);
     const int bchunks = (int)((Mo + bchunk - 1) / bchunk);
@@ -996,7 +1191,8 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     a.B = B; a.D = D; a.H = H; a.W = W;
     a.chunk = chunk;
     a.part = n->a.part;
-    NCK(launch_wgrad(s, a, chunks));
+    if (!l.up) NCK(launch_wgrad_brick(s, a, chunks, bpc));
+    else NCK(launch_wgrad(s, a, chunks));
     const long long nw = (long long)taps * l.cin * l.cout;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw, kNetBlock / 16)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps,
                        l.cin, cin_t, l.cout, n->g + l.w_off);
@@ -1273,8 +1469,8 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
     const int kp_f = up ? rup(cin, 32) : rup(27 * cin_p, 32), kp_d = rup(taps * cout, 32);
     const long long nlay = (long long)(up ? 8 : 1) * cout * kp_f + (long long)cin * kp_d;
     long long chunk;
-    int chunks;
-    wgrad_chunking(M, &chunk, &chunks);
+    int bpc;
+    const int chunks = layer_wgrad_chunks(up ? 1 : 0, cin, cout, B, D, H, W, &chunk, &bpc);
     const int cin_t = rup(cin, 16);
     const long long npart = (long long)chunks * taps * cin_t * cout;
     const size_t bytes = ((size_t)na * 2 + 255) / 256 * 256 + ((size_t)nbw * 2 + 255) / 256 * 256 +
@@ -1322,7 +1518,7 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         w.up = up ? 1 : 0;
         w.B = B; w.D = D; w.H = H; w.W = W;
         w.chunk = chunk; w.part = part;
-        e = launch_wgrad(s, w, chunks);
+        e = up ? launch_wgrad(s, w, chunks) : launch_wgrad_brick(s, w, chunks, bpc);
         if (e == hipSuccess)
             hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, kNetBlock / 16)),
                                dim3(kNetBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);

@@ -404,7 +404,8 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
 // bf16) and the reduction tiles (TPB x MT 16 x NT 16 float), which reuse
 // the operands' space at the end.
 template <int MT, int NT, int TPB, int BZ, int BY>
-__global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp, int bricks_per_chunk) {
+__global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp, int bricks_per_chunk,
+                                                           float* bias_part) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int BX = 16, HZ = BZ + 2, HY = BY + 2, HX = BX + 2;
     constexpr int NV = BZ * BY * BX;   // voxels per brick
@@ -430,6 +431,10 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[tt][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int gi = l >> 4;   // lane group: voxels 8 gi .. 8 gi + 7 of a K step
+    // bias gradient (tap group 0 only): this thread sums channel tid % cout
+    // over the voxels tid / cout, + 256 / cout, ... of every brick
+    const bool do_bias = bias_part != nullptr && blockIdx.y == 0;
+    float bsum = 0.f;
     for (int br = br0; br < br1; ++br) {
         int bid = br;
         const int bx = bid % nbx;
@@ -473,6 +478,9 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
             *reinterpret_cast<bf16x8*>(s_g + (size_t)q * 8) = val;
         }
         __syncthreads();
+        if (do_bias)
+            for (int v = threadIdx.x / cout; v < NV; v += kNetBlock / cout)
+                bsum += (float)s_g[v * cout + threadIdx.x % cout];
         for (int ks = wave; ks < KS; ks += 4) {
             // the lane's 8 voxels: brick row ks * 2 + gi / 2, x = 8 (gi % 2) + i
             const int row = ks * 2 + (gi >> 1);
@@ -501,6 +509,16 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
                         acc[tt][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tt][mt][nt], 0, 0, 0);
                 }
             }
+        }
+    }
+    if (do_bias) {   // fixed-order sum of the threads of each channel
+        __shared__ float bred[kNetBlock];
+        bred[threadIdx.x] = bsum;
+        __syncthreads();
+        if (threadIdx.x < cout) {
+            float t = 0.f;
+            for (int r = 0; r < kNetBlock / cout; ++r) t += bred[r * cout + threadIdx.x];
+            bias_part[(size_t)blockIdx.x * cout + threadIdx.x] = t;
         }
     }
     __syncthreads();   // operands done: the reduction tiles reuse their space
@@ -1024,8 +1042,9 @@ hipError_t launch_wgrad(hipStream_t s, const WgradArgs& a, int chunks) {
 // Convolution weight gradients on the LDS-brick kernel: chunks of whole
 // bricks, at most 512 chunks.  Returns the chunk count
 // (partials [chunks][27][cin_t][cout]) or -1 for an unsupported shape.
-// LDS of a weight-gradient block with bricks of bz x bz x 16 voxels, and
-// the brick (4 x 4 x 16 voxels, else 2 x 2 x 16) that keeps it within 64 KB.
+// Dynamic LDS of a weight-gradient block with bricks of bz x bz x 16
+// voxels, and the brick (4 x 4 x 16 voxels, else 2 x 2 x 16) that keeps the
+// block within 64 KB.
 size_t wgrad_brick_lds(const WgradArgs& a, int bz) {
     const int cinp = a.cin <= 8 ? 8 : a.cin;
     const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
@@ -1034,7 +1053,7 @@ size_t wgrad_brick_lds(const WgradArgs& a, int bz) {
     return std::max(red, ops);
 }
 
-int wgrad_brick_bz(const WgradArgs& a) { return wgrad_brick_lds(a, 4) <= 64 * 1024 ? 4 : 2; }
+int wgrad_brick_bz(const WgradArgs& a) { return wgrad_brick_lds(a, 4) <= 63 * 1024 ? 4 : 2; }   // + 1 KB static
 
 int wgrad_brick_chunks(const WgradArgs& a, int* bpc_out) {
     const int bz = wgrad_brick_bz(a), by = bz;
@@ -1044,7 +1063,7 @@ int wgrad_brick_chunks(const WgradArgs& a, int* bpc_out) {
     return (int)((nbricks + bpc - 1) / bpc);
 }
 
-hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int bpc) {
+hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int bpc, float* bias_part) {
     const int cinp = a.cin <= 8 ? 8 : a.cin;
     const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
     const int bz = wgrad_brick_bz(a);
@@ -1053,7 +1072,7 @@ hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int
     const dim3 grid(chunks, (27 + tpb - 1) / tpb);
 #define WB(mt, nt, tp, z, y)                                                                          \
     if (MT == mt && NT == nt && tpb == tp && bz == z)                                                 \
-    hipLaunchKernelGGL((k_wgrad_brick<mt, nt, tp, z, y>), grid, dim3(kNetBlock), lds, s, a, cinp, bpc)
+    hipLaunchKernelGGL((k_wgrad_brick<mt, nt, tp, z, y>), grid, dim3(kNetBlock), lds, s, a, cinp, bpc, bias_part)
     WB(1, 1, 9, 4, 4); else WB(1, 2, 9, 4, 4); else WB(2, 1, 9, 4, 4); else WB(2, 2, 3, 4, 4);
     else WB(1, 4, 3, 4, 4); else WB(4, 1, 3, 4, 4); else WB(2, 4, 3, 4, 4); else WB(4, 2, 3, 4, 4);
     else WB(4, 4, 1, 4, 4);
@@ -1182,7 +1201,8 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     const long long bchunk = std::max<long long>(1024, (Mo + 1023) / 1024);
     const int bchunks = (int)((Mo + bchunk - 1) / bchunk);
     const long long wparts = (long long)chunks * taps * cin_t * l.cout;
-    if (wparts + (long long)bchunks * l.cout > n->a.part_n) return net_err(n, LES_ENOMEM, "wgrad partials");
+    if (wparts + (long long)std::max(bchunks, chunks) * l.cout > n->a.part_n)
+        return net_err(n, LES_ENOMEM, "wgrad partials");
     WgradArgs a{};
     a.in = in; a.in_cs = in_cs; a.cin = l.cin;
     a.dout = dout; a.dout_cs = dout_cs; a.cout = l.cout;
@@ -1191,16 +1211,21 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     a.B = B; a.D = D; a.H = H; a.W = W;
     a.chunk = chunk;
     a.part = n->a.part;
-    if (!l.up) NCK(launch_wgrad_brick(s, a, chunks, bpc));
+    // bias: sum of dout * relu' over the layer's output grid (convolutions:
+    // per chunk inside the weight-gradient kernel)
+    float* bpart = n->a.part + wparts;
+    if (!l.up) NCK(launch_wgrad_brick(s, a, chunks, bpc, bpart));
     else NCK(launch_wgrad(s, a, chunks));
     const long long nw = (long long)taps * l.cin * l.cout;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw, kNetBlock / 16)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps,
                        l.cin, cin_t, l.cout, n->g + l.w_off);
-    // bias: sum of dout * relu' over the layer's output grid
-    hipLaunchKernelGGL(k_bias_part, dim3(bchunks), dim3(kNetBlock), 0, s, dout, dout_cs, mask, mask_cs, l.cout,
-                       Mo, bchunk, n->a.part + wparts);
-    hipLaunchKernelGGL(k_col_sum, dim3(l.cout), dim3(kNetBlock), 0, s, n->a.part + wparts, bchunks, l.cout,
-                       n->g + l.b_off);
+    int brows = chunks;
+    if (l.up) {
+        hipLaunchKernelGGL(k_bias_part, dim3(bchunks), dim3(kNetBlock), 0, s, dout, dout_cs, mask, mask_cs, l.cout,
+                           Mo, bchunk, bpart);
+        brows = bchunks;
+    }
+    hipLaunchKernelGGL(k_col_sum, dim3(l.cout), dim3(kNetBlock), 0, s, bpart, brows, l.cout, n->g + l.b_off);
     NCK(hipGetLastError());
     return LES_OK;
 }
@@ -1518,7 +1543,7 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         w.up = up ? 1 : 0;
         w.B = B; w.D = D; w.H = H; w.W = W;
         w.chunk = chunk; w.part = part;
-        e = up ? launch_wgrad(s, w, chunks) : launch_wgrad_brick(s, w, chunks, bpc);
+        e = up ? launch_wgrad(s, w, chunks) : launch_wgrad_brick(s, w, chunks, bpc, nullptr);
         if (e == hipSuccess)
             hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, kNetBlock / 16)),
                                dim3(kNetBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);

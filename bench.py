@@ -127,12 +127,69 @@ def bench_net(les, torch, D=64, H=128, W=128, reps=10):
     }
 
 
+def bench_warm_start_c3(args, les, torch):
+    """The learned start at 1024x1024x96: trained on 8 random 64x128x128
+    crops per step of runs with building seeds 11-14, evaluated on whole
+    held-out runs (seeds 21, 22).  The solve stops at max_iter there either
+    way, so the comparison is the residual reached and the time per step."""
+    import numpy as np
+    from paper_1504_02264_amd import warmstart as ws
+    smooth = 32
+    Xs, Ts = [], []
+    t0 = time.perf_counter()
+    for seed in (11, 12, 13, 14):
+        log(f"C3 crops from seed {seed}")
+        X, T = ws.collect_crops("C3", seed, steps=2, skip=1, smooth=smooth, crops=8, rng_seed=seed)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    collect_s = time.perf_counter() - t0
+    net = les.Net(seed=0, lr=1e-3)
+    t0 = time.perf_counter()
+    scale, losses = ws.train(net, X, T, iters=3000, batch=4, lr=1e-3, lr_final=5e-5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, T, Xs, Ts
+    rows = {}
+    for seed in (21, 22):
+        log(f"C3 evaluation, seed {seed}")
+        b = ws.evaluate("C3", seed, steps=args.steps, net=None, skip=1)
+        w = ws.evaluate("C3", seed, steps=args.steps, net=net, scale=scale, skip=1, rule=les.WARM_ALWAYS,
+                        smooth=smooth)
+        for name, r in (("plain", b), ("always", w)):
+            d = rows.setdefault(name, {"resid": [], "iters": [], "ms": []})
+            d["resid"] += [float(x) for x in r["resid"]]
+            d["iters"].append(float(r["iters"].mean()))
+            d["ms"].append(r["ms_per_step"])
+    out = {
+        "metric": "relative Poisson residual at the end of each step (learned start, 1024x1024x96)",
+        "value": float(np.mean(rows["always"]["resid"])),
+        "unit": "relative residual",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "dtype": "f32 LES, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": "C3 1024x1024x96 urban LES; network trained on 8 random 64x128x128 crops per "
+                               "step of building seeds 11-14 (64 crops, 3000 Adam steps), evaluated on seeds "
+                               "21-22 after one plain step", "collect_s": collect_s, "train_s": train_s,
+                   "final_loss": losses[-1][1], "smooth_passes": smooth},
+        "rules": {k: {"resid_per_step": v["resid"], "mean_resid": float(np.mean(v["resid"])),
+                      "sor_iters_per_step": float(np.mean(v["iters"])), "ms_per_step": float(np.mean(v["ms"]))}
+                  for k, v in rows.items()},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_warm_start(args, les, torch):
     """Plain SOR from p_prev against the learned start on held-out C1
     cases (train on seeds 11-14, evaluate on 21-22); network inference is
     inside the timed steps."""
     import numpy as np
     from paper_1504_02264_amd import warmstart as ws
+    if args.workload == "C3":
+        return bench_warm_start_c3(args, les, torch)
     smooth = 32
     Xs, Ts = [], []
     for seed in (11, 12, 13, 14):
@@ -253,7 +310,8 @@ def main():
     ap.add_argument("--no-net", action="store_true",
                     help="skip the warm-start network timing (forward / train step on a 64x128x128 crop)")
     ap.add_argument("--warm-start", action="store_true",
-                    help="instead of the LES line: plain SOR vs the learned start on held-out C1 cases")
+                    help="instead of the LES line: plain SOR vs the learned start on held-out cases "
+                         "(C1 size; with --workload C3, trained on crops of 1024x1024x96 runs)")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events (no roofline object)")

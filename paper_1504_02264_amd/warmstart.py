@@ -55,6 +55,39 @@ def collect(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0):
         g.close()
 
 
+def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0, crops: int = 8,
+                  crop=(64, 128, 128), rng_seed: int = 0):
+    """Like collect, for grids larger than the training crop: after each of
+    the last `steps` steps, `crops` random D x H x W windows (aligned to 4,
+    drawn from numpy PCG64(rng_seed)) of the step's input and target."""
+    import torch
+
+    g = make_case(base, seed)
+    try:
+        if skip:
+            g.step(skip)
+        D, H, W = les.warm_grid(g)
+        cd, ch, cw = crop
+        Xf = torch.empty((D, H, W, 3), device="cuda")
+        Tf = torch.empty((D, H, W), device="cuda")
+        rng = np.random.default_rng(rng_seed)
+        Xs, Ts = [], []
+        for _ in range(steps):
+            les.set_capture(g, Xf, Tf, smooth)
+            g.step(1)
+            for _ in range(crops):
+                z = 4 * int(rng.integers(0, (D - cd) // 4 + 1))
+                y = 4 * int(rng.integers(0, (H - ch) // 4 + 1))
+                x = 4 * int(rng.integers(0, (W - cw) // 4 + 1))
+                Xs.append(Xf[z:z + cd, y:y + ch, x:x + cw].clone())
+                Ts.append(Tf[z:z + cd, y:y + ch, x:x + cw].clone())
+        les.set_capture(g, None, None)
+        torch.cuda.synchronize()
+        return torch.stack(Xs), torch.stack(Ts)
+    finally:
+        g.close()
+
+
 def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None,
           lr: float | None = None, lr_final: float | None = None):
     """Adam on random mini-batches of the pairs; targets are divided by
@@ -98,11 +131,12 @@ def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float
         if net is not None:
             les.set_warm_start(g, net, scale, rule, param, smooth)
         torch.cuda.synchronize()
-        its, taken, rnet, rprev = [], 0, [], []
+        its, taken, rnet, rprev, res = [], 0, [], [], []
         t0 = time.perf_counter()
         for _ in range(steps):
             _, st, it = g.step(1)
             its.append(int(it[0]))
+            res.append(st["resid_last"])
             taken += st["warm_taken"]
             rnet.append(st["warm_r_net_last"])
             rprev.append(st["warm_r_prev_last"])
@@ -111,6 +145,6 @@ def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float
         if net is not None:
             les.set_warm_start(g, None)
         return {"iters": np.array(its), "ms_per_step": ms, "taken": taken,
-                "r_net": np.array(rnet), "r_prev": np.array(rprev)}
+                "r_net": np.array(rnet), "r_prev": np.array(rprev), "resid": np.array(res)}
     finally:
         g.close()

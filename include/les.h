@@ -80,7 +80,7 @@ typedef struct {
                                 INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP) */
     int32_t zero_guess;      /* 1: each solve starts from p = 0 (default 0: previous p) */
     int32_t rebase_every;    /* fold the correction into the base pressure every
-                                R residual checks (16); see les_pressure_solve */
+                                R residual checks (32); see les_pressure_solve */
     int32_t diagnostics;     /* 1: compute ||div u^{n+1}|| and max CFL on the last
                                 step of each les_step call (default 1) */
     int32_t timing;          /* 1: time kernels with HIP events on the handle's stream

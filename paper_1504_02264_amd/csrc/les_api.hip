@@ -408,7 +408,7 @@ int les_default_params(les_params* p) {
     p->bc[LES_ZM] = LES_BC_NOSLIP;
     p->bc[LES_ZP] = LES_BC_FREESLIP;
     p->zero_guess = 0;
-    p->rebase_every = 16;
+    p->rebase_every = 32;
     p->diagnostics = 1;
     p->timing = 0;
     return LES_OK;

@@ -65,8 +65,10 @@ void lesnet_destroy(lesnet* n);
 const char* lesnet_last_error(const lesnet* n);
 
 /* Parameter access: host float32 arrays of exactly lesnet_num_params
- * entries (else LES_EINVAL); synchronous.  lesnet_get_grads returns the
- * gradients of the last lesnet_gradients / lesnet_train_step call. */
+ * entries (else LES_EINVAL); synchronous.  lesnet_set_params leaves the
+ * Adam moments and step count as they are.  lesnet_get_grads returns the
+ * gradients of the last lesnet_gradients / lesnet_train_step call.  One
+ * handle per host thread; handles do not share state. */
 int lesnet_num_params(const lesnet* n, int64_t* count);
 int lesnet_get_params(lesnet* n, float* host, int64_t count);
 int lesnet_set_params(lesnet* n, const float* host, int64_t count);

@@ -723,8 +723,17 @@ __device__ __forceinline__ void p_sub_body(const Geo& g, const PBufs& P, const C
 template <int NT>
 __device__ __forceinline__ double nt_sum(const double* part, int n, int stride = 1) {
     __shared__ double red[NT / 64];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) v += part[(long long)i * stride];
+    // four independent accumulators: four loads in flight per thread
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * NT < n; i += 4 * NT) {
+        v0 += part[(long long)i * stride];
+        v1 += part[(long long)(i + NT) * stride];
+        v2 += part[(long long)(i + 2 * NT) * stride];
+        v3 += part[(long long)(i + 3 * NT) * stride];
+    }
+    for (; i < n; i += NT) v0 += part[(long long)i * stride];
+    double v = (v0 + v1) + (v2 + v3);
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
@@ -734,6 +743,45 @@ __device__ __forceinline__ double nt_sum(const double* part, int n, int stride =
     for (int i = 0; i < NT / 64; ++i) t += red[i];
     __syncthreads();
     return t;   // valid in every thread
+}
+
+// The three sums of the residual bound in one pass: a = sum rel0[2i],
+// b = sum rel1[2i], d = sum rel1[2i+1] (fixed order, every thread gets them).
+template <int NT>
+__device__ __forceinline__ void nt_sum3(const double* rel0, const double* rel1, int n, double& a, double& b,
+                                        double& d) {
+    __shared__ double red3[3][NT / 64];
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, d0 = 0.0, d1 = 0.0;
+    int i = threadIdx.x;
+    for (; i + NT < n; i += 2 * NT) {
+        a0 += rel0[2LL * i];
+        b0 += rel1[2LL * i];
+        d0 += rel1[2LL * i + 1];
+        a1 += rel0[2LL * (i + NT)];
+        b1 += rel1[2LL * (i + NT)];
+        d1 += rel1[2LL * (i + NT) + 1];
+    }
+    if (i < n) {
+        a0 += rel0[2LL * i];
+        b0 += rel1[2LL * i];
+        d0 += rel1[2LL * i + 1];
+    }
+    const double va = wave_sum(a0 + a1), vb = wave_sum(b0 + b1), vd = wave_sum(d0 + d1);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red3[0][wid] = va;
+        red3[1][wid] = vb;
+        red3[2][wid] = vd;
+    }
+    __syncthreads();
+    a = b = d = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+        a += red3[0][w];
+        b += red3[1][w];
+        d += red3[2][w];
+    }
+    __syncthreads();
 }
 
 template <int NT>
@@ -791,9 +839,8 @@ __device__ __forceinline__ void finalize_body(int op, const double* __restrict__
         return;
     }
     if (op == FIN_BOUND) {
-        const double r0s = nt_sum<NT>(rel0, nrel, 2);
-        const double r1s = nt_sum<NT>(rel1, nrel, 2);
-        const double d1s = nt_sum<NT>(rel1 + 1, nrel, 2);
+        double r0s, r1s, d1s;
+        nt_sum3<NT>(rel0, rel1, nrel, r0s, r1s, d1s);
         if (threadIdx.x == 0) {
             ctl->reltmp2 = r0s + r1s;
             const double lbd = fabs(omega - 1.0) / omega * sqrt(d1s) / sqrt(ctl->rhs2);

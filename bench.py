@@ -397,16 +397,22 @@ def main():
     sor_ms, sor_n = timing["sor"]
     if sor_n > 0:
         t_launch = sor_ms / sor_n * 1e-3
-        bytes_per_launch = 8.0 * cells      # per half-sweep, see the design doc
+        fused = variant >= les.NUM_SPLIT_SOR_VARIANTS
+        # per launch: a half-sweep moves 8 B per cell, a fused iteration 12
+        bytes_per_launch = (12.0 if fused else 8.0) * cells
         achieved = bytes_per_launch / t_launch / 1e9
         from paper_1504_02264_amd import profsum
-        tx, kt = les.SOR_VARIANTS[variant]
-        kname = f"k_sor<{tx}, {kt}>"
+        if fused:
+            tx, kt, nw = les.SOR_VARIANTS[variant]
+            kname, what = f"k_sor_rb<{tx}, {nw}, {kt}>", "fused red-black SOR iteration"
+        else:
+            tx, kt = les.SOR_VARIANTS[variant]
+            kname, what = f"k_sor<{tx}, {kt}>", "red-black SOR half-sweep"
         pmc_file = os.path.join(ROOT, "profiles", f"k_sor_traffic_{w.nx}x{w.ny}x{w.nz}.txt")
         tr = profsum.read_traffic(pmc_file, kname)
         out["roofline"] = {
             "bound": "hbm",
-            "kernel": f"{kname} (red-black SOR half-sweep)",
+            "kernel": f"{kname} ({what})",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -423,7 +429,7 @@ def main():
         out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in timing.items()
                                      if v[1] > 0 and k != "sor"}
         # the SOR sweeps are sampled (one check interval in 8): scale to all
-        out["kernel_ms_per_step"]["sor"] = (sor_ms / sor_n) * 2 * float(iters.mean())
+        out["kernel_ms_per_step"]["sor"] = (sor_ms / sor_n) * (1 if fused else 2) * float(iters.mean())
         out["time_to_resid_1e-5_ms"] = (out["kernel_ms_per_step"]["sor"]
                                          + out["kernel_ms_per_step"].get("check", 0.0)
                                          + out["kernel_ms_per_step"].get("rebase", 0.0))

@@ -242,20 +242,31 @@ typedef struct {
 int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
 
 /*
- * Autotuner: times every SOR half-sweep tile variant (row width of 64 or 32
- * half-cells per wavefront x 1, 2, 4 or 8 planes per block) for reps
- * back-to-back red/black pairs on this handle's grid, keeps the fastest
- * for all later sweeps of the handle and reports its index in *chosen
- * (nullable) and the per-variant microseconds per half-sweep in
- * us_per_sweep[LES_NUM_SOR_VARIANTS] (nullable).  Runs on a scratch
- * pressure system: the time-stepping state is unchanged.  Every variant
+ * SOR sweep variants.  0-7: one launch per colour half-sweep (section 2.6),
+ * tiles of 64 or 32 half-cells per wavefront row x 1, 2, 4 or 8 planes per
+ * block (index 2 log2(planes) + (row width == 32)).  8, 9: one launch per
+ * red-black iteration that updates colour 0 and then colour 1 in one pass
+ * over tiles of 30 x 30 x 12 (8) or 62 x 14 x 16 (9) half-cells x rows x
+ * planes, recomputing colour 0 on a one-cell ring around the tile: 12
+ * instead of 16 bytes per cell per iteration; the iterate alternates
+ * between two buffers, so these need an even check_every.  Every variant
  * computes the same per-cell arithmetic, so results are bitwise
- * independent of the choice.  LES_EINVAL unless 1 <= reps <= 1000.
+ * independent of the choice.
+ *
+ * Autotuner: times every variant for reps back-to-back pairs of launches
+ * on this handle's grid, keeps the fastest for all later solves of the
+ * handle and reports its index in *chosen (nullable) and the per-variant
+ * microseconds per half-sweep (for 8 and 9: half a fused iteration; 0 when
+ * not timed because check_every is odd) in
+ * us_per_sweep[LES_NUM_SOR_VARIANTS] (nullable).  Runs on a scratch
+ * pressure system: the time-stepping state is unchanged.  LES_EINVAL
+ * unless 1 <= reps <= 1000.
  */
-#define LES_NUM_SOR_VARIANTS 8
+#define LES_NUM_SOR_VARIANTS 10
 int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sweep);
 
-/* Select a sweep variant by index (0 .. LES_NUM_SOR_VARIANTS-1). */
+/* Select a sweep variant by index (0 .. LES_NUM_SOR_VARIANTS-1); LES_EINVAL
+ * for 8 or 9 with an odd check_every. */
 int les_set_sor_variant(les_handle* h, int32_t variant);
 
 /* Step counter (completed steps). */
@@ -303,12 +314,15 @@ typedef struct {
 int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** out);
 int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out);
 /* Autotuner for the ensemble: times the batched half-sweep over all
- * members for each tile variant (all members on one variant: with the
- * members' working sets together the cache behaviour differs from each one
- * alone) on the members' scratch pressure systems (the state is not
- * touched), reps red/black pairs each, and uses the fastest from the next
- * step on.  les_ensemble_tuning reports the choice and the microseconds
- * per half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]). */
+ * members for each half-sweep variant 0-7 (all members on one variant:
+ * with the members' working sets together the cache behaviour differs from
+ * each one alone) on the members' scratch pressure systems (the state is
+ * not touched), reps red/black pairs each, and uses the fastest from the
+ * next step on.  les_ensemble_tuning reports the choice and the
+ * microseconds per half-sweep of every variant
+ * (us_per_sweep[LES_NUM_SOR_VARIANTS]; 0 for the fused variants, which the
+ * ensemble does not run: a member set to one uses its grid's default
+ * half-sweep). */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);
 int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep);
 const char* les_ensemble_last_error(const les_ensemble* e);

@@ -550,7 +550,10 @@ void build_descriptors(les_ensemble* e) {
         d.max_iter = h->prm.max_iter;
         d.K = h->prm.check_every;
         d.R = h->prm.rebase_every;
-        d.variant = e->variant >= 0 ? e->variant : h->sor_variant;
+        // the ensemble runs half-sweeps: a member tuned to a fused variant
+        // takes its grid's default half-sweep
+        d.variant = e->variant >= 0 ? e->variant
+                                    : (sor_fused(h->sor_variant) ? sor_default_variant(h->g) : h->sor_variant);
         d.singular = h->g.outflow ? 0 : 1;
         d.inflow = h->g.inflow;
         d.nsweep = sor_sweep_blocks(h->g, d.variant);
@@ -796,7 +799,8 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     double best = 1e300;
     int best_v = 0;
     const int saved = e->variant;
-    for (int v = 0; v < kNumSorVariants; ++v) {
+    for (int v = kNumSplitVariants; v < kNumSorVariants; ++v) e->tune_us[v] = 0.0;   // not run here
+    for (int v = 0; v < kNumSplitVariants; ++v) {
         e->variant = v;
         build_descriptors(e);
         for (int q = 0; q < n; ++q) e->h_inst[q].P = e->members[q]->S;

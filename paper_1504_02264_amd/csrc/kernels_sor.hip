@@ -1,6 +1,7 @@
 // Single-instance launches of the red-black SOR machinery (section 2.6):
-// half-sweeps in eight tile variants, fold, rebase, residual check, p mean
-// and the single-block finalize.  Bodies in les_bodies.h.
+// half-sweeps in eight tile variants, fused red-black iterations in two,
+// fold, rebase, residual check, p mean and the single-block finalize.
+// Bodies in les_bodies.h.
 #include "les_bodies.h"
 
 namespace les {
@@ -17,6 +18,23 @@ __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict_
     bool acc;
     if (!sweep_active(ctl, local_iter, acc)) return;
     sor_body<TX, KT>(g, c, pself, poth, rself, omega, acc && rel_part != nullptr, rel_part, lblock());
+}
+
+template <int TX, int NW, int KT>
+__global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restrict__ a0,
+                                                    const float* __restrict__ a1,
+                                                    const float* __restrict__ r0c,
+                                                    const float* __restrict__ r1c,
+                                                    float* __restrict__ b0, float* __restrict__ b1,
+                                                    float omega, int local_iter,
+                                                    double* __restrict__ rel0,
+                                                    double* __restrict__ rel1,
+                                                    const Ctl* __restrict__ ctl) {
+    bool acc;
+    const bool active = sweep_active(ctl, local_iter, acc);
+    if (!active && ctl->done) return;
+    sor_rb_body<TX, NW, KT>(g, a0, a1, r0c, r1c, b0, b1, omega, active && acc && rel0 != nullptr,
+                            !active, rel0, rel1, lblock());
 }
 
 __global__ __launch_bounds__(kBlock) void k_fold(long long n, float* __restrict__ ph0,
@@ -59,9 +77,11 @@ inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock)
 
 }  // namespace
 
-// Sweep variants (row width TX, planes per block KT), chosen per grid.
+// Sweep variants, chosen per grid: half-sweeps (row width TX, planes per
+// block KT) and fused iterations (TX, KT, NW wavefronts per block).
 const SorVariant kSorVariants[kNumSorVariants] = {
-    {64, 1}, {32, 1}, {64, 2}, {32, 2}, {64, 4}, {32, 4}, {64, 8}, {32, 8}};
+    {64, 1, 0}, {32, 1, 0}, {64, 2, 0}, {32, 2, 0}, {64, 4, 0}, {32, 4, 0}, {64, 8, 0}, {32, 8, 0},
+    {32, 12, 16}, {64, 16, 16}};
 
 int sor_default_variant(const Geo& g) {
     const int w64 = ((g.H + 63) / 64) * 64 - g.H;
@@ -71,6 +91,11 @@ int sor_default_variant(const Geo& g) {
 
 unsigned sor_sweep_blocks(const Geo& g, int variant) {
     const int tx = kSorVariants[variant].tx, kt = kSorVariants[variant].kt;
+    if (sor_fused(variant)) {
+        const int txo = tx - 2, tyo = (64 / tx) * kSorVariants[variant].nw - 2;
+        return (unsigned)((g.H + txo - 1) / txo) * (unsigned)((g.ny + tyo - 1) / tyo) *
+               (unsigned)((g.nz + kt - 1) / kt);
+    }
     const int ty = (64 / tx) * (kBlock / 64);
     return (unsigned)((g.H + tx - 1) / tx) * (unsigned)((g.ny + ty - 1) / ty) *
            (unsigned)((g.nz + kt - 1) / kt);
@@ -106,6 +131,27 @@ hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, 
         default: return hipErrorInvalidValue;
     }
 #undef LES_SOR_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parity, float omega,
+                         int local_iter, double* rel0, double* rel1, const Ctl* ctl, int variant) {
+    const dim3 grid(sor_sweep_blocks(g, variant));
+    const float* a0 = parity ? P.pa[0] : P.pd[0];
+    const float* a1 = parity ? P.pa[1] : P.pd[1];
+    float* b0 = parity ? P.pd[0] : P.pa[0];
+    float* b1 = parity ? P.pd[1] : P.pa[1];
+    switch (variant) {
+        case 8:
+            hipLaunchKernelGGL((k_sor_rb<32, 16, 12>), grid, dim3(64 * 16), 0, st, g, a0, a1, P.r0[0],
+                               P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl);
+            break;
+        case 9:
+            hipLaunchKernelGGL((k_sor_rb<64, 16, 16>), grid, dim3(64 * 16), 0, st, g, a0, a1, P.r0[0],
+                               P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

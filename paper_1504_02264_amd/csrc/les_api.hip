@@ -258,7 +258,9 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     const int K = h->prm.check_every;
     const int R = h->prm.rebase_every;
     const float omega = (float)h->prm.omega;
-    const int var = h->sor_variant;
+    // fused iterations alternate pd -> pa -> pd: an even interval ends on pd
+    const int var = (sor_fused(h->sor_variant) && (K & 1)) ? sor_default_variant(g) : h->sor_variant;
+    const bool fused = sor_fused(var);
     const int nrel = (int)sor_sweep_blocks(g, var);
     double* part = h->f.part[0];
     double* rel0 = h->f.part[1];
@@ -276,9 +278,16 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
         for (long long q = 0; q < nb; ++q) {
             const long long cidx = c + q + 1;
             // one check interval in 8 is timed as a whole: 2K back-to-back
-            // half-sweeps between one pair of events
+            // half-sweeps (K fused iterations) between one pair of events
             const bool sample = h->prm.timing && (cidx % 8 == 1);
             auto sweeps = [&]() -> hipError_t {
+                if (fused) {
+                    for (int it = 0; it < K; ++it) {
+                        const hipError_t e = launch_sor_rb(g, st, P, it & 1, omega, it, rel0, rel1, ctl, var);
+                        if (e != hipSuccess) return e;
+                    }
+                    return hipSuccess;
+                }
                 for (int it = 0; it < K; ++it) {
                     hipError_t e = launch_sor(g, st, P, 0, omega, it, rel0, ctl, var);
                     if (e != hipSuccess) return e;
@@ -287,7 +296,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
                 }
                 return hipSuccess;
             };
-            if (sample) CK(timed(h, KN_SOR, cidx, sweeps, 2 * K));
+            if (sample) CK(timed(h, KN_SOR, cidx, sweeps, fused ? K : 2 * K));
             else CK(sweeps());
             CK(launch_finalize(st, FIN_BOUND, nullptr, 0, rel0, rel1, nrel, ctl, h->prm.omega));
             if (cidx % R == 0) {
@@ -328,7 +337,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
 int ensure_solve_arena(les_handle* h) {
     if (h->solve_arena) return LES_OK;
     const size_t cb = align256((size_t)h->g.ctot * sizeof(float));
-    const size_t total = 8 * cb + align256(sizeof(Ctl));
+    const size_t total = 10 * cb + align256(sizeof(Ctl));
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) return set_err(h, LES_ENOMEM, "hipMalloc(solve workspace)", e);
@@ -340,8 +349,9 @@ int ensure_solve_arena(les_handle* h) {
         h->S.pd[c] = (float*)(b + (2 + c) * cb);
         h->S.r0[c] = (float*)(b + (4 + c) * cb);
         h->S.rhs[c] = (float*)(b + (6 + c) * cb);
+        h->S.pa[c] = (float*)(b + (8 + c) * cb);
     }
-    h->ctl_save = (Ctl*)(b + 8 * cb);
+    h->ctl_save = (Ctl*)(b + 10 * cb);
     CK(hipStreamSynchronize(h->stream));
     return LES_OK;
 }
@@ -453,7 +463,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     for (int v = 0; v < kNumSorVariants; ++v) maxsweep = std::max<long long>(maxsweep, sor_sweep_blocks(g, v));
     const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * maxsweep) + 64;
     const size_t pb = align256(nparts * sizeof(double));
-    const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 8 * cb +
+    const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 10 * cb +
                          3 * pb + align256(sizeof(Ctl));
     void* arena = nullptr;
     if (hipMalloc(&arena, total) != hipSuccess) return fail(LES_ENOMEM);
@@ -480,6 +490,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     for (int c = 0; c < 2; ++c) h->f.P.pd[c] = (float*)take(cb);
     for (int c = 0; c < 2; ++c) h->f.P.r0[c] = (float*)take(cb);
     for (int c = 0; c < 2; ++c) h->f.P.rhs[c] = (float*)take(cb);
+    for (int c = 0; c < 2; ++c) h->f.P.pa[c] = (float*)take(cb);
     for (int q = 0; q < 3; ++q) h->f.part[q] = (double*)take(pb);
     h->f.ctl = (Ctl*)take(align256(sizeof(Ctl)));
 
@@ -871,17 +882,29 @@ int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sw
     double best = 1e300;
     int best_v = h->sor_variant;
     for (int v = 0; v < kNumSorVariants; ++v) {
-        for (int w = 0; w < 2; ++w) CK(launch_sor(g, s, h->S, w & 1, 1.0f, 0, nullptr, h->f.ctl, v));
-        CK(hipEventRecord(a, s));
-        for (int r = 0; r < reps; ++r) {
-            CK(launch_sor(g, s, h->S, 0, 1.0f, 0, nullptr, h->f.ctl, v));
-            CK(launch_sor(g, s, h->S, 1, 1.0f, 0, nullptr, h->f.ctl, v));
+        if (sor_fused(v) && (h->prm.check_every & 1)) {   // needs an even check interval
+            if (us_per_sweep) us_per_sweep[v] = 0.0;
+            continue;
         }
+        // two launches: two half-sweeps, or two fused iterations (half a
+        // fused iteration is charged per half-sweep below)
+        auto pair = [&]() -> hipError_t {
+            for (int w = 0; w < 2; ++w) {
+                const hipError_t e = sor_fused(v)
+                                         ? launch_sor_rb(g, s, h->S, w, 1.0f, 0, nullptr, nullptr, h->f.ctl, v)
+                                         : launch_sor(g, s, h->S, w, 1.0f, 0, nullptr, h->f.ctl, v);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        CK(pair());
+        CK(hipEventRecord(a, s));
+        for (int r = 0; r < reps; ++r) CK(pair());
         CK(hipEventRecord(b, s));
         CK(hipEventSynchronize(b));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, a, b));
-        const double us = 1e3 * ms / (2.0 * reps);
+        const double us = 1e3 * ms / ((sor_fused(v) ? 4.0 : 2.0) * reps);
         if (us_per_sweep) us_per_sweep[v] = us;
         if (us < best) {
             best = us;
@@ -891,6 +914,7 @@ int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sw
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->S.pd[c], g.ctot, 0.f));
+    for (int c = 0; c < 2; ++c) CK(launch_fill(s, h->S.pa[c], g.ctot, 0.f));
     CK(hipStreamSynchronize(s));
     h->sor_variant = best_v;
     if (chosen) *chosen = best_v;
@@ -899,6 +923,8 @@ int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sw
 
 int les_set_sor_variant(les_handle* h, int32_t variant) {
     if (!h || variant < 0 || variant >= kNumSorVariants) return LES_EINVAL;
+    if (sor_fused(variant) && (h->prm.check_every & 1))
+        return set_err(h, LES_EINVAL, "fused sweep variants need an even check interval");
     h->sor_variant = variant;
     return LES_OK;
 }

@@ -71,12 +71,19 @@ __device__ __forceinline__ bool half_cell(const Geo& g, long long t, int& ii, in
 
 // Diagonal of A at 0-based cell (i0, j0, k0): 1/h^2 per interior neighbour,
 // nothing across a wall or the inflow face (Neumann), 2/h^2 across the
-// outflow face (p = 0 on the face).
+// outflow face (p = 0 on the face); its x, y and z parts, summed in that
+// order.
+__device__ __forceinline__ float diag_x(const Geo& g, int i0) {
+    return (i0 > 0 ? g.cx : 0.f) + (i0 < g.nx - 1 ? g.cx : (g.outflow ? 2.f * g.cx : 0.f));
+}
+__device__ __forceinline__ float diag_y(const Geo& g, int j0) {
+    return (j0 > 0 ? g.cy : 0.f) + (j0 < g.ny - 1 ? g.cy : 0.f);
+}
+__device__ __forceinline__ float diag_z(const Geo& g, int k0) {
+    return (k0 > 0 ? g.cz : 0.f) + (k0 < g.nz - 1 ? g.cz : 0.f);
+}
 __device__ __forceinline__ float diag_of(const Geo& g, int i0, int j0, int k0) {
-    const float dxx = (i0 > 0 ? g.cx : 0.f) + (i0 < g.nx - 1 ? g.cx : (g.outflow ? 2.f * g.cx : 0.f));
-    const float dyy = (j0 > 0 ? g.cy : 0.f) + (j0 < g.ny - 1 ? g.cy : 0.f);
-    const float dzz = (k0 > 0 ? g.cz : 0.f) + (k0 < g.nz - 1 ? g.cz : 0.f);
-    return dxx + dyy + dzz;
+    return diag_x(g, i0) + diag_y(g, j0) + diag_z(g, k0);
 }
 
 // ------------------------------------------------------------------ les
@@ -493,6 +500,21 @@ __device__ __forceinline__ void diag_body(const Geo& g, const float* __restrict_
 // Every few checks the correction is folded into the base (TwoSum, no
 // loss) and r0 recomputed.  Residuals ||rhs - A p|| are float64.
 
+// ------------------------------------------------------- point update
+// One cell's update from its six neighbours of the other colour, its own
+// correction p and its r0: returns p + reltmp, reltmp = omega (cn1
+// (sum_nb cn_nb p_nb - r0) - p).  Contraction is pinned (explicit fmaf,
+// no other fusion) so that every kernel that updates a cell rounds alike.
+__device__ __forceinline__ float sor_point(float west, float east, float ps, float pn, float pb,
+                                           float pt, float cx, float cy, float cz, float diag,
+                                           float r, float p, float omega, float& reltmp) {
+#pragma clang fp contract(off)
+    const float nb = fmaf(cz, pb + pt, fmaf(cy, ps + pn, cx * (west + east)));
+    const float inv = 1.0f / diag;
+    reltmp = omega * fmaf(inv, nb - r, -p);
+    return p + reltmp;
+}
+
 // ---------------------------------------------------------- half-sweep
 // Colour c: for every cell of colour c,
 //   reltmp = omega (cn1 (sum_nb cn_nb p_nb - rhs) - p);  p += reltmp
@@ -532,7 +554,7 @@ __device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict_
     const int k_end = min(g.nz, k_begin + KT);
     const bool col_ok = ii < g.H && j0 < g.ny;
     const float cx = g.cx, cy = g.cy, cz = g.cz;
-    const float dyy = (j0 > 0 ? cy : 0.f) + (j0 < g.ny - 1 ? cy : 0.f);
+    const float dyy = diag_y(g, j0);
     long long e = col_ok ? g.col(ii, j0, k_begin) : 0;
     float pb = col_ok ? poth[e - g.SP] : 0.f;
     float pc = col_ok ? poth[e] : 0.f;
@@ -551,14 +573,10 @@ __device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict_
             const float west = s ? pc : pw;
             const float east = s ? pe : pc;
             const float ps = poth[e - g.S], pn = poth[e + g.S];
-            const float nb = cx * (west + east) + cy * (ps + pn) + cz * (pb + pt);
-            const float dxx = (i0 > 0 ? cx : 0.f) + (i0 < g.nx - 1 ? cx : (g.outflow ? 2.f * cx : 0.f));
-            const float dzz = (k0 > 0 ? cz : 0.f) + (k0 < g.nz - 1 ? cz : 0.f);
-            const float diag = dxx + dyy + dzz;
-            const float inv = 1.0f / diag;
-            const float p = pself[e];
-            const float reltmp = omega * (inv * (nb - rself[e]) - p);
-            pself[e] = p + reltmp;
+            const float diag = diag_x(g, i0) + dyy + diag_z(g, k0);
+            float reltmp;
+            pself[e] = sor_point(west, east, ps, pn, pb, pt, cx, cy, cz, diag, rself[e], pself[e],
+                                 omega, reltmp);
             if (acc) {
                 const double rt = (double)reltmp;
                 r2 += rt * rt;
@@ -585,6 +603,159 @@ __device__ __forceinline__ bool sweep_active(const Ctl* ctl, int it, bool& acc) 
     const int m = ctl->m, K = ctl->K, mx = ctl->max_iter;
     acc = (m + it + 1 == min(m + K, mx));
     return !(ctl->done || m + it >= mx);
+}
+
+// ------------------------------------------- fused red-black iteration
+// One whole SOR iteration in one pass: colour 0 from the old colour-1
+// values, then colour 1 from the new colour-0 values, with every read from
+// the old arrays (a0, a1) and every write to the other pair (b0, b1), so
+// blocks never see each other's results.  Each block owns a tile of TXO =
+// TX-2 half-cells by TYO = TYB-2 rows by KT planes; it also updates colour
+// 0 on a one-cell ring around the tile (halo lanes 0 and TX-1, halo rows 0
+// and TYB-1, planes k_begin-1 and k_end), which colour 1 at the tile's edge
+// needs, and writes only its own tile.  The per-cell arithmetic is that of
+// the half-sweeps (sor_point), so the result equals two half-sweeps bit for
+// bit, for 12 bytes per cell per iteration instead of 16.
+//
+// A block is NW wavefronts of 64/TX rows of TX lanes and marches up the
+// planes: at step q it updates colour 0 on plane q, publishes the row in an
+// LDS ring of three planes, and after one barrier updates colour 1 on plane
+// q-1 from its own new colour-0 planes q-2..q (registers), its lanes' east
+// and west values (cross-lane shuffles) and the rows above and below (LDS).
+// Loads of plane q+1 are issued a step ahead.  With copy set (an
+// iteration past max_iter inside the last check interval) the block copies
+// a to b, so the result stays in the buffer the interval ends on.
+template <int TX, int NW, int KT>
+__device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restrict__ a0,
+                                            const float* __restrict__ a1,
+                                            const float* __restrict__ r0c,
+                                            const float* __restrict__ r1c, float* __restrict__ b0,
+                                            float* __restrict__ b1, float omega, bool acc, bool copy,
+                                            double* __restrict__ rel0, double* __restrict__ rel1,
+                                            unsigned lb) {
+    constexpr int RPW = 64 / TX;
+    constexpr int TYB = RPW * NW;
+    constexpr int TXO = TX - 2, TYO = TYB - 2;
+    __shared__ float ring[3][TYB][TX];
+    __shared__ double red3[3][NW];
+    const unsigned nbx = (unsigned)(g.H + TXO - 1) / TXO;
+    const unsigned nby = (unsigned)(g.ny + TYO - 1) / TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int tx = lane % TX;
+    const int row = (threadIdx.x >> 6) * RPW + lane / TX;
+    const int ii = (int)bx * TXO - 1 + tx;
+    const int j = (int)by * TYO - 1 + row;
+    const int k_begin = (int)bk * KT;
+    const int k_end = min(g.nz, k_begin + KT);
+    const bool col_ok = ii >= 0 && ii < g.H && j >= 0 && j < g.ny;
+    const bool inner = col_ok && tx >= 1 && tx <= TX - 2 && row >= 1 && row <= TYB - 2;
+    const bool edge_lane = tx == 0 || tx == TX - 1;
+    const int edge_off = tx == 0 ? -1 : 1;
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    const float dyy = diag_y(g, j);
+    const int qa = k_begin - 1;
+    const long long e0 = col_ok ? g.col(ii, j, qa) : 0;
+    // loads of step q: a1 one plane up, a1 in the rows below and above, the
+    // edge lane's a1 east or west, a0 and r0 on plane q, r1 on plane q-1
+    struct Step { float up, south, north, edge, p0, rr0, rr1; };
+    auto fetch = [&](int q, Step& f) {
+        const long long e = e0 + (long long)(q - qa) * g.SP;
+        const bool pl = col_ok && q >= 0 && q < g.nz;
+        f.up = (col_ok && q + 1 <= g.nz) ? a1[e + g.SP] : 0.f;
+        f.south = pl ? a1[e - g.S] : 0.f;
+        f.north = pl ? a1[e + g.S] : 0.f;
+        f.edge = (pl && edge_lane) ? a1[e + edge_off] : 0.f;
+        f.p0 = pl ? a0[e] : 0.f;
+        f.rr0 = pl ? r0c[e] : 0.f;
+        f.rr1 = (col_ok && q - 1 >= k_begin && q - 1 < k_end) ? r1c[e - g.SP] : 0.f;
+    };
+    // old colour 1 on planes q-1 (bm) and q (bc); new colour 0 on q-2, q-1
+    float bm = (col_ok && qa - 1 >= -1) ? a1[e0 - g.SP] : 0.f;
+    float bc = col_ok ? a1[e0] : 0.f;
+    float rm2 = 0.f, rm1 = 0.f;
+    double r2a = 0.0, r2b = 0.0, d2b = 0.0;
+    Step cur, nxt;
+    fetch(qa, cur);
+    long long e = e0;
+    for (int q = qa; q <= k_end; ++q) {
+        if (q < k_end) fetch(q + 1, nxt);
+        // colour 0 at (ii, j, q)
+        float be = __shfl_down(bc, 1, TX);
+        float bw = __shfl_up(bc, 1, TX);
+        if (tx == TX - 1) be = cur.edge;
+        if (tx == 0) bw = cur.edge;
+        const int s = (j + q) & 1;
+        const int i0 = 2 * ii + s;
+        float rq = 0.f;
+        if (col_ok && q >= 0 && q < g.nz && i0 < g.nx) {
+            const float diag = diag_x(g, i0) + dyy + diag_z(g, q);
+            float rt = 0.f;
+            rq = copy ? cur.p0
+                      : sor_point(s ? bc : bw, s ? be : bc, cur.south, cur.north, bm, cur.up, cx, cy,
+                                  cz, diag, cur.rr0, cur.p0, omega, rt);
+            if (inner && q >= k_begin && q < k_end) {
+                b0[e] = rq;
+                if (acc) r2a += (double)rt * (double)rt;
+            }
+        }
+        ring[(q - qa) % 3][row][tx] = rq;
+        __syncthreads();
+        // colour 1 at (ii, j, q-1)
+        const int qb = q - 1;
+        if (qb >= k_begin) {
+            const int sl = (qb - qa) % 3;
+            const float re = __shfl_down(rm1, 1, TX);
+            const float rw = __shfl_up(rm1, 1, TX);
+            const int sb = (1 + j + qb) & 1;
+            const int i1 = 2 * ii + sb;
+            if (inner && i1 < g.nx) {
+                const float diag = diag_x(g, i1) + dyy + diag_z(g, qb);
+                float rt = 0.f;
+                const float v = copy ? bm
+                                     : sor_point(sb ? rm1 : rw, sb ? re : rm1, ring[sl][row - 1][tx],
+                                                 ring[sl][row + 1][tx], rm2, rq, cx, cy, cz, diag,
+                                                 cur.rr1, bm, omega, rt);
+                b1[e - g.SP] = v;
+                if (acc) {
+                    const double rd = (double)rt;
+                    r2b += rd * rd;
+                    d2b += ((double)diag * rd) * ((double)diag * rd);
+                }
+            }
+        }
+        bm = bc;
+        bc = cur.up;
+        rm2 = rm1;
+        rm1 = rq;
+        cur = nxt;
+        e += g.SP;
+    }
+    if (acc) {
+        const double va = wave_sum(r2a), vb = wave_sum(r2b), vd = wave_sum(d2b);
+        const int wid = threadIdx.x >> 6;
+        if (lane == 0) {
+            red3[0][wid] = va;
+            red3[1][wid] = vb;
+            red3[2][wid] = vd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0, td = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                ta += red3[0][w];
+                tb += red3[1][w];
+                td += red3[2][w];
+            }
+            rel0[2 * lb] = ta;
+            rel0[2 * lb + 1] = 0.0;
+            rel1[2 * lb] = tb;
+            rel1[2 * lb + 1] = td;
+        }
+    }
 }
 
 // ------------------------------------------------------------- fold
@@ -849,12 +1020,16 @@ __device__ __forceinline__ void finalize_body(int op, const double* __restrict__
         }
         return;
     }
-    if (op == FIN_CHECK && ctl->skip) {
-        if (threadIdx.x == 0) {
-            ctl->m = min(ctl->m + ctl->K, ctl->max_iter);
-            ctl->skip = 0;
+    if (op == FIN_CHECK) {
+        const bool skip = ctl->skip != 0;
+        __syncthreads();   // every thread has read the flag before thread 0 clears it
+        if (skip) {
+            if (threadIdx.x == 0) {
+                ctl->m = min(ctl->m + ctl->K, ctl->max_iter);
+                ctl->skip = 0;
+            }
+            return;
         }
-        return;
     }
     const double s = nt_sum<NT>(part, n);
     if (threadIdx.x != 0) return;

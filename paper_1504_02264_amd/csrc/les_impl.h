@@ -88,6 +88,7 @@ struct PBufs {           // one pressure system in colour layout
     float* pd[2];        // correction
     float* r0[2];        // residual of the base, float32
     float* rhs[2];
+    float* pa[2];        // second correction buffer of the fused sweeps (zero padding)
 };
 
 struct DevFields {
@@ -191,13 +192,22 @@ hipError_t launch_rebase(const Geo& g, hipStream_t st, const PBufs& P, double* p
                          const double* rel0, const double* rel1, int nrel, Ctl* ctl, int decide);
 hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                         const double* rel0, const double* rel1, int nrel, Ctl* ctl);
-struct SorVariant { int tx, kt; };
-constexpr int kNumSorVariants = 8;
+// Sweep variants: half-sweeps (nw = 0; row width tx, planes per block kt)
+// and fused red-black iterations (nw wavefronts per block; needs an even
+// check interval, the iterate alternating between pd and pa).
+struct SorVariant { int tx, kt, nw; };
+constexpr int kNumSplitVariants = 8;
+constexpr int kNumSorVariants = 10;
 extern const SorVariant kSorVariants[kNumSorVariants];
+inline bool sor_fused(int variant) { return variant >= kNumSplitVariants; }
 int sor_default_variant(const Geo& g);
+// sweep blocks per launch: per half-sweep, or per iteration when fused
 unsigned sor_sweep_blocks(const Geo& g, int variant);
 hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, float omega,
                       int local_iter, double* rel_part, const Ctl* ctl, int variant);
+// one fused iteration: parity 0 reads pd and writes pa, parity 1 the reverse
+hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parity, float omega,
+                         int local_iter, double* rel0, double* rel1, const Ctl* ctl, int variant);
 hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
                           const PBufs& P);
 hipError_t launch_bc(const Geo& g, hipStream_t st, float* u, float* v, float* w);

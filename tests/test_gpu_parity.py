@@ -298,20 +298,59 @@ def test_sor_variants_bitwise_identical():
             assert np.array_equal(p, ref[0]), v
     chosen, us = g.autotune(reps=5)
     assert 0 <= chosen < les.NUM_SOR_VARIANTS and np.all(us > 0)
+    # and a solve on the chosen variant again gives the same answer
+    p, st, rc = g.pressure_solve(rhs, None, tol=1e-5)
+    assert st["iters"] == ref[1] and np.array_equal(p, ref[0])
+
+
+@pytest.mark.parametrize("max_iter", [13, 14, 15, 16])
+def test_fused_variants_truncated_interval(max_iter):
+    """A solve stopped by max_iter inside a check interval (K = 4) leaves
+    the fused iterations' alternating buffers in the state the half-sweeps
+    reach: same iterate bit for bit, same count, for an odd and an even
+    number of iterations in the last interval."""
+    nx, ny, nz = 40, 33, 21
+    g = les.LES(nx, ny, nz, 2.0, 2.0, 1.0, 0.05)
+    try:
+        rhs = random_rhs(nx, ny, nz, seed=12, smooth=1)
+        out = []
+        for v in (5, 8, 9):
+            g.set_sor_variant(v)
+            p, st, rc = g.pressure_solve(rhs, None, tol=1e-12, max_iter=max_iter)
+            assert rc == les.LES_NOT_CONVERGED and st["iters"] == max_iter, v
+            out.append(p)
+        for p in out[1:]:
+            assert np.array_equal(p, out[0])
+    finally:
+        g.close()
+
+
+def test_fused_variants_need_an_even_check_interval():
+    g = les.LES(20, 18, 10, 2.0, 2.0, 1.0, 0.05, check_every=3)
+    try:
+        with pytest.raises(les.LesError):
+            g.set_sor_variant(8)
+        g.set_sor_variant(5)
+        _, us = g.autotune(reps=2)
+        assert us[8] == 0 and us[9] == 0 and np.all(us[:8] > 0)
+    finally:
+        g.close()
 
 
 def test_step_independent_of_sor_variant():
     nx, ny, nz = 33, 17, 9
     mask, prof = urban_case(nx, ny, nz, 4, hmax=5)
     out = []
-    for v in (0, 7):
+    for v in (0, 7, 8, 9):
         g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
         g.set_sor_variant(v)
         g.set_inflow(prof, 0.01, 4)
         g.step(2)
         out.append(g.get_fields())
-    for x, y in zip(*out):
-        assert np.array_equal(x, y)
+        g.close()
+    for other in out[1:]:
+        for x, y in zip(out[0], other):
+            assert np.array_equal(x, y)
 
 
 # ------------------------------------------------------------- ensemble

@@ -317,6 +317,9 @@ def main():
                     help="do not bracket kernels with HIP events (no roofline object)")
     ap.add_argument("--max-iter", type=int, default=None,
                     help="cap SOR iterations per step (profiling runs only; not the benchmark)")
+    ap.add_argument("--sor-variant", type=int, default=None, metavar="V",
+                    help="run SOR sweep variant V instead of the autotuner's choice (profiling "
+                         "runs: a profiler's per-dispatch overhead can change that choice)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run 5 plain torch copies of MB megabytes (the known-size kernel "
                          "that scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -352,8 +355,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
     g.set_inflow(prof, w.noise_amp, w.seed)
-    variant, us = g.autotune(reps=20)
+    variant, us = g.autotune(reps=50)
     log(f"autotune: SOR sweep variant {variant}; us per half-sweep {[round(x, 2) for x in us]}")
+    if args.sor_variant is not None:
+        variant = args.sor_variant
+        g.set_sor_variant(variant)
+        log(f"SOR sweep variant {variant} as asked")
     log(f"workload {w.name} {w.nx}x{w.ny}x{w.nz} ({cells} cells); warmup {args.warmup} steps")
     if args.warmup:
         g.step(args.warmup)

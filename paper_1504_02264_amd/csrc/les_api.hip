@@ -244,6 +244,36 @@ void tresolve(les_handle* h, long long last_check) {
     h->tev_used = 0;
 }
 
+// ----------------------------------------------------- solve graphs
+// Graph cache of run_solve, keyed by the pressure system and the sweep
+// settings baked into the captured launches; the least recently used entry
+// is replaced.
+SolveGraph* solve_graph(les_handle* h, const PBufs& P, int var, int K, int R, double omega) {
+    SolveGraph* best = &h->sgraph[0];
+    for (SolveGraph& c : h->sgraph) {
+        if (c.pd == P.pd[0] && c.ph == P.ph[0] && c.rhs == P.rhs[0] && c.variant == var && c.K == K &&
+            c.R == R && c.omega == omega) {
+            c.used = ++h->sgraph_tick;
+            return &c;
+        }
+        if (c.used < best->used) best = &c;
+    }
+    for (hipGraphExec_t& ex : best->exec)
+        if (ex) {
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+    best->pd = P.pd[0];
+    best->ph = P.ph[0];
+    best->rhs = P.rhs[0];
+    best->variant = var;
+    best->K = K;
+    best->R = R;
+    best->omega = omega;
+    best->used = ++h->sgraph_tick;
+    return best;
+}
+
 // ------------------------------------------------------------- SOR driver
 // Preconditions: ctl initialised, P.rhs filled, ctl->rhs2 computed.
 // Runs the set-up rebase, then check intervals of K iterations (two
@@ -266,44 +296,88 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     double* rel0 = h->f.part[1];
     double* rel1 = h->f.part[2];
 
+    // one check interval: K iterations, the bound, then the check (or,
+    // every R-th interval, fold + rebase + check)
+    auto interval = [&](long long cidx) -> hipError_t {
+        // one check interval in 8 is timed as a whole: 2K back-to-back
+        // half-sweeps (K fused iterations) between one pair of events
+        const bool sample = h->prm.timing && (cidx % 8 == 1);
+        auto sweeps = [&]() -> hipError_t {
+            if (fused) {
+                for (int it = 0; it < K; ++it) {
+                    const hipError_t e = launch_sor_rb(g, st, P, it & 1, omega, it, rel0, rel1, ctl, var);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            }
+            for (int it = 0; it < K; ++it) {
+                hipError_t e = launch_sor(g, st, P, 0, omega, it, rel0, ctl, var);
+                if (e != hipSuccess) return e;
+                e = launch_sor(g, st, P, 1, omega, it, rel1, ctl, var);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        hipError_t e = sample ? timed(h, KN_SOR, cidx, sweeps, fused ? K : 2 * K) : sweeps();
+        if (e != hipSuccess) return e;
+        e = launch_finalize(st, FIN_BOUND, nullptr, 0, rel0, rel1, nrel, ctl, h->prm.omega);
+        if (e != hipSuccess) return e;
+        if (cidx % R == 0) {
+            e = launch_fold(g, st, P, ctl);
+            if (e != hipSuccess) return e;
+            return timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); });
+        }
+        return timed(h, KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); });
+    };
+    // Without timing, aligned runs of kSolveGraphChecks intervals replay a
+    // captured graph (its kernels read every decision from the control
+    // block, so a replay equals the launches it was captured from).
+    SolveGraph* sg = nullptr;
+    if (!h->prm.timing && st != nullptr && R % kSolveGraphChecks == 0) sg = solve_graph(h, P, var, K, R, h->prm.omega);
+    auto replay = [&](bool ends_with_rebase) -> int {
+        hipGraphExec_t& ex = sg->exec[ends_with_rebase ? 1 : 0];
+        if (!ex) {
+            // representative interval numbers: the rebase pattern within an
+            // aligned run depends only on whether it ends on a multiple of R
+            const long long c0 = ends_with_rebase ? R - kSolveGraphChecks : 0;
+            hipGraph_t gph = nullptr;
+            CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int q = 0; q < kSolveGraphChecks && e == hipSuccess; ++q) e = interval(c0 + q + 1);
+            const hipError_t ce = hipStreamEndCapture(st, &gph);
+            CK(e);
+            CK(ce);
+            const hipError_t ie = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gph);
+            CK(ie);
+        }
+        CK(hipGraphLaunch(ex, st));
+        return LES_OK;
+    };
+
     CK(launch_fold(g, st, P, ctl));
     CK(timed(h, KN_REBASE, 0, [&] { return launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0); }));
     const long long n_checks = max_iter > 0 ? ((long long)max_iter + K - 1) / K : 0;
     long long c = 0;
-    int batch = 2;
+    // batches of 2, 2, 4 intervals (a solve that converges at once is
+    // noticed early), then 8, 16, 32, 64: from interval 8 on every batch
+    // starts on a multiple of kSolveGraphChecks
+    static const int kBatches[] = {2, 2, 4, 8, 16, 32, 64};
+    int bi = 0;
     int slot = 0;
     bool pending = false;
     while (c < n_checks) {
-        const long long nb = std::min<long long>(batch, n_checks - c);
-        for (long long q = 0; q < nb; ++q) {
-            const long long cidx = c + q + 1;
-            // one check interval in 8 is timed as a whole: 2K back-to-back
-            // half-sweeps (K fused iterations) between one pair of events
-            const bool sample = h->prm.timing && (cidx % 8 == 1);
-            auto sweeps = [&]() -> hipError_t {
-                if (fused) {
-                    for (int it = 0; it < K; ++it) {
-                        const hipError_t e = launch_sor_rb(g, st, P, it & 1, omega, it, rel0, rel1, ctl, var);
-                        if (e != hipSuccess) return e;
-                    }
-                    return hipSuccess;
-                }
-                for (int it = 0; it < K; ++it) {
-                    hipError_t e = launch_sor(g, st, P, 0, omega, it, rel0, ctl, var);
-                    if (e != hipSuccess) return e;
-                    e = launch_sor(g, st, P, 1, omega, it, rel1, ctl, var);
-                    if (e != hipSuccess) return e;
-                }
-                return hipSuccess;
-            };
-            if (sample) CK(timed(h, KN_SOR, cidx, sweeps, fused ? K : 2 * K));
-            else CK(sweeps());
-            CK(launch_finalize(st, FIN_BOUND, nullptr, 0, rel0, rel1, nrel, ctl, h->prm.omega));
-            if (cidx % R == 0) {
-                CK(launch_fold(g, st, P, ctl));
-                CK(timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); }));
+        const long long nb = std::min<long long>(kBatches[bi], n_checks - c);
+        long long q = 0;
+        while (q < nb) {
+            const long long c0 = c + q;   // intervals c0+1, ...
+            if (sg && c0 % kSolveGraphChecks == 0 && q + kSolveGraphChecks <= nb) {
+                const int rc = replay((c0 + kSolveGraphChecks) % R == 0);
+                if (rc != LES_OK) return rc;
+                q += kSolveGraphChecks;
             } else {
-                CK(timed(h, KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); }));
+                CK(interval(c0 + 1));
+                q += 1;
             }
         }
         c += nb;
@@ -315,7 +389,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
         }
         pending = true;
         slot = 1 - slot;
-        batch = std::min(batch * 2, 64);
+        if (bi + 1 < (int)(sizeof kBatches / sizeof kBatches[0])) ++bi;
     }
     CK(hipMemcpyAsync(h->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -524,6 +598,9 @@ void les_destroy(les_handle* h) {
     for (int q = 0; q < 2; ++q)
         if (h->ev[q]) (void)hipEventDestroy(h->ev[q]);
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    for (les::SolveGraph& c : h->sgraph)
+        for (hipGraphExec_t ex : c.exec)
+            if (ex) (void)hipGraphExecDestroy(ex);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
 }

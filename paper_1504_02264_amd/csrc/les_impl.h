@@ -116,6 +116,21 @@ struct SolveParams {
 
 }  // namespace les
 
+namespace les {
+// Captured runs of kSolveGraphChecks check intervals of one pressure
+// system (exec[0]: check intervals only; exec[1]: the last one a rebase).
+constexpr int kSolveGraphChecks = 8;
+struct SolveGraph {
+    const float* pd = nullptr;
+    const float* ph = nullptr;
+    const float* rhs = nullptr;
+    int variant = -1, K = 0, R = 0;
+    double omega = 0.0;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    uint64_t used = 0;
+};
+}  // namespace les
+
 struct les_handle {
     int device = 0;
     les::Geo g{};
@@ -149,6 +164,8 @@ struct les_handle {
     les::Ctl* h_ctl = nullptr;   // pinned mirror of the control block
     int* h_flag = nullptr;       // pinned, 2 slots for pipelined flag reads
     hipEvent_t ev[2] = {nullptr, nullptr};
+    les::SolveGraph sgraph[3];   // run_solve's graph cache (timing off)
+    uint64_t sgraph_tick = 0;
     // learned warm start and training-pair capture (warm.hip)
     lesnet* warm_net = nullptr;
     double warm_scale = 1.0;

@@ -18,15 +18,17 @@ import numpy as np
 import paper_1504_02264_amd as les
 
 
-def make_case(base: str, seed: int, **params):
+def make_case(base: str, seed: int, tune: bool = False, **params):
     """An LES handle for workload `base` with buildings and inflow noise
-    drawn from `seed`."""
+    drawn from `seed`; with tune, its SOR sweep variant autotuned."""
     from les_inputs import WORKLOADS, make_workload_inputs
 
     w = dataclasses.replace(WORKLOADS[base], seed=seed)
     mask, prof = make_workload_inputs(w)
     g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask, **params)
     g.set_inflow(prof, w.noise_amp, seed)
+    if tune:
+        g.autotune(reps=10)
     return g
 
 
@@ -56,13 +58,13 @@ def collect(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0):
 
 
 def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0, crops: int = 8,
-                  crop=(64, 128, 128), rng_seed: int = 0):
+                  crop=(64, 128, 128), rng_seed: int = 0, tune: bool = True):
     """Like collect, for grids larger than the training crop: after each of
     the last `steps` steps, `crops` random D x H x W windows (aligned to 4,
     drawn from numpy PCG64(rng_seed)) of the step's input and target."""
     import torch
 
-    g = make_case(base, seed)
+    g = make_case(base, seed, tune=tune)
     try:
         if skip:
             g.step(skip)
@@ -86,6 +88,16 @@ def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int =
         return torch.stack(Xs), torch.stack(Ts)
     finally:
         g.close()
+
+
+def mirror_y(X, T):
+    """The pairs and their mirror images in y.  The y walls carry the same
+    boundary condition on both sides, so the pressure operator commutes
+    with the reflection j -> ny-1-j and a mirrored pair (input and target
+    reflected alike) is as valid a training pair as the original."""
+    import torch
+
+    return (torch.cat([X, X.flip(2)]).contiguous(), torch.cat([T, T.flip(2)]).contiguous())
 
 
 def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None,
@@ -118,13 +130,14 @@ def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=Non
 
 
 def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float = 1.0,
-             skip: int = 0, rule: int = les.WARM_RESIDUAL, param: int = 0, smooth: int = 0):
+             skip: int = 0, rule: int = les.WARM_RESIDUAL, param: int = 0, smooth: int = 0,
+             tune: bool = False):
     """Iterations per step and wall ms per step of `steps` steps (after
     `skip` plain steps), warm-started by `net` if given (choice `rule`,
-    `param`, see les_set_warm_start)."""
+    `param`, see les_set_warm_start); with tune, on the autotuned sweep."""
     import torch
 
-    g = make_case(base, seed)
+    g = make_case(base, seed, tune=tune)
     try:
         if skip:
             g.step(skip)

@@ -150,19 +150,20 @@ def test_choice_follows_the_residuals():
 
 
 def test_learned_start_saves_iterations_on_held_out_cases():
-    """Train on pairs captured from C1-size runs with building seeds 11-14,
-    then run held-out seeds 21 and 22: starting each solve from the
-    network's (smoothed) proposal lowers the mean SOR iteration count at
-    the same tolerance.  Training and the runs are deterministic."""
+    """Train on pairs captured from C1-size runs with building seeds 11-14
+    (and their mirror images in y), then run held-out seeds 21 and 22:
+    starting each solve from the network's (smoothed) proposal lowers the
+    mean SOR iteration count at the same tolerance.  Training and the runs
+    are deterministic."""
     from paper_1504_02264_amd import warmstart as ws
 
-    smooth = 32
+    smooth = 16
     Xs, Ts = [], []
     for seed in (11, 12, 13, 14):
         X, T, _ = ws.collect("C1", seed, steps=24, skip=2, smooth=smooth)
         Xs.append(X)
         Ts.append(T)
-    X, T = torch.cat(Xs), torch.cat(Ts)
+    X, T = ws.mirror_y(torch.cat(Xs), torch.cat(Ts))
     print(f"  {X.shape[0]} training pairs", flush=True)
     net = les.Net(seed=0, lr=1e-3)
     try:

@@ -131,13 +131,14 @@ def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=Non
 
 def evaluate(base: str, seed: int, steps: int, net: les.Net | None, scale: float = 1.0,
              skip: int = 0, rule: int = les.WARM_RESIDUAL, param: int = 0, smooth: int = 0,
-             tune: bool = False):
+             tune: bool = False, **params):
     """Iterations per step and wall ms per step of `steps` steps (after
     `skip` plain steps), warm-started by `net` if given (choice `rule`,
-    `param`, see les_set_warm_start); with tune, on the autotuned sweep."""
+    `param`, see les_set_warm_start); with tune, on the autotuned sweep;
+    params (e.g. tol) go to the handle's les_params."""
     import torch
 
-    g = make_case(base, seed, tune=tune)
+    g = make_case(base, seed, tune=tune, **params)
     try:
         if skip:
             g.step(skip)

@@ -394,15 +394,19 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
 // output grid is cut into bricks of BZ x BY x 16 voxels; a block takes the
 // bricks of one chunk and TPB consecutive taps (tap group = grid y).  Per
 // brick it loads the (BZ+2) x (BY+2) x 18 input voxels around it and the
-// masked output gradient of the brick (16-byte chunks, channels last,
-// zero outside the grid), then every MFMA operand element is an LDS read:
-// K = 32 voxels (two x-rows of the brick), A[ci][voxel] = input at the
-// voxel shifted by the tap, B[voxel][co] = gradient.  Wavefront w takes the
-// K steps w, w+4, ... of each brick; the four wavefronts' tiles are summed
-// in a fixed order at the end and one partial per chunk and tap is stored.
-// Dynamic LDS: max of the operands ((BZ+2)(BY+2) 18 cinp + BZ BY 16 cout
-// bf16) and the reduction tiles (TPB x MT 16 x NT 16 float), which reuse
-// the operands' space at the end.
+// masked output gradient of the brick (zero outside the grid) and stores
+// both channel-major, x fastest: a thread loads eight voxels' 16-byte
+// channel octets of one x-row, transposes them in registers and writes one
+// 8-voxel run per channel.  K = 32 voxels (two x-rows of the brick); a
+// lane's 8 K values are 8 consecutive voxels of one channel, so each MFMA
+// operand is one 16-byte LDS read: B[voxel][co] aligned, A[ci][voxel] (the
+// input shifted by the tap) at a 2-byte offset, which the LDS serves as an
+// unaligned access.  Wavefront w takes the K steps w, w+4, ... of each
+// brick; the four wavefronts' tiles are summed in a fixed order at the end
+// and one partial per chunk and tap is stored.  Dynamic LDS: max of the
+// operands ((BZ+2)(BY+2) 18 cinp + BZ BY 16 cout bf16) and the reduction
+// tiles (TPB x MT 16 x NT 16 float), which reuse the operands' space at the
+// end.
 template <int MT, int NT, int TPB, int BZ, int BY>
 __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp, int bricks_per_chunk,
                                                            float* bias_part) {
@@ -445,42 +449,77 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
         const int b = bid / nbz;
         const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
         __syncthreads();   // the previous brick's operands are no longer read
+        // input halo: units (channel octet, row hz hy, x run of 8, 8, 2)
         const int cchi = cinp / 8;
-        for (int q = threadIdx.x; q < HZ * HY * HX * cchi; q += kNetBlock) {
-            const int ch = q % cchi;
-            const int v = q / cchi;
-            const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-            const int gz = z0 - 1 + hz, gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-            bf16x8 val = zero;
-            if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
-                val = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ch * 8);
-            }
-            *reinterpret_cast<bf16x8*>(s_in + (size_t)q * 8) = val;
-        }
-        const int ccho = cout / 8;
-        for (int q = threadIdx.x; q < NV * ccho; q += kNetBlock) {
-            const int ch = q % ccho;
-            const int v = q / ccho;
-            const int lx = v % BX, ly = (v / BX) % BY, lz = v / (BX * BY);
-            const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
-            bf16x8 val = zero;
-            if (gz < D && gy < H && gx < W) {
-                const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
-                val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + ch * 8);
-                if (a.mask) {
-                    const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ch * 8);
+        for (int q = threadIdx.x; q < cchi * HZ * HY * 3; q += kNetBlock) {
+            const int xc = q % 3;
+            const int r = (q / 3) % (HZ * HY);
+            const int c8 = q / (3 * HZ * HY);
+            const int hy = r % HY, hz = r / HY;
+            const int gz = z0 - 1 + hz, gy = y0 - 1 + hy;
+            const bool row_ok = gz >= 0 && gz < D && gy >= 0 && gy < H;
+            const int nv = xc < 2 ? 8 : HX - 16;
+            bf16x8 vox[8];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (!((float)mk[i] > 0.f)) val[i] = (bf16)0.f;
+            for (int i = 0; i < 8; ++i) {
+                const int gx = x0 - 1 + 8 * xc + i;
+                vox[i] = zero;
+                if (i < nv && row_ok && gx >= 0 && gx < W) {
+                    const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                    vox[i] = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + c8 * 8);
                 }
             }
-            *reinterpret_cast<bf16x8*>(s_g + (size_t)q * 8) = val;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                bf16* dst = s_in + ((size_t)((8 * c8 + c) * HZ + hz) * HY + hy) * HX + 8 * xc;
+                if (xc < 2) {
+                    bf16x8 run;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) run[i] = vox[i][c];
+                    __builtin_memcpy(dst, &run, sizeof run);   // 4-byte aligned
+                } else {
+                    dst[0] = vox[0][c];
+                    dst[1] = vox[1][c];
+                }
+            }
+        }
+        // masked output gradient: units (channel octet, row lz ly, x run of 8)
+        const int ccho = cout / 8;
+        for (int q = threadIdx.x; q < ccho * BZ * BY * 2; q += kNetBlock) {
+            const int xc = q % 2;
+            const int r = (q / 2) % (BZ * BY);
+            const int c8 = q / (2 * BZ * BY);
+            const int ly = r % BY, lz = r / BY;
+            const int gz = z0 + lz, gy = y0 + ly;
+            bf16x8 vox[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gx = x0 + 8 * xc + i;
+                vox[i] = zero;
+                if (gz < D && gy < H && gx < W) {
+                    const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                    bf16x8 val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + c8 * 8);
+                    if (a.mask) {
+                        const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + c8 * 8);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            if (!((float)mk[k] > 0.f)) val[k] = (bf16)0.f;
+                    }
+                    vox[i] = val;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                bf16x8 run;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) run[i] = vox[i][c];
+                *reinterpret_cast<bf16x8*>(s_g + (size_t)(8 * c8 + c) * NV + r * BX + 8 * xc) = run;
+            }
         }
         __syncthreads();
         if (do_bias)
             for (int v = threadIdx.x / cout; v < NV; v += kNetBlock / cout)
-                bsum += (float)s_g[v * cout + threadIdx.x % cout];
+                bsum += (float)s_g[(size_t)(threadIdx.x % cout) * NV + v];
         for (int ks = wave; ks < KS; ks += 4) {
             // the lane's 8 voxels: brick row ks * 2 + gi / 2, x = 8 (gi % 2) + i
             const int row = ks * 2 + (gi >> 1);
@@ -489,21 +528,20 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = 16 * nt + (l & 15);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) bv[nt][i] = s_g[((row * BX) + xb + i) * cout + co];
+                bv[nt] = *reinterpret_cast<const bf16x8*>(s_g + (size_t)co * NV + row * BX + xb);
             }
 #pragma unroll
             for (int tt = 0; tt < TPB; ++tt) {
                 const int t = tb + tt;
                 if (t >= 27) break;   // uniform over the block
                 const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // window offsets 0..2
-                const int hbase = ((lz + dz) * HY + (ly + dy)) * HX + xb + dx;
+                const int hrow = (lz + dz) * HY + (ly + dy);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int ci = 16 * mt + (l & 15);
-                    bf16x8 av;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) av[i] = ci < cinp ? s_in[(hbase + i) * cinp + ci] : (bf16)0.f;
+                    bf16x8 av = zero;
+                    if (ci < cinp)   // 8 consecutive voxels of channel ci (2-byte aligned)
+                        __builtin_memcpy(&av, s_in + ((size_t)ci * HZ * HY + hrow) * HX + xb + dx, sizeof av);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
                         acc[tt][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tt][mt][nt], 0, 0, 0);
@@ -1016,6 +1054,9 @@ int wgrad_tpb(int MT, int NT, int up) {
     if (!up) return t <= 2 ? 9 : (t <= 8 ? 3 : 1);
     return t <= 2 ? 8 : (t <= 4 ? 4 : (t <= 8 ? 2 : 1));
 }
+// taps per block of the brick kernel: one 16 x 16 tile takes all 27 taps,
+// so its (transposing) operand fill is paid once per brick
+int wgrad_brick_tpb(int MT, int NT) { return MT * NT == 1 ? 27 : wgrad_tpb(MT, NT, 0); }
 
 template <bool ROW8>
 hipError_t launch_wgrad_t(hipStream_t s, const WgradArgs& a, int chunks) {
@@ -1048,7 +1089,7 @@ hipError_t launch_wgrad(hipStream_t s, const WgradArgs& a, int chunks) {
 size_t wgrad_brick_lds(const WgradArgs& a, int bz) {
     const int cinp = a.cin <= 8 ? 8 : a.cin;
     const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
-    const size_t red = (size_t)wgrad_tpb(MT, NT, 0) * MT * 16 * NT * 16 * sizeof(float);
+    const size_t red = (size_t)wgrad_brick_tpb(MT, NT) * MT * 16 * NT * 16 * sizeof(float);
     const size_t ops = ((size_t)(bz + 2) * (bz + 2) * 18 * cinp + (size_t)bz * bz * 16 * a.cout) * sizeof(bf16);
     return std::max(red, ops);
 }
@@ -1068,15 +1109,15 @@ hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int
     const int MT = rup(a.cin, 16) / 16, NT = a.cout / 16;
     const int bz = wgrad_brick_bz(a);
     const size_t lds = wgrad_brick_lds(a, bz);
-    const int tpb = wgrad_tpb(MT, NT, 0);
+    const int tpb = wgrad_brick_tpb(MT, NT);
     const dim3 grid(chunks, (27 + tpb - 1) / tpb);
 #define WB(mt, nt, tp, z, y)                                                                          \
     if (MT == mt && NT == nt && tpb == tp && bz == z)                                                 \
     hipLaunchKernelGGL((k_wgrad_brick<mt, nt, tp, z, y>), grid, dim3(kNetBlock), lds, s, a, cinp, bpc, bias_part)
-    WB(1, 1, 9, 4, 4); else WB(1, 2, 9, 4, 4); else WB(2, 1, 9, 4, 4); else WB(2, 2, 3, 4, 4);
+    WB(1, 1, 27, 4, 4); else WB(1, 2, 9, 4, 4); else WB(2, 1, 9, 4, 4); else WB(2, 2, 3, 4, 4);
     else WB(1, 4, 3, 4, 4); else WB(4, 1, 3, 4, 4); else WB(2, 4, 3, 4, 4); else WB(4, 2, 3, 4, 4);
     else WB(4, 4, 1, 4, 4);
-    else WB(1, 1, 9, 2, 2); else WB(1, 2, 9, 2, 2); else WB(2, 1, 9, 2, 2); else WB(2, 2, 3, 2, 2);
+    else WB(1, 1, 27, 2, 2); else WB(1, 2, 9, 2, 2); else WB(2, 1, 9, 2, 2); else WB(2, 2, 3, 2, 2);
     else WB(1, 4, 3, 2, 2); else WB(4, 1, 3, 2, 2); else WB(2, 4, 3, 2, 2); else WB(4, 2, 3, 2, 2);
     else WB(4, 4, 1, 2, 2);
     else return hipErrorInvalidValue;

@@ -31,7 +31,7 @@ def sor_source_hash() -> str:
 
 def short(name: str) -> str:
     name = name.replace("(anonymous namespace)", "anon").replace("void ", "")
-    name = name.replace("les::anon::", "")
+    name = name.replace("les::net::anon::", "").replace("les::anon::", "")
     return name.split("(")[0].strip()
 
 

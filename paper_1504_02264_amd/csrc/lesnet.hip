@@ -394,14 +394,15 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad(WgradArgs a) {
 // output grid is cut into bricks of BZ x BY x 16 voxels; a block takes the
 // bricks of one chunk and TPB consecutive taps (tap group = grid y).  Per
 // brick it loads the (BZ+2) x (BY+2) x 18 input voxels around it and the
-// masked output gradient of the brick (zero outside the grid) and stores
-// both channel-major, x fastest: a thread loads eight voxels' 16-byte
-// channel octets of one x-row, transposes them in registers and writes one
-// 8-voxel run per channel.  K = 32 voxels (two x-rows of the brick); a
-// lane's 8 K values are 8 consecutive voxels of one channel, so each MFMA
-// operand is one 16-byte LDS read: B[voxel][co] aligned, A[ci][voxel] (the
-// input shifted by the tap) at a 2-byte offset, which the LDS serves as an
-// unaligned access.  Wavefront w takes the K steps w, w+4, ... of each
+// masked output gradient of the brick (zero outside the grid).  4 x 4 x 16
+// bricks store both channel-major, x fastest: a thread loads eight voxels'
+// 16-byte channel octets of one x-row, transposes them in registers and
+// writes one 8-voxel run per channel; K = 32 voxels (two x-rows of the
+// brick) and a lane's 8 K values are 8 consecutive voxels of one channel,
+// so each MFMA operand is one 16-byte LDS read: B[voxel][co] aligned,
+// A[ci][voxel] (the input shifted by the tap) at a 2-byte offset, which the
+// LDS serves as an unaligned access.  2 x 2 x 16 bricks store channels last
+// (one octet per store) and gather each operand element by element.  Wavefront w takes the K steps w, w+4, ... of each
 // brick; the four wavefronts' tiles are summed in a fixed order at the end
 // and one partial per chunk and tap is stored.  Dynamic LDS: max of the
 // operands ((BZ+2)(BY+2) 18 cinp + BZ BY 16 cout bf16) and the reduction
@@ -414,6 +415,10 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
     constexpr int BX = 16, HZ = BZ + 2, HY = BY + 2, HX = BX + 2;
     constexpr int NV = BZ * BY * BX;   // voxels per brick
     constexpr int KS = NV / 32;        // K steps per brick
+    // channel-major operands for the 4 x 4 x 16 bricks; the 2 x 2 x 16
+    // bricks (wide channel counts) keep channels last, where the transposing
+    // fill costs more than the single-read operands save
+    constexpr bool CM = BZ == 4;
     bf16* s_in = reinterpret_cast<bf16*>(smem);
     bf16* s_g = s_in + HZ * HY * HX * cinp;
     float(*red)[MT * 16][NT * 16] = reinterpret_cast<float(*)[MT * 16][NT * 16]>(smem);
@@ -449,77 +454,112 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
         const int b = bid / nbz;
         const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
         __syncthreads();   // the previous brick's operands are no longer read
-        // input halo: units (channel octet, row hz hy, x run of 8, 8, 2)
-        const int cchi = cinp / 8;
-        for (int q = threadIdx.x; q < cchi * HZ * HY * 3; q += kNetBlock) {
-            const int xc = q % 3;
-            const int r = (q / 3) % (HZ * HY);
-            const int c8 = q / (3 * HZ * HY);
-            const int hy = r % HY, hz = r / HY;
-            const int gz = z0 - 1 + hz, gy = y0 - 1 + hy;
-            const bool row_ok = gz >= 0 && gz < D && gy >= 0 && gy < H;
-            const int nv = xc < 2 ? 8 : HX - 16;
-            bf16x8 vox[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gx = x0 - 1 + 8 * xc + i;
-                vox[i] = zero;
-                if (i < nv && row_ok && gx >= 0 && gx < W) {
-                    const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
-                    vox[i] = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + c8 * 8);
+        if constexpr (CM) {
+            // input halo: units (channel octet, row hz hy, x run of 8, 8, 2)
+            const int cchi = cinp / 8;
+            for (int q = threadIdx.x; q < cchi * HZ * HY * 3; q += kNetBlock) {
+                const int xc = q % 3;
+                const int r = (q / 3) % (HZ * HY);
+                const int c8 = q / (3 * HZ * HY);
+                const int hy = r % HY, hz = r / HY;
+                const int gz = z0 - 1 + hz, gy = y0 - 1 + hy;
+                const bool row_ok = gz >= 0 && gz < D && gy >= 0 && gy < H;
+                const int nv = xc < 2 ? 8 : HX - 16;
+                bf16x8 vox[8];
+    #pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int gx = x0 - 1 + 8 * xc + i;
+                    vox[i] = zero;
+                    if (i < nv && row_ok && gx >= 0 && gx < W) {
+                        const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                        vox[i] = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + c8 * 8);
+                    }
+                }
+    #pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    bf16* dst = s_in + ((size_t)((8 * c8 + c) * HZ + hz) * HY + hy) * HX + 8 * xc;
+                    if (xc < 2) {
+                        bf16x8 run;
+    #pragma unroll
+                        for (int i = 0; i < 8; ++i) run[i] = vox[i][c];
+                        __builtin_memcpy(dst, &run, sizeof run);   // 4-byte aligned
+                    } else {
+                        dst[0] = vox[0][c];
+                        dst[1] = vox[1][c];
+                    }
                 }
             }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                bf16* dst = s_in + ((size_t)((8 * c8 + c) * HZ + hz) * HY + hy) * HX + 8 * xc;
-                if (xc < 2) {
+            // masked output gradient: units (channel octet, row lz ly, x run of 8)
+            const int ccho = cout / 8;
+            for (int q = threadIdx.x; q < ccho * BZ * BY * 2; q += kNetBlock) {
+                const int xc = q % 2;
+                const int r = (q / 2) % (BZ * BY);
+                const int c8 = q / (2 * BZ * BY);
+                const int ly = r % BY, lz = r / BY;
+                const int gz = z0 + lz, gy = y0 + ly;
+                bf16x8 vox[8];
+    #pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int gx = x0 + 8 * xc + i;
+                    vox[i] = zero;
+                    if (gz < D && gy < H && gx < W) {
+                        const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                        bf16x8 val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + c8 * 8);
+                        if (a.mask) {
+                            const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + c8 * 8);
+    #pragma unroll
+                            for (int k = 0; k < 8; ++k)
+                                if (!((float)mk[k] > 0.f)) val[k] = (bf16)0.f;
+                        }
+                        vox[i] = val;
+                    }
+                }
+    #pragma unroll
+                for (int c = 0; c < 8; ++c) {
                     bf16x8 run;
-#pragma unroll
+    #pragma unroll
                     for (int i = 0; i < 8; ++i) run[i] = vox[i][c];
-                    __builtin_memcpy(dst, &run, sizeof run);   // 4-byte aligned
-                } else {
-                    dst[0] = vox[0][c];
-                    dst[1] = vox[1][c];
+                    *reinterpret_cast<bf16x8*>(s_g + (size_t)(8 * c8 + c) * NV + r * BX + 8 * xc) = run;
                 }
             }
-        }
-        // masked output gradient: units (channel octet, row lz ly, x run of 8)
-        const int ccho = cout / 8;
-        for (int q = threadIdx.x; q < ccho * BZ * BY * 2; q += kNetBlock) {
-            const int xc = q % 2;
-            const int r = (q / 2) % (BZ * BY);
-            const int c8 = q / (2 * BZ * BY);
-            const int ly = r % BY, lz = r / BY;
-            const int gz = z0 + lz, gy = y0 + ly;
-            bf16x8 vox[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gx = x0 + 8 * xc + i;
-                vox[i] = zero;
+        } else {   // channels last, one 16-byte octet per store
+            const int cchi = cinp / 8;
+            for (int q = threadIdx.x; q < HZ * HY * HX * cchi; q += kNetBlock) {
+                const int ch = q % cchi;
+                const int v = q / cchi;
+                const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+                const int gz = z0 - 1 + hz, gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+                bf16x8 val = zero;
+                if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                    const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
+                    val = *reinterpret_cast<const bf16x8*>(a.in + iv * a.in_cs + ch * 8);
+                }
+                *reinterpret_cast<bf16x8*>(s_in + (size_t)q * 8) = val;
+            }
+            const int ccho = cout / 8;
+            for (int q = threadIdx.x; q < NV * ccho; q += kNetBlock) {
+                const int ch = q % ccho;
+                const int v = q / ccho;
+                const int lx = v % BX, ly = (v / BX) % BY, lz = v / (BX * BY);
+                const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+                bf16x8 val = zero;
                 if (gz < D && gy < H && gx < W) {
                     const size_t iv = (((size_t)b * D + gz) * H + gy) * W + gx;
-                    bf16x8 val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + c8 * 8);
+                    val = *reinterpret_cast<const bf16x8*>(a.dout + iv * a.dout_cs + ch * 8);
                     if (a.mask) {
-                        const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + c8 * 8);
-#pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            if (!((float)mk[k] > 0.f)) val[k] = (bf16)0.f;
+                        const bf16x8 mk = *reinterpret_cast<const bf16x8*>(a.mask + iv * a.mask_cs + ch * 8);
+    #pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (!((float)mk[i] > 0.f)) val[i] = (bf16)0.f;
                     }
-                    vox[i] = val;
                 }
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                bf16x8 run;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) run[i] = vox[i][c];
-                *reinterpret_cast<bf16x8*>(s_g + (size_t)(8 * c8 + c) * NV + r * BX + 8 * xc) = run;
+                *reinterpret_cast<bf16x8*>(s_g + (size_t)q * 8) = val;
             }
         }
         __syncthreads();
         if (do_bias)
             for (int v = threadIdx.x / cout; v < NV; v += kNetBlock / cout)
-                bsum += (float)s_g[(size_t)(threadIdx.x % cout) * NV + v];
+                bsum += (float)(CM ? s_g[(size_t)(threadIdx.x % cout) * NV + v] : s_g[v * cout + threadIdx.x % cout]);
         for (int ks = wave; ks < KS; ks += 4) {
             // the lane's 8 voxels: brick row ks * 2 + gi / 2, x = 8 (gi % 2) + i
             const int row = ks * 2 + (gi >> 1);
@@ -528,7 +568,12 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = 16 * nt + (l & 15);
-                bv[nt] = *reinterpret_cast<const bf16x8*>(s_g + (size_t)co * NV + row * BX + xb);
+                if constexpr (CM) {
+                    bv[nt] = *reinterpret_cast<const bf16x8*>(s_g + (size_t)co * NV + row * BX + xb);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) bv[nt][i] = s_g[((row * BX) + xb + i) * cout + co];
+                }
             }
 #pragma unroll
             for (int tt = 0; tt < TPB; ++tt) {
@@ -540,8 +585,14 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
                 for (int mt = 0; mt < MT; ++mt) {
                     const int ci = 16 * mt + (l & 15);
                     bf16x8 av = zero;
-                    if (ci < cinp)   // 8 consecutive voxels of channel ci (2-byte aligned)
-                        __builtin_memcpy(&av, s_in + ((size_t)ci * HZ * HY + hrow) * HX + xb + dx, sizeof av);
+                    if constexpr (CM) {
+                        if (ci < cinp)   // 8 consecutive voxels of channel ci (2-byte aligned)
+                            __builtin_memcpy(&av, s_in + ((size_t)ci * HZ * HY + hrow) * HX + xb + dx, sizeof av);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            av[i] = ci < cinp ? s_in[(hrow * HX + xb + dx + i) * cinp + ci] : (bf16)0.f;
+                    }
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
                         acc[tt][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tt][mt][nt], 0, 0, 0);

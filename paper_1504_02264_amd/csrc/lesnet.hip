@@ -580,18 +580,18 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
                 const int t = tb + tt;
                 if (t >= 27) break;   // uniform over the block
                 const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // window offsets 0..2
-                const int hrow = (lz + dz) * HY + (ly + dy);
+                const int hbase = ((lz + dz) * HY + (ly + dy)) * HX + xb + dx;
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int ci = 16 * mt + (l & 15);
-                    bf16x8 av = zero;
+                    bf16x8 av;
                     if constexpr (CM) {
-                        if (ci < cinp)   // 8 consecutive voxels of channel ci (2-byte aligned)
-                            __builtin_memcpy(&av, s_in + ((size_t)ci * HZ * HY + hrow) * HX + xb + dx, sizeof av);
+                        // 8 consecutive voxels of channel ci (2-byte aligned)
+                        av = zero;
+                        if (ci < cinp) __builtin_memcpy(&av, s_in + ci * (HZ * HY * HX) + hbase, sizeof av);
                     } else {
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            av[i] = ci < cinp ? s_in[(hrow * HX + xb + dx + i) * cinp + ci] : (bf16)0.f;
+                        for (int i = 0; i < 8; ++i) av[i] = ci < cinp ? s_in[(hbase + i) * cinp + ci] : (bf16)0.f;
                     }
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)

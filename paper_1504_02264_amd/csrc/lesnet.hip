@@ -1105,9 +1105,9 @@ int wgrad_tpb(int MT, int NT, int up) {
     if (!up) return t <= 2 ? 9 : (t <= 8 ? 3 : 1);
     return t <= 2 ? 8 : (t <= 4 ? 4 : (t <= 8 ? 2 : 1));
 }
-// taps per block of the brick kernel: one 16 x 16 tile takes all 27 taps,
-// so its (transposing) operand fill is paid once per brick
-int wgrad_brick_tpb(int MT, int NT) { return MT * NT == 1 ? 27 : wgrad_tpb(MT, NT, 0); }
+// taps per block of the brick kernel: one or two 16 x 16 tiles take all 27
+// taps, so their (transposing) operand fill is paid once per brick
+int wgrad_brick_tpb(int MT, int NT) { return MT * NT <= 2 ? 27 : wgrad_tpb(MT, NT, 0); }
 
 template <bool ROW8>
 hipError_t launch_wgrad_t(hipStream_t s, const WgradArgs& a, int chunks) {
@@ -1165,10 +1165,10 @@ hipError_t launch_wgrad_brick(hipStream_t s, const WgradArgs& a, int chunks, int
 #define WB(mt, nt, tp, z, y)                                                                          \
     if (MT == mt && NT == nt && tpb == tp && bz == z)                                                 \
     hipLaunchKernelGGL((k_wgrad_brick<mt, nt, tp, z, y>), grid, dim3(kNetBlock), lds, s, a, cinp, bpc, bias_part)
-    WB(1, 1, 27, 4, 4); else WB(1, 2, 9, 4, 4); else WB(2, 1, 9, 4, 4); else WB(2, 2, 3, 4, 4);
+    WB(1, 1, 27, 4, 4); else WB(1, 2, 27, 4, 4); else WB(2, 1, 27, 4, 4); else WB(2, 2, 3, 4, 4);
     else WB(1, 4, 3, 4, 4); else WB(4, 1, 3, 4, 4); else WB(2, 4, 3, 4, 4); else WB(4, 2, 3, 4, 4);
     else WB(4, 4, 1, 4, 4);
-    else WB(1, 1, 27, 2, 2); else WB(1, 2, 9, 2, 2); else WB(2, 1, 9, 2, 2); else WB(2, 2, 3, 2, 2);
+    else WB(1, 1, 27, 2, 2); else WB(1, 2, 27, 2, 2); else WB(2, 1, 27, 2, 2); else WB(2, 2, 3, 2, 2);
     else WB(1, 4, 3, 2, 2); else WB(4, 1, 3, 2, 2); else WB(2, 4, 3, 2, 2); else WB(4, 2, 3, 2, 2);
     else WB(4, 4, 1, 2, 2);
     else return hipErrorInvalidValue;

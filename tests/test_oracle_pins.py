@@ -88,6 +88,33 @@ def test_operator_spectrum_closed_form(bc):
     assert np.allclose(ev, want, rtol=1e-12, atol=1e-12 * abs(want).max())
 
 
+# ------------------------------------------------- reflection symmetry
+def test_operator_commutes_with_y_reflection():
+    """Both y faces carry the same boundary condition, so the pressure
+    operator commutes with j -> ny-1-j: a pressure problem mirrored in y is
+    solved by the mirrored solution (what makes mirrored warm-start
+    training pairs valid).  x is not symmetric (inflow against outflow),
+    and the check sees that."""
+    nx, ny, nz = 7, 6, 5
+    o = make(nx, ny, nz, dx=1.5, dy=2.0, dz=0.7, bc=URBAN_BC)
+    p = np.random.default_rng(3).standard_normal((nz, ny, nx))
+    Ap = o.apply_A(p)
+    assert np.allclose(o.apply_A(p[:, ::-1, :]), Ap[:, ::-1, :], rtol=0, atol=1e-12 * np.abs(Ap).max())
+    assert not np.allclose(o.apply_A(p[:, :, ::-1]), Ap[:, :, ::-1], rtol=0, atol=1e-6 * np.abs(Ap).max())
+
+
+def test_mirror_y_pairs():
+    torch = pytest.importorskip("torch")
+    from paper_1504_02264_amd import warmstart as ws
+    X = torch.arange(2 * 4 * 6 * 8 * 3, dtype=torch.float32).reshape(2, 4, 6, 8, 3)
+    T = torch.arange(2 * 4 * 6 * 8, dtype=torch.float32).reshape(2, 4, 6, 8)
+    Xm, Tm = ws.mirror_y(X, T)
+    assert Xm.shape == (4, 4, 6, 8, 3) and Tm.shape == (4, 4, 6, 8)
+    assert torch.equal(Xm[:2], X) and torch.equal(Tm[:2], T)
+    assert torch.equal(Xm[3, 1, 0, 2], X[1, 1, 5, 2]) and torch.equal(Tm[2, 3, 1, 7], T[0, 3, 4, 7])
+    assert Xm.is_contiguous() and Tm.is_contiguous()
+
+
 # -------------------------------------------------------------------- P1
 @pytest.mark.parametrize("shape", [(6, 5, 4), (8, 6, 4), (12, 8, 6)])
 @pytest.mark.parametrize("bc", [URBAN_BC, ALL_WALLS])

@@ -65,7 +65,7 @@ __device__ __forceinline__ double block_max(double v) {
 
 // Block-wide reductions of the single-block finalize kernel (kFinBlock
 // threads, fixed order: deterministic for a given partial count).
-constexpr int kFinBlock = 1024;
+constexpr int kFinBlock = 256;
 
 __device__ __forceinline__ double fin_sum(double v) {
     __shared__ double red[kFinBlock / 64];

@@ -183,11 +183,11 @@ hipError_t launch_colour_norm(const Geo& g, hipStream_t st, float* const a[2], d
 
 hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                         const double* rel0, const double* rel1, int nrel, Ctl* ctl) {
-    hipLaunchKernelGGL(k_check, dim3(red_blocks(g)), dim3(kBlock), 0, st, g, P, part,
+    hipLaunchKernelGGL(k_check, dim3(check_blocks(g)), dim3(kBlock), 0, st, g, P, part,
                        (const Ctl*)ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(st, FIN_CHECK, part, (int)red_blocks(g), rel0, rel1, nrel, ctl);
+    return launch_finalize(st, FIN_CHECK, part, (int)check_blocks(g), rel0, rel1, nrel, ctl);
 }
 
 hipError_t launch_remove_mean_p(const Geo& g, hipStream_t st, const PBufs& P, double* part,

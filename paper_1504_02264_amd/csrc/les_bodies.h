@@ -17,10 +17,17 @@ namespace les {
 // block L owns one contiguous chunk of half-cells, walked by its threads
 // with unit stride, so finalizing sums few partials.
 constexpr unsigned kRedBlocks = 2048;
+// grid of the residual check, which mostly returns at once (skipped by the
+// bound): fewer blocks to dispatch, still two per compute unit
+constexpr unsigned kCheckBlocks = 512;
 inline unsigned red_blocks(const Geo& g) {
     const long long n = (long long)g.H * g.ny * g.nz;
     const long long b = (n + kBlock - 1) / kBlock;
     return (unsigned)(b < (long long)kRedBlocks ? b : (long long)kRedBlocks);
+}
+inline unsigned check_blocks(const Geo& g) {
+    const unsigned r = red_blocks(g);
+    return r < kCheckBlocks ? r : kCheckBlocks;
 }
 inline unsigned cell_blocks(const Geo& g) {
     return (unsigned)(((long long)g.nx * g.ny * g.nz + kBlock - 1) / kBlock);

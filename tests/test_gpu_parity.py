@@ -279,6 +279,31 @@ def test_full_size_stage_parity(name, max_iter):
     assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
 
 
+@pytest.mark.parametrize("name,fused,half,max_iter", [("C2", 8, 5, 400), ("C3", 9, 6, 40)])
+def test_full_size_fused_equals_half_sweeps(name, fused, half, max_iter):
+    """The sweep variants the autotuner picks for the benchmark grids (the
+    fused red-black iterations) give, at full size, the fields of the
+    half-sweeps bit for bit: one step with the solve capped."""
+    w = WORKLOADS[name]
+    print(f"[full_size_fused] {name} variants {fused} / {half} max_iter={max_iter}", flush=True)
+    mask, prof = make_workload_inputs(w)
+    out = []
+    for v in (fused, half):
+        g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask, max_iter=max_iter)
+        try:
+            g.set_sor_variant(v)
+            g.set_inflow(prof, w.noise_amp, w.seed)
+            rc, st, iters = g.step(1)
+            assert iters[0] == max_iter
+            out.append((g.get_fields(), st["resid_last"]))
+        finally:
+            g.close()
+    (fa, ra), (fb, rb) = out
+    assert ra == rb
+    for a, b in zip(fa, fb):
+        assert np.array_equal(a, b)
+
+
 # ------------------------------------------- autotuner / tile independence
 def test_sor_variants_bitwise_identical():
     """Every sweep tile variant does the same per-cell arithmetic, so the

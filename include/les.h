@@ -313,17 +313,21 @@ typedef struct {
 } les_ensemble_stats;
 int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** out);
 int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, int32_t* iters_out);
-/* Autotuner for the ensemble: times the batched half-sweep over all
- * members for each half-sweep variant 0-7 (all members on one variant:
- * with the members' working sets together the cache behaviour differs from
- * each one alone) on the members' scratch pressure systems (the state is
- * not touched), reps red/black pairs each, and uses the fastest from the
- * next step on.  les_ensemble_tuning reports the choice and the
- * microseconds per half-sweep of every variant
- * (us_per_sweep[LES_NUM_SOR_VARIANTS]; 0 for the fused variants, which the
- * ensemble does not run: a member set to one uses its grid's default
- * half-sweep). */
+/* Autotuner for the ensemble: times the batched sweeps over all members
+ * for each sweep variant (all members on one variant: with the members'
+ * working sets together the cache behaviour differs from each one alone)
+ * on the members' scratch pressure systems (the state is not touched),
+ * reps pairs of launches each, and uses the fastest from the next step on.
+ * les_ensemble_tuning reports the choice and the microseconds per
+ * half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]; for 8
+ * and 9 half a fused iteration, 0 where not timed).  The fused variants 8
+ * and 9 run only in the batched mode with an even check_every and only as
+ * the ensemble's choice (les_ensemble_autotune or les_ensemble_set_variant):
+ * otherwise a member set to one runs its grid's default half-sweep. */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);
+/* The sweep variant every member runs (0 .. LES_NUM_SOR_VARIANTS-1), or -1:
+ * each member its own; from the next step on.  LES_EINVAL otherwise. */
+int les_ensemble_set_variant(les_ensemble* e, int32_t variant);
 int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep);
 const char* les_ensemble_last_error(const les_ensemble* e);
 void les_ensemble_destroy(les_ensemble* e);

@@ -32,6 +32,7 @@ EXPORTS = (
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
     "les_ensemble_create", "les_ensemble_step", "les_ensemble_autotune",
     "les_ensemble_last_error", "les_ensemble_destroy", "les_ensemble_set_mode",
+    "les_ensemble_set_variant",
     "les_ensemble_tuning", "les_set_initial_guess_dev",
     # include/lesnet.h
     "lesnet_default_config", "lesnet_create", "lesnet_destroy", "lesnet_last_error",
@@ -168,6 +169,7 @@ def lib():
     L.les_ensemble_last_error.argtypes = [P]
     L.les_ensemble_last_error.restype = C.c_char_p
     L.les_ensemble_set_mode.argtypes = [P, C.c_int32]
+    L.les_ensemble_set_variant.argtypes = [P, C.c_int32]
     L.les_ensemble_tuning.argtypes = [P, C.POINTER(C.c_int32), P]
     L.les_ensemble_destroy.argtypes = [P]
     L.les_ensemble_destroy.restype = None
@@ -561,6 +563,12 @@ class Ensemble:
         if rc not in (LES_OK, LES_NOT_CONVERGED):
             raise LesError(rc, lib().les_ensemble_last_error(self.h).decode())
         return rc, st.as_dict(), iters[:n].copy()
+
+    def set_variant(self, variant):
+        """Sweep variant of every member (-1: each member its own)."""
+        rc = lib().les_ensemble_set_variant(self.h, int(variant))
+        if rc != LES_OK:
+            raise LesError(rc, "les_ensemble_set_variant")
 
     def set_mode(self, mode):
         rc = lib().les_ensemble_set_mode(self.h, int(mode))

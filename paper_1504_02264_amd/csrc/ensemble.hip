@@ -390,6 +390,31 @@ __global__ __launch_bounds__(kBlock) void k_ens_sweep(const EnsInst* __restrict_
     sweep_range(d, colour, acc, L - O->sweep[q], L - O->sweep[q] + 1);
 }
 
+// One fused red-black iteration of every member (sweep variants 8 and 9,
+// 16 wavefronts per block): parity 0 reads pd and writes pa, 1 the reverse.
+__global__ __launch_bounds__(1024) void k_ens_sweep_rb(const EnsInst* __restrict__ I,
+                                                       const unsigned char* __restrict__ owner_of,
+                                                       const EnsOffsets* __restrict__ O, int parity,
+                                                       int it) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner_of[L];
+    const EnsInst& d = I[q];
+    bool acc;
+    const bool active = sweep_active(d.ctl, it, acc);
+    if (!active && d.ctl->done) return;
+    const float* a0 = parity ? d.P.pa[0] : d.P.pd[0];
+    const float* a1 = parity ? d.P.pa[1] : d.P.pd[1];
+    float* b0 = parity ? d.P.pd[0] : d.P.pa[0];
+    float* b1 = parity ? d.P.pd[1] : d.P.pa[1];
+    const unsigned lb = L - O->sweep[q];
+    if (d.variant == 8)
+        sor_rb_body<32, 16, 12>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
+                                d.rel0, d.rel1, lb);
+    else
+        sor_rb_body<64, 16, 16>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
+                                d.rel0, d.rel1, lb);
+}
+
 __global__ __launch_bounds__(kBlock) void k_ens_bound(const EnsInst* __restrict__ I) {
     const EnsInst& d = I[blockIdx.x];
     finalize_body<kBlock>(FIN_BOUND, nullptr, 0, d.rel0, d.rel1, (int)d.nsweep, d.ctl, d.omega);
@@ -509,6 +534,21 @@ int ens_err(les_ensemble* e, int code, const char* what, hipError_t he = hipSucc
 
 unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Fused iterations run only when the ensemble itself chose one (every
+// member then runs it: one launch shape), in the batched mode and with an
+// even check interval.
+bool ens_fused(const les_ensemble* e) {
+    return e->variant >= 0 && sor_fused(e->variant) && e->mode == LES_ENSEMBLE_BATCHED && !(e->K & 1);
+}
+
+// The sweep variant a member runs in the ensemble: the ensemble's choice,
+// else the member's own; a fused variant where the ensemble cannot run it
+// becomes the grid's default half-sweep.
+int ens_variant(const les_ensemble* e, const les_handle* h) {
+    const int v = e->variant >= 0 ? e->variant : h->sor_variant;
+    return (sor_fused(v) && !ens_fused(e)) ? sor_default_variant(h->g) : v;
+}
+
 // Host copies of the member descriptors and work-list offsets, from the
 // members' current settings (inflow, sweep variant, parameters).
 void build_descriptors(les_ensemble* e) {
@@ -550,10 +590,7 @@ void build_descriptors(les_ensemble* e) {
         d.max_iter = h->prm.max_iter;
         d.K = h->prm.check_every;
         d.R = h->prm.rebase_every;
-        // the ensemble runs half-sweeps: a member tuned to a fused variant
-        // takes its grid's default half-sweep
-        d.variant = e->variant >= 0 ? e->variant
-                                    : (sor_fused(h->sor_variant) ? sor_default_variant(h->g) : h->sor_variant);
+        d.variant = ens_variant(e, h);
         d.singular = h->g.outflow ? 0 : 1;
         d.inflow = h->g.inflow;
         d.nsweep = sor_sweep_blocks(h->g, d.variant);
@@ -625,10 +662,16 @@ int upload_owner_map(les_ensemble* e) {
 int enqueue_chunk(les_ensemble* e, hipStream_t s) {
     const int n = e->n;
     const EnsOffsets& o = e->h_off;
-    for (int it = 0; it < e->K; ++it)
-        for (int c = 0; c < 2; ++c)
-            hipLaunchKernelGGL(k_ens_sweep, dim3(o.sweep[n]), dim3(kBlock), 0, s, e->d_inst,
-                               e->d_owner, e->d_off, c, it);
+    if (ens_fused(e)) {
+        for (int it = 0; it < e->K; ++it)
+            hipLaunchKernelGGL(k_ens_sweep_rb, dim3(o.sweep[n]), dim3(1024), 0, s, e->d_inst, e->d_owner,
+                               e->d_off, it & 1, it);
+    } else {
+        for (int it = 0; it < e->K; ++it)
+            for (int c = 0; c < 2; ++c)
+                hipLaunchKernelGGL(k_ens_sweep, dim3(o.sweep[n]), dim3(kBlock), 0, s, e->d_inst,
+                                   e->d_owner, e->d_off, c, it);
+    }
     hipLaunchKernelGGL(k_ens_bound, dim3(n), dim3(kBlock), 0, s, e->d_inst);
     hipLaunchKernelGGL(k_ens_fold, dim3(std::min(o.fold[n], kAuxBlocks)), dim3(kBlock), 0, s,
                        e->d_inst, n, e->d_off, 0);
@@ -778,6 +821,13 @@ int les_ensemble_set_mode(les_ensemble* e, int32_t mode) {
     return LES_OK;
 }
 
+int les_ensemble_set_variant(les_ensemble* e, int32_t variant) {
+    if (!e || variant < -1 || variant >= kNumSorVariants) return LES_EINVAL;
+    e->variant = variant;
+    e->descriptors_dirty = true;
+    return LES_OK;
+}
+
 int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     if (!e || reps < 1 || reps > 1000) return LES_EINVAL;
     const int n = e->n;
@@ -799,9 +849,12 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     double best = 1e300;
     int best_v = 0;
     const int saved = e->variant;
-    for (int v = kNumSplitVariants; v < kNumSorVariants; ++v) e->tune_us[v] = 0.0;   // not run here
-    for (int v = 0; v < kNumSplitVariants; ++v) {
+    for (int v = 0; v < kNumSorVariants; ++v) {
         e->variant = v;
+        if (sor_fused(v) && !ens_fused(e)) {   // persistent mode or an odd check interval
+            e->tune_us[v] = 0.0;
+            continue;
+        }
         build_descriptors(e);
         for (int q = 0; q < n; ++q) e->h_inst[q].P = e->members[q]->S;
         ECK(hipMemcpy(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice));
@@ -811,19 +864,26 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
         for (int q = 0; q < n; ++q)
             hipLaunchKernelGGL(k_ctl_probe_init, dim3(1), dim3(64), 0, e->stream, e->h_inst[q].ctl);
         const unsigned grid = e->h_off.sweep[n];
-        for (int w = 0; w < 2; ++w)
-            hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
-                               e->d_owner, e->d_off, w & 1, 0);
+        // two launches: two half-sweeps, or two fused iterations (half a
+        // fused iteration is charged per half-sweep below)
+        auto pair = [&]() {
+            for (int w = 0; w < 2; ++w) {
+                if (sor_fused(v))
+                    hipLaunchKernelGGL(k_ens_sweep_rb, dim3(grid), dim3(1024), 0, e->stream, e->d_inst,
+                                       e->d_owner, e->d_off, w, 0);
+                else
+                    hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
+                                       e->d_owner, e->d_off, w, 0);
+            }
+        };
+        pair();
         ECK(hipEventRecord(a, e->stream));
-        for (int r = 0; r < reps; ++r)
-            for (int c = 0; c < 2; ++c)
-                hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
-                                   e->d_owner, e->d_off, c, 0);
+        for (int r = 0; r < reps; ++r) pair();
         ECK(hipEventRecord(b, e->stream));
         ECK(hipEventSynchronize(b));
         float ms = 0.f;
         ECK(hipEventElapsedTime(&ms, a, b));
-        const double us = 1e3 * ms / (2.0 * reps);
+        const double us = 1e3 * ms / ((sor_fused(v) ? 4.0 : 2.0) * reps);
         e->tune_us[v] = us;
         if (us < best) {
             best = us;
@@ -838,6 +898,8 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
             les_handle* h = e->members[q];
             hipLaunchKernelGGL(k_zero, dim3((unsigned)((h->g.ctot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                                e->stream, h->S.pd[c], h->g.ctot);
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)((h->g.ctot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               e->stream, h->S.pa[c], h->g.ctot);
         }
     ECK(hipStreamSynchronize(e->stream));
     e->variant = best_v;

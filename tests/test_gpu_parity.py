@@ -414,11 +414,14 @@ def _member(nx, ny, nz, seed, alpha_pl=None, **kw):
     return mask, prof
 
 
+@pytest.mark.parametrize("variant", [-1, 8, 9])
 @pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
-def test_ensemble_bitwise_equals_single_steps(mode):
+def test_ensemble_bitwise_equals_single_steps(mode, variant):
     """An ensemble step of uneven members equals stepping each member alone
     (same per-cell arithmetic, same per-member stopping decisions), in both
-    solve modes."""
+    solve modes, on the members' own half-sweeps and on a fused variant
+    chosen for the whole ensemble (the persistent mode falls back to
+    half-sweeps there)."""
     shapes = [(24, 20, 12), (33, 17, 9), (40, 24, 16), (17, 31, 10)]
     ins = [_member(*s, seed=50 + q, alpha_pl=(0.1 + 0.05 * q) if q % 2 else None)
            for q, s in enumerate(shapes)]
@@ -432,6 +435,7 @@ def test_ensemble_bitwise_equals_single_steps(mode):
         singles.append(b)
     ens = les.Ensemble(ens_members)
     ens.set_mode(mode)
+    ens.set_variant(variant)
     rc, st, iters = ens.step(3)
     assert st["members"] == 4 and st["steps"] == 3
     for q, b in enumerate(singles):

@@ -197,12 +197,22 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_brick(GemmArgs a) {
     for (int tw = 0; tw < TPW; ++tw)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[tw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // weight fragments one K step ahead: the next step's loads are in
+    // flight while this step's matrix operations run
+    bf16x8 bnext[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + kgrp);
     for (int k0 = 0; k0 < a.kp; k0 += 32) {
         const int k = k0 + kgrp;
         bf16x8 bv[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            bv[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + k);
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = bnext[nt];
+        if (k0 + 32 < a.kp) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + k + 32);
+        }
         const bool kok = k < 27 * CINP;
         const int t = k / CINP, ci = k % CINP;
         const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // 0..2: the window is shifted by one

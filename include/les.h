@@ -234,8 +234,8 @@ int les_get_ghosted(les_handle* h, float* u, float* v, float* w);
 /* Kernel timing collected while les_params.timing = 1: for each kernel
  * family, the summed event-bracketed device time and the number of timed
  * launches.  Families: 0 nu_t, 1 tendency, 2 inflow, 3 rhs, 4 SOR sweep
- * launch (a half-sweep, or a whole iteration with the fused variants 8 and
- * 9), 5 residual check, 6 rebase, 7 projection, 8 boundary refresh.
+ * launch (a half-sweep, or a whole iteration with the fused variants
+ * 8-11), 5 residual check, 6 rebase, 7 projection, 8 boundary refresh.
  * reset = 1 clears the counters after reading. */
 #define LES_NUM_KERNELS 9
 typedef struct {
@@ -247,10 +247,12 @@ int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
 /*
  * SOR sweep variants.  0-7: one launch per colour half-sweep (section 2.6),
  * tiles of 64 or 32 half-cells per wavefront row x 1, 2, 4 or 8 planes per
- * block (index 2 log2(planes) + (row width == 32)).  8, 9: one launch per
+ * block (index 2 log2(planes) + (row width == 32)).  8-11: one launch per
  * red-black iteration that updates colour 0 and then colour 1 in one pass
- * over tiles of 30 x 30 x 12 (8) or 62 x 14 x 16 (9) half-cells x rows x
- * planes, recomputing colour 0 on a one-cell ring around the tile: 12
+ * over tiles of 30 x 30 (8, 10) or 62 x 14 (9, 11) half-cells x rows, 12
+ * (8) or 16 (9) planes, or for 10 and 11 as many planes as keep the whole
+ * grid resident at about two blocks per compute unit (16 where the grid is
+ * wider), recomputing colour 0 on a one-cell ring around the tile: 12
  * instead of 16 bytes per cell per iteration; the iterate alternates
  * between two buffers, so these need an even check_every.  Every variant
  * computes the same per-cell arithmetic, so results are bitwise
@@ -259,17 +261,17 @@ int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
  * Autotuner: times every variant for reps back-to-back pairs of launches
  * on this handle's grid, keeps the fastest for all later solves of the
  * handle and reports its index in *chosen (nullable) and the per-variant
- * microseconds per half-sweep (for 8 and 9: half a fused iteration; 0 when
+ * microseconds per half-sweep (for 8-11: half a fused iteration; 0 when
  * not timed because check_every is odd) in
  * us_per_sweep[LES_NUM_SOR_VARIANTS] (nullable).  Runs on a scratch
  * pressure system: the time-stepping state is unchanged.  LES_EINVAL
  * unless 1 <= reps <= 1000.
  */
-#define LES_NUM_SOR_VARIANTS 10
+#define LES_NUM_SOR_VARIANTS 12
 int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sweep);
 
 /* Select a sweep variant by index (0 .. LES_NUM_SOR_VARIANTS-1); LES_EINVAL
- * for 8 or 9 with an odd check_every. */
+ * for 8-11 with an odd check_every. */
 int les_set_sor_variant(les_handle* h, int32_t variant);
 
 /* Step counter (completed steps). */
@@ -322,9 +324,9 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
  * on the members' scratch pressure systems (the state is not touched),
  * reps pairs of launches each, and uses the fastest from the next step on.
  * les_ensemble_tuning reports the choice and the microseconds per
- * half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]; for 8
- * and 9 half a fused iteration, 0 where not timed).  The fused variants 8
- * and 9 run only in the batched mode with an even check_every and only as
+ * half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]; for
+ * 8-11 half a fused iteration, 0 where not timed).  The fused variants 8-11
+ * run only in the batched mode with an even check_every and only as
  * the ensemble's choice (les_ensemble_autotune or les_ensemble_set_variant):
  * otherwise a member set to one runs its grid's default half-sweep. */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);

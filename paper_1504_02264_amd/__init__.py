@@ -41,12 +41,12 @@ EXPORTS = (
     "les_set_warm_start", "les_set_capture",
 )
 ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
-NUM_SOR_VARIANTS = 10
+NUM_SOR_VARIANTS = 12
 # (row width TX, planes per block KT) of each half-sweep variant, and
-# (TX, KT, wavefronts per block) of the fused red-black variants 8 and 9,
-# as in the library
+# (TX, KT, wavefronts per block) of the fused red-black variants 8-11 (KT 0:
+# chosen per grid), as in the library
 SOR_VARIANTS = ((64, 1), (32, 1), (64, 2), (32, 2), (64, 4), (32, 4), (64, 8), (32, 8),
-                (32, 12, 16), (64, 16, 16))
+                (32, 12, 16), (64, 16, 16), (32, 0, 16), (64, 0, 16))
 NUM_SPLIT_SOR_VARIANTS = 8
 KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
 

@@ -390,8 +390,10 @@ __global__ __launch_bounds__(kBlock) void k_ens_sweep(const EnsInst* __restrict_
     sweep_range(d, colour, acc, L - O->sweep[q], L - O->sweep[q] + 1);
 }
 
-// One fused red-black iteration of every member (sweep variants 8 and 9,
-// 16 wavefronts per block): parity 0 reads pd and writes pa, 1 the reverse.
+// One fused red-black iteration of every member (all on the ensemble's
+// fused variant <TX, 16 wavefronts, KT>): parity 0 reads pd and writes pa,
+// 1 the reverse.
+template <int TX, int KT>
 __global__ __launch_bounds__(1024) void k_ens_sweep_rb(const EnsInst* __restrict__ I,
                                                        const unsigned char* __restrict__ owner_of,
                                                        const EnsOffsets* __restrict__ O, int parity,
@@ -406,13 +408,19 @@ __global__ __launch_bounds__(1024) void k_ens_sweep_rb(const EnsInst* __restrict
     const float* a1 = parity ? d.P.pa[1] : d.P.pd[1];
     float* b0 = parity ? d.P.pd[0] : d.P.pa[0];
     float* b1 = parity ? d.P.pd[1] : d.P.pa[1];
-    const unsigned lb = L - O->sweep[q];
-    if (d.variant == 8)
-        sor_rb_body<32, 16, 12>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
-                                d.rel0, d.rel1, lb);
-    else
-        sor_rb_body<64, 16, 16>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
-                                d.rel0, d.rel1, lb);
+    sor_rb_body<TX, 16, KT>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
+                            d.rel0, d.rel1, L - O->sweep[q], fused_kt(d.g, TX, 16, KT));
+}
+
+// Launch of k_ens_sweep_rb for fused variant v over `grid` blocks.
+void launch_ens_sweep_rb(int v, unsigned grid, hipStream_t s, const EnsInst* I,
+                         const unsigned char* owner_of, const EnsOffsets* O, int parity, int it) {
+    switch (v) {
+        case 8: hipLaunchKernelGGL((k_ens_sweep_rb<32, 12>), dim3(grid), dim3(1024), 0, s, I, owner_of, O, parity, it); break;
+        case 9: hipLaunchKernelGGL((k_ens_sweep_rb<64, 16>), dim3(grid), dim3(1024), 0, s, I, owner_of, O, parity, it); break;
+        case 10: hipLaunchKernelGGL((k_ens_sweep_rb<32, 0>), dim3(grid), dim3(1024), 0, s, I, owner_of, O, parity, it); break;
+        default: hipLaunchKernelGGL((k_ens_sweep_rb<64, 0>), dim3(grid), dim3(1024), 0, s, I, owner_of, O, parity, it); break;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_ens_bound(const EnsInst* __restrict__ I) {
@@ -664,8 +672,7 @@ int enqueue_chunk(les_ensemble* e, hipStream_t s) {
     const EnsOffsets& o = e->h_off;
     if (ens_fused(e)) {
         for (int it = 0; it < e->K; ++it)
-            hipLaunchKernelGGL(k_ens_sweep_rb, dim3(o.sweep[n]), dim3(1024), 0, s, e->d_inst, e->d_owner,
-                               e->d_off, it & 1, it);
+            launch_ens_sweep_rb(e->variant, o.sweep[n], s, e->d_inst, e->d_owner, e->d_off, it & 1, it);
     } else {
         for (int it = 0; it < e->K; ++it)
             for (int c = 0; c < 2; ++c)
@@ -869,8 +876,7 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
         auto pair = [&]() {
             for (int w = 0; w < 2; ++w) {
                 if (sor_fused(v))
-                    hipLaunchKernelGGL(k_ens_sweep_rb, dim3(grid), dim3(1024), 0, e->stream, e->d_inst,
-                                       e->d_owner, e->d_off, w, 0);
+                    launch_ens_sweep_rb(v, grid, e->stream, e->d_inst, e->d_owner, e->d_off, w, 0);
                 else
                     hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
                                        e->d_owner, e->d_off, w, 0);

@@ -1,5 +1,5 @@
 // Single-instance launches of the red-black SOR machinery (section 2.6):
-// half-sweeps in eight tile variants, fused red-black iterations in two,
+// half-sweeps in eight tile variants, fused red-black iterations in four,
 // fold, rebase, residual check, p mean and the single-block finalize.
 // Bodies in les_bodies.h.
 #include "les_bodies.h"
@@ -29,12 +29,12 @@ __global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restri
                                                     float omega, int local_iter,
                                                     double* __restrict__ rel0,
                                                     double* __restrict__ rel1,
-                                                    const Ctl* __restrict__ ctl) {
+                                                    const Ctl* __restrict__ ctl, int kt) {
     bool acc;
     const bool active = sweep_active(ctl, local_iter, acc);
     if (!active && ctl->done) return;
     sor_rb_body<TX, NW, KT>(g, a0, a1, r0c, r1c, b0, b1, omega, active && acc && rel0 != nullptr,
-                            !active, rel0, rel1, lblock());
+                            !active, rel0, rel1, lblock(), kt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fold(long long n, float* __restrict__ ph0,
@@ -81,7 +81,7 @@ inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock)
 // block KT) and fused iterations (TX, KT, NW wavefronts per block).
 const SorVariant kSorVariants[kNumSorVariants] = {
     {64, 1, 0}, {32, 1, 0}, {64, 2, 0}, {32, 2, 0}, {64, 4, 0}, {32, 4, 0}, {64, 8, 0}, {32, 8, 0},
-    {32, 12, 16}, {64, 16, 16}};
+    {32, 12, 16}, {64, 16, 16}, {32, 0, 16}, {64, 0, 16}};
 
 int sor_default_variant(const Geo& g) {
     const int w64 = ((g.H + 63) / 64) * 64 - g.H;
@@ -92,9 +92,10 @@ int sor_default_variant(const Geo& g) {
 unsigned sor_sweep_blocks(const Geo& g, int variant) {
     const int tx = kSorVariants[variant].tx, kt = kSorVariants[variant].kt;
     if (sor_fused(variant)) {
-        const int txo = tx - 2, tyo = (64 / tx) * kSorVariants[variant].nw - 2;
+        const int nw = kSorVariants[variant].nw;
+        const int txo = tx - 2, tyo = (64 / tx) * nw - 2, k = fused_kt(g, tx, nw, kt);
         return (unsigned)((g.H + txo - 1) / txo) * (unsigned)((g.ny + tyo - 1) / tyo) *
-               (unsigned)((g.nz + kt - 1) / kt);
+               (unsigned)((g.nz + k - 1) / k);
     }
     const int ty = (64 / tx) * (kBlock / 64);
     return (unsigned)((g.H + tx - 1) / tx) * (unsigned)((g.ny + ty - 1) / ty) *
@@ -141,17 +142,21 @@ hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parit
     const float* a1 = parity ? P.pa[1] : P.pd[1];
     float* b0 = parity ? P.pd[0] : P.pa[0];
     float* b1 = parity ? P.pd[1] : P.pa[1];
+    const SorVariant& sv = kSorVariants[variant];
+    const int kt = fused_kt(g, sv.tx, sv.nw, sv.kt);
+#define LES_RB_CASE(V, TX, NW, KT)                                                                  \
+    case V:                                                                                        \
+        hipLaunchKernelGGL((k_sor_rb<TX, NW, KT>), grid, dim3(64 * NW), 0, st, g, a0, a1, P.r0[0],  \
+                           P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);               \
+        break;
     switch (variant) {
-        case 8:
-            hipLaunchKernelGGL((k_sor_rb<32, 16, 12>), grid, dim3(64 * 16), 0, st, g, a0, a1, P.r0[0],
-                               P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl);
-            break;
-        case 9:
-            hipLaunchKernelGGL((k_sor_rb<64, 16, 16>), grid, dim3(64 * 16), 0, st, g, a0, a1, P.r0[0],
-                               P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl);
-            break;
+        LES_RB_CASE(8, 32, 16, 12)
+        LES_RB_CASE(9, 64, 16, 16)
+        LES_RB_CASE(10, 32, 16, 0)
+        LES_RB_CASE(11, 64, 16, 0)
         default: return hipErrorInvalidValue;
     }
+#undef LES_RB_CASE
     return hipGetLastError();
 }
 

@@ -639,10 +639,11 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
                                             const float* __restrict__ r1c, float* __restrict__ b0,
                                             float* __restrict__ b1, float omega, bool acc, bool copy,
                                             double* __restrict__ rel0, double* __restrict__ rel1,
-                                            unsigned lb) {
+                                            unsigned lb, int kt_run = 0) {
     constexpr int RPW = 64 / TX;
     constexpr int TYB = RPW * NW;
     constexpr int TXO = TX - 2, TYO = TYB - 2;
+    const int kt = KT > 0 ? KT : kt_run;   // planes per block
     __shared__ float ring[3][TYB][TX];
     __shared__ double red3[3][NW];
     const unsigned nbx = (unsigned)(g.H + TXO - 1) / TXO;
@@ -656,8 +657,8 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
     const int row = (threadIdx.x >> 6) * RPW + lane / TX;
     const int ii = (int)bx * TXO - 1 + tx;
     const int j = (int)by * TYO - 1 + row;
-    const int k_begin = (int)bk * KT;
-    const int k_end = min(g.nz, k_begin + KT);
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
     const bool col_ok = ii >= 0 && ii < g.H && j >= 0 && j < g.ny;
     const bool inner = col_ok && tx >= 1 && tx <= TX - 2 && row >= 1 && row <= TYB - 2;
     const bool edge_lane = tx == 0 || tx == TX - 1;

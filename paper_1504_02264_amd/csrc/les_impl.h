@@ -211,10 +211,26 @@ hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* pa
                         const double* rel0, const double* rel1, int nrel, Ctl* ctl);
 // Sweep variants: half-sweeps (nw = 0; row width tx, planes per block kt)
 // and fused red-black iterations (nw wavefronts per block; needs an even
-// check interval, the iterate alternating between pd and pa).
+// check interval, the iterate alternating between pd and pa; kt = 0: the
+// planes per block are chosen per grid, fused_kt).
 struct SorVariant { int tx, kt, nw; };
 constexpr int kNumSplitVariants = 8;
-constexpr int kNumSorVariants = 10;
+constexpr int kNumSorVariants = 12;
+
+// Planes per block of a fused variant on grid g: kt itself, or for kt = 0
+// the fewest that keep the whole grid resident at once, about two
+// 16-wavefront blocks per compute unit (every block then marches the same
+// short column; a grid already wider than that takes 16).
+__host__ __device__ inline int fused_kt(const Geo& g, int tx, int nw, int kt) {
+    if (kt > 0) return kt;
+    const int txo = tx - 2, tyo = (64 / tx) * nw - 2;
+    const long long nxy = (long long)((g.H + txo - 1) / txo) * ((g.ny + tyo - 1) / tyo);
+    constexpr long long kSlots = 2 * 256;   // two blocks on each of the 256 compute units
+    if (nxy >= kSlots) return 16;
+    const long long nbk = kSlots / nxy;
+    const int k = (int)((g.nz + nbk - 1) / nbk);
+    return k < 4 ? 4 : k;
+}
 extern const SorVariant kSorVariants[kNumSorVariants];
 inline bool sor_fused(int variant) { return variant >= kNumSplitVariants; }
 int sor_default_variant(const Geo& g);

@@ -279,7 +279,8 @@ def test_full_size_stage_parity(name, max_iter):
     assert st["div_new_last"] / st["div_star_last"] == pytest.approx(st["resid_last"], rel=0.05)
 
 
-@pytest.mark.parametrize("name,fused,half,max_iter", [("C2", 8, 5, 400), ("C3", 9, 6, 40)])
+@pytest.mark.parametrize("name,fused,half,max_iter", [("C2", 8, 5, 400), ("C2", 10, 5, 400),
+                                                      ("C3", 9, 6, 40)])
 def test_full_size_fused_equals_half_sweeps(name, fused, half, max_iter):
     """The sweep variants the autotuner picks for the benchmark grids (the
     fused red-black iterations) give, at full size, the fields of the
@@ -339,7 +340,7 @@ def test_fused_variants_truncated_interval(max_iter):
     try:
         rhs = random_rhs(nx, ny, nz, seed=12, smooth=1)
         out = []
-        for v in (5, 8, 9):
+        for v in (5, 8, 9, 10, 11):
             g.set_sor_variant(v)
             p, st, rc = g.pressure_solve(rhs, None, tol=1e-12, max_iter=max_iter)
             assert rc == les.LES_NOT_CONVERGED and st["iters"] == max_iter, v
@@ -357,12 +358,12 @@ def test_fused_variants_need_an_even_check_interval():
             g.set_sor_variant(8)
         g.set_sor_variant(5)
         _, us = g.autotune(reps=2)
-        assert us[8] == 0 and us[9] == 0 and np.all(us[:8] > 0)
+        assert np.all(us[8:] == 0) and np.all(us[:8] > 0)
     finally:
         g.close()
 
 
-@pytest.mark.parametrize("variant", [1, 8])
+@pytest.mark.parametrize("variant", [1, 8, 10])
 def test_graph_replay_equals_direct_launches(variant):
     """With kernel timing off the solver replays captured graphs of eight
     check intervals (one ending on the rebase interval); with timing on it
@@ -392,7 +393,7 @@ def test_step_independent_of_sor_variant():
     nx, ny, nz = 33, 17, 9
     mask, prof = urban_case(nx, ny, nz, 4, hmax=5)
     out = []
-    for v in (0, 7, 8, 9):
+    for v in (0, 7, 8, 9, 10, 11):
         g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
         g.set_sor_variant(v)
         g.set_inflow(prof, 0.01, 4)
@@ -414,7 +415,7 @@ def _member(nx, ny, nz, seed, alpha_pl=None, **kw):
     return mask, prof
 
 
-@pytest.mark.parametrize("variant", [-1, 8, 9])
+@pytest.mark.parametrize("variant", [-1, 8, 9, 10])
 @pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
 def test_ensemble_bitwise_equals_single_steps(mode, variant):
     """An ensemble step of uneven members equals stepping each member alone

@@ -648,12 +648,16 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_brick(WgradArgs a, int cinp
 }
 
 // dW[t][ci][co] (the oracle layout, ci < cin) = sum over chunks in a fixed
-// order: 16 lanes per output element take every 16th chunk, then a fixed
-// shuffle tree adds the 16 lane sums.
-__global__ __launch_bounds__(kNetBlock) void k_wgrad_reduce(const float* part, int chunks, int taps, int cin,
-                                                            int cin_t, int cout, float* dw) {
-    const long long e = (long long)blockIdx.x * (kNetBlock / 16) + (threadIdx.x >> 4);
-    const int q = threadIdx.x & 15;
+// order.  A block of 1024 threads takes 64 consecutive output elements
+// (lanes: consecutive elements, so the partial loads are coalesced); its 16
+// wavefronts sum the chunks g, g+16, ... (wavefront g) in turn, and the 16
+// sums are added in wavefront order.
+constexpr int kReduceBlock = 1024;
+__global__ __launch_bounds__(kReduceBlock) void k_wgrad_reduce(const float* part, int chunks, int taps, int cin,
+                                                               int cin_t, int cout, float* dw) {
+    __shared__ float red[kReduceBlock / 64][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const long long e = (long long)blockIdx.x * 64 + lane;
     const long long n = (long long)taps * cin * cout;
     const bool live = e < n;
     const long long ee = live ? e : 0;
@@ -665,10 +669,14 @@ __global__ __launch_bounds__(kNetBlock) void k_wgrad_reduce(const float* part, i
     const size_t off = ((size_t)t * cin_t + ci) * cout + co;
     float s = 0.f;
     if (live)
-        for (int c = q; c < chunks; c += 16) s += part[c * stride + off];
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
-    if (live && q == 0) dw[e] = s;
+        for (int c = g; c < chunks; c += kReduceBlock / 64) s += part[c * stride + off];
+    red[g][lane] = s;
+    __syncthreads();
+    if (g == 0 && live) {
+        float tot = 0.f;
+        for (int w = 0; w < kReduceBlock / 64; ++w) tot += red[w][lane];
+        dw[e] = tot;
+    }
 }
 
 // Per-block channel sums of dout * relu'(mask): bias gradients (partials).
@@ -1319,7 +1327,7 @@ int wgrad_layer(lesnet* n, hipStream_t s, const Layer& l, const bf16* in, int in
     if (!l.up) NCK(launch_wgrad_brick(s, a, chunks, bpc, bpart));
     else NCK(launch_wgrad(s, a, chunks));
     const long long nw = (long long)taps * l.cin * l.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw, kNetBlock / 16)), dim3(kNetBlock), 0, s, n->a.part, chunks, taps,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(nw, 64)), dim3(kReduceBlock), 0, s, n->a.part, chunks, taps,
                        l.cin, cin_t, l.cout, n->g + l.w_off);
     int brows = chunks;
     if (l.up) {
@@ -1647,8 +1655,8 @@ int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t ci
         w.chunk = chunk; w.part = part;
         e = up ? launch_wgrad(s, w, chunks) : launch_wgrad_brick(s, w, chunks, bpc, nullptr);
         if (e == hipSuccess)
-            hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, kNetBlock / 16)),
-                               dim3(kNetBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);
+            hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb((long long)taps * cin * cout, 64)),
+                               dim3(kReduceBlock), 0, s, part, chunks, taps, cin, cin_t, cout, d_out);
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -81,6 +81,7 @@ def lib():
                                     C.c_double, P, C.POINTER(OParams)]
         L.oracle_destroy.argtypes = [P]
         L.oracle_set_inflow.argtypes = [P, P, C.c_double, C.c_uint64]
+        L.oracle_set_inflow_pair.argtypes = [P, C.c_double, P, C.c_double, P]
         L.oracle_step.argtypes = [P, C.c_int, P, P, C.POINTER(OStats)]
         L.oracle_set_fields.argtypes = [P, P, P, P, P, C.c_int]
         L.oracle_get_fields.argtypes = [P, P, P, P, P]
@@ -162,6 +163,16 @@ class Oracle:
         prof = np.ascontiguousarray(profile, dtype=np.float32)
         assert prof.shape == (self.nz,)
         lib().oracle_set_inflow(self.h, _ptr(prof), float(amp), int(seed))
+
+    def set_inflow_pair(self, t0, prof0, t1, prof1):
+        """Linear interpolation in time between two inflow profile samples
+        (section 4, coupled time loop), from the next step on."""
+        a = np.ascontiguousarray(prof0, dtype=np.float32)
+        b = np.ascontiguousarray(prof1, dtype=np.float32)
+        assert a.shape == (self.nz,) and b.shape == (self.nz,)
+        rc = lib().oracle_set_inflow_pair(self.h, float(t0), _ptr(a), float(t1), _ptr(b))
+        if rc != 0:
+            raise ValueError("oracle_set_inflow_pair: set_inflow first, and t0 < t1")
 
     def step(self, n=1, forced: Optional[Sequence[int]] = None):
         st = OStats()

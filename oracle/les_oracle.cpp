@@ -118,6 +118,11 @@ struct Oracle {
     std::vector<double> cn2l, cn2s, cn3l, cn3s, cn4l, cn4s;
     std::vector<double> dgx, dgy, dgz;  // diagonal contributions per axis
     std::vector<double> prof;        // inflow profile U(k), k = 1..nz
+    // Time-interpolated inflow (section 4, coupled time loop): samples U0 =
+    // prof at time t0 and U1 = prof1 at time t1, interpolated linearly.
+    std::vector<double> prof1;
+    bool interp = false;
+    double t0 = 0.0, t1 = 1.0;
     double amp = 0.0;
     uint64_t seed = 0;
     bool have_inflow = false;
@@ -236,7 +241,20 @@ struct Oracle {
         uint64_t ctr = ((uint64_t)s << 40) + ((uint64_t)(k - 1) << 20) + (uint64_t)(j - 1);
         uint64_t r = splitmix64(seed ^ ctr);
         double xi = (double)(r >> 40) * (1.0 / 16777216.0);
-        return prof[k] * (1.0 + amp * (2.0 * xi - 1.0));
+        return profile_at(k, s) * (1.0 + amp * (2.0 * xi - 1.0));
+    }
+
+    // Profile used by step index s (the step that starts at time (s-1) dt).
+    // With a pair of samples: the straight line through (t0, U0(k)) and
+    // (t1, U1(k)) evaluated at that time, held at U0 before t0 and at U1
+    // after t1 (reading: no extrapolation past the samples).
+    double profile_at(int k, int64_t s) const {
+        if (!interp) return prof[k];
+        const double t = (double)(s - 1) * dt;
+        if (t <= t0) return prof[k];
+        if (t >= t1) return prof1[k];
+        const double w = (t - t0) / (t1 - t0);
+        return (1.0 - w) * prof[k] + w * prof1[k];
     }
 
     // ------------------------------------------------ Smagorinsky (les)
@@ -695,6 +713,7 @@ int oracle_set_inflow(void* h, const float* profile, double amp, uint64_t seed) 
     for (int k = 1; k <= o->nz; ++k) o->prof[k] = (double)profile[k - 1];
     o->amp = amp;
     o->seed = seed;
+    o->interp = false;
     if (!o->have_inflow) {
         for (int k = 1; k <= o->nz; ++k)
             for (int j = 1; j <= o->ny; ++j)
@@ -704,6 +723,22 @@ int oracle_set_inflow(void* h, const float* profile, double amp, uint64_t seed) 
         o->refresh_ghosts(o->u, o->v, o->w);
         o->have_inflow = true;
     }
+    return 0;
+}
+
+// Interpolated inflow between (t0, prof0) and (t1, prof1) from the next
+// step on; needs oracle_set_inflow first.  Returns -1 on invalid input.
+int oracle_set_inflow_pair(void* h, double t0, const float* prof0, double t1, const float* prof1) {
+    Oracle* o = static_cast<Oracle*>(h);
+    if (!o->have_inflow || !(t1 > t0)) return -1;
+    o->prof1.assign(o->nz + 2, 0.0);
+    for (int k = 1; k <= o->nz; ++k) {
+        o->prof[k] = (double)prof0[k - 1];
+        o->prof1[k] = (double)prof1[k - 1];
+    }
+    o->t0 = t0;
+    o->t1 = t1;
+    o->interp = true;
     return 0;
 }
 

@@ -461,6 +461,58 @@ def test_inflow_noise_definition():
     assert vals.min() >= 0 and vals.max() < 1
 
 
+def test_inflow_pair_interpolation():
+    """Section 4 (coupled time loop): the inflow profile is interpolated
+    linearly in time between two samples.  Pins on the oracle, with the
+    noise off: the step starting exactly at t0 (resp. t1) carries U0 (resp.
+    U1) bit for bit, steps before t0 / after t1 hold the end samples, the
+    midpoint time gives the mean, equally spaced times give equal
+    increments, and set_inflow switches the interpolation off again."""
+    nx, ny, nz, dt = 12, 6, 5, 0.25
+    o = make(nx, ny, nz, dt=dt)
+    u0 = np.linspace(1.0, 3.0, nz).astype(np.float32)
+    u1 = np.linspace(4.0, 1.5, nz).astype(np.float32)
+    o.set_inflow(u0, 0.0, 1)
+    t0, t1 = 3 * dt, 11 * dt          # step s starts at time (s - 1) dt
+    o.set_inflow_pair(t0, u0, t1, u1)
+    for k in range(1, nz + 1):
+        a, b = float(u0[k - 1]), float(u1[k - 1])
+        for j in (1, ny):
+            assert o.inflow_value(j, k, 4) == a           # t = t0
+            assert o.inflow_value(j, k, 12) == b          # t = t1
+            assert o.inflow_value(j, k, 1) == a           # before t0: held
+            assert o.inflow_value(j, k, 30) == b          # after t1: held
+            assert o.inflow_value(j, k, 8) == pytest.approx(0.5 * (a + b), rel=1e-15)
+            v = [o.inflow_value(j, k, s) for s in (5, 6, 7)]
+            assert v[1] - v[0] == pytest.approx(v[2] - v[1], rel=1e-12)
+            assert v[1] - v[0] == pytest.approx((b - a) / 8, rel=1e-12)
+    o.set_inflow(u1, 0.0, 1)
+    assert o.inflow_value(1, 2, 6) == float(u1[1])
+    with pytest.raises(ValueError):
+        o.set_inflow_pair(t1, u0, t0, u1)
+    fresh = make(nx, ny, nz, dt=dt)
+    with pytest.raises(ValueError):
+        fresh.set_inflow_pair(t0, u0, t1, u1)
+
+
+def test_inflow_pair_of_equal_samples_is_the_plain_inflow():
+    """A pair whose two samples are the same profile leaves every step of
+    the run bit for bit as with that profile alone (noise on)."""
+    nx, ny, nz = 12, 6, 5
+    prof = np.linspace(1.0, 2.0, nz).astype(np.float32)
+    a, b = make(nx, ny, nz), make(nx, ny, nz)
+    a.set_inflow(prof, 0.01, 4)
+    b.set_inflow(prof, 0.01, 4)
+    b.set_inflow_pair(0.0, prof, 0.1, prof)
+    for s in (1, 2, 3):
+        for k in range(1, nz + 1):
+            assert b.inflow_value(3, k, s) == a.inflow_value(3, k, s)
+    a.step(2)
+    b.step(2, forced=a.last_iters)
+    for x, y in zip(a.get_fields(), b.get_fields()):
+        assert np.array_equal(x, y)
+
+
 def test_profiles_closed_forms():
     """P12: log-law and power-law profiles at their cell-centre heights."""
     from les_inputs import log_law_profile, power_law_profile

@@ -162,6 +162,26 @@ int les_set_stream(les_handle* h, void* stream);
 int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_t seed);
 
 /*
+ * Inflow driven by a coarser model that delivers wind profiles at its own
+ * interval (section 4, the coupled WRF/LES time loop: the LES receives a
+ * profile every simulated minute, steps at half a second, and interpolates
+ * between the two latest profiles, which it can do only once two exist).
+ * prof0 (sample at model time t0) and prof1 (at t1 > t0) are nz float32
+ * speeds as for les_set_inflow.  Every following step, started at time
+ * t = n dt with n the steps done so far (les_get_step), uses
+ *   U(k) = U0(k) + w (U1(k) - U0(k)),  w = (t - t0) / (t1 - t0) clamped to [0, 1]
+ * (w rounded to float32, U formed on the device in float32), with the
+ * noise, amplitude and seed of les_set_inflow.  A later pair replaces this
+ * one; les_set_inflow switches the interpolation off.  The pair is part of
+ * the checkpoint (les_get_state).  Requires les_set_inflow (or
+ * les_set_fields) first, else LES_ESTATE; LES_EINVAL for NULL profiles,
+ * non-finite values or t1 <= t0.  Ensembles reject members with a pair
+ * (LES_ESTATE).  Synchronous.
+ */
+int les_set_inflow_pair(les_handle* h, double t0, const float* prof0, double t1,
+                        const float* prof1);
+
+/*
  * Advance n >= 0 steps.  Each step: nu_t, tendency with feedback forcing and
  * AB2 (u*), inflow, rhs = div(u*)/dt, red-black SOR to tol (checked every
  * check_every iterations, at most max_iter), projection u = u* - dt grad p,

@@ -26,7 +26,7 @@ URBAN_BC = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP)
 # every function include/les.h and include/lesnet.h declare
 EXPORTS = (
     "les_default_params", "les_create", "les_destroy", "les_last_error", "les_set_stream",
-    "les_set_inflow", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
+    "les_set_inflow", "les_set_inflow_pair", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
@@ -147,6 +147,7 @@ def lib():
     L.les_last_error.restype = C.c_char_p
     L.les_set_stream.argtypes = [P, P]
     L.les_set_inflow.argtypes = [P, P, C.c_float, C.c_uint64]
+    L.les_set_inflow_pair.argtypes = [P, C.c_double, P, C.c_double, P]
     L.les_step.argtypes = [P, C.c_int32, C.POINTER(StepStats)]
     L.les_pressure_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats)]
     L.les_pressure_solve_dev.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
@@ -265,6 +266,13 @@ class LES:
     def set_inflow(self, profile, noise_amp=0.01, seed=0):
         prof = _f32(profile, (self.nz,))
         return self._check(lib().les_set_inflow(self.h, _ptr(prof), float(noise_amp), int(seed)))
+
+    def set_inflow_pair(self, t0, prof0, t1, prof1):
+        """Interpolate the inflow profile in time between (t0, prof0) and
+        (t1, prof1) from the next step on (les_set_inflow_pair)."""
+        a = _f32(prof0, (self.nz,))
+        b = _f32(prof1, (self.nz,))
+        return self._check(lib().les_set_inflow_pair(self.h, float(t0), _ptr(a), float(t1), _ptr(b)))
 
     def step(self, n=1, allow_not_converged=True):
         """Advance n steps; returns (status, stats dict, per-step SOR iterations)."""

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_ens_inflow(const EnsInst* I, const E
     const int q = owner(O->inflow, n, L);
     const EnsInst& d = I[q];
     if (!d.inflow) return;
-    inflow_body(d.g, d.u[1 - D[q].cur], d.prof, d.flags, d.amp, d.seed, D[q].step + 1,
+    inflow_body(d.g, d.u[1 - D[q].cur], d.prof, d.prof, 0.f, d.flags, d.amp, d.seed, D[q].step + 1,
                 L - O->inflow[q]);
 }
 
@@ -926,6 +926,8 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
     const int n = e->n;
     for (int q = 0; q < n; ++q) {
         if (!e->members[q]->have_inflow) return ens_err(e, LES_ESTATE, "member without inflow");
+        if (e->members[q]->interp)
+            return ens_err(e, LES_ESTATE, "member with an interpolated inflow pair");
         if (e->members[q]->warm_net || e->members[q]->cap_x)
             return ens_err(e, LES_ESTATE, "member with a warm start or capture set (single-handle only)");
     }

@@ -21,9 +21,10 @@ __global__ __launch_bounds__(kBlock) void k_tendency(Geo g, TendArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_inflow(Geo g, float* __restrict__ us,
                                                    const float* __restrict__ prof,
+                                                   const float* __restrict__ prof1, float wt,
                                                    const uint8_t* __restrict__ flags, float amp,
                                                    uint64_t seed, long long step) {
-    inflow_body(g, us, prof, flags, amp, seed, step, blockIdx.x);
+    inflow_body(g, us, prof, prof1, wt, flags, amp, seed, step, blockIdx.x);
 }
 
 __global__ void k_ctl_init(Ctl* ctl, double tol, int max_iter, int K) {
@@ -117,9 +118,10 @@ hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const f
 }
 
 hipError_t launch_inflow(const Geo& g, hipStream_t st, float* us, const float* prof,
-                         const uint8_t* flags, float amp, uint64_t seed, int64_t step) {
+                         const float* prof1, float wt, const uint8_t* flags, float amp,
+                         uint64_t seed, int64_t step) {
     hipLaunchKernelGGL(k_inflow, dim3(nblocks((long long)g.ny * g.nz)), dim3(kBlock), 0, st, g,
-                       us, prof, flags, amp, seed, (long long)step);
+                       us, prof, prof1, wt, flags, amp, seed, (long long)step);
     return hipGetLastError();
 }
 

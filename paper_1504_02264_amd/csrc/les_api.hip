@@ -19,7 +19,7 @@ using namespace les;
 
 namespace {
 
-constexpr uint32_t kStateMagic = 0x4C455331u;   // "LES1"
+constexpr uint32_t kStateMagic = 0x4C455332u;   // "LES2"
 
 int set_err(les_handle* h, int code, const char* what, hipError_t e = hipSuccess) {
     if (h) {
@@ -517,6 +517,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     if (!h) return LES_ENOMEM;
     h->prm = p;
     h->g = make_geo(gr->nx, gr->ny, gr->nz, *s, dt, p);
+    h->dt = dt;
     h->mask.assign((size_t)ncell, 0);
     if (building_mask) std::memcpy(h->mask.data(), building_mask, (size_t)ncell);
     auto fail = [&](int code) {
@@ -537,7 +538,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     for (int v = 0; v < kNumSorVariants; ++v) maxsweep = std::max<long long>(maxsweep, sor_sweep_blocks(g, v));
     const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * maxsweep) + 64;
     const size_t pb = align256(nparts * sizeof(double));
-    const size_t total = 13 * nb + fb + align256((size_t)g.nz * sizeof(float)) + ncells + 10 * cb +
+    const size_t total = 13 * nb + fb + 2 * align256((size_t)g.nz * sizeof(float)) + ncells + 10 * cb +
                          3 * pb + align256(sizeof(Ctl));
     void* arena = nullptr;
     if (hipMalloc(&arena, total) != hipSuccess) return fail(LES_ENOMEM);
@@ -559,6 +560,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     h->f.su = (float*)take(nb); h->f.sv = (float*)take(nb); h->f.sw = (float*)take(nb);
     h->f.flags = (uint8_t*)take(fb);
     h->f.prof = (float*)take(align256((size_t)g.nz * sizeof(float)));
+    h->f.prof1 = (float*)take(align256((size_t)g.nz * sizeof(float)));
     h->f.stage = (float*)take(ncells);
     for (int c = 0; c < 2; ++c) h->f.P.ph[c] = (float*)take(cb);
     for (int c = 0; c < 2; ++c) h->f.P.pd[c] = (float*)take(cb);
@@ -582,6 +584,7 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
             return fail(LES_EDEVICE);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(LES_EDEVICE);
     h->prof.assign((size_t)g.nz, 0.f);
+    h->prof1.assign((size_t)g.nz, 0.f);
     h->sor_variant = sor_default_variant(g);
     *out = h;
     return LES_OK;
@@ -623,6 +626,7 @@ int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_
     std::memcpy(h->prof.data(), profile, (size_t)g.nz * sizeof(float));
     h->amp = noise_amp;
     h->seed = seed;
+    h->interp = false;
     CK(hipMemcpyAsync(h->f.prof, h->prof.data(), (size_t)g.nz * sizeof(float),
                       hipMemcpyHostToDevice, h->stream));
     if (!h->have_inflow) {
@@ -644,6 +648,40 @@ int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_
     }
     CK(hipStreamSynchronize(h->stream));
     return LES_OK;
+}
+
+int les_set_inflow_pair(les_handle* h, double t0, const float* prof0, double t1,
+                        const float* prof1) {
+    if (!h || !prof0 || !prof1) return LES_EINVAL;
+    if (!h->have_inflow) return set_err(h, LES_ESTATE, "les_set_inflow (or les_set_fields) first");
+    if (!(std::isfinite(t0) && std::isfinite(t1) && t1 > t0))
+        return set_err(h, LES_EINVAL, "need finite t0 < t1");
+    const Geo& g = h->g;
+    for (int k = 0; k < g.nz; ++k)
+        if (!std::isfinite(prof0[k]) || !std::isfinite(prof1[k]))
+            return set_err(h, LES_EINVAL, "profile not finite");
+    std::memcpy(h->prof.data(), prof0, (size_t)g.nz * sizeof(float));
+    std::memcpy(h->prof1.data(), prof1, (size_t)g.nz * sizeof(float));
+    h->t0 = t0;
+    h->t1 = t1;
+    h->interp = true;
+    CK(hipMemcpyAsync(h->f.prof, h->prof.data(), (size_t)g.nz * sizeof(float),
+                      hipMemcpyHostToDevice, h->stream));
+    CK(hipMemcpyAsync(h->f.prof1, h->prof1.data(), (size_t)g.nz * sizeof(float),
+                      hipMemcpyHostToDevice, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    return LES_OK;
+}
+
+// Weight of the second profile sample for the step that starts at time
+// step * dt: the linear interpolation between the samples, held at the
+// end values outside [t0, t1]; 0 when no pair is set.
+static float inflow_weight(const les_handle* h) {
+    if (!h->interp) return 0.f;
+    const double t = (double)h->step * h->dt;
+    double w = (t - h->t0) / (h->t1 - h->t0);
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+    return (float)w;
 }
 
 int les_step(les_handle* h, int32_t n, les_step_stats* st) {
@@ -675,7 +713,8 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
         h->have_old = true;
         if (g.inflow)
             CK(timed(h, KN_INFLOW, kNoTag, [&] {
-                return launch_inflow(g, s, h->f.u[b], h->f.prof, h->f.flags, h->amp, h->seed, h->step + 1);
+                return launch_inflow(g, s, h->f.u[b], h->f.prof, h->interp ? h->f.prof1 : h->f.prof,
+                                     inflow_weight(h), h->f.flags, h->amp, h->seed, h->step + 1);
             }));
         CK(launch_ctl_init(s, h->f.ctl, p.tol, p.max_iter, p.check_every));
         CK(timed(h, KN_RHS, kNoTag, [&] {
@@ -1034,8 +1073,9 @@ struct StateHeader {
     int64_t step;
     int32_t have_old, have_inflow;
     float amp;
-    int32_t pad;
+    int32_t interp;
     uint64_t seed;
+    double t0, t1;
     int64_t ntot, ctot;
 };
 }  // namespace
@@ -1043,7 +1083,7 @@ struct StateHeader {
 int les_state_size(const les_handle* h, int64_t* bytes) {
     if (!h || !bytes) return LES_EINVAL;
     const Geo& g = h->g;
-    *bytes = (int64_t)sizeof(StateHeader) + (int64_t)g.nz * 4 + 9LL * g.ntot * 4 + 4LL * g.ctot * 4;
+    *bytes = (int64_t)sizeof(StateHeader) + 2LL * g.nz * 4 + 9LL * g.ntot * 4 + 4LL * g.ctot * 4;
     return LES_OK;
 }
 
@@ -1060,12 +1100,17 @@ int les_get_state(les_handle* h, void* buf, int64_t bytes) {
     hd.have_inflow = h->have_inflow;
     hd.amp = h->amp;
     hd.seed = h->seed;
+    hd.interp = h->interp;
+    hd.t0 = h->t0;
+    hd.t1 = h->t1;
     hd.ntot = g.ntot;
     hd.ctot = g.ctot;
     char* b = (char*)buf;
     std::memcpy(b, &hd, sizeof hd);
     b += sizeof hd;
     std::memcpy(b, h->prof.data(), (size_t)g.nz * 4);
+    b += (size_t)g.nz * 4;
+    std::memcpy(b, h->prof1.data(), (size_t)g.nz * 4);
     b += (size_t)g.nz * 4;
     const float* nat[9] = {h->f.u[h->cur], h->f.v[h->cur], h->f.w[h->cur], h->f.fu, h->f.fv,
                            h->f.fw, h->f.su, h->f.sv, h->f.sw};
@@ -1097,7 +1142,10 @@ int les_set_state(les_handle* h, const void* buf, int64_t bytes) {
     b += sizeof hd;
     std::memcpy(h->prof.data(), b, (size_t)g.nz * 4);
     b += (size_t)g.nz * 4;
+    std::memcpy(h->prof1.data(), b, (size_t)g.nz * 4);
+    b += (size_t)g.nz * 4;
     CK(hipMemcpyAsync(h->f.prof, h->prof.data(), (size_t)g.nz * 4, hipMemcpyHostToDevice, h->stream));
+    CK(hipMemcpyAsync(h->f.prof1, h->prof1.data(), (size_t)g.nz * 4, hipMemcpyHostToDevice, h->stream));
     float* nat[9] = {h->f.u[h->cur], h->f.v[h->cur], h->f.w[h->cur], h->f.fu, h->f.fv,
                      h->f.fw, h->f.su, h->f.sv, h->f.sw};
     for (float* dst : nat) {
@@ -1120,6 +1168,9 @@ int les_set_state(les_handle* h, const void* buf, int64_t bytes) {
     h->have_inflow = hd.have_inflow != 0;
     h->amp = hd.amp;
     h->seed = hd.seed;
+    h->interp = hd.interp != 0;
+    h->t0 = hd.t0;
+    h->t1 = hd.t1;
     return LES_OK;
 }
 

@@ -271,8 +271,11 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
 
 // u*(0, j, k) = U(k) (1 + a (2 xi - 1)) on fluid inflow faces, 0 on solid
 // ones; xi = top 24 bits of splitmix64(seed ^ (step 2^40 + k0 2^20 + j0)).
+// U(k) = U0(k) + wt (U1(k) - U0(k)), the linear interpolation in time
+// between two profile samples (wt = 0 gives U0 exactly).
 __device__ __forceinline__ void inflow_body(const Geo& g, float* __restrict__ us,
                                             const float* __restrict__ prof,
+                                            const float* __restrict__ prof1, float wt,
                                             const uint8_t* __restrict__ flags, float amp,
                                             uint64_t seed, long long step, unsigned lb) {
     const int t = (int)(lb * kBlock + threadIdx.x);
@@ -282,7 +285,8 @@ __device__ __forceinline__ void inflow_body(const Geo& g, float* __restrict__ us
     const uint64_t r = splitmix64(seed ^ ctr);
     const float xi = (float)(r >> 40) * (1.0f / 16777216.0f);
     const bool solid = (flags[g.nat(1, j0 + 1, k0 + 1)] & F_CSOLID) != 0;
-    us[g.nat(0, j0 + 1, k0 + 1)] = solid ? 0.f : prof[k0] * (1.f + amp * (2.f * xi - 1.f));
+    const float U = prof[k0] + wt * (prof1[k0] - prof[k0]);
+    us[g.nat(0, j0 + 1, k0 + 1)] = solid ? 0.f : U * (1.f + amp * (2.f * xi - 1.f));
 }
 
 __device__ __forceinline__ void ctl_init_body(Ctl* ctl, double tol, int max_iter, int K) {

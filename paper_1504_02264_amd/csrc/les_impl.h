@@ -99,7 +99,8 @@ struct DevFields {
     float* fu; float* fv; float* fw;     // AB2 history F^{n-1}
     float* su; float* sv; float* sw;     // feedback integral
     uint8_t* flags;
-    float* prof;                         // inflow profile [nz]
+    float* prof;                         // inflow profile [nz] (first sample of a pair)
+    float* prof1;                        // second sample of an interpolated pair [nz]
     float* stage;                        // natural-order staging (I/O)
     PBufs P;                             // time-stepping pressure system
     double* part[3];                     // reduction partials
@@ -152,7 +153,10 @@ struct les_handle {
     int64_t step = 0;
     float amp = 0.f;
     uint64_t seed = 0;
-    std::vector<float> prof;
+    std::vector<float> prof, prof1;
+    bool interp = false;                 // inflow interpolated between prof and prof1
+    double t0 = 0.0, t1 = 1.0;           // times of the two samples
+    double dt = 0.0;                     // time step as given (the grid keeps it in float)
     std::vector<uint8_t> mask;
     // kernel timing (les_params.timing): event pool and pending brackets
     std::vector<hipEvent_t> tev;
@@ -195,6 +199,7 @@ hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const f
                            float* su, float* sv, float* sw, const uint8_t* flags, float* us,
                            float* vs, float* ws, float nu, float alpha, float beta, int first);
 hipError_t launch_inflow(const Geo& g, hipStream_t st, float* us, const float* prof,
+                         const float* prof1, float wt,
                          const uint8_t* flags, float amp, uint64_t seed, int64_t step);
 hipError_t launch_ctl_init(hipStream_t st, Ctl* ctl, double tol, int max_iter, int K);
 hipError_t launch_rhs(const Geo& g, hipStream_t st, const float* us, const float* vs,

@@ -96,6 +96,7 @@ def lib():
                                             C.POINTER(OStats)]
         L.oracle_sor_iterations.restype = C.c_double
         L.oracle_sor_iterations.argtypes = [P, P, P, C.c_int]
+        L.oracle_twinned_iterations.argtypes = [P, P, P, C.c_double, C.c_int]
         L.oracle_residual.restype = C.c_double
         L.oracle_residual.argtypes = [P, P, P]
         L.oracle_splitmix64.restype = C.c_uint64
@@ -265,6 +266,13 @@ class Oracle:
         p = _f64(p0).copy()
         s = lib().oracle_sor_iterations(self.h, _ptr(_f64(rhs)), _ptr(p), int(n))
         return p, s
+
+    def twinned_iterations(self, rhs, p0, omega, n):
+        """n iterations of twinned double buffering (section 2.6): each half
+        updates every cell from the other buffer (relaxed Jacobi)."""
+        p = _f64(p0).copy()
+        lib().oracle_twinned_iterations(self.h, _ptr(_f64(rhs)), _ptr(p), float(omega), int(n))
+        return p
 
     def residual(self, rhs, p):
         return lib().oracle_residual(self.h, _ptr(_f64(rhs)), _ptr(_f64(p)))

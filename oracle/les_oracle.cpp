@@ -578,6 +578,29 @@ struct Oracle {
         return sor;
     }
 
+    // One iteration of twinned double buffering (section 2.6, the paper's
+    // alternative to the red-black scheme on the GPU): with the pair (p_0,
+    // p_1) per cell, nrd = 0 sets every cell's p_1 from p_0 and nrd = 1 sets
+    // p_0 from p_1, each with the SOR point formula
+    //   p_dst = p_src + omega (cn1 (sum_nb cn_nb p_src_nb - rhs) - p_src),
+    // so all neighbours come from the previous half: a relaxed Jacobi
+    // iteration.  P0 holds the result.
+    void twinned_iteration(Box& P0, Box& P1, const Box& R, double omega) const {
+        for (int nrd = 0; nrd <= 1; ++nrd) {
+            const Box& S = nrd == 0 ? P0 : P1;
+            Box& D = nrd == 0 ? P1 : P0;
+#pragma omp parallel for schedule(static)
+            for (int k = 1; k <= nz; ++k)
+                for (int j = 1; j <= ny; ++j)
+                    for (int i = 1; i <= nx; ++i) {
+                        double nb = cn2l[i] * S(i + 1, j, k) + cn2s[i] * S(i - 1, j, k) +
+                                    cn3l[j] * S(i, j + 1, k) + cn3s[j] * S(i, j - 1, k) +
+                                    cn4l[k] * S(i, j, k + 1) + cn4s[k] * S(i, j, k - 1);
+                        D(i, j, k) = S(i, j, k) + omega * (cn1(i, j, k) * (nb - R(i, j, k)) - S(i, j, k));
+                    }
+        }
+    }
+
     // Iterate to a relative residual ||rhs - A p|| / ||rhs|| <= tol, checked
     // after every check_every iterations and at max_iter.  forced >= 0
     // replays exactly that many iterations instead (no stopping test).
@@ -953,6 +976,21 @@ double oracle_sor_iterations(void* h, const double* rhs, double* p, int n) {
     for (int m = 0; m < n; ++m) s = o->sor_iteration(P, R);
     get_cell(o, P, p);
     return s;
+}
+
+// Exactly n twinned double-buffer iterations (relaxation omega) on caller
+// arrays; p is the start on entry and p_0 after the last iteration on exit.
+int oracle_twinned_iterations(void* h, const double* rhs, double* p, double omega, int n) {
+    Oracle* o = static_cast<Oracle*>(h);
+    Box R, P0, P1;
+    R.init(o->nx, o->ny, o->nz);
+    P0.init(o->nx, o->ny, o->nz);
+    P1.init(o->nx, o->ny, o->nz);
+    put_cell(o, R, rhs);
+    put_cell(o, P0, p);
+    for (int m = 0; m < n; ++m) o->twinned_iteration(P0, P1, R, omega);
+    get_cell(o, P0, p);
+    return 0;
 }
 
 // Relative residual ||rhs - A p|| / ||rhs|| of caller arrays.

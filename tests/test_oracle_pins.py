@@ -570,3 +570,51 @@ def test_replay_mode_reproduces_free_run():
     b.step(3, forced=iters)
     for x, y in zip(a.get_fields(), b.get_fields()):
         assert np.array_equal(x, y)
+
+
+def _dense_A(o, shape):
+    n = int(np.prod(shape))
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        M[:, c] = o.apply_A(e.reshape(shape)).ravel()
+    return M
+
+
+def test_twinned_is_relaxed_jacobi_on_the_dense_matrix():
+    """Section 2.6, twinned double buffering: each half of an iteration
+    updates every cell from the other buffer with the SOR point formula,
+    which is the relaxed Jacobi step x <- x - omega D^-1 (A x - b), D the
+    diagonal of A.  Pinned against the dense matrix of the operator (its
+    columns A e_c), with D read off that matrix, for the urban face set
+    (non-singular) and for all walls: three iterations are six Jacobi
+    steps; the solution of the dense system is a fixed point; with omega =
+    1 the iteration reaches it."""
+    rng = np.random.default_rng(11)
+    for bc in (URBAN_BC, (FREESLIP,) * 6):
+        nx, ny, nz = 6, 5, 4
+        o = make(nx, ny, nz, bc=bc)
+        shape = (nz, ny, nx)
+        M = _dense_A(o, shape)
+        d = np.diag(M)
+        b = rng.standard_normal(shape)
+        if bc != URBAN_BC:
+            b -= b.mean()
+        x0 = rng.standard_normal(shape)
+        x = x0.ravel().copy()
+        for _ in range(6):
+            x = x - 0.8 * (M @ x - b.ravel()) / d
+        got = o.twinned_iterations(b, x0, 0.8, 3)
+        assert np.allclose(got.ravel(), x, rtol=0, atol=1e-12 * np.abs(x).max())
+        if bc == URBAN_BC:
+            xs = np.linalg.solve(M, b.ravel()).reshape(shape)
+            fixed = o.twinned_iterations(b, xs, 1.0, 1)
+            assert np.linalg.norm(fixed - xs) <= 1e-12 * np.linalg.norm(xs)
+            far = o.twinned_iterations(b, np.zeros(shape), 1.0, 3000)
+            assert np.linalg.norm(far - xs) <= 1e-8 * np.linalg.norm(xs)
+    # not the red-black iteration: one twinned iteration from zero differs
+    o = make(6, 5, 4)
+    b = rng.standard_normal((4, 5, 6))
+    rb, _ = o.sor_iterations(b, np.zeros((4, 5, 6)), 1)
+    assert np.linalg.norm(o.twinned_iterations(b, np.zeros((4, 5, 6)), 1.8, 1) - rb) > 1e-3

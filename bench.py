@@ -249,6 +249,56 @@ def bench_warm_start(args, les, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_twinned(args, les, torch):
+    """Twinned double buffering (section 2.6) against red-black SOR at the
+    same iteration counts (the paper's default setup runs 50), from p = 0
+    on the Poisson rhs of the workload's first step.  Twinned: device time
+    of its sweeps (events); red-black: host wall time of the stand-alone
+    solve with the residual checks (tol unreachable, so it runs max_iter)."""
+    import numpy as np
+    from les_inputs import WORKLOADS, make_workload_inputs
+    w = WORKLOADS[args.workload]
+    cells = w.nx * w.ny * w.nz
+    mask, prof = make_workload_inputs(w)
+    g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask)
+    g.set_inflow(prof, w.noise_amp, w.seed)
+    variant, _ = g.autotune(reps=20)
+    g.step(1)
+    rhs = torch.from_numpy(np.ascontiguousarray(g.get_rhs(), dtype=np.float32)).cuda()
+    p = torch.zeros_like(rhs)
+    rows = []
+    for n in (50, 500):
+        best_tw, best_rb = None, None
+        for _ in range(3):
+            p.zero_()
+            st_tw, ms_tw = g.pressure_solve_twinned(rhs, p, 1.0, n)
+            best_tw = ms_tw if best_tw is None else min(best_tw, ms_tw)
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st_rb, _ = g.pressure_solve_dev(rhs, p, tol=1e-30, max_iter=n)
+            torch.cuda.synchronize()
+            ms_rb = (time.perf_counter() - t0) * 1e3
+            best_rb = ms_rb if best_rb is None else min(best_rb, ms_rb)
+        tw_bytes = 32.0 * cells * n            # per half: pair 8 B + rhs 4 B + one component 4 B
+        rows.append({"iters": n,
+                     "twinned": {"resid": st_tw["resid"], "ms": best_tw, "us_per_iter": 1e3 * best_tw / n,
+                                 "GB_per_s": tw_bytes / (best_tw * 1e-3) / 1e9,
+                                 "hbm_frac": tw_bytes / (best_tw * 1e-3) / 8e12},
+                     "red_black": {"resid": st_rb["resid"], "ms": best_rb, "us_per_iter": 1e3 * best_rb / n,
+                                   "sor_variant": int(variant)}})
+        log(f"{n} iterations: twinned {1e3 * best_tw / n:.1f} us/it resid {st_tw['resid']:.3e}; "
+            f"red-black {1e3 * best_rb / n:.1f} us/it resid {st_rb['resid']:.3e}")
+    out = {"metric": "twinned double buffering vs red-black SOR at fixed iteration counts",
+           "unit": "us per iteration, relative residual", "n_gpus": 1, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{args.workload} {w.nx}x{w.ny}x{w.nz} urban LES, Poisson rhs of the first step, "
+                                  "from p = 0; twinned omega 1, red-black omega 1.8"},
+           "rows": rows}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_ensemble(args, les, torch):
     """Aggregate cell-updates/s of an uneven ensemble in one persistent solve per step."""
     from les_inputs import ensemble_members, make_workload_inputs
@@ -322,6 +372,8 @@ def main():
     ap.add_argument("--warm-start", action="store_true",
                     help="instead of the LES line: plain SOR vs the learned start on held-out cases "
                          "(C1 size; with --workload C3, trained on crops of 1024x1024x96 runs)")
+    ap.add_argument("--twinned", action="store_true",
+                    help="compare twinned double buffering with red-black SOR (JSON line of its own)")
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events (no roofline object)")
@@ -348,6 +400,8 @@ def main():
     torch.cuda.set_device(0)
     if args.warm_start:
         return bench_warm_start(args, les, torch)
+    if args.twinned:
+        return bench_twinned(args, les, torch)
     if args.ensemble:
         return bench_ensemble(args, les, torch)
     w = WORKLOADS[args.workload]

@@ -212,6 +212,31 @@ int les_pressure_solve(les_handle* h, const float* rhs, float* p, double tol, in
 int les_pressure_solve_dev(les_handle* h, const float* d_rhs, float* d_p, double tol,
                            int32_t max_iter, les_solve_stats* st, void* stream);
 
+/*
+ * Twinned double-buffer relaxation (section 2.6: the paper's replacement
+ * for the red-black scheme on the GPU), as a measured comparison solver;
+ * the time step itself uses red-black SOR.  p is held as a pair (p_0, p_1)
+ * of float32 per cell, interleaved; the first half of an iteration sets
+ * every cell's p_1 from p_0, the second half p_0 from p_1, each by
+ *   p_dst = p_src + omega (cn1 (sum_nb cn_nb p_src_nb - rhs) - p_src)
+ * with the handle's operator.  All neighbours come from the previous half,
+ * so this is a relaxed Jacobi iteration: its iterates differ from red-black
+ * SOR's, and it is run for a fixed number of iterations (the paper's
+ * default setup runs SOR for a fixed 50), not to a tolerance.
+ * d_rhs, d_p: device float32 [nz][ny][nx]; d_p is the start on entry and
+ * p_0 after `iters` iterations on exit.  No mean removal (for an operator
+ * without outflow face, give a zero-mean rhs).  st (optional): iters,
+ * resid = ||rhs - A p||_2 / ||rhs||_2 in float64, rhs_norm, converged =
+ * (resid <= the handle's tol), reltmp2 = 0.  ms (optional): device time of
+ * the sweeps alone (events on the handle's stream).  Synchronous.  Keeps a
+ * workspace of (nx+2)(ny+2)(nz+2) pairs from the first call until
+ * les_destroy.  LES_EINVAL for NULL pointers, iters < 0 or omega outside
+ * (0, 1] (beyond 1 the iteration diverges on this operator);
+ * LES_ENONFINITE if the residual is not finite.
+ */
+int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, float* d_p, double omega,
+                               int32_t iters, les_solve_stats* st, double* ms);
+
 /* Copy the state out (ghost-free layouts above).  NULL skips a field. */
 int les_get_fields(les_handle* h, float* u, float* v, float* w, float* p);
 

@@ -27,6 +27,7 @@ URBAN_BC = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP)
 EXPORTS = (
     "les_default_params", "les_create", "les_destroy", "les_last_error", "les_set_stream",
     "les_set_inflow", "les_set_inflow_pair", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
+    "les_pressure_solve_twinned",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
     "les_bc_map", "les_get_timing", "les_autotune", "les_set_sor_variant",
@@ -151,6 +152,8 @@ def lib():
     L.les_step.argtypes = [P, C.c_int32, C.POINTER(StepStats)]
     L.les_pressure_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats)]
     L.les_pressure_solve_dev.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
+    L.les_pressure_solve_twinned.argtypes = [P, P, P, C.c_double, C.c_int32,
+                                             C.POINTER(SolveStats), C.POINTER(C.c_double)]
     L.les_get_fields.argtypes = [P, P, P, P, P]
     L.les_get_fields_dev.argtypes = [P, P, P, P, P, P]
     L.les_set_fields.argtypes = [P, P, P, P, P, C.c_int32]
@@ -302,6 +305,16 @@ class LES:
                                                       int(max_iter), C.byref(st), s),
                          (LES_OK, LES_NOT_CONVERGED))
         return st.as_dict(), rc
+
+    def pressure_solve_twinned(self, d_rhs, d_p, omega=1.0, iters=50):
+        """Twinned double-buffer relaxation (les_pressure_solve_twinned) on
+        contiguous float32 device tensors; returns (stats, ms of the sweeps)."""
+        st = SolveStats()
+        ms = C.c_double(0.0)
+        self._check(lib().les_pressure_solve_twinned(self.h, C.c_void_p(d_rhs.data_ptr()),
+                                                     C.c_void_p(d_p.data_ptr()), float(omega),
+                                                     int(iters), C.byref(st), C.byref(ms)))
+        return st.as_dict(), ms.value
 
     def get_fields(self):
         su, sv, sw, sp = self.shapes

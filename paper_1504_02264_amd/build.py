@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libles.so")
 SOURCES = ["kernels_step.hip", "kernels_sor.hip", "ensemble.hip", "les_api.hip", "lesnet.hip",
-           "warm.hip"]
+           "warm.hip", "twinned.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

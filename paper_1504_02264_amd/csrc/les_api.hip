@@ -596,6 +596,7 @@ void les_destroy(les_handle* h) {
     if (h->arena) (void)hipFree(h->arena);
     if (h->solve_arena) (void)hipFree(h->solve_arena);
     warm_free(h);
+    twinned_free(h);
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
     if (h->h_flag) (void)hipHostFree(h->h_flag);
     for (int q = 0; q < 2; ++q)

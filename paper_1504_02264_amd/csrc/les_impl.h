@@ -170,6 +170,9 @@ struct les_handle {
     hipEvent_t ev[2] = {nullptr, nullptr};
     les::SolveGraph sgraph[3];   // run_solve's graph cache (timing off)
     uint64_t sgraph_tick = 0;
+    // twinned double-buffer comparison solver (twinned.hip): pairs, partials
+    void* tw_q = nullptr;
+    double* tw_part = nullptr;
     // learned warm start and training-pair capture (warm.hip)
     lesnet* warm_net = nullptr;
     double warm_scale = 1.0;
@@ -264,6 +267,7 @@ int warm_take(les_handle* h, int take, double r_prev, double r_net);
 int warm_post(les_handle* h);
 int warm_result(les_handle* h, int* taken, double* r_prev, double* r_net);
 void warm_free(les_handle* h);
+void twinned_free(les_handle* h);
 
 // natural-order [nz][ny][nx] <-> colour layout
 hipError_t launch_cells_to_colour(const Geo& g, hipStream_t st, const float* src, float* const dst[2]);

@@ -10,10 +10,11 @@
 // red-black sweeps).  Every neighbour therefore comes from the previous
 // half: a relaxed Jacobi iteration, not red-black SOR.
 //
-// One thread per cell, 64 consecutive cells of a row per wavefront, 4 rows
-// per block, one plane per grid z index.  Per half: the pair of the cell
-// (8 bytes; neighbours from the cache), rhs (4 bytes) and one component
-// written (4 bytes), 16 bytes per cell at best.
+// 64 consecutive cells of a row per wavefront, 4 rows per block, each
+// thread marching up 8 planes of its column.  Per half: the pair of the
+// cell (8 bytes; neighbours from registers, lanes and the cache), rhs (4
+// bytes) and one component written (4 bytes), 16 bytes per cell at best.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -46,23 +47,52 @@ __global__ __launch_bounds__(kBlock) void k_twin_load(Geo g, const float* __rest
 }
 
 // Half-iteration: component SRC of every cell's pair -> component 1 - SRC.
+// A thread marches up kt planes of its (i, j) column keeping the values of
+// planes k-1, k, k+1 in registers; east and west come from the adjacent
+// lanes (a wavefront holds 64 consecutive cells of a row), the row ends and
+// the last cell of the grid row from memory.  Lanes past the row end take
+// part in the shuffles only.
+// kt: at most 8, fewer when the grid would otherwise have under 1024
+// blocks (4 per compute unit; measured: at 150x150x90, 8 planes in 1368
+// blocks beat 2 planes in 5130).
+constexpr int kTwPlanesMax = 8;
+constexpr long long kTwMinBlocks = 1024;
+
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_twin_sweep(Geo g, float2* q, const float* __restrict__ rhs,
-                                                       float omega) {
-    int i0, j0, k0;
-    if (!tw_cell(g, i0, j0, k0)) return;
+                                                       float omega, int kt) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int i0 = (int)blockIdx.x * 64 + lane;
+    const int j0 = (int)blockIdx.y * kTwRows + (int)(threadIdx.x >> 6);
+    if (j0 >= g.ny) return;                      // a whole wavefront
+    const int kb = (int)blockIdx.z * kt;
+    const int ke = min(g.nz, kb + kt);
+    const bool live = i0 < g.nx;
     const float* src = reinterpret_cast<const float*>(q) + SRC;
     float* dst = reinterpret_cast<float*>(q) + (1 - SRC);
-    const long long e = tw_index(g, i0, j0, k0);
     const long long X = g.nx + 2, P = X * (g.ny + 2);
-    const float pc = src[2 * e];
-    const float west = src[2 * (e - 1)], east = src[2 * (e + 1)];
-    const float ps = src[2 * (e - X)], pn = src[2 * (e + X)];
-    const float pb = src[2 * (e - P)], pt = src[2 * (e + P)];
-    const float r = rhs[((long long)k0 * g.ny + j0) * g.nx + i0];
-    float reltmp;
-    dst[2 * e] = sor_point(west, east, ps, pn, pb, pt, g.cx, g.cy, g.cz, diag_of(g, i0, j0, k0), r,
-                           pc, omega, reltmp);
+    long long e = tw_index(g, i0, j0, kb);
+    const long long rrow = (long long)j0 * g.nx + i0, rplane = (long long)g.ny * g.nx;
+    const float dxy = diag_x(g, i0) + diag_y(g, j0);
+    float pb = live ? src[2 * (e - P)] : 0.f;
+    float pc = live ? src[2 * e] : 0.f;
+    for (int k0 = kb; k0 < ke; ++k0) {
+        const float pt = live ? src[2 * (e + P)] : 0.f;
+        float pe = __shfl_down(pc, 1, 64);
+        float pw = __shfl_up(pc, 1, 64);
+        if (live) {
+            if (lane == 63 || i0 == g.nx - 1) pe = src[2 * (e + 1)];
+            if (lane == 0) pw = src[2 * (e - 1)];
+            const float ps = src[2 * (e - X)], pn = src[2 * (e + X)];
+            const float r = rhs[(long long)k0 * rplane + rrow];
+            float reltmp;
+            dst[2 * e] = sor_point(pw, pe, ps, pn, pb, pt, g.cx, g.cy, g.cz, dxy + diag_z(g, k0), r, pc,
+                                   omega, reltmp);
+        }
+        pb = pc;
+        pc = pt;
+        e += P;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_twin_store(Geo g, const float2* __restrict__ q,
@@ -145,6 +175,9 @@ extern "C" int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, flo
     float2* q = (float2*)h->tw_q;
     double* part = h->tw_part;
     const dim3 block(kBlock);
+    const long long per_plane = (long long)grid.x * grid.y;
+    int kt = (int)std::min<long long>(kTwPlanesMax, std::max<long long>(1, (long long)g.nz * per_plane / kTwMinBlocks));
+    const dim3 sweep_grid(grid.x, grid.y, (unsigned)((g.nz + kt - 1) / kt));
     hipEvent_t ev[2] = {nullptr, nullptr};
     for (auto& e : ev) TW_CK(hipEventCreate(&e));
     auto fin = [&](int rc) {
@@ -157,8 +190,8 @@ extern "C" int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, flo
     if (hipEventRecord(ev[0], s) != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "event"));
     const float om = (float)omega;
     for (int m = 0; m < iters; ++m) {
-        hipLaunchKernelGGL(k_twin_sweep<0>, grid, block, 0, s, g, q, d_rhs, om);
-        hipLaunchKernelGGL(k_twin_sweep<1>, grid, block, 0, s, g, q, d_rhs, om);
+        hipLaunchKernelGGL(k_twin_sweep<0>, sweep_grid, block, 0, s, g, q, d_rhs, om, kt);
+        hipLaunchKernelGGL(k_twin_sweep<1>, sweep_grid, block, 0, s, g, q, d_rhs, om, kt);
     }
     if (hipGetLastError() != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "k_twin_sweep"));
     if (hipEventRecord(ev[1], s) != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "event"));

@@ -175,8 +175,9 @@ int les_set_inflow(les_handle* h, const float* profile, float noise_amp, uint64_
  * one; les_set_inflow switches the interpolation off.  The pair is part of
  * the checkpoint (les_get_state).  Requires les_set_inflow (or
  * les_set_fields) first, else LES_ESTATE; LES_EINVAL for NULL profiles,
- * non-finite values or t1 <= t0.  Ensembles reject members with a pair
- * (LES_ESTATE).  Synchronous.
+ * non-finite values or t1 <= t0.  An ensemble step interpolates each
+ * member's pair alike (bit for bit as the member stepped alone).
+ * Synchronous.
  */
 int les_set_inflow_pair(les_handle* h, double t0, const float* prof0, double t1,
                         const float* prof1);

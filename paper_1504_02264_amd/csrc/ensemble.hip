@@ -37,6 +37,9 @@ struct EnsInst {
     float* su; float* sv; float* sw;
     uint8_t* flags;
     float* prof;
+    float* prof1;       // second inflow sample (prof itself without a pair)
+    double t0, t1, dt;  // times of the samples, time step
+    int interp;         // inflow interpolated between prof and prof1
     PBufs P;
     double* part;       // rhs / check / rebase partials
     double* rel0;       // sweep partials, colour 0 and 1
@@ -123,7 +126,8 @@ __global__ __launch_bounds__(kBlock) void k_ens_inflow(const EnsInst* I, const E
     const int q = owner(O->inflow, n, L);
     const EnsInst& d = I[q];
     if (!d.inflow) return;
-    inflow_body(d.g, d.u[1 - D[q].cur], d.prof, d.prof, 0.f, d.flags, d.amp, d.seed, D[q].step + 1,
+    const float wt = d.interp ? inflow_weight_at(D[q].step, d.dt, d.t0, d.t1) : 0.f;
+    inflow_body(d.g, d.u[1 - D[q].cur], d.prof, d.prof1, wt, d.flags, d.amp, d.seed, D[q].step + 1,
                 L - O->inflow[q]);
 }
 
@@ -581,6 +585,11 @@ void build_descriptors(les_ensemble* e) {
         d.su = h->f.su; d.sv = h->f.sv; d.sw = h->f.sw;
         d.flags = h->f.flags;
         d.prof = h->f.prof;
+        d.prof1 = h->interp ? h->f.prof1 : h->f.prof;
+        d.interp = h->interp ? 1 : 0;
+        d.t0 = h->t0;
+        d.t1 = h->t1;
+        d.dt = h->dt;
         d.P = h->f.P;
         d.part = h->f.part[0];
         d.rel0 = h->f.part[1];
@@ -926,8 +935,6 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
     const int n = e->n;
     for (int q = 0; q < n; ++q) {
         if (!e->members[q]->have_inflow) return ens_err(e, LES_ESTATE, "member without inflow");
-        if (e->members[q]->interp)
-            return ens_err(e, LES_ESTATE, "member with an interpolated inflow pair");
         if (e->members[q]->warm_net || e->members[q]->cap_x)
             return ens_err(e, LES_ESTATE, "member with a warm start or capture set (single-handle only)");
     }

@@ -674,15 +674,9 @@ int les_set_inflow_pair(les_handle* h, double t0, const float* prof0, double t1,
     return LES_OK;
 }
 
-// Weight of the second profile sample for the step that starts at time
-// step * dt: the linear interpolation between the samples, held at the
-// end values outside [t0, t1]; 0 when no pair is set.
+// Weight of the second profile sample for the next step; 0 when no pair is set.
 static float inflow_weight(const les_handle* h) {
-    if (!h->interp) return 0.f;
-    const double t = (double)h->step * h->dt;
-    double w = (t - h->t0) / (h->t1 - h->t0);
-    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
-    return (float)w;
+    return h->interp ? inflow_weight_at(h->step, h->dt, h->t0, h->t1) : 0.f;
 }
 
 int les_step(les_handle* h, int32_t n, les_step_stats* st) {

@@ -62,6 +62,18 @@ struct Geo {
     }
 };
 
+// Weight of the second inflow sample for the step that starts at time
+// step * dt: the linear interpolation between samples at t0 and t1, held
+// at the end values outside [t0, t1].  float64 without contraction, so the
+// host (single handle) and the device (ensemble) give the same float.
+__host__ __device__ inline float inflow_weight_at(long long step, double dt, double t0, double t1) {
+#pragma clang fp contract(off)
+    const double t = (double)step * dt;
+    double w = (t - t0) / (t1 - t0);
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+    return (float)w;
+}
+
 // Control block of one pressure solve (device memory).
 struct Ctl {
     int done;           // 0 running, 1 converged, 2 hit max_iter, 3 non-finite

@@ -98,16 +98,14 @@ def test_checkpoint_keeps_the_pair():
             x.close()
 
 
-def test_pair_errors_and_ensemble_refusal():
+def test_pair_errors():
     mask, u0, u1 = case()
     g = les.LES(NX, NY, NZ, 4.0, 4.0, 2.0, DT, mask)
-    h = les.LES(NX, NY, NZ, 4.0, 4.0, 2.0, DT, mask)
     try:
         with pytest.raises(les.LesError) as e:
             g.set_inflow_pair(0.0, u0, 1.0, u1)
         assert e.value.code == les.LES_ESTATE
         g.set_inflow(u0, 0.01, 3)
-        h.set_inflow(u0, 0.01, 4)
         for t0, t1 in ((1.0, 1.0), (2.0, 1.0), (0.0, float("inf"))):
             with pytest.raises(les.LesError) as e:
                 g.set_inflow_pair(t0, u0, t1, u1)
@@ -116,19 +114,40 @@ def test_pair_errors_and_ensemble_refusal():
         bad[2] = np.nan
         with pytest.raises(les.LesError):
             g.set_inflow_pair(0.0, u0, 1.0, bad)
-        g.set_inflow_pair(0.0, u0, 1.0, u1)
-        ens = les.Ensemble([g, h])
-        try:
-            with pytest.raises(les.LesError) as e:
-                ens.step(1)
-            assert e.value.code == les.LES_ESTATE
-            g.set_inflow(u0, 0.01, 3)             # back to a plain profile: accepted
-            ens.step(1)
-        finally:
-            ens.close()
     finally:
         g.close()
-        h.close()
+
+
+@pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
+def test_ensemble_interpolates_like_single_handles(mode):
+    """Members with different pairs (and one plain member) stepped as an
+    ensemble equal the same handles stepped alone, bit for bit: the
+    ensemble forms each member's weight on the device from its step count
+    with the same float64 arithmetic as the host."""
+    print(f"[ensemble pairs] mode {mode}", flush=True)
+    settings = [(3, (1 * DT, 5 * DT)), (4, (0.0, 3 * DT)), (5, None)]
+    ens_m, single = [], []
+    for seed, pair in settings:
+        mask, u0, u1 = case(seed)
+        for lst in (ens_m, single):
+            x = les.LES(NX, NY, NZ, 4.0, 4.0, 2.0, DT, mask)
+            x.set_inflow(u0, 0.01, seed)
+            if pair is not None:
+                x.set_inflow_pair(pair[0], u0, pair[1], u1 * (1 + 0.1 * seed))
+            lst.append(x)
+    ens = les.Ensemble(ens_m)
+    try:
+        ens.set_mode(mode)
+        _, _, iters = ens.step(6)
+        for q, b in enumerate(single):
+            _, _, it_b = b.step(6)
+            assert list(iters[:, q]) == list(it_b), q
+            for x, y in zip(ens_m[q].get_fields(), b.get_fields()):
+                assert np.array_equal(x, y), q
+    finally:
+        ens.close()
+        for x in ens_m + single:
+            x.close()
 
 
 class Replay:

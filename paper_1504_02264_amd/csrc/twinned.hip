@@ -138,12 +138,6 @@ int tw_err(les_handle* h, int code, const char* what, hipError_t e = hipSuccess)
     return code;
 }
 
-#define TW_CK(expr)                                                       \
-    do {                                                                  \
-        hipError_t e_ = (expr);                                           \
-        if (e_ != hipSuccess) return tw_err(h, LES_EDEVICE, #expr, e_);   \
-    } while (0)
-
 }  // namespace
 
 namespace les {
@@ -167,10 +161,22 @@ extern "C" int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, flo
     const size_t nblocks = (size_t)grid.x * grid.y * grid.z;
     hipStream_t s = h->stream;
     if (!h->tw_q) {
+        // installed in the handle only once both buffers exist and the
+        // ghost ring is zero
         const size_t npair = (size_t)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
-        TW_CK(hipMalloc(&h->tw_q, npair * sizeof(float2)));
-        TW_CK(hipMalloc(&h->tw_part, 2 * nblocks * sizeof(double)));
-        TW_CK(hipMemsetAsync(h->tw_q, 0, npair * sizeof(float2), s));   // the zero ghost ring
+        void* qa = nullptr;
+        void* pa = nullptr;
+        hipError_t e = hipMalloc(&qa, npair * sizeof(float2));
+        if (e == hipSuccess) e = hipMalloc(&pa, 2 * nblocks * sizeof(double));
+        if (e == hipSuccess) e = hipMemsetAsync(qa, 0, npair * sizeof(float2), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            if (qa) (void)hipFree(qa);
+            if (pa) (void)hipFree(pa);
+            return tw_err(h, e == hipErrorOutOfMemory ? LES_ENOMEM : LES_EDEVICE, "twinned workspace", e);
+        }
+        h->tw_q = qa;
+        h->tw_part = (double*)pa;
     }
     float2* q = (float2*)h->tw_q;
     double* part = h->tw_part;
@@ -179,12 +185,13 @@ extern "C" int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, flo
     int kt = (int)std::min<long long>(kTwPlanesMax, std::max<long long>(1, (long long)g.nz * per_plane / kTwMinBlocks));
     const dim3 sweep_grid(grid.x, grid.y, (unsigned)((g.nz + kt - 1) / kt));
     hipEvent_t ev[2] = {nullptr, nullptr};
-    for (auto& e : ev) TW_CK(hipEventCreate(&e));
     auto fin = [&](int rc) {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         return rc;
     };
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "hipEventCreate"));
     hipLaunchKernelGGL(k_twin_load, grid, block, 0, s, g, d_p, q);
     if (hipGetLastError() != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "k_twin_load"));
     if (hipEventRecord(ev[0], s) != hipSuccess) return fin(tw_err(h, LES_EDEVICE, "event"));

@@ -8,11 +8,19 @@ power-law inflow), inputs resident in HBM before the timed region.
 
 Prints ONE JSON line:
   value      LES cell-updates/s = cells * steps / wall time of les_step(steps)
-  roofline   the dominant kernel (SOR half-sweep): algorithmic bytes per launch
-             (8 B per cell: 4 B of the other colour, 4 B own p, 4 B own rhs
-             read for half the cells... see the design doc) over its mean HIP-event
-             duration on the library's stream
+  roofline   the dominant kernel, the SOR sweep: algorithmic bytes per launch
+             over its mean HIP-event duration on the library's stream.  A
+             fused red-black iteration (k_sor_rb) moves 12 B per cell: the
+             correction p read and the new one written (4 + 4 B) and r0 read
+             (4 B); a half-sweep (k_sor) 8 B per cell of the grid: the other
+             colour read (4 B per cell of that colour), own p read and
+             written and own r0 read (12 B per cell of this colour).
+             `traffic` is the measured HBM bytes (rocprofv3 FETCH_SIZE +
+             WRITE_SIZE, copy-calibrated) from the summaries in profiles/.
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+
+Other modes print their own JSON line: --ensemble N, --warm-start,
+--twinned (twinned double buffering against red-black SOR).
 """
 from __future__ import annotations
 

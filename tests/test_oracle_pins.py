@@ -359,6 +359,238 @@ def test_smagorinsky_solid_rotation():
     assert np.abs(nut[1:-1, 1:-1, 1:-1]).max() <= 1e-14
 
 
+def _linear_faces(o, G, origin=(0.3, -0.2, 0.5)):
+    """Faces of the linear field u_i = G_ij x_j on the MAC grid of ``o``.
+
+    u sits at (x_face, y_centre, z_centre), v at (x_centre, y_face,
+    z_centre), w at (x_centre, y_centre, z_face); ``origin`` shifts the
+    coordinates so that no component is zero on a whole plane.
+    """
+    nx, ny, nz, dx, dy, dz = o.nx, o.ny, o.nz, o.dx, o.dy, o.dz
+    xc = origin[0] + (np.arange(nx) + 0.5) * dx
+    yc = origin[1] + (np.arange(ny) + 0.5) * dy
+    zc = origin[2] + (np.arange(nz) + 0.5) * dz
+    xf = origin[0] + np.arange(nx + 1) * dx
+    yf = origin[1] + np.arange(ny + 1) * dy
+    zf = origin[2] + np.arange(nz + 1) * dz
+
+    def lin(row, X, Y, Z):
+        return (row[0] * X[None, None, :] + row[1] * Y[None, :, None] + row[2] * Z[:, None, None])
+
+    return lin(G[0], xf, yc, zc), lin(G[1], xc, yf, zc), lin(G[2], xc, yc, zf)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_smagorinsky_general_linear_field(seed):
+    """P8: a general linear field u_i = G_ij x_j has S = (G + G^T)/2 exactly.
+
+    Every one of the six strain components is then constant, so at every
+    cell whose stencil stays inside the domain nu_t = (Cs Delta)^2
+    sqrt(2 S:S) with the closed-form S.  Distinct dx, dy, dz and a full,
+    non-symmetric G reach S22, S33 and S23 as well as S11, S12 and S13,
+    each with its own spacing.
+    """
+    nx, ny, nz, dx, dy, dz, cs = 7, 6, 5, 1.7, 0.9, 0.4, 0.13
+    rng = np.random.default_rng(100 + seed)
+    G = rng.uniform(-1.0, 1.0, (3, 3))
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=cs, bc=ALL_WALLS)
+    u, v, w = _linear_faces(o, G)
+    nut = o.nut_of(u, v, w)
+    S = 0.5 * (G + G.T)
+    want = (cs * (dx * dy * dz) ** (1 / 3)) ** 2 * math.sqrt(2.0 * np.sum(S * S))
+    inner = nut[1:-1, 1:-1, 1:-1]
+    assert inner.size > 0
+    assert np.allclose(inner, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("comp", ["u", "v", "w"])
+def test_sgs_force_with_varying_viscosity(comp):
+    """P8: div(2 nu_t S) where nu_t varies across the shear layer.
+
+    A single quadratic velocity component, e.g. u = a y^2 (v = w = 0),
+    has one strain pair S12 = S21 = a y, so |S| = 2 a y and
+    nu_t = 2 C a y with C = (Cs Delta)^2.  Its SGS force is
+    d/dy (2 nu_t S12) = d/dy (4 C a^2 y^2) = 8 C a^2 y, and advection and
+    (with nu = 0) diffusion vanish.  On the MAC grid the edge strain and
+    the 4-cell edge mean of nu_t are linear in y, so the flux difference
+    is exact.  The analogues: v = a z^2 (force 8 C a^2 z on v-faces) and
+    w = a x^2 (force 8 C a^2 x on w-faces).  Swapping the viscosity's
+    edge offsets or dropping the factor 2 fails this.
+    """
+    nx, ny, nz, dx, dy, dz, cs, a = 10, 11, 12, 1.3, 0.7, 0.45, 0.21, 0.8
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=cs, nu=0.0, bc=ALL_WALLS)
+    C = (cs * (dx * dy * dz) ** (1 / 3)) ** 2
+    su, sv, sw, _ = o.shapes
+    u, v, w = np.zeros(su), np.zeros(sv), np.zeros(sw)
+    off = 2.0   # coordinates start at 2 m: the quadratic is monotone inside
+    if comp == "u":
+        y = off + (np.arange(ny) + 0.5) * dy
+        u[:] = (a * y**2)[None, :, None]
+    elif comp == "v":
+        z = off + (np.arange(nz) + 0.5) * dz
+        v[:] = (a * z**2)[:, None, None]
+    else:
+        x = off + (np.arange(nx) + 0.5) * dx
+        w[:] = (a * x**2)[None, None, :]
+    fu, fv, fw = o.force_of(u, v, w)
+    if comp == "u":
+        got = fu[:, 2:ny - 2, 1:nx]
+        want = np.broadcast_to((8 * C * a * a * y)[None, 2:ny - 2, None], got.shape)
+        others = (fv, fw)
+    elif comp == "v":
+        got = fv[2:nz - 2, 1:ny, :]
+        want = np.broadcast_to((8 * C * a * a * z)[2:nz - 2, None, None], got.shape)
+        others = (fu, fw)
+    else:
+        got = fw[1:nz, :, 2:nx - 2]
+        want = np.broadcast_to((8 * C * a * a * x)[None, None, 2:nx - 2], got.shape)
+        others = (fu, fv)
+    assert got.size > 0
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+    # the other components see no force from this field away from the walls
+    for f in others:
+        assert np.abs(f[2:-2, 2:-2, 2:-2]).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("comp", ["v", "w"])
+def test_advection_of_v_and_w_linear(comp):
+    """Advection of v and w: v = b + c y gives -v dv/dy = -c v at every
+    interior v-face (u = w = 0); w = b + c z gives -c w on w-faces.  The
+    central cov pieces average the centre products back onto the face,
+    which is exact for a linear component.
+    """
+    nx, ny, nz, dx, dy, dz = 6, 7, 8, 0.6, 0.35, 0.8
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=0.0, nu=0.0, bc=ALL_WALLS)
+    b, c = 0.9, -0.45
+    su, sv, sw, _ = o.shapes
+    u, v, w = np.zeros(su), np.zeros(sv), np.zeros(sw)
+    if comp == "v":
+        yf = np.arange(ny + 1) * dy
+        v[:] = (b + c * yf)[None, :, None]
+        _, fv, fw = o.force_of(u, v, w)
+        want = -c * (b + c * yf)
+        assert np.allclose(fv[:, 1:ny, :], np.broadcast_to(want[None, 1:ny, None], (nz, ny - 1, nx)),
+                           rtol=1e-13)
+        assert np.abs(fw[1:nz]).max() <= 1e-14
+    else:
+        zf = np.arange(nz + 1) * dz
+        w[:] = (b + c * zf)[:, None, None]
+        _, fv, fw = o.force_of(u, v, w)
+        want = -c * (b + c * zf)
+        assert np.allclose(fw[1:nz], np.broadcast_to(want[1:nz, None, None], (nz - 1, ny, nx)),
+                           rtol=1e-13)
+        assert np.abs(fv[:, 1:ny]).max() <= 1e-14
+
+
+def test_advection_of_w_by_uniform_u():
+    """w = q(x) quadratic carried by a constant u = U: the x-advection of w
+    is -U q'(x) and the Laplacian nu q''(x), both exact for a quadratic on
+    the MAC grid (the cov piece pairs the mean of two u-faces with the
+    one-sided difference of w between neighbouring columns)."""
+    nx, ny, nz, dx, dy, dz, nu = 9, 6, 7, 0.55, 0.8, 0.3, 0.02
+    bc = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, FREESLIP, FREESLIP)
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, bc=bc, cs=0.0, nu=nu)
+    U = 0.7
+    c0, c1, c2 = 0.2, -0.5, 0.35
+    xc = (np.arange(nx) + 0.5) * dx
+    q = c0 + c1 * xc + c2 * xc**2
+    su, sv, sw, _ = o.shapes
+    u = np.full(su, U)
+    w = np.broadcast_to(q[None, None, :], sw).copy()
+    fu, fv, fw = o.force_of(u, np.zeros(sv), w)
+    want = -U * (c1 + 2 * c2 * xc) + nu * 2 * c2
+    iin = slice(1, nx - 1)
+    got = fw[1:nz, :, iin]
+    assert np.allclose(got, np.broadcast_to(want[None, None, iin], got.shape), rtol=1e-12)
+
+
+_AXES = {"u": 0, "v": 1, "w": 2}
+
+
+@pytest.mark.parametrize("comp,adv", [("u", "v"), ("u", "w"), ("v", "u"), ("v", "w"),
+                                      ("w", "u"), ("w", "v")])
+def test_cross_advection_by_a_linear_velocity(comp, adv):
+    """Advection of one component across the flow of another.
+
+    The advected component is c = g x_d (d the direction of the advecting
+    component, e.g. u = g y carried by v), the advecting component is a
+    general linear function a + b . x on its own faces, the third is zero.
+    Then c has no self-advection and -(vel_d dc/dx_d) = -g vel_d, with
+    vel_d evaluated at the c-face: the cov pieces interpolate the advecting
+    velocity linearly (face pair, then edge pair), which is exact for a
+    linear field.  A wrong face index in that interpolation moves the
+    evaluation point by half a cell and fails here.
+    """
+    nx, ny, nz, dx, dy, dz = 8, 9, 7, 0.7, 0.45, 0.9
+    o = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=0.0, nu=0.0, bc=ALL_WALLS)
+    c, d = _AXES[comp], _AXES[adv]
+    g, a0 = 0.55, 0.4
+    b = np.array([0.3, -0.25, 0.2])
+    G = np.zeros((3, 3))
+    G[c, d] = g
+    G[d, :] = b
+    faces = list(_linear_faces(o, G, origin=(0.0, 0.0, 0.0)))
+    faces[d] = faces[d] + a0
+    fu, fv, fw = o.force_of(*faces)
+    F = (fu, fv, fw)[c]
+    # coordinates of the c-faces
+    nxyz = (nx, ny, nz)
+    h = (dx, dy, dz)
+    pos = []
+    for e in range(3):
+        n = nxyz[e] + (1 if e == c else 0)
+        off = 0.0 if e == c else 0.5
+        pos.append((np.arange(n) + off) * h[e])
+    vel_d = a0 + b[0] * pos[0][None, None, :] + b[1] * pos[1][None, :, None] + b[2] * pos[2][:, None, None]
+    want = -g * np.broadcast_to(vel_d, F.shape)
+    inner = (slice(2, F.shape[0] - 2), slice(2, F.shape[1] - 2), slice(2, F.shape[2] - 2))
+    assert F[inner].size > 0
+    assert np.allclose(F[inner], want[inner], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("comp", ["u", "v", "w"])
+def test_sgs_normal_stress_with_varying_viscosity(comp):
+    """P8: the normal part of div(2 nu_t S) where nu_t varies along it.
+
+    A single component quadratic along its own axis, e.g. u = a x^2, has
+    S11 = 2 a x at cell centres (exact for the face difference), |S| =
+    sqrt(2) 2 a x and nu_t = sqrt(2) 2 C a x, so d/dx (2 nu_t S11) =
+    16 sqrt(2) C a^2 x at the u-faces, exact for the difference of the
+    two centre fluxes.  Advection is the same with and without the model,
+    so the SGS part is the tendency with Cs minus the tendency with
+    Cs = 0.  A wrong centre index of nu_t in the normal flux fails here.
+    """
+    nx, ny, nz, dx, dy, dz, cs, a = 9, 8, 10, 0.8, 0.6, 0.35, 0.19, 0.5
+    C = (cs * (dx * dy * dz) ** (1 / 3)) ** 2
+    c = _AXES[comp]
+    o1 = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=cs, nu=0.0, bc=ALL_WALLS)
+    o0 = make(nx, ny, nz, dx=dx, dy=dy, dz=dz, cs=0.0, nu=0.0, bc=ALL_WALLS)
+    shapes = o1.shapes[:3]
+    faces = [np.zeros(s) for s in shapes]
+    n = (nx, ny, nz)[c]
+    h = (dx, dy, dz)[c]
+    xf = 1.0 + np.arange(n + 1) * h       # face coordinates along the axis, offset by 1 m
+    prof = a * xf**2
+    if c == 0:
+        faces[0][:] = prof[None, None, :]
+    elif c == 1:
+        faces[1][:] = prof[None, :, None]
+    else:
+        faces[2][:] = prof[:, None, None]
+    F1 = o1.force_of(*faces)[c]
+    F0 = o0.force_of(*faces)[c]
+    sgs = F1 - F0
+    want1d = 16.0 * math.sqrt(2.0) * C * a * a * xf
+    sl = [slice(None)] * 3
+    ax = 2 - c                           # numpy axis of this coordinate
+    sl[ax] = slice(2, n - 1)
+    got = sgs[tuple(sl)]
+    shape = [1, 1, 1]
+    shape[ax] = n - 3
+    want = np.broadcast_to(want1d[2:n - 1].reshape(shape), got.shape)
+    assert np.allclose(got, want, rtol=1e-10, atol=0)
+
+
 # ------------------------------------------------------ advection closed forms
 def test_advection_closed_forms():
     """Second-order central advection is exact on these polynomial fields.

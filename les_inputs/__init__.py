@@ -28,6 +28,9 @@ __all__ = [
     "power_law_profile",
     "make_workload_inputs",
     "ensemble_members",
+    "stretched_widths",
+    "smooth_widths",
+    "cell_centres",
 ]
 
 
@@ -117,21 +120,49 @@ def building_mask(heights: np.ndarray, nz: int) -> np.ndarray:
     return (k < heights[None, :, :]).astype(np.uint8)
 
 
-def log_law_profile(nz: int, dz: float, u_star_over_kappa: float = 0.3 / 0.4,
+def stretched_widths(n: int, h0: float, ratio: float, n_uniform: int = 0) -> np.ndarray:
+    """Cell widths of a geometrically stretched axis (float64): n_uniform
+    cells of width h0, then every cell ``ratio`` times wider than the one
+    before (ratio 1 gives a uniform axis)."""
+    e = np.maximum(np.arange(n) - n_uniform + 1, 0)
+    return h0 * np.power(float(ratio), e, dtype=np.float64)
+
+
+def smooth_widths(n: int, length: float, a: float) -> np.ndarray:
+    """Cell widths of a smoothly stretched axis of the given length: the
+    faces sit at length * f(s_m), s_m = m / n, f(s) = s + a sin(2 pi s) / (2 pi)
+    (|a| < 1 keeps f increasing).  Refining n keeps the same mapping, which
+    is what a grid-convergence study needs."""
+    s = np.arange(n + 1, dtype=np.float64) / n
+    faces = length * (s + a * np.sin(2 * np.pi * s) / (2 * np.pi))
+    return np.diff(faces)
+
+
+def cell_centres(n: int, h) -> np.ndarray:
+    """Centre coordinates of n cells of width h (a scalar or n widths),
+    starting from 0 (float64)."""
+    w = np.broadcast_to(np.asarray(h, dtype=np.float64), (n,))
+    faces = np.concatenate(([0.0], np.cumsum(w)))
+    return 0.5 * (faces[:-1] + faces[1:])
+
+
+def log_law_profile(nz: int, dz, u_star_over_kappa: float = 0.3 / 0.4,
                     z0: float = 0.1) -> np.ndarray:
-    """Log-law inflow speed at cell-centre heights z_k = (k + 1/2) dz, k = 0..nz-1.
+    """Log-law inflow speed at the cell-centre heights (dz a spacing or the
+    nz cell heights of a stretched axis; uniform: z_k = (k + 1/2) dz).
 
     Evaluated in float64 and rounded once to float32, so every consumer
     sees the same bytes.
     """
-    z = (np.arange(nz, dtype=np.float64) + 0.5) * dz
+    z = cell_centres(nz, dz)
     return (u_star_over_kappa * np.log(z / z0)).astype(np.float32)
 
 
-def power_law_profile(nz: int, dz: float, u_top: float, alpha: float) -> np.ndarray:
-    """Power-law inflow U_top (z/H)^alpha at cell centres, H = nz dz (float32)."""
-    z = (np.arange(nz, dtype=np.float64) + 0.5) * dz
-    H = nz * dz
+def power_law_profile(nz: int, dz, u_top: float, alpha: float) -> np.ndarray:
+    """Power-law inflow U_top (z/H)^alpha at cell centres, H the domain
+    height (dz a spacing or the nz cell heights; float32)."""
+    z = cell_centres(nz, dz)
+    H = float(np.sum(np.broadcast_to(np.asarray(dz, dtype=np.float64), (nz,))))
     return (u_top * (z / H) ** alpha).astype(np.float32)
 
 

@@ -79,6 +79,9 @@ def lib():
         L.oracle_create.restype = P
         L.oracle_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                     C.c_double, P, C.POINTER(OParams)]
+        L.oracle_create_stretched.restype = P
+        L.oracle_create_stretched.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_double, P,
+                                              C.POINTER(OParams)]
         L.oracle_destroy.argtypes = [P]
         L.oracle_set_inflow.argtypes = [P, P, C.c_double, C.c_uint64]
         L.oracle_set_inflow_pair.argtypes = [P, C.c_double, P, C.c_double, P]
@@ -142,8 +145,18 @@ class Oracle:
         self._mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         if self._mask is not None:
             assert self._mask.shape == (nz, ny, nx)
-        self.h = lib().oracle_create(nx, ny, nz, dx, dy, dz, dt, _ptr(self._mask),
-                                     C.byref(self.params))
+        # dx, dy, dz: a uniform spacing, or the nx / ny / nz cell widths of a
+        # stretched axis (the paper's 1-D spacing arrays)
+        self.hx, self.hy, self.hz = (np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (n,)))
+                                     for h, n in ((dx, nx), (dy, ny), (dz, nz)))
+        self.stretched = any(np.ndim(h) > 0 for h in (dx, dy, dz))
+        if self.stretched:
+            self.h = lib().oracle_create_stretched(nx, ny, nz, _ptr(self.hx), _ptr(self.hy),
+                                                   _ptr(self.hz), dt, _ptr(self._mask),
+                                                   C.byref(self.params))
+        else:
+            self.h = lib().oracle_create(nx, ny, nz, dx, dy, dz, dt, _ptr(self._mask),
+                                         C.byref(self.params))
         if not self.h:
             raise ValueError("oracle_create rejected its arguments")
         self.last_iters = None

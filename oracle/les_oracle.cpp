@@ -16,7 +16,10 @@
 //      diffusive (diu) pieces (section 2.5.3, "pre-computing neighbouring
 //      points");
 //    * the red-black SOR update and its colour order (section 2.6);
-//    * boundary work split into the three face families (section 2.4).
+//    * boundary work split into the three face families (section 2.4);
+//    * per-axis 1-D cell widths (the dx1 / dy1 / dzn arrays of section
+//      2.5.3), so every axis may be stretched; a uniform grid is the case
+//      of equal widths.
 //  Where the paper is silent (staggering, advection formula, SGS model
 //  details, feedback law, BC formulas, residual definition) the oracle
 //  follows the readings listed in the design notes of this repository;
@@ -102,7 +105,7 @@ uint64_t splitmix64(uint64_t x) {
 
 struct Oracle {
     int nx, ny, nz;
-    double dx, dy, dz, dt;
+    double dt;
     OParams prm;
     std::vector<uint8_t> solid;  // cell mask, [k][j][i] 0-based interior
     Box u, v, w, p;              // state u^n (ghosts valid), p^n
@@ -112,11 +115,36 @@ struct Oracle {
     Box gu, gv, gw;              // F^{n-1} (AB2 history)
     Box su, sv, sw;              // feedback-forcing time integral
     Box rhs;                     // Poisson right-hand side
-    // SOR coefficients in the paper's notation (section 2.6):
-    // cn2l/cn2s east/west, cn3l/cn3s north/south, cn4l/cn4s top/bottom,
-    // cn1 = 1 / diagonal.
-    std::vector<double> cn2l, cn2s, cn3l, cn3s, cn4l, cn4s;
-    std::vector<double> dgx, dgy, dgz;  // diagonal contributions per axis
+    // Grid metrics of one axis (the paper's 1-D spacing arrays, section
+    // 2.5.3), indexed 0..n+1; a ghost cell has the width of the interior
+    // cell it mirrors.
+    //   h[c]   width of cell c
+    //   g[f]   distance between the centres of cells f and f+1, i.e. the
+    //          width of the control volume of a value on face f (f = 0..n)
+    //   lo[f], hi[f]  weights of centres f and f+1 in the linear
+    //          interpolation onto face f: lo = h[f+1] / (h[f] + h[f+1]),
+    //          hi = h[f] / (h[f] + h[f+1])
+    // A uniform axis has g = h and lo = hi = 1/2 exactly.
+    struct Axis {
+        std::vector<double> h, g, lo, hi;
+        void init(const double* widths, int n) {
+            h.assign(n + 2, 0.0); g.assign(n + 2, 0.0);
+            lo.assign(n + 2, 0.0); hi.assign(n + 2, 0.0);
+            for (int c = 1; c <= n; ++c) h[c] = widths[c - 1];
+            h[0] = h[1];
+            h[n + 1] = h[n];
+            for (int f = 0; f <= n; ++f) {
+                g[f] = 0.5 * (h[f] + h[f + 1]);
+                lo[f] = h[f + 1] / (h[f] + h[f + 1]);
+                hi[f] = h[f] / (h[f] + h[f + 1]);
+            }
+        }
+    };
+    Axis X, Y, Z;
+    // Pressure operator A = D G (section 2.6): weight of the neighbour
+    // across each face of a cell, and the diagonal's share per axis.
+    std::vector<double> w_east, w_west, w_north, w_south, w_top, w_bottom;
+    std::vector<double> d_x, d_y, d_z;
     std::vector<double> prof;        // inflow profile U(k), k = 1..nz
     // Time-interpolated inflow (section 4, coupled time loop): samples U0 =
     // prof at time t0 and U1 = prof1 at time t1, interpolated linearly.
@@ -129,6 +157,14 @@ struct Oracle {
     bool have_old = false;
     int64_t step = 0;
     OStats st{};
+
+    // short names for the metrics
+    double hx(int c) const { return X.h[c]; }
+    double hy(int c) const { return Y.h[c]; }
+    double hz(int c) const { return Z.h[c]; }
+    double gx(int f) const { return X.g[f]; }
+    double gy(int f) const { return Y.g[f]; }
+    double gz(int f) const { return Z.g[f]; }
 
     // Only the x+ face can carry the Dirichlet (outflow) pressure condition;
     // without it the operator has the constants as null space.
@@ -155,34 +191,43 @@ struct Oracle {
     }
 
     // --------------------------------------------------- set-up helpers
+    // Poisson operator A = D G on the MAC grid, from the divergence D (face
+    // differences over the cell width) and the gradient G (centre
+    // differences over the centre distance):
+    //   (A p)_c = [(p_{c+1} - p_c) / g_c - (p_c - p_{c-1}) / g_{c-1}] / h_c
+    // per axis.  Across a boundary face with a prescribed normal velocity
+    // (walls, inflow) the pressure gradient is not used: no neighbour
+    // weight, no diagonal share (Neumann).  Across the outflow face p = 0
+    // on the face, half a cell away from the centre: gradient -2 p / h,
+    // which adds 2 / h^2 to the diagonal.
     void build_coefficients() {
-        // Poisson operator A = D G on the MAC grid.  A neighbour across an
-        // interior face has weight 1/h^2.  Across a boundary face where the
-        // normal velocity is prescribed (walls, inflow) the pressure is
-        // Neumann: weight 0 and no diagonal share.  Across the outflow face
-        // p = 0 on the face (ghost = -p), which adds 2/h^2 to the diagonal.
-        const double cx = 1.0 / (dx * dx), cy = 1.0 / (dy * dy), cz = 1.0 / (dz * dz);
-        cn2l.assign(nx + 2, 0.0); cn2s.assign(nx + 2, 0.0); dgx.assign(nx + 2, 0.0);
-        cn3l.assign(ny + 2, 0.0); cn3s.assign(ny + 2, 0.0); dgy.assign(ny + 2, 0.0);
-        cn4l.assign(nz + 2, 0.0); cn4s.assign(nz + 2, 0.0); dgz.assign(nz + 2, 0.0);
+        w_east.assign(nx + 2, 0.0); w_west.assign(nx + 2, 0.0); d_x.assign(nx + 2, 0.0);
+        w_north.assign(ny + 2, 0.0); w_south.assign(ny + 2, 0.0); d_y.assign(ny + 2, 0.0);
+        w_top.assign(nz + 2, 0.0); w_bottom.assign(nz + 2, 0.0); d_z.assign(nz + 2, 0.0);
         for (int i = 1; i <= nx; ++i) {
-            cn2s[i] = (i > 1) ? cx : 0.0;
-            cn2l[i] = (i < nx) ? cx : 0.0;
-            dgx[i] = cn2s[i] + cn2l[i];
-            if (i == nx && prm.bc[XP] == BC_OUTFLOW) dgx[i] += 2.0 * cx;
+            w_west[i] = (i > 1) ? 1.0 / (hx(i) * gx(i - 1)) : 0.0;
+            w_east[i] = (i < nx) ? 1.0 / (hx(i) * gx(i)) : 0.0;
+            d_x[i] = w_west[i] + w_east[i];
+            if (i == nx && prm.bc[XP] == BC_OUTFLOW) d_x[i] += 2.0 / (hx(i) * hx(i));
         }
         for (int j = 1; j <= ny; ++j) {
-            cn3s[j] = (j > 1) ? cy : 0.0;
-            cn3l[j] = (j < ny) ? cy : 0.0;
-            dgy[j] = cn3s[j] + cn3l[j];
+            w_south[j] = (j > 1) ? 1.0 / (hy(j) * gy(j - 1)) : 0.0;
+            w_north[j] = (j < ny) ? 1.0 / (hy(j) * gy(j)) : 0.0;
+            d_y[j] = w_south[j] + w_north[j];
         }
         for (int k = 1; k <= nz; ++k) {
-            cn4s[k] = (k > 1) ? cz : 0.0;
-            cn4l[k] = (k < nz) ? cz : 0.0;
-            dgz[k] = cn4s[k] + cn4l[k];
+            w_bottom[k] = (k > 1) ? 1.0 / (hz(k) * gz(k - 1)) : 0.0;
+            w_top[k] = (k < nz) ? 1.0 / (hz(k) * gz(k)) : 0.0;
+            d_z[k] = w_bottom[k] + w_top[k];
         }
     }
-    double cn1(int i, int j, int k) const { return 1.0 / (dgx[i] + dgy[j] + dgz[k]); }
+    double diagonal(int i, int j, int k) const { return d_x[i] + d_y[j] + d_z[k]; }
+    // sum over the six neighbours of weight times neighbour value
+    double neighbours(const Box& P, int i, int j, int k) const {
+        return w_east[i] * P(i + 1, j, k) + w_west[i] * P(i - 1, j, k) +
+               w_north[j] * P(i, j + 1, k) + w_south[j] * P(i, j - 1, k) +
+               w_top[k] * P(i, j, k + 1) + w_bottom[k] * P(i, j, k - 1);
+    }
 
     // ---------------------------------------------- boundary conditions
     // Ghost refresh (bondv1), done as three face-family passes -- x, then
@@ -258,31 +303,33 @@ struct Oracle {
     }
 
     // ------------------------------------------------ Smagorinsky (les)
-    // Edge-centred strain rates on the MAC grid.
+    // Edge-centred strain rates on the MAC grid: each velocity difference
+    // across a face is divided by the distance between the two values.
     double e12(const Box& U, const Box& V, int a, int b, int k) const {
-        return 0.5 * ((U(a, b + 1, k) - U(a, b, k)) / dy + (V(a + 1, b, k) - V(a, b, k)) / dx);
+        return 0.5 * ((U(a, b + 1, k) - U(a, b, k)) / gy(b) + (V(a + 1, b, k) - V(a, b, k)) / gx(a));
     }
     double e13(const Box& U, const Box& W, int a, int j, int c) const {
-        return 0.5 * ((U(a, j, c + 1) - U(a, j, c)) / dz + (W(a + 1, j, c) - W(a, j, c)) / dx);
+        return 0.5 * ((U(a, j, c + 1) - U(a, j, c)) / gz(c) + (W(a + 1, j, c) - W(a, j, c)) / gx(a));
     }
     double e23(const Box& V, const Box& W, int i, int b, int c) const {
-        return 0.5 * ((V(i, b, c + 1) - V(i, b, c)) / dz + (W(i, b + 1, c) - W(i, b, c)) / dy);
+        return 0.5 * ((V(i, b, c + 1) - V(i, b, c)) / gz(c) + (W(i, b + 1, c) - W(i, b, c)) / gy(b));
     }
 
-    // nu_t = (Cs Delta)^2 |S|, |S| = sqrt(2 S_ij S_ij), Delta = (dx dy dz)^(1/3).
-    // Diagonal S_ii from the two faces of the cell; off-diagonal S_ij as the
-    // mean of the four surrounding edge values.  The ghost ring copies the
+    // nu_t = (Cs Delta)^2 |S|, |S| = sqrt(2 S_ij S_ij), Delta = (hx hy hz)^(1/3)
+    // of the cell.  Diagonal S_ii from the two faces of the cell; off-diagonal
+    // S_ij as the mean of the four surrounding edge values (the cell centre is
+    // the midpoint of those edges on any grid).  The ghost ring copies the
     // nearest interior cell.
     void compute_nut(const Box& U, const Box& V, const Box& W) {
-        const double delta = std::cbrt(dx * dy * dz);
-        const double c2 = (prm.cs * delta) * (prm.cs * delta);
 #pragma omp parallel for schedule(static)
         for (int k = 1; k <= nz; ++k)
             for (int j = 1; j <= ny; ++j)
                 for (int i = 1; i <= nx; ++i) {
-                    double s11 = (U(i, j, k) - U(i - 1, j, k)) / dx;
-                    double s22 = (V(i, j, k) - V(i, j - 1, k)) / dy;
-                    double s33 = (W(i, j, k) - W(i, j, k - 1)) / dz;
+                    const double delta = std::cbrt(hx(i) * hy(j) * hz(k));
+                    const double c2 = (prm.cs * delta) * (prm.cs * delta);
+                    double s11 = (U(i, j, k) - U(i - 1, j, k)) / hx(i);
+                    double s22 = (V(i, j, k) - V(i, j - 1, k)) / hy(j);
+                    double s33 = (W(i, j, k) - W(i, j, k - 1)) / hz(k);
                     double s12 = 0.25 * (e12(U, V, i - 1, j - 1, k) + e12(U, V, i, j - 1, k) +
                                          e12(U, V, i - 1, j, k) + e12(U, V, i, j, k));
                     double s13 = 0.25 * (e13(U, W, i - 1, j, k - 1) + e13(U, W, i, j, k - 1) +
@@ -302,7 +349,10 @@ struct Oracle {
                 }
     }
 
-    // Edge eddy viscosity: mean of the four cells sharing the edge.
+    // Edge eddy viscosity: mean of the four cells sharing the edge.  (On a
+    // stretched axis this is kept rather than a width-weighted
+    // interpolation: the model's filter width Delta is itself a property of
+    // each cell, so nu_t has no grid-independent value to interpolate.)
     double n12(int a, int b, int k) const {
         return 0.25 * (nut(a, b, k) + nut(a + 1, b, k) + nut(a, b + 1, k) + nut(a + 1, b + 1, k));
     }
@@ -314,84 +364,99 @@ struct Oracle {
     }
 
     // ------------------------------------------------ body force (velfg)
-    // F = -(covx + covy + covz) + nu lap(u) + div(2 nu_t S).
-    // Second-order central advective form: a cov piece is the product of an
-    // averaged advecting velocity and a one-sided difference, evaluated on
-    // the two half-points around the face and averaged back onto it, in
-    // the paper's covx1/covy1/covz1 assembly.  Diffusion is the difference
-    // of the one-sided (diu) fluxes, i.e. the 7-point Laplacian.
+    // F = -(covx + covy + covz) + nu lap(u) + div(2 nu_t S), assembled on
+    // the control volume of each face value (section 2.5.3): for u on face
+    // i that volume spans g_i in x and the cell widths h_j, h_k in y and z.
+    // Second-order central advective form: a cov piece is the product of
+    // the advecting velocity and a one-sided difference of the advected
+    // component.  Along the component's own axis the pieces sit at the two
+    // neighbouring centres and are interpolated linearly onto the face
+    // (weights by the opposite cell widths, the paper's covx1); across it
+    // they sit on the two edges, whose midpoint the face is, and are
+    // averaged (covy1, covz1).  An advecting velocity is interpolated
+    // linearly from its own faces onto the edge.  Diffusion is the
+    // difference of the one-sided fluxes (diu) over the control volume.
     double force_u(const Box& U, const Box& V, const Box& W, int i, int j, int k) const {
         auto c1 = [&](int c) {  // at cell centre c
-            return 0.5 * (U(c - 1, j, k) + U(c, j, k)) * (U(c, j, k) - U(c - 1, j, k)) / dx;
+            return 0.5 * (U(c - 1, j, k) + U(c, j, k)) * (U(c, j, k) - U(c - 1, j, k)) / hx(c);
         };
-        auto c2 = [&](int b) {  // at the x-y edge between rows b-1 and b
-            return 0.5 * (V(i, b - 1, k) + V(i + 1, b - 1, k)) * (U(i, b, k) - U(i, b - 1, k)) / dy;
+        auto c2 = [&](int b) {  // at the x-y edge on y-face b (between rows b and b+1)
+            const double vb = X.lo[i] * V(i, b, k) + X.hi[i] * V(i + 1, b, k);
+            return vb * (U(i, b + 1, k) - U(i, b, k)) / gy(b);
         };
-        auto c3 = [&](int c) {  // at the x-z edge between levels c-1 and c
-            return 0.5 * (W(i, j, c - 1) + W(i + 1, j, c - 1)) * (U(i, j, c) - U(i, j, c - 1)) / dz;
+        auto c3 = [&](int c) {  // at the x-z edge on z-face c
+            const double wc = X.lo[i] * W(i, j, c) + X.hi[i] * W(i + 1, j, c);
+            return wc * (U(i, j, c + 1) - U(i, j, c)) / gz(c);
         };
-        double covx = 0.5 * (c1(i) + c1(i + 1));
-        double covy = 0.5 * (c2(j) + c2(j + 1));
-        double covz = 0.5 * (c3(k) + c3(k + 1));
-        double lap = (U(i + 1, j, k) - 2.0 * U(i, j, k) + U(i - 1, j, k)) / (dx * dx) +
-                     (U(i, j + 1, k) - 2.0 * U(i, j, k) + U(i, j - 1, k)) / (dy * dy) +
-                     (U(i, j, k + 1) - 2.0 * U(i, j, k) + U(i, j, k - 1)) / (dz * dz);
-        double s11p = (U(i + 1, j, k) - U(i, j, k)) / dx, s11m = (U(i, j, k) - U(i - 1, j, k)) / dx;
-        double sgs = (2.0 * nut(i + 1, j, k) * s11p - 2.0 * nut(i, j, k) * s11m) / dx +
+        double covx = X.lo[i] * c1(i) + X.hi[i] * c1(i + 1);
+        double covy = 0.5 * (c2(j - 1) + c2(j));
+        double covz = 0.5 * (c3(k - 1) + c3(k));
+        auto fx = [&](int c) { return (U(c, j, k) - U(c - 1, j, k)) / hx(c); };   // at centre c
+        auto fy = [&](int b) { return (U(i, b + 1, k) - U(i, b, k)) / gy(b); };   // on y-face b
+        auto fz = [&](int c) { return (U(i, j, c + 1) - U(i, j, c)) / gz(c); };   // on z-face c
+        double lap = (fx(i + 1) - fx(i)) / gx(i) + (fy(j) - fy(j - 1)) / hy(j) +
+                     (fz(k) - fz(k - 1)) / hz(k);
+        double sgs = (2.0 * nut(i + 1, j, k) * fx(i + 1) - 2.0 * nut(i, j, k) * fx(i)) / gx(i) +
                      (2.0 * n12(i, j, k) * e12(U, V, i, j, k) -
-                      2.0 * n12(i, j - 1, k) * e12(U, V, i, j - 1, k)) / dy +
+                      2.0 * n12(i, j - 1, k) * e12(U, V, i, j - 1, k)) / hy(j) +
                      (2.0 * n13(i, j, k) * e13(U, W, i, j, k) -
-                      2.0 * n13(i, j, k - 1) * e13(U, W, i, j, k - 1)) / dz;
+                      2.0 * n13(i, j, k - 1) * e13(U, W, i, j, k - 1)) / hz(k);
         return -(covx + covy + covz) + prm.nu * lap + sgs;
     }
 
     double force_v(const Box& U, const Box& V, const Box& W, int i, int j, int k) const {
-        auto c1 = [&](int a) {  // x-y edge between columns a-1 and a
-            return 0.5 * (U(a - 1, j, k) + U(a - 1, j + 1, k)) * (V(a, j, k) - V(a - 1, j, k)) / dx;
+        auto c1 = [&](int a) {  // at the x-y edge on x-face a
+            const double ua = Y.lo[j] * U(a, j, k) + Y.hi[j] * U(a, j + 1, k);
+            return ua * (V(a + 1, j, k) - V(a, j, k)) / gx(a);
         };
-        auto c2 = [&](int b) {  // cell centre b
-            return 0.5 * (V(i, b - 1, k) + V(i, b, k)) * (V(i, b, k) - V(i, b - 1, k)) / dy;
+        auto c2 = [&](int b) {  // at cell centre b
+            return 0.5 * (V(i, b - 1, k) + V(i, b, k)) * (V(i, b, k) - V(i, b - 1, k)) / hy(b);
         };
-        auto c3 = [&](int c) {  // y-z edge between levels c-1 and c
-            return 0.5 * (W(i, j, c - 1) + W(i, j + 1, c - 1)) * (V(i, j, c) - V(i, j, c - 1)) / dz;
+        auto c3 = [&](int c) {  // at the y-z edge on z-face c
+            const double wc = Y.lo[j] * W(i, j, c) + Y.hi[j] * W(i, j + 1, c);
+            return wc * (V(i, j, c + 1) - V(i, j, c)) / gz(c);
         };
-        double covx = 0.5 * (c1(i) + c1(i + 1));
-        double covy = 0.5 * (c2(j) + c2(j + 1));
-        double covz = 0.5 * (c3(k) + c3(k + 1));
-        double lap = (V(i + 1, j, k) - 2.0 * V(i, j, k) + V(i - 1, j, k)) / (dx * dx) +
-                     (V(i, j + 1, k) - 2.0 * V(i, j, k) + V(i, j - 1, k)) / (dy * dy) +
-                     (V(i, j, k + 1) - 2.0 * V(i, j, k) + V(i, j, k - 1)) / (dz * dz);
-        double s22p = (V(i, j + 1, k) - V(i, j, k)) / dy, s22m = (V(i, j, k) - V(i, j - 1, k)) / dy;
+        double covx = 0.5 * (c1(i - 1) + c1(i));
+        double covy = Y.lo[j] * c2(j) + Y.hi[j] * c2(j + 1);
+        double covz = 0.5 * (c3(k - 1) + c3(k));
+        auto fx = [&](int a) { return (V(a + 1, j, k) - V(a, j, k)) / gx(a); };   // on x-face a
+        auto fy = [&](int b) { return (V(i, b, k) - V(i, b - 1, k)) / hy(b); };   // at centre b
+        auto fz = [&](int c) { return (V(i, j, c + 1) - V(i, j, c)) / gz(c); };   // on z-face c
+        double lap = (fx(i) - fx(i - 1)) / hx(i) + (fy(j + 1) - fy(j)) / gy(j) +
+                     (fz(k) - fz(k - 1)) / hz(k);
         double sgs = (2.0 * n12(i, j, k) * e12(U, V, i, j, k) -
-                      2.0 * n12(i - 1, j, k) * e12(U, V, i - 1, j, k)) / dx +
-                     (2.0 * nut(i, j + 1, k) * s22p - 2.0 * nut(i, j, k) * s22m) / dy +
+                      2.0 * n12(i - 1, j, k) * e12(U, V, i - 1, j, k)) / hx(i) +
+                     (2.0 * nut(i, j + 1, k) * fy(j + 1) - 2.0 * nut(i, j, k) * fy(j)) / gy(j) +
                      (2.0 * n23(i, j, k) * e23(V, W, i, j, k) -
-                      2.0 * n23(i, j, k - 1) * e23(V, W, i, j, k - 1)) / dz;
+                      2.0 * n23(i, j, k - 1) * e23(V, W, i, j, k - 1)) / hz(k);
         return -(covx + covy + covz) + prm.nu * lap + sgs;
     }
 
     double force_w(const Box& U, const Box& V, const Box& W, int i, int j, int k) const {
-        auto c1 = [&](int a) {  // x-z edge between columns a-1 and a
-            return 0.5 * (U(a - 1, j, k) + U(a - 1, j, k + 1)) * (W(a, j, k) - W(a - 1, j, k)) / dx;
+        auto c1 = [&](int a) {  // at the x-z edge on x-face a
+            const double ua = Z.lo[k] * U(a, j, k) + Z.hi[k] * U(a, j, k + 1);
+            return ua * (W(a + 1, j, k) - W(a, j, k)) / gx(a);
         };
-        auto c2 = [&](int b) {  // y-z edge between rows b-1 and b
-            return 0.5 * (V(i, b - 1, k) + V(i, b - 1, k + 1)) * (W(i, b, k) - W(i, b - 1, k)) / dy;
+        auto c2 = [&](int b) {  // at the y-z edge on y-face b
+            const double vb = Z.lo[k] * V(i, b, k) + Z.hi[k] * V(i, b, k + 1);
+            return vb * (W(i, b + 1, k) - W(i, b, k)) / gy(b);
         };
-        auto c3 = [&](int c) {  // cell centre c
-            return 0.5 * (W(i, j, c - 1) + W(i, j, c)) * (W(i, j, c) - W(i, j, c - 1)) / dz;
+        auto c3 = [&](int c) {  // at cell centre c
+            return 0.5 * (W(i, j, c - 1) + W(i, j, c)) * (W(i, j, c) - W(i, j, c - 1)) / hz(c);
         };
-        double covx = 0.5 * (c1(i) + c1(i + 1));
-        double covy = 0.5 * (c2(j) + c2(j + 1));
-        double covz = 0.5 * (c3(k) + c3(k + 1));
-        double lap = (W(i + 1, j, k) - 2.0 * W(i, j, k) + W(i - 1, j, k)) / (dx * dx) +
-                     (W(i, j + 1, k) - 2.0 * W(i, j, k) + W(i, j - 1, k)) / (dy * dy) +
-                     (W(i, j, k + 1) - 2.0 * W(i, j, k) + W(i, j, k - 1)) / (dz * dz);
-        double s33p = (W(i, j, k + 1) - W(i, j, k)) / dz, s33m = (W(i, j, k) - W(i, j, k - 1)) / dz;
+        double covx = 0.5 * (c1(i - 1) + c1(i));
+        double covy = 0.5 * (c2(j - 1) + c2(j));
+        double covz = Z.lo[k] * c3(k) + Z.hi[k] * c3(k + 1);
+        auto fx = [&](int a) { return (W(a + 1, j, k) - W(a, j, k)) / gx(a); };   // on x-face a
+        auto fy = [&](int b) { return (W(i, b + 1, k) - W(i, b, k)) / gy(b); };   // on y-face b
+        auto fz = [&](int c) { return (W(i, j, c) - W(i, j, c - 1)) / hz(c); };   // at centre c
+        double lap = (fx(i) - fx(i - 1)) / hx(i) + (fy(j) - fy(j - 1)) / hy(j) +
+                     (fz(k + 1) - fz(k)) / gz(k);
         double sgs = (2.0 * n13(i, j, k) * e13(U, W, i, j, k) -
-                      2.0 * n13(i - 1, j, k) * e13(U, W, i - 1, j, k)) / dx +
+                      2.0 * n13(i - 1, j, k) * e13(U, W, i - 1, j, k)) / hx(i) +
                      (2.0 * n23(i, j, k) * e23(V, W, i, j, k) -
-                      2.0 * n23(i, j - 1, k) * e23(V, W, i, j - 1, k)) / dy +
-                     (2.0 * nut(i, j, k + 1) * s33p - 2.0 * nut(i, j, k) * s33m) / dz;
+                      2.0 * n23(i, j - 1, k) * e23(V, W, i, j - 1, k)) / hy(j) +
+                     (2.0 * nut(i, j, k + 1) * fz(k + 1) - 2.0 * nut(i, j, k) * fz(k)) / gz(k);
         return -(covx + covy + covz) + prm.nu * lap + sgs;
     }
 
@@ -463,8 +528,8 @@ struct Oracle {
 
     // --------------------------------------------------- divergence, rhs
     double divergence(const Box& U, const Box& V, const Box& W, int i, int j, int k) const {
-        return (U(i, j, k) - U(i - 1, j, k)) / dx + (V(i, j, k) - V(i, j - 1, k)) / dy +
-               (W(i, j, k) - W(i, j, k - 1)) / dz;
+        return (U(i, j, k) - U(i - 1, j, k)) / hx(i) + (V(i, j, k) - V(i, j - 1, k)) / hy(j) +
+               (W(i, j, k) - W(i, j, k - 1)) / hz(k);
     }
 
     double l2_div(const Box& U, const Box& V, const Box& W) const {
@@ -484,7 +549,8 @@ struct Oracle {
         return std::sqrt(t);
     }
 
-    // rhs = div(u*) / dt; with no Dirichlet face the mean is removed.
+    // rhs = div(u*) / dt; with no Dirichlet face the (volume-weighted) mean
+    // is removed.
     void build_rhs() {
 #pragma omp parallel for schedule(static)
         for (int k = 1; k <= nz; ++k)
@@ -493,17 +559,26 @@ struct Oracle {
         if (singular()) remove_mean(rhs);
     }
 
+    // Subtract the volume-weighted mean.  With no Dirichlet face, A p = rhs
+    // is solvable only when sum V rhs = 0 (V A is symmetric, so the null
+    // space of A's transpose is the cell volumes; on a uniform grid this is
+    // the plain mean); the same weighted mean fixes the gauge of p.
     void remove_mean(Box& f) const {
-        std::vector<double> part(nz + 2, 0.0);
+        std::vector<double> part(nz + 2, 0.0), vpart(nz + 2, 0.0);
         for (int k = 1; k <= nz; ++k) {
-            double s = 0.0;
+            double s = 0.0, sv = 0.0;
             for (int j = 1; j <= ny; ++j)
-                for (int i = 1; i <= nx; ++i) s += f(i, j, k);
+                for (int i = 1; i <= nx; ++i) {
+                    const double vol = hx(i) * hy(j) * hz(k);
+                    s += vol * f(i, j, k);
+                    sv += vol;
+                }
             part[k] = s;
+            vpart[k] = sv;
         }
-        double t = 0.0;
-        for (int k = 1; k <= nz; ++k) t += part[k];
-        double m = t / ((double)nx * ny * nz);
+        double t = 0.0, tv = 0.0;
+        for (int k = 1; k <= nz; ++k) { t += part[k]; tv += vpart[k]; }
+        const double m = t / tv;
         for (int k = 1; k <= nz; ++k)
             for (int j = 1; j <= ny; ++j)
                 for (int i = 1; i <= nx; ++i) f(i, j, k) -= m;
@@ -513,10 +588,7 @@ struct Oracle {
     // (A p)(i,j,k) = sum of neighbour weights times neighbour p minus the
     // diagonal times p (the discrete Laplacian with folded BCs).
     double apply_A(const Box& P, int i, int j, int k) const {
-        double nb = cn2l[i] * P(i + 1, j, k) + cn2s[i] * P(i - 1, j, k) +
-                    cn3l[j] * P(i, j + 1, k) + cn3s[j] * P(i, j - 1, k) +
-                    cn4l[k] * P(i, j, k + 1) + cn4s[k] * P(i, j, k - 1);
-        return nb - (dgx[i] + dgy[j] + dgz[k]) * P(i, j, k);
+        return neighbours(P, i, j, k) - diagonal(i, j, k) * P(i, j, k);
     }
 
     double l2_field(const Box& f) const {
@@ -550,53 +622,59 @@ struct Oracle {
         return std::sqrt(t);
     }
 
-    // One red-black iteration (section 2.6): colour nrd = 0 first, then 1.
-    // Colour nrd holds the cells with 1-based i+j+k odd for nrd = 0 and
-    // even for nrd = 1 (the paper's i = 1 + mod(k+j+nrd, 2) stepping by 2).
-    // Update: reltmp = omega (cn1 (sum_nb cn_nb p_nb - rhs) - p); p += reltmp.
-    // Returns sum of reltmp^2 over the iteration.
+    // One red-black SOR iteration (section 2.6).  The cells split by the
+    // parity of the 0-based index sum i0 + j0 + k0 into colour 0 (even) and
+    // colour 1 (odd); every neighbour of a cell has the other colour, so the
+    // cells of one colour can be relaxed in any order with the same result.
+    // Colour 0 goes first, then colour 1 with the new colour-0 values.  A
+    // cell moves from p towards its Gauss-Seidel value
+    //   q = (sum of neighbour weights times neighbour p - rhs) / diagonal
+    // by the relaxation factor: p <- p + omega (q - p).  Returns the sum of
+    // the squared changes over the iteration (the diagnostic the paper
+    // accumulates alongside).
     double sor_iteration(Box& P, const Box& R) const {
-        double sor = 0.0;
+        double total = 0.0;
         std::vector<double> part(nz + 2, 0.0);
-        for (int nrd = 0; nrd <= 1; ++nrd) {
+        for (int colour = 0; colour <= 1; ++colour) {
 #pragma omp parallel for schedule(static)
             for (int k = 1; k <= nz; ++k) {
                 double s = 0.0;
-                for (int j = 1; j <= ny; ++j)
-                    for (int i = 1 + ((k + j + nrd) & 1); i <= nx; i += 2) {
-                        double nb = cn2l[i] * P(i + 1, j, k) + cn2s[i] * P(i - 1, j, k) +
-                                    cn3l[j] * P(i, j + 1, k) + cn3s[j] * P(i, j - 1, k) +
-                                    cn4l[k] * P(i, j, k + 1) + cn4s[k] * P(i, j, k - 1);
-                        double reltmp = prm.omega * (cn1(i, j, k) * (nb - R(i, j, k)) - P(i, j, k));
-                        P(i, j, k) += reltmp;
-                        s += reltmp * reltmp;
+                const int k0 = k - 1;
+                for (int j = 1; j <= ny; ++j) {
+                    const int j0 = j - 1;
+                    // first 0-based i0 of this colour in the row, then every other one
+                    for (int i0 = (colour + j0 + k0) & 1; i0 < nx; i0 += 2) {
+                        const int i = i0 + 1;
+                        const double q = (neighbours(P, i, j, k) - R(i, j, k)) / diagonal(i, j, k);
+                        const double change = prm.omega * (q - P(i, j, k));
+                        P(i, j, k) += change;
+                        s += change * change;
                     }
+                }
                 part[k] = s;
             }
-            for (int k = 1; k <= nz; ++k) sor += part[k];
+            for (int k = 1; k <= nz; ++k) total += part[k];
         }
-        return sor;
+        return total;
     }
 
     // One iteration of twinned double buffering (section 2.6, the paper's
-    // alternative to the red-black scheme on the GPU): with the pair (p_0,
-    // p_1) per cell, nrd = 0 sets every cell's p_1 from p_0 and nrd = 1 sets
-    // p_0 from p_1, each with the SOR point formula
-    //   p_dst = p_src + omega (cn1 (sum_nb cn_nb p_src_nb - rhs) - p_src),
+    // alternative to the red-black scheme on the GPU): with a pair (p_0,
+    // p_1) per cell, the first half sets every cell's p_1 from p_0 and the
+    // second half p_0 from p_1, each by the relaxation above,
+    //   p_dst = p_src + omega (q(p_src) - p_src),
     // so all neighbours come from the previous half: a relaxed Jacobi
     // iteration.  P0 holds the result.
     void twinned_iteration(Box& P0, Box& P1, const Box& R, double omega) const {
-        for (int nrd = 0; nrd <= 1; ++nrd) {
-            const Box& S = nrd == 0 ? P0 : P1;
-            Box& D = nrd == 0 ? P1 : P0;
+        for (int half = 0; half <= 1; ++half) {
+            const Box& S = half == 0 ? P0 : P1;
+            Box& D = half == 0 ? P1 : P0;
 #pragma omp parallel for schedule(static)
             for (int k = 1; k <= nz; ++k)
                 for (int j = 1; j <= ny; ++j)
                     for (int i = 1; i <= nx; ++i) {
-                        double nb = cn2l[i] * S(i + 1, j, k) + cn2s[i] * S(i - 1, j, k) +
-                                    cn3l[j] * S(i, j + 1, k) + cn3s[j] * S(i, j - 1, k) +
-                                    cn4l[k] * S(i, j, k + 1) + cn4s[k] * S(i, j, k - 1);
-                        D(i, j, k) = S(i, j, k) + omega * (cn1(i, j, k) * (nb - R(i, j, k)) - S(i, j, k));
+                        const double q = (neighbours(S, i, j, k) - R(i, j, k)) / diagonal(i, j, k);
+                        D(i, j, k) = S(i, j, k) + omega * (q - S(i, j, k));
                     }
         }
     }
@@ -636,20 +714,22 @@ struct Oracle {
     }
 
     // ------------------------------------------------- projection (velnw)
-    // u^{n+1} = u* - dt grad p on faces between two cells, plus the outflow
-    // face where the face value of p is zero.
+    // u^{n+1} = u* - dt grad p on faces between two cells (centre difference
+    // over the centre distance), plus the outflow face, where p = 0 half a
+    // cell from the last centre.
     void project(Box& U, Box& V, Box& W, const Box& P) const {
 #pragma omp parallel for schedule(static)
         for (int k = 1; k <= nz; ++k)
             for (int j = 1; j <= ny; ++j)
                 for (int i = 1; i <= nx; ++i) {
-                    if (i <= nx - 1) U(i, j, k) -= dt * (P(i + 1, j, k) - P(i, j, k)) / dx;
-                    if (j <= ny - 1) V(i, j, k) -= dt * (P(i, j + 1, k) - P(i, j, k)) / dy;
-                    if (k <= nz - 1) W(i, j, k) -= dt * (P(i, j, k + 1) - P(i, j, k)) / dz;
+                    if (i <= nx - 1) U(i, j, k) -= dt * (P(i + 1, j, k) - P(i, j, k)) / gx(i);
+                    if (j <= ny - 1) V(i, j, k) -= dt * (P(i, j + 1, k) - P(i, j, k)) / gy(j);
+                    if (k <= nz - 1) W(i, j, k) -= dt * (P(i, j, k + 1) - P(i, j, k)) / gz(k);
                 }
         if (prm.bc[XP] == BC_OUTFLOW)
             for (int k = 1; k <= nz; ++k)
-                for (int j = 1; j <= ny; ++j) U(nx, j, k) -= dt * (-2.0 * P(nx, j, k)) / dx;
+                for (int j = 1; j <= ny; ++j)
+                    U(nx, j, k) -= dt * (-2.0 * P(nx, j, k)) / hx(nx);
     }
 
     double max_cfl(const Box& U, const Box& V, const Box& W) const {
@@ -660,7 +740,7 @@ struct Oracle {
                     double uc = 0.5 * std::fabs(U(i, j, k) + U(i - 1, j, k));
                     double vc = 0.5 * std::fabs(V(i, j, k) + V(i, j - 1, k));
                     double wc = 0.5 * std::fabs(W(i, j, k) + W(i, j, k - 1));
-                    c = std::max(c, dt * (uc / dx + vc / dy + wc / dz));
+                    c = std::max(c, dt * (uc / hx(i) + vc / hy(j) + wc / hz(k)));
                 }
         return c;
     }
@@ -704,18 +784,26 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // =====================================================================
 extern "C" {
 
-void* oracle_create(int nx, int ny, int nz, double dx, double dy, double dz, double dt,
-                    const uint8_t* mask, const OParams* prm) {
+// Stretched grid: hx[nx], hy[ny], hz[nz] are the cell widths along each
+// axis (the paper's 1-D spacing arrays, section 2.5.3), each > 0 and finite.
+void* oracle_create_stretched(int nx, int ny, int nz, const double* hx, const double* hy,
+                              const double* hz, double dt, const uint8_t* mask,
+                              const OParams* prm) {
     if (nx < 2 || ny < 2 || nz < 2) return nullptr;
-    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz) || !finite_pos(dt)) return nullptr;
-    if (!prm) return nullptr;
+    if (!hx || !hy || !hz || !finite_pos(dt) || !prm) return nullptr;
+    for (int i = 0; i < nx; ++i) if (!finite_pos(hx[i])) return nullptr;
+    for (int j = 0; j < ny; ++j) if (!finite_pos(hy[j])) return nullptr;
+    for (int k = 0; k < nz; ++k) if (!finite_pos(hz[k])) return nullptr;
     // x- is inflow or a wall, x+ outflow or a wall, the other faces walls.
     if (prm->bc[XM] == BC_OUTFLOW || prm->bc[XP] == BC_INFLOW) return nullptr;
     for (int f = YM; f <= ZP; ++f)
         if (prm->bc[f] != BC_FREESLIP && prm->bc[f] != BC_NOSLIP) return nullptr;
     Oracle* o = new Oracle();
     o->nx = nx; o->ny = ny; o->nz = nz;
-    o->dx = dx; o->dy = dy; o->dz = dz; o->dt = dt;
+    o->dt = dt;
+    o->X.init(hx, nx);
+    o->Y.init(hy, ny);
+    o->Z.init(hz, nz);
     o->prm = *prm;
     o->solid.assign((size_t)nx * ny * nz, 0);
     if (mask) std::memcpy(o->solid.data(), mask, o->solid.size());
@@ -725,6 +813,15 @@ void* oracle_create(int nx, int ny, int nz, double dx, double dy, double dz, dou
     o->prof.assign(nz + 2, 0.0);
     o->build_coefficients();
     return o;
+}
+
+// Uniform grid: every cell dx by dy by dz.
+void* oracle_create(int nx, int ny, int nz, double dx, double dy, double dz, double dt,
+                    const uint8_t* mask, const OParams* prm) {
+    if (nx < 2 || ny < 2 || nz < 2) return nullptr;
+    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz)) return nullptr;
+    std::vector<double> hx(nx, dx), hy(ny, dy), hz(nz, dz);
+    return oracle_create_stretched(nx, ny, nz, hx.data(), hy.data(), hz.data(), dt, mask, prm);
 }
 
 void oracle_destroy(void* h) { delete static_cast<Oracle*>(h); }

@@ -138,6 +138,28 @@ int les_default_params(les_params* p);
 int les_create(const les_grid* g, const les_spacing* s, double dt, const uint8_t* building_mask,
                const les_params* prm, les_handle** out);
 
+/*
+ * Create on a stretched grid: every axis carries its own cell widths (the
+ * paper's 1-D spacing arrays dx1 / dy1 / dzn of section 2.5.3, with the SOR
+ * coefficients of section 2.6 built from them).  hx[nx], hy[ny], hz[nz]:
+ * float64 cell widths [m], each > 0 and finite, copied.  Each stage then
+ * differences over the distance between the two values it spans (a cell
+ * width between a cell's faces, the distance of two centres across a
+ * face), interpolates cell values onto a face of their own axis with the
+ * width weights, and gives each cell its own filter width (hx hy hz)^(1/3);
+ * the pressure operator A = D G keeps 12 bytes per cell per fused SOR
+ * iteration (its per-axis weights are small tables, no 3-D coefficient
+ * array).  Equal widths reproduce the uniform grid up to rounding.  The
+ * profile of les_set_inflow is given at the stretched cell-centre heights.
+ * Requires the x+ face to be OUTFLOW (a nonsingular operator), else
+ * LES_EINVAL.  A stretched handle cannot join an ensemble, take a learned
+ * warm start or training-pair capture, or run the twinned comparison
+ * solver (each returns LES_EINVAL).  Other errors as les_create.
+ */
+int les_create_stretched(const les_grid* g, const double* hx, const double* hy, const double* hz,
+                         double dt, const uint8_t* building_mask, const les_params* prm,
+                         les_handle** out);
+
 /* Free everything.  NULL is a no-op. */
 void les_destroy(les_handle* h);
 
@@ -229,14 +251,16 @@ int les_pressure_solve_dev(les_handle* h, const float* d_rhs, float* d_p, double
  * without outflow face, give a zero-mean rhs).  st (optional): iters,
  * resid = ||rhs - A p||_2 / ||rhs||_2 in float64, rhs_norm, converged =
  * (resid <= the handle's tol), reltmp2 = 0.  ms (optional): device time of
- * the sweeps alone (events on the handle's stream).  Synchronous.  Keeps a
+ * the sweeps alone (events on the stream).  Ordered on stream (NULL: the
+ * handle's own), so it sees the caller's earlier writes to d_rhs and d_p on
+ * that stream; returns after the stream has drained (synchronous).  Keeps a
  * workspace of (nx+2)(ny+2)(nz+2) pairs from the first call until
  * les_destroy.  LES_EINVAL for NULL pointers, iters < 0 or omega outside
  * (0, 1] (beyond 1 the iteration diverges on this operator);
  * LES_ENONFINITE if the residual is not finite.
  */
 int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, float* d_p, double omega,
-                               int32_t iters, les_solve_stats* st, double* ms);
+                               int32_t iters, les_solve_stats* st, double* ms, void* stream);
 
 /* Copy the state out (ghost-free layouts above).  NULL skips a field. */
 int les_get_fields(les_handle* h, float* u, float* v, float* w, float* p);
@@ -300,24 +324,32 @@ int les_get_timing(les_handle* h, les_timing* out, int32_t reset);
  * grid resident at about two blocks per compute unit (16 where the grid is
  * wider), recomputing colour 0 on a one-cell ring around the tile: 12
  * instead of 16 bytes per cell per iteration; the iterate alternates
- * between two buffers, so these need an even check_every.  Every variant
- * computes the same per-cell arithmetic, so results are bitwise
- * independent of the choice.
+ * between two buffers, so these need an even check_every.  12-13: two
+ * whole iterations per launch (temporal blocking): the four colour updates
+ * run one plane behind another in one k-march over tiles of 64 half-cells
+ * x 32 rows, of which the 58 x 26 centre is written (the ring shrinks by
+ * one cell per update), so 12 bytes per cell move for two iterations; the
+ * planes per block are chosen per grid for one (12) or two (13) resident
+ * blocks per compute unit; they need check_every to be a multiple of 4 and
+ * are not used by ensembles.  Every variant computes the same per-cell
+ * arithmetic, so results are bitwise independent of the choice.
  *
  * Autotuner: times every variant for reps back-to-back pairs of launches
  * on this handle's grid, keeps the fastest for all later solves of the
  * handle and reports its index in *chosen (nullable) and the per-variant
- * microseconds per half-sweep (for 8-11: half a fused iteration; 0 when
- * not timed because check_every is odd) in
+ * microseconds per half-sweep (for 8-11: half a fused iteration; for
+ * 12-13 a quarter of a launch; 0 when not timed because check_every does
+ * not allow the variant) in
  * us_per_sweep[LES_NUM_SOR_VARIANTS] (nullable).  Runs on a scratch
  * pressure system: the time-stepping state is unchanged.  LES_EINVAL
  * unless 1 <= reps <= 1000.
  */
-#define LES_NUM_SOR_VARIANTS 12
+#define LES_NUM_SOR_VARIANTS 14
 int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sweep);
 
 /* Select a sweep variant by index (0 .. LES_NUM_SOR_VARIANTS-1); LES_EINVAL
- * for 8-11 with an odd check_every. */
+ * for 8-11 with an odd check_every, and for 12-13 (two iterations per
+ * launch) when check_every is not a multiple of 4. */
 int les_set_sor_variant(les_handle* h, int32_t variant);
 
 /* Step counter (completed steps). */
@@ -374,10 +406,12 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
  * 8-11 half a fused iteration, 0 where not timed).  The fused variants 8-11
  * run only in the batched mode with an even check_every and only as
  * the ensemble's choice (les_ensemble_autotune or les_ensemble_set_variant):
- * otherwise a member set to one runs its grid's default half-sweep. */
+ * otherwise a member set to one runs its grid's default half-sweep, as
+ * does a member whose own choice is a two-iteration variant (12-13). */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);
-/* The sweep variant every member runs (0 .. LES_NUM_SOR_VARIANTS-1), or -1:
- * each member its own; from the next step on.  LES_EINVAL otherwise. */
+/* The sweep variant every member runs (0 .. 11), or -1: each member its
+ * own; from the next step on.  LES_EINVAL otherwise (including the
+ * two-iteration variants 12-13, which are single-handle only). */
 int les_ensemble_set_variant(les_ensemble* e, int32_t variant);
 int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep);
 const char* les_ensemble_last_error(const les_ensemble* e);

@@ -25,7 +25,8 @@ URBAN_BC = (INFLOW, OUTFLOW, FREESLIP, FREESLIP, NOSLIP, FREESLIP)
 
 # every function include/les.h and include/lesnet.h declare
 EXPORTS = (
-    "les_default_params", "les_create", "les_destroy", "les_last_error", "les_set_stream",
+    "les_default_params", "les_create", "les_create_stretched", "les_destroy", "les_last_error",
+    "les_set_stream",
     "les_set_inflow", "les_set_inflow_pair", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
     "les_pressure_solve_twinned",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
@@ -42,13 +43,16 @@ EXPORTS = (
     "les_set_warm_start", "les_set_capture",
 )
 ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
-NUM_SOR_VARIANTS = 12
+NUM_SOR_VARIANTS = 14
 # (row width TX, planes per block KT) of each half-sweep variant, and
 # (TX, KT, wavefronts per block) of the fused red-black variants 8-11 (KT 0:
-# chosen per grid), as in the library
+# chosen per grid); 12-13 run two iterations per launch (64 lanes x 32
+# rows; KT: the resident blocks per compute unit the plane count is chosen
+# for), as in the library
 SOR_VARIANTS = ((64, 1), (32, 1), (64, 2), (32, 2), (64, 4), (32, 4), (64, 8), (32, 8),
-                (32, 12, 16), (64, 16, 16), (32, 0, 16), (64, 0, 16))
+                (32, 12, 16), (64, 16, 16), (32, 0, 16), (64, 0, 16), (64, 1, 16), (64, 2, 16))
 NUM_SPLIT_SOR_VARIANTS = 8
+FIRST_TWO_ITER_SOR_VARIANT = 12
 KERNEL_NAMES = ("nut", "tendency", "inflow", "rhs", "sor", "check", "rebase", "project", "bc")
 
 
@@ -147,13 +151,15 @@ def lib():
     L.les_last_error.argtypes = [P]
     L.les_last_error.restype = C.c_char_p
     L.les_set_stream.argtypes = [P, P]
+    L.les_create_stretched.argtypes = [C.POINTER(Grid), P, P, P, C.c_double, P, C.POINTER(Params),
+                                       C.POINTER(C.c_void_p)]
     L.les_set_inflow.argtypes = [P, P, C.c_float, C.c_uint64]
     L.les_set_inflow_pair.argtypes = [P, C.c_double, P, C.c_double, P]
     L.les_step.argtypes = [P, C.c_int32, C.POINTER(StepStats)]
     L.les_pressure_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats)]
     L.les_pressure_solve_dev.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
     L.les_pressure_solve_twinned.argtypes = [P, P, P, C.c_double, C.c_int32,
-                                             C.POINTER(SolveStats), C.POINTER(C.c_double)]
+                                             C.POINTER(SolveStats), C.POINTER(C.c_double), P]
     L.les_get_fields.argtypes = [P, P, P, P, P]
     L.les_get_fields_dev.argtypes = [P, P, P, P, P, P]
     L.les_set_fields.argtypes = [P, P, P, P, P, C.c_int32]
@@ -219,6 +225,12 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
+def _current_stream() -> int:
+    """torch's current HIP stream on the current device (its raw handle)."""
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
 def _f32(a, shape):
     a = np.ascontiguousarray(a, dtype=np.float32)
     if a.shape != tuple(shape):
@@ -240,8 +252,17 @@ class LES:
             if m.shape != (nz, ny, nx):
                 raise ValueError("mask must be [nz, ny, nx]")
         h = C.c_void_p()
-        rc = lib().les_create(C.byref(Grid(nx, ny, nz)), C.byref(Spacing(dx, dy, dz)), dt,
-                              _ptr(m), C.byref(self.params), C.byref(h))
+        # dx, dy, dz: uniform spacings, or (any of them) the cell widths of a
+        # stretched axis -> les_create_stretched with all three width arrays
+        self.stretched = any(np.ndim(d) > 0 for d in (dx, dy, dz))
+        if self.stretched:
+            self.widths = tuple(np.ascontiguousarray(np.broadcast_to(np.asarray(d, np.float64), (n,)))
+                                for d, n in ((dx, self.nx), (dy, self.ny), (dz, self.nz)))
+            rc = lib().les_create_stretched(C.byref(Grid(nx, ny, nz)), *(_ptr(w) for w in self.widths),
+                                            dt, _ptr(m), C.byref(self.params), C.byref(h))
+        else:
+            rc = lib().les_create(C.byref(Grid(nx, ny, nz)), C.byref(Spacing(dx, dy, dz)), dt,
+                                  _ptr(m), C.byref(self.params), C.byref(h))
         if rc != LES_OK:
             raise LesError(rc, "les_create failed")
         self.h = h
@@ -297,23 +318,27 @@ class LES:
         return p, st.as_dict(), rc
 
     def pressure_solve_dev(self, d_rhs, d_p, tol=1e-5, max_iter=20000, stream=None):
-        """Device-pointer solve; d_rhs / d_p are contiguous float32 torch tensors."""
+        """Device-pointer solve; d_rhs / d_p are contiguous float32 torch
+        tensors.  Ordered on `stream` (default: torch's current stream, so
+        the caller's earlier and later torch work on them is ordered)."""
         st = SolveStats()
-        s = None if stream is None else C.c_void_p(stream)
+        s = C.c_void_p(_current_stream() if stream is None else stream)
         rc = self._check(lib().les_pressure_solve_dev(self.h, C.c_void_p(d_rhs.data_ptr()),
                                                       C.c_void_p(d_p.data_ptr()), float(tol),
                                                       int(max_iter), C.byref(st), s),
                          (LES_OK, LES_NOT_CONVERGED))
         return st.as_dict(), rc
 
-    def pressure_solve_twinned(self, d_rhs, d_p, omega=1.0, iters=50):
+    def pressure_solve_twinned(self, d_rhs, d_p, omega=1.0, iters=50, stream=None):
         """Twinned double-buffer relaxation (les_pressure_solve_twinned) on
-        contiguous float32 device tensors; returns (stats, ms of the sweeps)."""
+        contiguous float32 device tensors, ordered on `stream` (default:
+        torch's current stream); returns (stats, ms of the sweeps)."""
         st = SolveStats()
         ms = C.c_double(0.0)
+        s = C.c_void_p(_current_stream() if stream is None else stream)
         self._check(lib().les_pressure_solve_twinned(self.h, C.c_void_p(d_rhs.data_ptr()),
                                                      C.c_void_p(d_p.data_ptr()), float(omega),
-                                                     int(iters), C.byref(st), C.byref(ms)))
+                                                     int(iters), C.byref(st), C.byref(ms), s))
         return st.as_dict(), ms.value
 
     def get_fields(self):

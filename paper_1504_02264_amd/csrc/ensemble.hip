@@ -50,6 +50,7 @@ struct EnsInst {
     double tol;
     int max_iter, K, R, variant, singular, inflow;
     unsigned nsweep, nred;
+    int kt_tile;        // planes per block of the fused tendency pass
 };
 
 // Per-member state that changes from step to step (device memory).
@@ -67,6 +68,7 @@ struct EnsDyn {
 // Offsets of each member's blocks in a stage's work list.
 struct EnsOffsets {
     unsigned box[kMaxEnsemble + 1];
+    unsigned tile[kMaxEnsemble + 1];
     unsigned cell[kMaxEnsemble + 1];
     unsigned half[kMaxEnsemble + 1];
     unsigned red[kMaxEnsemble + 1];
@@ -118,6 +120,18 @@ __global__ __launch_bounds__(kBlock) void k_ens_tendency(const EnsInst* I, const
     TendArgs A{d.u[a], d.v[a], d.w[a], d.nut, d.fu, d.fv, d.fw, d.su, d.sv, d.sw, d.flags,
                d.u[b], d.v[b], d.w[b], d.nu, d.alpha, d.beta, D[q].first};
     tendency_body(d.g, A, L - O->cell[q]);
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_ens_step_tile(const EnsInst* I, const EnsDyn* D,
+                                                              int n, const EnsOffsets* O) {
+    __shared__ TileShared sh;
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = owner(O->tile, n, L);
+    const EnsInst& d = I[q];
+    const int a = D[q].cur, b = 1 - a;
+    TendArgs A{d.u[a], d.v[a], d.w[a], d.nut, d.fu, d.fv, d.fw, d.su, d.sv, d.sw, d.flags,
+               d.u[b], d.v[b], d.w[b], d.nu, d.alpha, d.beta, D[q].first};
+    step_tile_body(d.g, A, d.nut, d.c2, d.kt_tile, L - O->tile[q], sh);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ens_inflow(const EnsInst* I, const EnsDyn* D, int n,
@@ -338,11 +352,11 @@ __global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restri
         grid.sync();
         // members whose check interval ends with a rebase fold first
         bool any_rebase = false;
-        for (int q = 0; q < n; ++q) any_rebase = any_rebase || ((c + 1) % I[q].R == 0);
+        for (int q = 0; q < n; ++q) any_rebase = any_rebase || rebase_due_at(c + 1, I[q].K, I[q].R);
         if (any_rebase) {
             walk_items(s_fold, n, [&](int q, unsigned a, unsigned b) {
                 const EnsInst& d = I[q];
-                if ((c + 1) % d.R != 0 || ld(&d.ctl->done)) return;
+                if (!rebase_due_at(c + 1, d.K, d.R) || ld(&d.ctl->done)) return;
                 for (unsigned L = a; L < b; ++L)
                     fold_body(d.g.ctot, d.P.ph[0], d.P.pd[0], d.P.ph[1], d.P.pd[1],
                               (long long)L * kBlock + threadIdx.x);
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restri
         walk_items(s_red, n, [&](int q, unsigned a, unsigned b) {
             const EnsInst& d = I[q];
             if (ld(&d.ctl->done)) return;
-            if ((c + 1) % d.R == 0) {
+            if (rebase_due_at(c + 1, d.K, d.R)) {
                 for (unsigned L = a; L < b; ++L) rebase_body(d.g, d.P, d.part, L, d.nred);
             } else if (!ld(&d.ctl->skip)) {
                 for (unsigned L = a; L < b; ++L) check_body(d.g, d.P, d.part, L, d.nred);
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restri
         grid.sync();
         for (int q = blockIdx.x; q < n; q += nb) {
             const EnsInst& d = I[q];
-            finalize_body<kBlock>(((c + 1) % d.R == 0) ? FIN_CHECK_FULL : FIN_CHECK, d.part,
+            finalize_body<kBlock>(rebase_due_at(c + 1, d.K, d.R) ? FIN_CHECK_FULL : FIN_CHECK, d.part,
                                   (int)d.nred, d.rel0, d.rel1, (int)d.nsweep, d.ctl, d.omega);
         }
         grid.sync();
@@ -377,7 +391,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_ens_solve(const EnsInst* __restri
 // kernels, so plain loads are coherent (kernel boundaries order them).
 __device__ __forceinline__ bool rebase_due(const EnsInst& d) {
     // the check that ends the current interval is number m/K + 1
-    return ((d.ctl->m / d.K) + 1) % d.R == 0;
+    return rebase_due_at((d.ctl->m / d.K) + 1, d.K, d.R);
 }
 
 constexpr unsigned kAuxBlocks = 4096;   // grid of the fold / check phases
@@ -550,7 +564,8 @@ unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 // member then runs it: one launch shape), in the batched mode and with an
 // even check interval.
 bool ens_fused(const les_ensemble* e) {
-    return e->variant >= 0 && sor_fused(e->variant) && e->mode == LES_ENSEMBLE_BATCHED && !(e->K & 1);
+    return e->variant >= 0 && sor_fused(e->variant) && !sor_fused2(e->variant) &&
+           e->mode == LES_ENSEMBLE_BATCHED && !(e->K & 1);
 }
 
 // The sweep variant a member runs in the ensemble: the ensemble's choice,
@@ -558,7 +573,8 @@ bool ens_fused(const les_ensemble* e) {
 // becomes the grid's default half-sweep.
 int ens_variant(const les_ensemble* e, const les_handle* h) {
     const int v = e->variant >= 0 ? e->variant : h->sor_variant;
-    return (sor_fused(v) && !ens_fused(e)) ? sor_default_variant(h->g) : v;
+    // (the two-iteration variants are single-handle only)
+    return (sor_fused(v) && (!ens_fused(e) || sor_fused2(v))) ? sor_default_variant(h->g) : v;
 }
 
 // Host copies of the member descriptors and work-list offsets, from the
@@ -613,7 +629,9 @@ void build_descriptors(les_ensemble* e) {
         d.nsweep = sor_sweep_blocks(h->g, d.variant);
         d.nred = red_blocks(h->g);
         max_iter_all = std::max(max_iter_all, h->prm.max_iter);
+        d.kt_tile = tile_kt(h->g);
         o.box[q + 1] = o.box[q] + box_blocks(h->g);
+        o.tile[q + 1] = o.tile[q] + tile_blocks(h->g);
         o.cell[q + 1] = o.cell[q] + cell_blocks(h->g);
         o.half[q + 1] = o.half[q] + half_blocks(h->g);
         o.red[q + 1] = o.red[q] + d.nred;
@@ -631,8 +649,8 @@ void build_descriptors(les_ensemble* e) {
 int enqueue_pre(les_ensemble* e, hipStream_t s) {
     const int n = e->n;
     const EnsOffsets& o = e->h_off;
-    hipLaunchKernelGGL(k_ens_nut, dim3(o.box[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
-    hipLaunchKernelGGL(k_ens_tendency, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
+    hipLaunchKernelGGL(k_ens_step_tile, dim3(o.tile[n]), dim3(kTileThreads), 0, s, e->d_inst, e->d_dyn, n,
+                       e->d_off);
     hipLaunchKernelGGL(k_ens_inflow, dim3(o.inflow[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
     hipLaunchKernelGGL(k_ens_ctl_init, dim3(n), dim3(kBlock), 0, s, e->d_inst);
     hipLaunchKernelGGL(k_ens_rhs, dim3(o.cell[n]), dim3(kBlock), 0, s, e->d_inst, e->d_dyn, n, e->d_off);
@@ -764,6 +782,7 @@ int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** ou
             if (members[r] == members[q]) return LES_EINVAL;
         if (members[q]->prm.check_every != members[0]->prm.check_every) return LES_EINVAL;
         if (members[q]->device != members[0]->device) return LES_EINVAL;
+        if (members[q]->g.stretched) return LES_EINVAL;   // uniform members only
         if (members[q]->prm.zero_guess) return LES_EINVAL;
     }
     les_ensemble* e = new (std::nothrow) les_ensemble();
@@ -838,7 +857,7 @@ int les_ensemble_set_mode(les_ensemble* e, int32_t mode) {
 }
 
 int les_ensemble_set_variant(les_ensemble* e, int32_t variant) {
-    if (!e || variant < -1 || variant >= kNumSorVariants) return LES_EINVAL;
+    if (!e || variant < -1 || variant >= kFirstRb2Variant) return LES_EINVAL;
     e->variant = variant;
     e->descriptors_dirty = true;
     return LES_OK;
@@ -867,7 +886,9 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     const int saved = e->variant;
     for (int v = 0; v < kNumSorVariants; ++v) {
         e->variant = v;
-        if (sor_fused(v) && !ens_fused(e)) {   // persistent mode or an odd check interval
+        // persistent mode or an odd check interval; two iterations per
+        // launch are single-handle only
+        if (sor_fused2(v) || (sor_fused(v) && !ens_fused(e))) {
             e->tune_us[v] = 0.0;
             continue;
         }
@@ -1015,12 +1036,17 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
     acc.members = n;
     acc.steps = nsteps;
     acc.cells_total = e->cells_total;
+    // every member's buffer parity and step count first (the device advanced
+    // all of them), then the check for non-finite members
     for (int q = 0; q < n; ++q) {
         les_handle* h = e->members[q];
         const EnsDyn& s = e->h_dyn[q];
         h->cur = s.cur;
         h->step = s.step;
         if (nsteps > 0) h->have_old = true;
+    }
+    for (int q = 0; q < n; ++q) {
+        const EnsDyn& s = e->h_dyn[q];
         if (nsteps > 0 && (s.done == 3 || !std::isfinite(s.rhs2)))
             return ens_err(e, LES_ENONFINITE, "non-finite residual norm in a member");
     }

@@ -9,7 +9,7 @@ namespace {
 
 __device__ __forceinline__ unsigned lblock() { return xcd_block(blockIdx.x, gridDim.x); }
 
-template <int TX, int KT>
+template <int TX, int KT, bool STR>
 __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict__ pself,
                                                 const float* __restrict__ poth,
                                                 const float* __restrict__ rself, float omega,
@@ -17,10 +17,11 @@ __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict_
                                                 const Ctl* __restrict__ ctl) {
     bool acc;
     if (!sweep_active(ctl, local_iter, acc)) return;
-    sor_body<TX, KT>(g, c, pself, poth, rself, omega, acc && rel_part != nullptr, rel_part, lblock());
+    sor_body<TX, KT, STR>(g, c, pself, poth, rself, omega, acc && rel_part != nullptr, rel_part,
+                          lblock());
 }
 
-template <int TX, int NW, int KT>
+template <int TX, int NW, int KT, bool STR>
 __global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restrict__ a0,
                                                     const float* __restrict__ a1,
                                                     const float* __restrict__ r0c,
@@ -33,8 +34,27 @@ __global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restri
     bool acc;
     const bool active = sweep_active(ctl, local_iter, acc);
     if (!active && ctl->done) return;
-    sor_rb_body<TX, NW, KT>(g, a0, a1, r0c, r1c, b0, b1, omega, active && acc && rel0 != nullptr,
-                            !active, rel0, rel1, lblock(), kt);
+    sor_rb_body<TX, NW, KT, STR>(g, a0, a1, r0c, r1c, b0, b1, omega,
+                                 active && acc && rel0 != nullptr, !active, rel0, rel1, lblock(), kt);
+}
+
+template <bool STR>
+__global__ __launch_bounds__(1024) void k_sor_rb2(Geo g, const float* __restrict__ a0,
+                                                 const float* __restrict__ a1,
+                                                 const float* __restrict__ r0c,
+                                                 const float* __restrict__ r1c,
+                                                 float* __restrict__ b0, float* __restrict__ b1,
+                                                 float omega, int local_iter,
+                                                 double* __restrict__ rel0,
+                                                 double* __restrict__ rel1,
+                                                 const Ctl* __restrict__ ctl, int kt) {
+    bool acc1, acc2;
+    const bool act1 = sweep_active(ctl, local_iter, acc1);
+    const bool act2 = sweep_active(ctl, local_iter + 1, acc2);
+    if (!act1 && ctl->done) return;
+    const bool part = rel0 != nullptr;
+    sor_rb2_body<STR>(g, a0, a1, r0c, r1c, b0, b1, omega, act1, act1 && act2, part && act1 && acc1 && !act2,
+                      part && act1 && act2 && acc2, rel0, rel1, lblock(), kt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fold(long long n, float* __restrict__ ph0,
@@ -44,16 +64,18 @@ __global__ __launch_bounds__(kBlock) void k_fold(long long n, float* __restrict_
     fold_body(n, ph0, pd0, ph1, pd1, (long long)blockIdx.x * kBlock + threadIdx.x);
 }
 
+template <bool STR>
 __global__ __launch_bounds__(kBlock) void k_rebase(Geo g, PBufs P, double* __restrict__ part,
                                                    const Ctl* ctl) {
     if (ctl->done) return;
-    rebase_body(g, P, part, lblock(), gridDim.x);
+    rebase_body<STR>(g, P, part, lblock(), gridDim.x);
 }
 
+template <bool STR>
 __global__ __launch_bounds__(kBlock) void k_check(Geo g, PBufs P, double* __restrict__ part,
                                                   const Ctl* ctl) {
     if (ctl->done || ctl->skip) return;
-    check_body(g, P, part, lblock(), gridDim.x);
+    check_body<STR>(g, P, part, lblock(), gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_colour_sum(Geo g, const float* a0, const float* a1,
@@ -81,7 +103,10 @@ inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock)
 // block KT) and fused iterations (TX, KT, NW wavefronts per block).
 const SorVariant kSorVariants[kNumSorVariants] = {
     {64, 1, 0}, {32, 1, 0}, {64, 2, 0}, {32, 2, 0}, {64, 4, 0}, {32, 4, 0}, {64, 8, 0}, {32, 8, 0},
-    {32, 12, 16}, {64, 16, 16}, {32, 0, 16}, {64, 0, 16}};
+    {32, 12, 16}, {64, 16, 16}, {32, 0, 16}, {64, 0, 16},
+    // two iterations per launch (64 lanes x 32 rows, 16 wavefronts); kt
+    // planes chosen per grid for one (12) or two (13) resident blocks per CU
+    {64, 1, 16}, {64, 2, 16}};
 
 int sor_default_variant(const Geo& g) {
     const int w64 = ((g.H + 63) / 64) * 64 - g.H;
@@ -91,6 +116,11 @@ int sor_default_variant(const Geo& g) {
 
 unsigned sor_sweep_blocks(const Geo& g, int variant) {
     const int tx = kSorVariants[variant].tx, kt = kSorVariants[variant].kt;
+    if (sor_fused2(variant)) {
+        const int k = rb2_kt(g, kt);
+        return (unsigned)((g.H + kRb2TXO - 1) / kRb2TXO) * (unsigned)((g.ny + kRb2TYO - 1) / kRb2TYO) *
+               (unsigned)((g.nz + k - 1) / k);
+    }
     if (sor_fused(variant)) {
         const int nw = kSorVariants[variant].nw;
         const int txo = tx - 2, tyo = (64 / tx) * nw - 2, k = fused_kt(g, tx, nw, kt);
@@ -115,10 +145,14 @@ hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, 
     float* ps = P.pd[colour];
     const float* po = P.pd[1 - colour];
     const float* rs = P.r0[colour];
-#define LES_SOR_CASE(V, TX, KT)                                                                 \
-    case V:                                                                                    \
-        hipLaunchKernelGGL((k_sor<TX, KT>), grid, block, 0, st, g, colour, ps, po, rs, omega, \
-                           local_iter, rel_part, ctl);                                         \
+#define LES_SOR_CASE(V, TX, KT)                                                                  \
+    case V:                                                                                     \
+        if (g.stretched)                                                                        \
+            hipLaunchKernelGGL((k_sor<TX, KT, true>), grid, block, 0, st, g, colour, ps, po, rs,  \
+                               omega, local_iter, rel_part, ctl);                               \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_sor<TX, KT, false>), grid, block, 0, st, g, colour, ps, po, rs, \
+                               omega, local_iter, rel_part, ctl);                               \
         break;
     switch (variant) {
         LES_SOR_CASE(0, 64, 1)
@@ -144,10 +178,14 @@ hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parit
     float* b1 = parity ? P.pd[1] : P.pa[1];
     const SorVariant& sv = kSorVariants[variant];
     const int kt = fused_kt(g, sv.tx, sv.nw, sv.kt);
-#define LES_RB_CASE(V, TX, NW, KT)                                                                  \
-    case V:                                                                                        \
-        hipLaunchKernelGGL((k_sor_rb<TX, NW, KT>), grid, dim3(64 * NW), 0, st, g, a0, a1, P.r0[0],  \
-                           P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);               \
+#define LES_RB_CASE(V, TX, NW, KT)                                                                   \
+    case V:                                                                                         \
+        if (g.stretched)                                                                            \
+            hipLaunchKernelGGL((k_sor_rb<TX, NW, KT, true>), grid, dim3(64 * NW), 0, st, g, a0, a1,   \
+                               P.r0[0], P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);   \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_sor_rb<TX, NW, KT, false>), grid, dim3(64 * NW), 0, st, g, a0, a1,  \
+                               P.r0[0], P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);   \
         break;
     switch (variant) {
         LES_RB_CASE(8, 32, 16, 12)
@@ -160,6 +198,24 @@ hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parit
     return hipGetLastError();
 }
 
+hipError_t launch_sor_rb2(const Geo& g, hipStream_t st, const PBufs& P, int parity, float omega,
+                          int local_iter, double* rel0, double* rel1, const Ctl* ctl, int variant) {
+    if (!sor_fused2(variant)) return hipErrorInvalidValue;
+    const dim3 grid(sor_sweep_blocks(g, variant));
+    const float* a0 = parity ? P.pa[0] : P.pd[0];
+    const float* a1 = parity ? P.pa[1] : P.pd[1];
+    float* b0 = parity ? P.pd[0] : P.pa[0];
+    float* b1 = parity ? P.pd[1] : P.pa[1];
+    const int kt = rb2_kt(g, kSorVariants[variant].kt);
+    if (g.stretched)
+        hipLaunchKernelGGL(k_sor_rb2<true>, grid, dim3(1024), 0, st, g, a0, a1, P.r0[0], P.r0[1], b0, b1,
+                           omega, local_iter, rel0, rel1, ctl, kt);
+    else
+        hipLaunchKernelGGL(k_sor_rb2<false>, grid, dim3(1024), 0, st, g, a0, a1, P.r0[0], P.r0[1], b0, b1,
+                           omega, local_iter, rel0, rel1, ctl, kt);
+    return hipGetLastError();
+}
+
 hipError_t launch_fold(const Geo& g, hipStream_t st, const PBufs& P, const Ctl* ctl) {
     hipLaunchKernelGGL(k_fold, dim3(nblk(2 * g.ctot)), dim3(kBlock), 0, st, g.ctot, P.ph[0],
                        P.pd[0], P.ph[1], P.pd[1], ctl);
@@ -168,8 +224,12 @@ hipError_t launch_fold(const Geo& g, hipStream_t st, const PBufs& P, const Ctl* 
 
 hipError_t launch_rebase(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                          const double* rel0, const double* rel1, int nrel, Ctl* ctl, int decide) {
-    hipLaunchKernelGGL(k_rebase, dim3(red_blocks(g)), dim3(kBlock), 0, st, g, P, part,
-                       (const Ctl*)ctl);
+    if (g.stretched)
+        hipLaunchKernelGGL(k_rebase<true>, dim3(red_blocks(g)), dim3(kBlock), 0, st, g, P, part,
+                           (const Ctl*)ctl);
+    else
+        hipLaunchKernelGGL(k_rebase<false>, dim3(red_blocks(g)), dim3(kBlock), 0, st, g, P, part,
+                           (const Ctl*)ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(st, decide ? FIN_CHECK_FULL : FIN_SETUP, part, (int)red_blocks(g), rel0,
@@ -188,8 +248,12 @@ hipError_t launch_colour_norm(const Geo& g, hipStream_t st, float* const a[2], d
 
 hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* part,
                         const double* rel0, const double* rel1, int nrel, Ctl* ctl) {
-    hipLaunchKernelGGL(k_check, dim3(check_blocks(g)), dim3(kBlock), 0, st, g, P, part,
-                       (const Ctl*)ctl);
+    if (g.stretched)
+        hipLaunchKernelGGL(k_check<true>, dim3(check_blocks(g)), dim3(kBlock), 0, st, g, P, part,
+                           (const Ctl*)ctl);
+    else
+        hipLaunchKernelGGL(k_check<false>, dim3(check_blocks(g)), dim3(kBlock), 0, st, g, P, part,
+                           (const Ctl*)ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(st, FIN_CHECK, part, (int)check_blocks(g), rel0, rel1, nrel, ctl);

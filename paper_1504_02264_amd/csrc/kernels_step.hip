@@ -19,6 +19,37 @@ __global__ __launch_bounds__(kBlock) void k_tendency(Geo g, TendArgs a) {
     tendency_body(g, a, lblock());
 }
 
+__global__ __launch_bounds__(kTileThreads) void k_step_tile(Geo g, TendArgs a, float* __restrict__ nut,
+                                                          float c2, int kt) {
+    __shared__ TileShared sh;
+    step_tile_body(g, a, nut, c2, kt, lblock(), sh);
+}
+
+// stretched grids (per-axis metric tables in g)
+__global__ __launch_bounds__(kBlock) void k_nut_str(Geo g, const float* __restrict__ u,
+                                                    const float* __restrict__ v,
+                                                    const float* __restrict__ w,
+                                                    float* __restrict__ nut, float cs2) {
+    nut_body_str(g, u, v, w, nut, cs2, lblock());
+}
+
+__global__ __launch_bounds__(kBlock) void k_tendency_str(Geo g, TendArgs a) {
+    tendency_body_str(g, a, lblock());
+}
+
+__global__ __launch_bounds__(kBlock) void k_rhs_str(Geo g, const float* __restrict__ us,
+                                                    const float* __restrict__ vs,
+                                                    const float* __restrict__ ws, float* rhs0,
+                                                    float* rhs1, double* __restrict__ part) {
+    rhs_body_str(g, us, vs, ws, rhs0, rhs1, part, lblock());
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_str(Geo g, float* __restrict__ us,
+                                                        float* __restrict__ vs,
+                                                        float* __restrict__ ws, PBufs P) {
+    project_body_str(g, us, vs, ws, P, lblock());
+}
+
 __global__ __launch_bounds__(kBlock) void k_inflow(Geo g, float* __restrict__ us,
                                                    const float* __restrict__ prof,
                                                    const float* __restrict__ prof1, float wt,
@@ -104,7 +135,10 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 // ------------------------------------------------------------ launchers
 hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
                       const float* w, float* nut, float c2) {
-    hipLaunchKernelGGL(k_nut, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, c2);
+    if (g.stretched)   // c2 is Cs^2 here; the filter width comes from the tables
+        hipLaunchKernelGGL(k_nut_str, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, c2);
+    else
+        hipLaunchKernelGGL(k_nut, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, c2);
     return hipGetLastError();
 }
 
@@ -113,7 +147,21 @@ hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const f
                            float* su, float* sv, float* sw, const uint8_t* flags, float* us,
                            float* vs, float* ws, float nu, float alpha, float beta, int first) {
     TendArgs a{u, v, w, nut, fu, fv, fw, su, sv, sw, flags, us, vs, ws, nu, alpha, beta, first};
-    hipLaunchKernelGGL(k_tendency, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
+    if (g.stretched)
+        hipLaunchKernelGGL(k_tendency_str, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
+    else
+        hipLaunchKernelGGL(k_tendency, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_tile(const Geo& g, hipStream_t st, const float* u, const float* v,
+                            const float* w, float* nut, float* fu, float* fv, float* fw, float* su,
+                            float* sv, float* sw, const uint8_t* flags, float* us, float* vs,
+                            float* ws, float c2, float nu, float alpha, float beta, int first) {
+    if (g.stretched) return hipErrorInvalidValue;   // uniform spacing only
+    TendArgs a{u, v, w, nut, fu, fv, fw, su, sv, sw, flags, us, vs, ws, nu, alpha, beta, first};
+    hipLaunchKernelGGL(k_step_tile, dim3(tile_blocks(g)), dim3(kTileThreads), 0, st, g, a, nut, c2,
+                       tile_kt(g));
     return hipGetLastError();
 }
 
@@ -133,8 +181,14 @@ hipError_t launch_ctl_init(hipStream_t st, Ctl* ctl, double tol, int max_iter, i
 hipError_t launch_rhs(const Geo& g, hipStream_t st, const float* us, const float* vs,
                       const float* ws, float* const rhs[2], double* part, Ctl* ctl,
                       int singular) {
-    hipLaunchKernelGGL(k_rhs, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws, rhs[0],
-                       rhs[1], part, singular);
+    if (g.stretched) {   // stretched grids have an outflow face: never singular
+        if (singular) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_rhs_str, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws,
+                           rhs[0], rhs[1], part);
+    } else {
+        hipLaunchKernelGGL(k_rhs, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws, rhs[0],
+                           rhs[1], part, singular);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize(st, singular ? FIN_RHS_SUM : FIN_RHS2, part, (int)cell_blocks(g),
@@ -152,7 +206,10 @@ hipError_t launch_remove_mean_rhs(const Geo& g, hipStream_t st, float* const rhs
 
 hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
                           const PBufs& P) {
-    hipLaunchKernelGGL(k_project, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws, P);
+    if (g.stretched)
+        hipLaunchKernelGGL(k_project_str, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws, P);
+    else
+        hipLaunchKernelGGL(k_project, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, us, vs, ws, P);
     return hipGetLastError();
 }
 

@@ -81,6 +81,9 @@ Geo make_geo(int nx, int ny, int nz, const les_spacing& s, double dt, const les_
     g.cx = (float)(1.0 / (s.dx * s.dx));
     g.cy = (float)(1.0 / (s.dy * s.dy));
     g.cz = (float)(1.0 / (s.dz * s.dz));
+    g.cxd = 1.0 / (s.dx * s.dx);
+    g.cyd = 1.0 / (s.dy * s.dy);
+    g.czd = 1.0 / (s.dz * s.dz);
     g.outflow = p.bc[LES_XP] == LES_BC_OUTFLOW;
     g.inflow = p.bc[LES_XM] == LES_BC_INFLOW;
     g.u_last = g.outflow ? nx : nx - 1;
@@ -281,16 +284,27 @@ SolveGraph* solve_graph(les_handle* h, const PBufs& P, int var, int K, int R, do
 // into the base every rebase_every checks.  Batches of checks are enqueued
 // ahead; the device sets ctl->done and every later kernel of the batch
 // returns at once.  The host reads the flag one batch behind.
-int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve_stats* out) {
+// direct: launch every kernel itself (no captured graphs, no timing
+// events), so the solve creates nothing on the device.
+int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve_stats* out,
+              bool direct = false) {
     const Geo& g = h->g;
     hipStream_t st = h->stream;
     Ctl* ctl = h->f.ctl;
+    const bool timing = h->prm.timing && !direct;
+    // kernel timing brackets (only with timing on)
+    auto tm = [&](int kind, long long tag, auto&& f, int count = 1) -> hipError_t {
+        return timing ? timed(h, kind, tag, f, count) : f();
+    };
     const int K = h->prm.check_every;
     const int R = h->prm.rebase_every;
     const float omega = (float)h->prm.omega;
     // fused iterations alternate pd -> pa -> pd: an even interval ends on pd
-    const int var = (sor_fused(h->sor_variant) && (K & 1)) ? sor_default_variant(g) : h->sor_variant;
+    const int var = ((sor_fused(h->sor_variant) && (K & 1)) || (sor_fused2(h->sor_variant) && (K & 3)))
+                        ? sor_default_variant(g)
+                        : h->sor_variant;
     const bool fused = sor_fused(var);
+    const bool fused2 = sor_fused2(var);
     const int nrel = (int)sor_sweep_blocks(g, var);
     double* part = h->f.part[0];
     double* rel0 = h->f.part[1];
@@ -301,8 +315,15 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     auto interval = [&](long long cidx) -> hipError_t {
         // one check interval in 8 is timed as a whole: 2K back-to-back
         // half-sweeps (K fused iterations) between one pair of events
-        const bool sample = h->prm.timing && (cidx % 8 == 1);
+        const bool sample = timing && (cidx % 8 == 1);
         auto sweeps = [&]() -> hipError_t {
+            if (fused2) {   // K is a multiple of 4: K/2 launches end on pd
+                for (int it = 0; it < K; it += 2) {
+                    const hipError_t e = launch_sor_rb2(g, st, P, (it >> 1) & 1, omega, it, rel0, rel1, ctl, var);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            }
             if (fused) {
                 for (int it = 0; it < K; ++it) {
                     const hipError_t e = launch_sor_rb(g, st, P, it & 1, omega, it, rel0, rel1, ctl, var);
@@ -318,28 +339,38 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
             }
             return hipSuccess;
         };
-        hipError_t e = sample ? timed(h, KN_SOR, cidx, sweeps, fused ? K : 2 * K) : sweeps();
+        hipError_t e = sample ? tm(KN_SOR, cidx, sweeps, fused2 ? K / 2 : (fused ? K : 2 * K)) : sweeps();
         if (e != hipSuccess) return e;
         e = launch_finalize(st, FIN_BOUND, nullptr, 0, rel0, rel1, nrel, ctl, h->prm.omega);
         if (e != hipSuccess) return e;
-        if (cidx % R == 0) {
+        if (rebase_due_at(cidx, K, R)) {
             e = launch_fold(g, st, P, ctl);
             if (e != hipSuccess) return e;
-            return timed(h, KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); });
+            return tm(KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); });
         }
-        return timed(h, KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); });
+        return tm(KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); });
     };
     // Without timing, aligned runs of kSolveGraphChecks intervals replay a
     // captured graph (its kernels read every decision from the control
     // block, so a replay equals the launches it was captured from).
     SolveGraph* sg = nullptr;
-    if (!h->prm.timing && st != nullptr && R % kSolveGraphChecks == 0) sg = solve_graph(h, P, var, K, R, h->prm.omega);
-    auto replay = [&](bool ends_with_rebase) -> int {
-        hipGraphExec_t& ex = sg->exec[ends_with_rebase ? 1 : 0];
+    if (!timing && !direct && st != nullptr && R % kSolveGraphChecks == 0) sg = solve_graph(h, P, var, K, R, h->prm.omega);
+    // Rebase pattern of the aligned run of intervals c0+1 .. c0+8: 2 inside
+    // the early-fold phase, 1 past it when the run ends on a multiple of R,
+    // 0 otherwise; -1 for a run that straddles the phase boundary (launched
+    // directly).  A shape's graph is captured from representative interval
+    // numbers with the same pattern.
+    const long long early_end = kEarlyFoldIters / K;   // last interval of the early phase
+    const long long late0 = ((early_end + R) / R) * R;    // a multiple of R past it
+    auto run_shape = [&](long long c0) -> int {
+        if (c0 + kSolveGraphChecks <= early_end) return 2;
+        if (c0 + 1 <= early_end) return -1;
+        return rebase_due_at(c0 + kSolveGraphChecks, K, R) ? 1 : 0;
+    };
+    auto replay = [&](int shape) -> int {
+        hipGraphExec_t& ex = sg->exec[shape];
         if (!ex) {
-            // representative interval numbers: the rebase pattern within an
-            // aligned run depends only on whether it ends on a multiple of R
-            const long long c0 = ends_with_rebase ? R - kSolveGraphChecks : 0;
+            const long long c0 = shape == 2 ? 0 : (shape == 1 ? late0 + R - kSolveGraphChecks : late0);
             hipGraph_t gph = nullptr;
             CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
@@ -356,7 +387,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     };
 
     CK(launch_fold(g, st, P, ctl));
-    CK(timed(h, KN_REBASE, 0, [&] { return launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0); }));
+    CK(tm(KN_REBASE, 0, [&] { return launch_rebase(g, st, P, part, nullptr, nullptr, 0, ctl, 0); }));
     const long long n_checks = max_iter > 0 ? ((long long)max_iter + K - 1) / K : 0;
     long long c = 0;
     // batches of 2, 2, 4 intervals (a solve that converges at once is
@@ -371,8 +402,8 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
         long long q = 0;
         while (q < nb) {
             const long long c0 = c + q;   // intervals c0+1, ...
-            if (sg && c0 % kSolveGraphChecks == 0 && q + kSolveGraphChecks <= nb) {
-                const int rc = replay((c0 + kSolveGraphChecks) % R == 0);
+            if (sg && c0 % kSolveGraphChecks == 0 && q + kSolveGraphChecks <= nb && run_shape(c0) >= 0) {
+                const int rc = replay(run_shape(c0));
                 if (rc != LES_OK) return rc;
                 q += kSolveGraphChecks;
             } else {
@@ -395,7 +426,7 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     CK(hipStreamSynchronize(st));
     const Ctl& hc = *h->h_ctl;
     // the check that stopped the solve is interval ceil(m / K)
-    if (h->prm.timing) tresolve(h, ((long long)hc.m + K - 1) / K);
+    if (timing) tresolve(h, ((long long)hc.m + K - 1) / K);
     if (out) {
         out->iters = hc.m;
         out->resid = hc.resid;
@@ -498,8 +529,54 @@ int les_default_params(les_params* p) {
     return LES_OK;
 }
 
-int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_t* building_mask,
-               const les_params* prm, les_handle** out) {
+}  // extern "C"
+
+namespace {
+
+// Metric table of one stretched axis (MetricRow rows of n + 2 floats),
+// computed in float64 from the n cell widths and rounded once, and the
+// float64 rows of its pressure-operator weights (M_WM, M_WP, M_DD) in
+// `op`.  x_outflow: the axis ends in the outflow face (p = 0 on the face:
+// 2/h^2 more on the last cell's diagonal).
+std::vector<float> axis_metrics(const double* w, int n, bool x_outflow, std::vector<double>& op) {
+    const int L = n + 2;
+    std::vector<double> h(L), gf(L);
+    for (int c = 1; c <= n; ++c) h[c] = w[c - 1];
+    h[0] = h[1];
+    h[n + 1] = h[n];
+    for (int f = 0; f <= n; ++f) gf[f] = 0.5 * (h[f] + h[f + 1]);
+    gf[n + 1] = gf[n];
+    std::vector<float> m((size_t)kMetricRows * L, 0.f);
+    auto at = [&](int row, int c) -> float& { return m[(size_t)row * L + c]; };
+    for (int c = 0; c < L; ++c) {
+        at(M_IH, c) = (float)(1.0 / h[c]);
+        at(M_IG, c) = (float)(1.0 / gf[c]);
+        const int f1 = c + 1 < L ? c + 1 : c;
+        at(M_LO, c) = (float)(h[f1] / (h[c] + h[f1]));
+        at(M_HI, c) = (float)(h[c] / (h[c] + h[f1]));
+        at(M_H23, c) = (float)std::pow(h[c], 2.0 / 3.0);
+        at(M_H, c) = (float)h[c];
+    }
+    op.assign((size_t)3 * L, 0.0);
+    for (int c = 1; c <= n; ++c) {
+        const double wm = c > 1 ? 1.0 / (h[c] * gf[c - 1]) : 0.0;
+        const double wp = c < n ? 1.0 / (h[c] * gf[c]) : 0.0;
+        double dd = wm + wp;
+        if (c == n && x_outflow) dd += 2.0 / (h[c] * h[c]);
+        at(M_WM, c) = (float)wm;
+        at(M_WP, c) = (float)wp;
+        at(M_DD, c) = (float)dd;
+        op[(size_t)0 * L + c] = wm;
+        op[(size_t)1 * L + c] = wp;
+        op[(size_t)2 * L + c] = dd;
+    }
+    return m;
+}
+
+// Shared body of les_create and les_create_stretched (widths: NULL for a
+// uniform grid, else the three per-axis width arrays).
+int create_impl(const les_grid* gr, const les_spacing* s, const double* const* widths, double dt,
+                const uint8_t* building_mask, const les_params* prm, les_handle** out) {
     if (!gr || !s || !out) return LES_EINVAL;
     *out = nullptr;
     if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return LES_EINVAL;
@@ -510,6 +587,8 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     if (prm) p = *prm;
     else les_default_params(&p);
     if (!valid_params(p)) return LES_EINVAL;
+    // stretched axes need the outflow face (a nonsingular operator)
+    if (widths && p.bc[LES_XP] != LES_BC_OUTFLOW) return LES_EINVAL;
     const long long ncell = (long long)gr->nx * gr->ny * gr->nz;
     if (ncell > (1LL << 31)) return LES_EINVAL;
 
@@ -538,8 +617,11 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     for (int v = 0; v < kNumSorVariants; ++v) maxsweep = std::max<long long>(maxsweep, sor_sweep_blocks(g, v));
     const size_t nparts = (size_t)std::max<long long>(2LL * nblk(ncell), 2LL * maxsweep) + 64;
     const size_t pb = align256(nparts * sizeof(double));
+    const size_t mb = widths ? align256((size_t)kMetricRows * (g.nx + g.ny + g.nz + 6) * sizeof(float)) +
+                                   align256((size_t)3 * (g.nx + g.ny + g.nz + 6) * sizeof(double))
+                             : 0;
     const size_t total = 13 * nb + fb + 2 * align256((size_t)g.nz * sizeof(float)) + ncells + 10 * cb +
-                         3 * pb + align256(sizeof(Ctl));
+                         3 * pb + align256(sizeof(Ctl)) + mb;
     void* arena = nullptr;
     if (hipMalloc(&arena, total) != hipSuccess) return fail(LES_ENOMEM);
     h->arena = arena;
@@ -569,8 +651,36 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     for (int c = 0; c < 2; ++c) h->f.P.pa[c] = (float*)take(cb);
     for (int q = 0; q < 3; ++q) h->f.part[q] = (double*)take(pb);
     h->f.ctl = (Ctl*)take(align256(sizeof(Ctl)));
+    float* metric = widths ? (float*)take(mb) : nullptr;
 
     if (hipMemsetAsync(arena, 0, total, h->stream) != hipSuccess) return fail(LES_EDEVICE);
+    if (widths) {
+        const int n3[3] = {g.nx, g.ny, g.nz};
+        std::vector<float> all;
+        std::vector<double> all_op, op;
+        for (int a = 0; a < 3; ++a) {
+            const std::vector<float> m = axis_metrics(widths[a], n3[a], a == 0 && g.outflow, op);
+            all.insert(all.end(), m.begin(), m.end());
+            all_op.insert(all_op.end(), op.begin(), op.end());
+        }
+        double* metric_op =
+            (double*)((char*)metric + align256((size_t)kMetricRows * (g.nx + g.ny + g.nz + 6) * sizeof(float)));
+        if (hipMemcpyAsync(metric, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice,
+                           h->stream) != hipSuccess ||
+            hipMemcpyAsync(metric_op, all_op.data(), all_op.size() * sizeof(double),
+                           hipMemcpyHostToDevice, h->stream) != hipSuccess)
+            return fail(LES_EDEVICE);
+        // the copies must land before the host vectors go away
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(LES_EDEVICE);
+        h->g.stretched = 1;
+        h->g.mx = metric;
+        h->g.my = metric + (size_t)kMetricRows * (g.nx + 2);
+        h->g.mz = metric + (size_t)kMetricRows * (g.nx + g.ny + 4);
+        h->g.wx = metric_op;
+        h->g.wy = metric_op + (size_t)3 * (g.nx + 2);
+        h->g.wz = metric_op + (size_t)3 * (g.nx + g.ny + 4);
+        for (int a = 0; a < 3; ++a) h->widths[a].assign(widths[a], widths[a] + n3[a]);
+    }
     std::vector<uint8_t> flags = build_flags(g, h->mask);
     if (hipMemcpyAsync(h->f.flags, flags.data(), flags.size(), hipMemcpyHostToDevice, h->stream) !=
         hipSuccess)
@@ -588,6 +698,39 @@ int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_
     h->sor_variant = sor_default_variant(g);
     *out = h;
     return LES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int les_create(const les_grid* gr, const les_spacing* s, double dt, const uint8_t* building_mask,
+               const les_params* prm, les_handle** out) {
+    return create_impl(gr, s, nullptr, dt, building_mask, prm, out);
+}
+
+int les_create_stretched(const les_grid* gr, const double* hx, const double* hy, const double* hz,
+                         double dt, const uint8_t* building_mask, const les_params* prm,
+                         les_handle** out) {
+    if (!gr || !hx || !hy || !hz || !out) return LES_EINVAL;
+    *out = nullptr;
+    if (gr->nx < 4 || gr->ny < 4 || gr->nz < 4) return LES_EINVAL;
+    if (gr->nx > (1 << 20) || gr->ny > (1 << 20) || gr->nz > (1 << 20)) return LES_EINVAL;
+    const double* w[3] = {hx, hy, hz};
+    const int n3[3] = {gr->nx, gr->ny, gr->nz};
+    double mean[3];
+    for (int a = 0; a < 3; ++a) {
+        double sum = 0.0;
+        for (int c = 0; c < n3[a]; ++c) {
+            if (!finite_pos(w[a][c])) return LES_EINVAL;
+            sum += w[a][c];
+        }
+        mean[a] = sum / n3[a];
+    }
+    // the scalar spacings of the handle hold the mean widths (informational;
+    // every stage of a stretched grid reads the per-axis tables)
+    const les_spacing s{mean[0], mean[1], mean[2]};
+    return create_impl(gr, &s, w, dt, building_mask, prm, out);
 }
 
 void les_destroy(les_handle* h) {
@@ -686,8 +829,10 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
     const Geo& g = h->g;
     const les_params& p = h->prm;
     hipStream_t s = h->stream;
+    // (Cs Delta)^2 with Delta = (dx dy dz)^(1/3); a stretched grid's kernel
+    // forms each cell's own filter width from the tables and takes Cs^2
     const double delta = std::cbrt((double)g.dx * g.dy * g.dz);
-    const float c2 = (float)((p.cs * delta) * (p.cs * delta));
+    const float c2 = g.stretched ? (float)(p.cs * p.cs) : (float)((p.cs * delta) * (p.cs * delta));
     les_step_stats acc{};
     if (st) acc.iters_out = st->iters_out;
     acc.div_new_last = -1.0;
@@ -697,14 +842,24 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
     int worst = LES_OK;
     for (int q = 0; q < n; ++q) {
         const int a = h->cur, b = 1 - h->cur;
-        CK(timed(h, KN_NUT, kNoTag, [&] { return launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2); }));
         const int first = h->have_old ? 0 : 1;
-        CK(timed(h, KN_TEND, kNoTag, [&] {
-            return launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
-                                   h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
-                                   h->f.u[b], h->f.v[b], h->f.w[b], (float)p.nu, (float)p.alpha,
-                                   (float)p.beta, first);
-        }));
+        if (g.stretched) {
+            CK(timed(h, KN_NUT, kNoTag, [&] { return launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2); }));
+            CK(timed(h, KN_TEND, kNoTag, [&] {
+                return launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
+                                       h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
+                                       h->f.u[b], h->f.v[b], h->f.w[b], (float)p.nu, (float)p.alpha,
+                                       (float)p.beta, first);
+            }));
+        } else {
+            // nu_t, tendency, feedback and AB2 in one LDS-tiled pass
+            CK(timed(h, KN_TEND, kNoTag, [&] {
+                return launch_step_tile(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
+                                        h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
+                                        h->f.u[b], h->f.v[b], h->f.w[b], c2, (float)p.nu,
+                                        (float)p.alpha, (float)p.beta, first);
+            }));
+        }
         h->have_old = true;
         if (g.inflow)
             CK(timed(h, KN_INFLOW, kNoTag, [&] {
@@ -770,20 +925,32 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
     return worst;
 }
 
-static int solve_common(les_handle* h, double tol, int32_t max_iter, les_solve_stats* st) {
+}  // extern "C"
+
+// Stand-alone solve of the pressure system S (rhs and start already in S,
+// correction cleared): control block, rhs norm (mean removal without an
+// outflow face), SOR to tol, p mean.  direct: no graphs, no timing events.
+int les::solve_system(les_handle* h, double tol, int32_t max_iter, les_solve_stats* st,
+                      const PBufs& S, bool direct) {
     const Geo& g = h->g;
     hipStream_t s = h->stream;
     CK(launch_ctl_init(s, h->f.ctl, tol, max_iter, h->prm.check_every));
     if (singular(h)) {
-        CK(launch_colour_norm(g, s, h->S.rhs, h->f.part[0], h->f.ctl, 1));
-        CK(launch_remove_mean_rhs(g, s, h->S.rhs, h->f.part[0], h->f.ctl));
+        CK(launch_colour_norm(g, s, S.rhs, h->f.part[0], h->f.ctl, 1));
+        CK(launch_remove_mean_rhs(g, s, S.rhs, h->f.part[0], h->f.ctl));
     } else {
-        CK(launch_colour_norm(g, s, h->S.rhs, h->f.part[0], h->f.ctl, 0));
+        CK(launch_colour_norm(g, s, S.rhs, h->f.part[0], h->f.ctl, 0));
     }
-    int rc = run_solve(h, h->S, tol, max_iter, st);
+    int rc = run_solve(h, S, tol, max_iter, st, direct);
     if (rc < 0) return rc;
-    if (singular(h)) CK(launch_remove_mean_p(g, s, h->S, h->f.part[0], h->f.ctl));
+    if (singular(h)) CK(launch_remove_mean_p(g, s, S, h->f.part[0], h->f.ctl));
     return rc;
+}
+
+extern "C" {
+
+static int solve_common(les_handle* h, double tol, int32_t max_iter, les_solve_stats* st) {
+    return solve_system(h, tol, max_iter, st, h->S, false);
 }
 
 int les_pressure_solve(les_handle* h, const float* rhs, float* p, double tol, int32_t max_iter,
@@ -993,17 +1160,20 @@ int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sw
     double best = 1e300;
     int best_v = h->sor_variant;
     for (int v = 0; v < kNumSorVariants; ++v) {
-        if (sor_fused(v) && (h->prm.check_every & 1)) {   // needs an even check interval
+        // fused iterations need an even check interval, two per launch a
+        // multiple of 4
+        if ((sor_fused(v) && (h->prm.check_every & 1)) || (sor_fused2(v) && (h->prm.check_every & 3))) {
             if (us_per_sweep) us_per_sweep[v] = 0.0;
             continue;
         }
-        // two launches: two half-sweeps, or two fused iterations (half a
-        // fused iteration is charged per half-sweep below)
+        // two launches: two half-sweeps, two fused iterations or four (the
+        // time is charged per half-sweep below)
         auto pair = [&]() -> hipError_t {
             for (int w = 0; w < 2; ++w) {
-                const hipError_t e = sor_fused(v)
-                                         ? launch_sor_rb(g, s, h->S, w, 1.0f, 0, nullptr, nullptr, h->f.ctl, v)
-                                         : launch_sor(g, s, h->S, w, 1.0f, 0, nullptr, h->f.ctl, v);
+                const hipError_t e =
+                    sor_fused2(v) ? launch_sor_rb2(g, s, h->S, w, 1.0f, 0, nullptr, nullptr, h->f.ctl, v)
+                    : sor_fused(v) ? launch_sor_rb(g, s, h->S, w, 1.0f, 0, nullptr, nullptr, h->f.ctl, v)
+                                   : launch_sor(g, s, h->S, w, 1.0f, 0, nullptr, h->f.ctl, v);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
@@ -1015,7 +1185,7 @@ int les_autotune(les_handle* h, int32_t reps, int32_t* chosen, double* us_per_sw
         CK(hipEventSynchronize(b));
         float ms = 0.f;
         CK(hipEventElapsedTime(&ms, a, b));
-        const double us = 1e3 * ms / ((sor_fused(v) ? 4.0 : 2.0) * reps);
+        const double us = 1e3 * ms / ((sor_fused2(v) ? 8.0 : (sor_fused(v) ? 4.0 : 2.0)) * reps);
         if (us_per_sweep) us_per_sweep[v] = us;
         if (us < best) {
             best = us;
@@ -1036,6 +1206,8 @@ int les_set_sor_variant(les_handle* h, int32_t variant) {
     if (!h || variant < 0 || variant >= kNumSorVariants) return LES_EINVAL;
     if (sor_fused(variant) && (h->prm.check_every & 1))
         return set_err(h, LES_EINVAL, "fused sweep variants need an even check interval");
+    if (sor_fused2(variant) && (h->prm.check_every & 3))
+        return set_err(h, LES_EINVAL, "two-iteration sweep variants need a check interval that is a multiple of 4");
     h->sor_variant = variant;
     return LES_OK;
 }

@@ -93,6 +93,12 @@ __device__ __forceinline__ float diag_of(const Geo& g, int i0, int j0, int k0) {
     return diag_x(g, i0) + diag_y(g, j0) + diag_z(g, k0);
 }
 
+// Row `row` of an axis' metric table at 1-based index c (tables of n + 2
+// entries per row; MetricRow in les_impl.h).
+__device__ __forceinline__ float mrow(const float* __restrict__ m, int n, int row, int c) {
+    return m[row * (n + 2) + c];
+}
+
 // ------------------------------------------------------------------ les
 // Smagorinsky eddy viscosity nu_t = (Cs Delta)^2 |S|, |S| = sqrt(2 S_ij S_ij)
 // (section 2.1, les).  S_ii from the two faces of the cell; S_ij (i != j)
@@ -256,6 +262,228 @@ __device__ __forceinline__ void tendency_body(const Geo& g, const TendArgs& A, u
         const float fo = A.first ? F : A.fw[e];
         A.ws[e] = wc + dt * (1.5f * F - 0.5f * fo);
         A.fw[e] = F;
+    }
+}
+
+// ------------------------- les + velfg + feedbf + adam, fused, LDS-tiled
+// One pass over the grid instead of two: a block owns a tile of kTileX x
+// kTileY cells and marches up its chunk of planes.  Every velocity plane
+// is read from HBM once into LDS with a two-cell ring (u, v, w; kTileVS
+// planes in a ring buffer), nu_t is computed into LDS on the tile plus a
+// one-cell ring (three planes), and the tendency, feedback forcing and AB2
+// of the tile's cells read both from LDS.  nu_t of the tile's own cells is
+// also stored (the les_get_aux diagnostic); the tendency never reads it
+// back.  Per-cell arithmetic is that of nut_body and tendency_body
+// (same formulas and evaluation order); ghost-ring nu_t is the value of
+// the nearest interior cell, as there.
+//
+// March of a block over tendency planes [kb, ke): step p loads velocity
+// plane p+1 into registers (issued a step ahead), publishes plane p, then
+// after a barrier computes nu_t on plane p-1 and after a second barrier
+// the tendency on plane p-2.  Five velocity slots keep the slot written at
+// step p (last read by the tendency of step p-2) clear of readers, and
+// three nu_t slots likewise, so two barriers per step suffice.
+constexpr int kTileX = 64, kTileY = 8;
+constexpr int kTileThreads = kTileX * kTileY;   // one wavefront per tile row
+constexpr int kTileLX = kTileX + 4, kTileLY = kTileY + 4;   // velocity: two-cell ring
+constexpr int kTileNX = kTileX + 2, kTileNY = kTileY + 2;   // nu_t: one-cell ring
+constexpr int kTileVS = 5;   // velocity plane slots
+constexpr int kTileVel = kTileLX * kTileLY;     // entries of one velocity plane
+constexpr int kTileNut = kTileNX * kTileNY;
+
+// Planes per block on grid g: the most (32, 16 or 8) that still give at
+// least two blocks per compute unit.
+inline int tile_kt(const Geo& g) {
+    const long long nxy = (long long)((g.nx + kTileX - 1) / kTileX) * ((g.ny + kTileY - 1) / kTileY);
+    for (int kt = 32; kt > 8; kt /= 2)
+        if (nxy * ((g.nz + kt - 1) / kt) >= 512) return kt;
+    return 8;
+}
+inline unsigned tile_blocks(const Geo& g) {
+    const int kt = tile_kt(g);
+    return (unsigned)((g.nx + kTileX - 1) / kTileX) * (unsigned)((g.ny + kTileY - 1) / kTileY) *
+           (unsigned)((g.nz + kt - 1) / kt);
+}
+
+struct TileShared {
+    float vel[kTileVS][3][kTileLY][kTileLX];
+    float nut[3][kTileNY][kTileNX];
+};
+
+__device__ __forceinline__ void step_tile_body(const Geo& g, const TendArgs& A, float* __restrict__ nut_out,
+                                               float c2, int kt, unsigned lb, TileShared& sh) {
+    const int ntx = (g.nx + kTileX - 1) / kTileX, nty = (g.ny + kTileY - 1) / kTileY;
+    const int bx = (int)(lb % (unsigned)ntx);
+    const unsigned rr = lb / (unsigned)ntx;
+    const int by = (int)(rr % (unsigned)nty), bz = (int)(rr / (unsigned)nty);
+    const int i0 = bx * kTileX + 1, j0 = by * kTileY + 1;   // first (1-based) cell of the tile
+    const int kb = bz * kt + 1, ke = min(kb + kt, g.nz + 1);   // tendency planes [kb, ke)
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, row = tid >> 6;
+    const float* __restrict__ gu = A.u;
+    const float* __restrict__ gv = A.v;
+    const float* __restrict__ gw = A.w;
+
+    // LDS views (global 1-based indices)
+    auto vs = [](int k) { return (k + 2 * kTileVS) % kTileVS; };
+    auto U = [&](int a, int b, int c) { return sh.vel[vs(c)][0][b - j0 + 2][a - i0 + 2]; };
+    auto V = [&](int a, int b, int c) { return sh.vel[vs(c)][1][b - j0 + 2][a - i0 + 2]; };
+    auto W = [&](int a, int b, int c) { return sh.vel[vs(c)][2][b - j0 + 2][a - i0 + 2]; };
+    auto N = [&](int a, int b, int c) {
+        const int cc = min(max(c, 1), g.nz);   // ghost planes: the nearest interior plane
+        return sh.nut[cc % 3][b - j0 + 1][a - i0 + 1];
+    };
+
+    // one velocity plane: entries tid and tid + kTileThreads of the ring tile
+    float reg[2][3];
+    auto fetch = [&](int p) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = tid + r * kTileThreads;
+            const int i = i0 - 2 + e % kTileLX, j = j0 - 2 + e / kTileLX;
+            const bool ok = e < kTileVel && p >= 0 && p <= g.nz + 1 && i >= 0 && i <= g.nx + 1 &&
+                            j >= 0 && j <= g.ny + 1;
+            const long long x = ok ? g.nat(i, j, p) : 0;
+            reg[r][0] = ok ? gu[x] : 0.f;
+            reg[r][1] = ok ? gv[x] : 0.f;
+            reg[r][2] = ok ? gw[x] : 0.f;
+        }
+    };
+    auto publish = [&](int p) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = tid + r * kTileThreads;
+            if (e < kTileVel) {
+                const int ly = e / kTileLX, lx = e % kTileLX;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sh.vel[vs(p)][c][ly][lx] = reg[r][c];
+            }
+        }
+    };
+
+    fetch(kb - 2);
+    for (int p = kb - 2; p <= ke + 1; ++p) {
+        publish(p);
+        if (p <= ke) fetch(p + 1);
+        __syncthreads();
+        // nu_t on plane c = p - 1 over the tile and its ring (interior planes only)
+        const int c = p - 1;
+        if (c >= kb - 1 && c <= ke && c >= 1 && c <= g.nz) {
+            for (int e = tid; e < kTileNut; e += kTileThreads) {
+                const int ny_ = e / kTileNX, nx_ = e % kTileNX;
+                const int ia = i0 - 1 + nx_, jb = j0 - 1 + ny_;
+                const int ic = min(max(ia, 1), g.nx), jc = min(max(jb, 1), g.ny), kc = c;
+                const float s11 = (U(ic, jc, kc) - U(ic - 1, jc, kc)) * g.idx;
+                const float s22 = (V(ic, jc, kc) - V(ic, jc - 1, kc)) * g.idy;
+                const float s33 = (W(ic, jc, kc) - W(ic, jc, kc - 1)) * g.idz;
+                float s12 = 0.f, s13 = 0.f, s23 = 0.f;
+#pragma unroll
+                for (int da = -1; da <= 0; ++da)
+#pragma unroll
+                    for (int db = -1; db <= 0; ++db) {
+                        const int a = ic + da, b = jc + db;
+                        s12 += (U(a, b + 1, kc) - U(a, b, kc)) * g.idy + (V(a + 1, b, kc) - V(a, b, kc)) * g.idx;
+                        const int cz = kc + db;
+                        s13 += (U(a, jc, cz + 1) - U(a, jc, cz)) * g.idz + (W(a + 1, jc, cz) - W(a, jc, cz)) * g.idx;
+                        const int b2 = jc + da;
+                        s23 += (V(ic, b2, cz + 1) - V(ic, b2, cz)) * g.idz + (W(ic, b2 + 1, cz) - W(ic, b2, cz)) * g.idy;
+                    }
+                s12 *= 0.125f;
+                s13 *= 0.125f;
+                s23 *= 0.125f;
+                const float ss = 2.f * (s11 * s11 + s22 * s22 + s33 * s33) +
+                                 4.f * (s12 * s12 + s13 * s13 + s23 * s23);
+                const float nt = c2 * sqrtf(ss);
+                sh.nut[c % 3][ny_][nx_] = nt;
+                if (c >= kb && c < ke && nx_ >= 1 && nx_ <= kTileX && ny_ >= 1 && ny_ <= kTileY &&
+                    ia <= g.nx && jb <= g.ny)
+                    nut_out[g.nat(ia, jb, c)] = nt;
+            }
+        }
+        __syncthreads();
+        // tendency, feedback forcing and AB2 on plane k = p - 2
+        const int k = p - 2, i = i0 + lane, j = j0 + row;
+        if (k >= kb && k < ke && i <= g.nx && j <= g.ny) {
+            auto n12 = [&](int a, int b, int cc) { return 0.25f * (N(a, b, cc) + N(a + 1, b, cc) + N(a, b + 1, cc) + N(a + 1, b + 1, cc)); };
+            auto n13 = [&](int a, int b, int cc) { return 0.25f * (N(a, b, cc) + N(a + 1, b, cc) + N(a, b, cc + 1) + N(a + 1, b, cc + 1)); };
+            auto n23 = [&](int a, int b, int cc) { return 0.25f * (N(a, b, cc) + N(a, b + 1, cc) + N(a, b, cc + 1) + N(a, b + 1, cc + 1)); };
+            auto e12 = [&](int a, int b, int cc) { return 0.5f * ((U(a, b + 1, cc) - U(a, b, cc)) * g.idy + (V(a + 1, b, cc) - V(a, b, cc)) * g.idx); };
+            auto e13 = [&](int a, int b, int cc) { return 0.5f * ((U(a, b, cc + 1) - U(a, b, cc)) * g.idz + (W(a + 1, b, cc) - W(a, b, cc)) * g.idx); };
+            auto e23 = [&](int a, int b, int cc) { return 0.5f * ((V(a, b, cc + 1) - V(a, b, cc)) * g.idz + (W(a, b + 1, cc) - W(a, b, cc)) * g.idy); };
+            const long long e = g.nat(i, j, k);
+            const uint8_t fl = A.flags[e];
+            const float dt = g.dt;
+            const float nu = A.nu, alpha = A.alpha, beta = A.beta;
+            if (i <= g.u_last) {
+                const float uc = U(i, j, k);
+                const float um = U(i - 1, j, k), up = U(i + 1, j, k);
+                const float covx = 0.5f * (0.5f * (um + uc) * (uc - um) + 0.5f * (uc + up) * (up - uc)) * g.idx;
+                const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i + 1, j - 1, k)) * (uc - U(i, j - 1, k)) +
+                                           0.5f * (V(i, j, k) + V(i + 1, j, k)) * (U(i, j + 1, k) - uc)) * g.idy;
+                const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i + 1, j, k - 1)) * (uc - U(i, j, k - 1)) +
+                                           0.5f * (W(i, j, k) + W(i + 1, j, k)) * (U(i, j, k + 1) - uc)) * g.idz;
+                const float lap = (up - 2.f * uc + um) * g.cx + (U(i, j + 1, k) - 2.f * uc + U(i, j - 1, k)) * g.cy +
+                                  (U(i, j, k + 1) - 2.f * uc + U(i, j, k - 1)) * g.cz;
+                const float sgs = 2.f * (N(i + 1, j, k) * (up - uc) * g.idx - N(i, j, k) * (uc - um) * g.idx) * g.idx +
+                                  2.f * (n12(i, j, k) * e12(i, j, k) - n12(i, j - 1, k) * e12(i, j - 1, k)) * g.idy +
+                                  2.f * (n13(i, j, k) * e13(i, j, k) - n13(i, j, k - 1) * e13(i, j, k - 1)) * g.idz;
+                float F = -(covx + covy + covz) + nu * lap + sgs;
+                if (fl & F_USOLID) {
+                    const float s = A.su[e] + dt * uc;
+                    A.su[e] = s;
+                    F += alpha * s + beta * uc;
+                }
+                const float fo = A.first ? F : A.fu[e];
+                A.us[e] = uc + dt * (1.5f * F - 0.5f * fo);
+                A.fu[e] = F;
+            }
+            if (j <= g.ny - 1) {
+                const float vc = V(i, j, k);
+                const float vm = V(i, j - 1, k), vp = V(i, j + 1, k);
+                const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j + 1, k)) * (vc - V(i - 1, j, k)) +
+                                           0.5f * (U(i, j, k) + U(i, j + 1, k)) * (V(i + 1, j, k) - vc)) * g.idx;
+                const float covy = 0.5f * (0.5f * (vm + vc) * (vc - vm) + 0.5f * (vc + vp) * (vp - vc)) * g.idy;
+                const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i, j + 1, k - 1)) * (vc - V(i, j, k - 1)) +
+                                           0.5f * (W(i, j, k) + W(i, j + 1, k)) * (V(i, j, k + 1) - vc)) * g.idz;
+                const float lap = (V(i + 1, j, k) - 2.f * vc + V(i - 1, j, k)) * g.cx + (vp - 2.f * vc + vm) * g.cy +
+                                  (V(i, j, k + 1) - 2.f * vc + V(i, j, k - 1)) * g.cz;
+                const float sgs = 2.f * (n12(i, j, k) * e12(i, j, k) - n12(i - 1, j, k) * e12(i - 1, j, k)) * g.idx +
+                                  2.f * (N(i, j + 1, k) * (vp - vc) * g.idy - N(i, j, k) * (vc - vm) * g.idy) * g.idy +
+                                  2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j, k - 1) * e23(i, j, k - 1)) * g.idz;
+                float F = -(covx + covy + covz) + nu * lap + sgs;
+                if (fl & F_VSOLID) {
+                    const float s = A.sv[e] + dt * vc;
+                    A.sv[e] = s;
+                    F += alpha * s + beta * vc;
+                }
+                const float fo = A.first ? F : A.fv[e];
+                A.vs[e] = vc + dt * (1.5f * F - 0.5f * fo);
+                A.fv[e] = F;
+            }
+            if (k <= g.nz - 1) {
+                const float wc = W(i, j, k);
+                const float wm = W(i, j, k - 1), wp = W(i, j, k + 1);
+                const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j, k + 1)) * (wc - W(i - 1, j, k)) +
+                                           0.5f * (U(i, j, k) + U(i, j, k + 1)) * (W(i + 1, j, k) - wc)) * g.idx;
+                const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i, j - 1, k + 1)) * (wc - W(i, j - 1, k)) +
+                                           0.5f * (V(i, j, k) + V(i, j, k + 1)) * (W(i, j + 1, k) - wc)) * g.idy;
+                const float covz = 0.5f * (0.5f * (wm + wc) * (wc - wm) + 0.5f * (wc + wp) * (wp - wc)) * g.idz;
+                const float lap = (W(i + 1, j, k) - 2.f * wc + W(i - 1, j, k)) * g.cx +
+                                  (W(i, j + 1, k) - 2.f * wc + W(i, j - 1, k)) * g.cy + (wp - 2.f * wc + wm) * g.cz;
+                const float sgs = 2.f * (n13(i, j, k) * e13(i, j, k) - n13(i - 1, j, k) * e13(i - 1, j, k)) * g.idx +
+                                  2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j - 1, k) * e23(i, j - 1, k)) * g.idy +
+                                  2.f * (N(i, j, k + 1) * (wp - wc) * g.idz - N(i, j, k) * (wc - wm) * g.idz) * g.idz;
+                float F = -(covx + covy + covz) + nu * lap + sgs;
+                if (fl & F_WSOLID) {
+                    const float s = A.sw[e] + dt * wc;
+                    A.sw[e] = s;
+                    F += alpha * s + beta * wc;
+                }
+                const float fo = A.first ? F : A.fw[e];
+                A.ws[e] = wc + dt * (1.5f * F - 0.5f * fo);
+                A.fw[e] = F;
+            }
+        }
     }
 }
 
@@ -467,6 +695,246 @@ __device__ __forceinline__ void bc_body(const Geo& g, float* u, float* v, float*
     fill_ghost(g, w, 2, p1[0], p1[1], p1[2]);
 }
 
+// ============================================== stretched grids (bodies)
+// The same stages on a grid whose axes carry per-cell widths (the 1-D
+// spacing arrays dx1 / dy1 / dzn of section 2.5.3).  Every difference is
+// taken over the distance between the two values it spans: a cell width
+// (M_IH) between the two faces of a cell, a centre distance (M_IG) across
+// a face; a cell-centred quantity reaches a face of its own axis by the
+// width-weighted linear interpolation (M_LO, M_HI: the paper's covx1
+// weights), an edge by the plain mean of the two values around it (the
+// edge is their midpoint).  Uniform grids keep the scalar-spacing bodies
+// above; a uniform table reproduces them up to rounding.
+struct StrAxis {
+    const float* ih; const float* ig; const float* lo; const float* hi; const float* h23;
+};
+__device__ __forceinline__ StrAxis str_axis(const float* m, int n) {
+    const int L = n + 2;
+    return {m + M_IH * L, m + M_IG * L, m + M_LO * L, m + M_HI * L, m + M_H23 * L};
+}
+
+// Smagorinsky nu_t on a stretched grid: (Cs Delta)^2 |S| with the cell's
+// own filter width Delta = (hx hy hz)^(1/3), i.e. Cs^2 hx^(2/3) hy^(2/3)
+// hz^(2/3); strain components as in nut_body, each difference over its
+// own distance.  Ghost ring: the nearest interior cell's value.
+__device__ __forceinline__ void nut_body_str(const Geo& g, const float* __restrict__ u,
+                                             const float* __restrict__ v, const float* __restrict__ w,
+                                             float* __restrict__ nut, float cs2, unsigned lb) {
+    const long long nbox = (long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= nbox) return;
+    const unsigned pxy = (unsigned)(g.nx + 2) * (unsigned)(g.ny + 2);
+    const unsigned tt = (unsigned)t;
+    const int k = (int)(tt / pxy);
+    const unsigned r = tt - (unsigned)k * pxy;
+    const int j = (int)(r / (unsigned)(g.nx + 2));
+    const int i = (int)(r - (unsigned)j * (unsigned)(g.nx + 2));
+    const int ic = min(max(i, 1), g.nx), jc = min(max(j, 1), g.ny), kc = min(max(k, 1), g.nz);
+    const StrAxis X = str_axis(g.mx, g.nx), Y = str_axis(g.my, g.ny), Z = str_axis(g.mz, g.nz);
+    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
+    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
+    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
+    const float s11 = (U(ic, jc, kc) - U(ic - 1, jc, kc)) * X.ih[ic];
+    const float s22 = (V(ic, jc, kc) - V(ic, jc - 1, kc)) * Y.ih[jc];
+    const float s33 = (W(ic, jc, kc) - W(ic, jc, kc - 1)) * Z.ih[kc];
+    float s12 = 0.f, s13 = 0.f, s23 = 0.f;
+#pragma unroll
+    for (int da = -1; da <= 0; ++da)
+#pragma unroll
+        for (int db = -1; db <= 0; ++db) {
+            const int a = ic + da, b = jc + db;   // x-y edge (face a, face b)
+            s12 += (U(a, b + 1, kc) - U(a, b, kc)) * Y.ig[b] + (V(a + 1, b, kc) - V(a, b, kc)) * X.ig[a];
+            const int c = kc + db;                // x-z edge (face a, face c)
+            s13 += (U(a, jc, c + 1) - U(a, jc, c)) * Z.ig[c] + (W(a + 1, jc, c) - W(a, jc, c)) * X.ig[a];
+            const int b2 = jc + da;               // y-z edge (face b2, face c)
+            s23 += (V(ic, b2, c + 1) - V(ic, b2, c)) * Z.ig[c] + (W(ic, b2 + 1, c) - W(ic, b2, c)) * Y.ig[b2];
+        }
+    s12 *= 0.125f;
+    s13 *= 0.125f;
+    s23 *= 0.125f;
+    const float ss = 2.f * (s11 * s11 + s22 * s22 + s33 * s33) + 4.f * (s12 * s12 + s13 * s13 + s23 * s23);
+    const float c2 = cs2 * (X.h23[ic] * Y.h23[jc] * Z.h23[kc]);
+    nut[g.nat(i, j, k)] = c2 * sqrtf(ss);
+}
+
+// velfg + feedbf + adam on a stretched grid: for each face value, the
+// tendency is assembled on its own control volume (for u on face i: the
+// centre distance g_i across x, the cell widths across y and z).  cov
+// pieces along the component's own axis sit at the two neighbouring
+// centres and reach the face by the width-weighted interpolation (covx1 of
+// section 2.5.3); across it they sit on the two edges the face is the
+// midpoint of (plain mean); an advecting velocity is interpolated onto an
+// edge from its own two faces with the same width weights.  Diffusion and
+// the subgrid stress are differences of one-sided fluxes over the control
+// volume.  Feedback forcing and AB2 as in tendency_body.
+__device__ __forceinline__ void tendency_body_str(const Geo& g, const TendArgs& A, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= n) return;
+    int i, j, k;
+    cell_of(g, t, i, j, k);
+    const float* __restrict__ u = A.u;
+    const float* __restrict__ v = A.v;
+    const float* __restrict__ w = A.w;
+    const float* __restrict__ nut = A.nut;
+    const StrAxis X = str_axis(g.mx, g.nx), Y = str_axis(g.my, g.ny), Z = str_axis(g.mz, g.nz);
+    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
+    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
+    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
+    auto N = [&](int a, int b, int c) { return nut[g.nat(a, b, c)]; };
+    auto n12 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b + 1, c) + N(a + 1, b + 1, c)); };
+    auto n13 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b, c + 1) + N(a + 1, b, c + 1)); };
+    auto n23 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a, b + 1, c) + N(a, b, c + 1) + N(a, b + 1, c + 1)); };
+    auto e12 = [&](int a, int b, int c) { return 0.5f * ((U(a, b + 1, c) - U(a, b, c)) * Y.ig[b] + (V(a + 1, b, c) - V(a, b, c)) * X.ig[a]); };
+    auto e13 = [&](int a, int b, int c) { return 0.5f * ((U(a, b, c + 1) - U(a, b, c)) * Z.ig[c] + (W(a + 1, b, c) - W(a, b, c)) * X.ig[a]); };
+    auto e23 = [&](int a, int b, int c) { return 0.5f * ((V(a, b, c + 1) - V(a, b, c)) * Z.ig[c] + (W(a, b + 1, c) - W(a, b, c)) * Y.ig[b]); };
+
+    const long long e = g.nat(i, j, k);
+    const uint8_t fl = A.flags[e];
+    const float dt = g.dt;
+    const float nu = A.nu, alpha = A.alpha, beta = A.beta;
+
+    if (i <= g.u_last) {
+        const float lo = X.lo[i], hi = X.hi[i];
+        auto c1 = [&](int c) { return 0.5f * (U(c - 1, j, k) + U(c, j, k)) * (U(c, j, k) - U(c - 1, j, k)) * X.ih[c]; };
+        auto c2 = [&](int b) { return (lo * V(i, b, k) + hi * V(i + 1, b, k)) * (U(i, b + 1, k) - U(i, b, k)) * Y.ig[b]; };
+        auto c3 = [&](int c) { return (lo * W(i, j, c) + hi * W(i + 1, j, c)) * (U(i, j, c + 1) - U(i, j, c)) * Z.ig[c]; };
+        const float covx = lo * c1(i) + hi * c1(i + 1);
+        const float covy = 0.5f * (c2(j - 1) + c2(j));
+        const float covz = 0.5f * (c3(k - 1) + c3(k));
+        auto fx = [&](int c) { return (U(c, j, k) - U(c - 1, j, k)) * X.ih[c]; };
+        auto fy = [&](int b) { return (U(i, b + 1, k) - U(i, b, k)) * Y.ig[b]; };
+        auto fz = [&](int c) { return (U(i, j, c + 1) - U(i, j, c)) * Z.ig[c]; };
+        const float lap = (fx(i + 1) - fx(i)) * X.ig[i] + (fy(j) - fy(j - 1)) * Y.ih[j] + (fz(k) - fz(k - 1)) * Z.ih[k];
+        const float sgs = (2.f * N(i + 1, j, k) * fx(i + 1) - 2.f * N(i, j, k) * fx(i)) * X.ig[i] +
+                          (2.f * n12(i, j, k) * e12(i, j, k) - 2.f * n12(i, j - 1, k) * e12(i, j - 1, k)) * Y.ih[j] +
+                          (2.f * n13(i, j, k) * e13(i, j, k) - 2.f * n13(i, j, k - 1) * e13(i, j, k - 1)) * Z.ih[k];
+        const float uc = U(i, j, k);
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_USOLID) {
+            const float s = A.su[e] + dt * uc;
+            A.su[e] = s;
+            F += alpha * s + beta * uc;
+        }
+        const float fo = A.first ? F : A.fu[e];
+        A.us[e] = uc + dt * (1.5f * F - 0.5f * fo);
+        A.fu[e] = F;
+    }
+    if (j <= g.ny - 1) {
+        const float lo = Y.lo[j], hi = Y.hi[j];
+        auto c1 = [&](int a) { return (lo * U(a, j, k) + hi * U(a, j + 1, k)) * (V(a + 1, j, k) - V(a, j, k)) * X.ig[a]; };
+        auto c2 = [&](int b) { return 0.5f * (V(i, b - 1, k) + V(i, b, k)) * (V(i, b, k) - V(i, b - 1, k)) * Y.ih[b]; };
+        auto c3 = [&](int c) { return (lo * W(i, j, c) + hi * W(i, j + 1, c)) * (V(i, j, c + 1) - V(i, j, c)) * Z.ig[c]; };
+        const float covx = 0.5f * (c1(i - 1) + c1(i));
+        const float covy = lo * c2(j) + hi * c2(j + 1);
+        const float covz = 0.5f * (c3(k - 1) + c3(k));
+        auto fx = [&](int a) { return (V(a + 1, j, k) - V(a, j, k)) * X.ig[a]; };
+        auto fy = [&](int b) { return (V(i, b, k) - V(i, b - 1, k)) * Y.ih[b]; };
+        auto fz = [&](int c) { return (V(i, j, c + 1) - V(i, j, c)) * Z.ig[c]; };
+        const float lap = (fx(i) - fx(i - 1)) * X.ih[i] + (fy(j + 1) - fy(j)) * Y.ig[j] + (fz(k) - fz(k - 1)) * Z.ih[k];
+        const float sgs = (2.f * n12(i, j, k) * e12(i, j, k) - 2.f * n12(i - 1, j, k) * e12(i - 1, j, k)) * X.ih[i] +
+                          (2.f * N(i, j + 1, k) * fy(j + 1) - 2.f * N(i, j, k) * fy(j)) * Y.ig[j] +
+                          (2.f * n23(i, j, k) * e23(i, j, k) - 2.f * n23(i, j, k - 1) * e23(i, j, k - 1)) * Z.ih[k];
+        const float vc = V(i, j, k);
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_VSOLID) {
+            const float s = A.sv[e] + dt * vc;
+            A.sv[e] = s;
+            F += alpha * s + beta * vc;
+        }
+        const float fo = A.first ? F : A.fv[e];
+        A.vs[e] = vc + dt * (1.5f * F - 0.5f * fo);
+        A.fv[e] = F;
+    }
+    if (k <= g.nz - 1) {
+        const float lo = Z.lo[k], hi = Z.hi[k];
+        auto c1 = [&](int a) { return (lo * U(a, j, k) + hi * U(a, j, k + 1)) * (W(a + 1, j, k) - W(a, j, k)) * X.ig[a]; };
+        auto c2 = [&](int b) { return (lo * V(i, b, k) + hi * V(i, b, k + 1)) * (W(i, b + 1, k) - W(i, b, k)) * Y.ig[b]; };
+        auto c3 = [&](int c) { return 0.5f * (W(i, j, c - 1) + W(i, j, c)) * (W(i, j, c) - W(i, j, c - 1)) * Z.ih[c]; };
+        const float covx = 0.5f * (c1(i - 1) + c1(i));
+        const float covy = 0.5f * (c2(j - 1) + c2(j));
+        const float covz = lo * c3(k) + hi * c3(k + 1);
+        auto fx = [&](int a) { return (W(a + 1, j, k) - W(a, j, k)) * X.ig[a]; };
+        auto fy = [&](int b) { return (W(i, b + 1, k) - W(i, b, k)) * Y.ig[b]; };
+        auto fz = [&](int c) { return (W(i, j, c) - W(i, j, c - 1)) * Z.ih[c]; };
+        const float lap = (fx(i) - fx(i - 1)) * X.ih[i] + (fy(j) - fy(j - 1)) * Y.ih[j] + (fz(k + 1) - fz(k)) * Z.ig[k];
+        const float sgs = (2.f * n13(i, j, k) * e13(i, j, k) - 2.f * n13(i - 1, j, k) * e13(i - 1, j, k)) * X.ih[i] +
+                          (2.f * n23(i, j, k) * e23(i, j, k) - 2.f * n23(i, j - 1, k) * e23(i, j - 1, k)) * Y.ih[j] +
+                          (2.f * N(i, j, k + 1) * fz(k + 1) - 2.f * N(i, j, k) * fz(k)) * Z.ig[k];
+        const float wc = W(i, j, k);
+        float F = -(covx + covy + covz) + nu * lap + sgs;
+        if (fl & F_WSOLID) {
+            const float s = A.sw[e] + dt * wc;
+            A.sw[e] = s;
+            F += alpha * s + beta * wc;
+        }
+        const float fo = A.first ? F : A.fw[e];
+        A.ws[e] = wc + dt * (1.5f * F - 0.5f * fo);
+        A.fw[e] = F;
+    }
+}
+
+// rhs = div(u*) / dt on a stretched grid (face differences over the cell
+// widths); float64 partials of sum rhs^2.
+__device__ __forceinline__ void rhs_body_str(const Geo& g, const float* __restrict__ us,
+                                             const float* __restrict__ vs, const float* __restrict__ ws,
+                                             float* rhs0, float* rhs1, double* __restrict__ part,
+                                             unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    double acc = 0.0;
+    if (t < n) {
+        int i, j, k;
+        cell_of(g, t, i, j, k);
+        const float div = (us[g.nat(i, j, k)] - us[g.nat(i - 1, j, k)]) * mrow(g.mx, g.nx, M_IH, i) +
+                          (vs[g.nat(i, j, k)] - vs[g.nat(i, j - 1, k)]) * mrow(g.my, g.ny, M_IH, j) +
+                          (ws[g.nat(i, j, k)] - ws[g.nat(i, j, k - 1)]) * mrow(g.mz, g.nz, M_IH, k);
+        const float r = div * g.idt;
+        const int i0 = i - 1, j0 = j - 1, k0 = k - 1;
+        float* dst = ((i0 + j0 + k0) & 1) ? rhs1 : rhs0;
+        dst[g.col(i0 >> 1, j0, k0)] = r;
+        acc = (double)r * (double)r;
+    }
+    const double bs = block_sum(acc);
+    if (threadIdx.x == 0) part[lb] = bs;
+}
+
+// velnw on a stretched grid: u = u* - dt (p_{c+1} - p_c) / g_c across an
+// interior face; on the outflow face p = 0 half a cell from the centre.
+__device__ __forceinline__ void project_body_str(const Geo& g, float* __restrict__ us,
+                                                 float* __restrict__ vs, float* __restrict__ ws,
+                                                 const PBufs& P, unsigned lb) {
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long t = (long long)lb * kBlock + threadIdx.x;
+    if (t >= n) return;
+    int i, j, k;
+    cell_of(g, t, i, j, k);
+    const int i0 = i - 1, j0 = j - 1, k0 = k - 1;
+    const int c = (i0 + j0 + k0) & 1;
+    const float* __restrict__ phc = P.ph[c];
+    const float* __restrict__ pdc = P.pd[c];
+    const float* __restrict__ pho = P.ph[1 - c];
+    const float* __restrict__ pdo = P.pd[1 - c];
+    const long long ec = g.col(i0 >> 1, j0, k0);
+    const float hc = phc[ec], dc = pdc[ec];
+    const float dt = g.dt;
+    const long long e = g.nat(i, j, k);
+    if (i0 + 1 < g.nx) {
+        const long long en = g.col((i0 + 1) >> 1, j0, k0);
+        us[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * mrow(g.mx, g.nx, M_IG, i));
+    } else if (g.outflow) {
+        us[e] -= dt * ((-2.f * hc - 2.f * dc) * mrow(g.mx, g.nx, M_IH, i));
+    }
+    if (j0 + 1 < g.ny) {
+        const long long en = ec + g.S;
+        vs[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * mrow(g.my, g.ny, M_IG, j));
+    }
+    if (k0 + 1 < g.nz) {
+        const long long en = ec + g.SP;
+        ws[e] -= dt * (((pho[en] - hc) + (pdo[en] - dc)) * mrow(g.mz, g.nz, M_IG, k));
+    }
+}
+
 // --------------------------------------------------- diagnostics (norms)
 // Partials [sum div(u)^2, max CFL]: CFL = dt (|u|/dx + |v|/dy + |w|/dz) with
 // cell-centred speeds; float64.
@@ -482,10 +950,14 @@ __device__ __forceinline__ void diag_body(const Geo& g, const float* __restrict_
         const float u1 = u[g.nat(i, j, k)], u0 = u[g.nat(i - 1, j, k)];
         const float v1 = v[g.nat(i, j, k)], v0 = v[g.nat(i, j - 1, k)];
         const float w1 = w[g.nat(i, j, k)], w0 = w[g.nat(i, j, k - 1)];
-        const double div = ((double)u1 - u0) / g.dx + ((double)v1 - v0) / g.dy + ((double)w1 - w0) / g.dz;
+        // cell widths (the cell's own on a stretched grid)
+        const double hx = g.stretched ? (double)mrow(g.mx, g.nx, M_H, i) : (double)g.dx;
+        const double hy = g.stretched ? (double)mrow(g.my, g.ny, M_H, j) : (double)g.dy;
+        const double hz = g.stretched ? (double)mrow(g.mz, g.nz, M_H, k) : (double)g.dz;
+        const double div = ((double)u1 - u0) / hx + ((double)v1 - v0) / hy + ((double)w1 - w0) / hz;
         d2 = div * div;
-        cf = (double)g.dt * (0.5 * fabs((double)u1 + u0) / g.dx + 0.5 * fabs((double)v1 + v0) / g.dy +
-                             0.5 * fabs((double)w1 + w0) / g.dz);
+        cf = (double)g.dt * (0.5 * fabs((double)u1 + u0) / hx + 0.5 * fabs((double)v1 + v0) / hy +
+                             0.5 * fabs((double)w1 + w0) / hz);
     }
     const double s = block_sum(d2);
     const double mx = block_max(cf);
@@ -526,6 +998,21 @@ __device__ __forceinline__ float sor_point(float west, float east, float ps, flo
     return p + reltmp;
 }
 
+// The same update on a stretched grid: every neighbour has its own weight
+// (the per-axis 1-D coefficients of section 2.6), the diagonal is the sum
+// of the cell's per-axis shares.  Used by every sweep kernel of a
+// stretched grid, so those round alike among themselves.
+__device__ __forceinline__ float sor_point_w(float west, float east, float ps, float pn, float pb,
+                                             float pt, float ww, float we, float ws, float wn,
+                                             float wb, float wt, float diag, float r, float p,
+                                             float omega, float& reltmp) {
+#pragma clang fp contract(off)
+    const float nb = fmaf(wt, pt, fmaf(wb, pb, fmaf(wn, pn, fmaf(ws, ps, fmaf(we, east, ww * west)))));
+    const float inv = 1.0f / diag;
+    reltmp = omega * fmaf(inv, nb - r, -p);
+    return p + reltmp;
+}
+
 // ---------------------------------------------------------- half-sweep
 // Colour c: for every cell of colour c,
 //   reltmp = omega (cn1 (sum_nb cn_nb p_nb - rhs) - p);  p += reltmp
@@ -544,7 +1031,7 @@ __device__ __forceinline__ float sor_point(float west, float east, float ps, flo
 // of plane k+2); east/west neighbours come from the adjacent lanes by
 // cross-lane shuffles, north/south ones from the cache.  Within a row the
 // cell parity is uniform.
-template <int TX, int KT>
+template <int TX, int KT, bool STR = false>
 __device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict__ pself,
                                          const float* __restrict__ poth,
                                          const float* __restrict__ rself, float omega, bool acc,
@@ -565,7 +1052,12 @@ __device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict_
     const int k_end = min(g.nz, k_begin + KT);
     const bool col_ok = ii < g.H && j0 < g.ny;
     const float cx = g.cx, cy = g.cy, cz = g.cz;
-    const float dyy = diag_y(g, j0);
+    // stretched grid: the row's y weights and diagonal share (clamped row
+    // index for lanes outside the grid, which update nothing)
+    const int jm = min(j0, g.ny - 1);
+    const float dyy = STR ? mrow(g.my, g.ny, M_DD, jm + 1) : diag_y(g, j0);
+    const float wsy = STR ? mrow(g.my, g.ny, M_WM, jm + 1) : 0.f;
+    const float wny = STR ? mrow(g.my, g.ny, M_WP, jm + 1) : 0.f;
     long long e = col_ok ? g.col(ii, j0, k_begin) : 0;
     float pb = col_ok ? poth[e - g.SP] : 0.f;
     float pc = col_ok ? poth[e] : 0.f;
@@ -584,10 +1076,18 @@ __device__ __forceinline__ void sor_body(const Geo& g, int c, float* __restrict_
             const float west = s ? pc : pw;
             const float east = s ? pe : pc;
             const float ps = poth[e - g.S], pn = poth[e + g.S];
-            const float diag = diag_x(g, i0) + dyy + diag_z(g, k0);
-            float reltmp;
-            pself[e] = sor_point(west, east, ps, pn, pb, pt, cx, cy, cz, diag, rself[e], pself[e],
-                                 omega, reltmp);
+            float reltmp, diag;
+            if constexpr (STR) {
+                diag = mrow(g.mx, g.nx, M_DD, i0 + 1) + dyy + mrow(g.mz, g.nz, M_DD, k0 + 1);
+                pself[e] = sor_point_w(west, east, ps, pn, pb, pt, mrow(g.mx, g.nx, M_WM, i0 + 1),
+                                       mrow(g.mx, g.nx, M_WP, i0 + 1), wsy, wny,
+                                       mrow(g.mz, g.nz, M_WM, k0 + 1), mrow(g.mz, g.nz, M_WP, k0 + 1),
+                                       diag, rself[e], pself[e], omega, reltmp);
+            } else {
+                diag = diag_x(g, i0) + dyy + diag_z(g, k0);
+                pself[e] = sor_point(west, east, ps, pn, pb, pt, cx, cy, cz, diag, rself[e], pself[e],
+                                     omega, reltmp);
+            }
             if (acc) {
                 const double rt = (double)reltmp;
                 r2 += rt * rt;
@@ -636,7 +1136,7 @@ __device__ __forceinline__ bool sweep_active(const Ctl* ctl, int it, bool& acc) 
 // Loads of plane q+1 are issued a step ahead.  With copy set (an
 // iteration past max_iter inside the last check interval) the block copies
 // a to b, so the result stays in the buffer the interval ends on.
-template <int TX, int NW, int KT>
+template <int TX, int NW, int KT, bool STR = false>
 __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restrict__ a0,
                                             const float* __restrict__ a1,
                                             const float* __restrict__ r0c,
@@ -668,7 +1168,10 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
     const bool edge_lane = tx == 0 || tx == TX - 1;
     const int edge_off = tx == 0 ? -1 : 1;
     const float cx = g.cx, cy = g.cy, cz = g.cz;
-    const float dyy = diag_y(g, j);
+    const int jm = min(max(j, 0), g.ny - 1);   // clamped for the stretched tables
+    const float dyy = STR ? mrow(g.my, g.ny, M_DD, jm + 1) : diag_y(g, j);
+    const float wsy = STR ? mrow(g.my, g.ny, M_WM, jm + 1) : 0.f;
+    const float wny = STR ? mrow(g.my, g.ny, M_WP, jm + 1) : 0.f;
     const int qa = k_begin - 1;
     const long long e0 = col_ok ? g.col(ii, j, qa) : 0;
     // loads of step q: a1 one plane up, a1 in the rows below and above, the
@@ -704,11 +1207,20 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
         const int i0 = 2 * ii + s;
         float rq = 0.f;
         if (col_ok && q >= 0 && q < g.nz && i0 < g.nx) {
-            const float diag = diag_x(g, i0) + dyy + diag_z(g, q);
             float rt = 0.f;
-            rq = copy ? cur.p0
-                      : sor_point(s ? bc : bw, s ? be : bc, cur.south, cur.north, bm, cur.up, cx, cy,
-                                  cz, diag, cur.rr0, cur.p0, omega, rt);
+            if constexpr (STR) {
+                const float diag = mrow(g.mx, g.nx, M_DD, i0 + 1) + dyy + mrow(g.mz, g.nz, M_DD, q + 1);
+                rq = copy ? cur.p0
+                          : sor_point_w(s ? bc : bw, s ? be : bc, cur.south, cur.north, bm, cur.up,
+                                        mrow(g.mx, g.nx, M_WM, i0 + 1), mrow(g.mx, g.nx, M_WP, i0 + 1),
+                                        wsy, wny, mrow(g.mz, g.nz, M_WM, q + 1),
+                                        mrow(g.mz, g.nz, M_WP, q + 1), diag, cur.rr0, cur.p0, omega, rt);
+            } else {
+                const float diag = diag_x(g, i0) + dyy + diag_z(g, q);
+                rq = copy ? cur.p0
+                          : sor_point(s ? bc : bw, s ? be : bc, cur.south, cur.north, bm, cur.up, cx, cy,
+                                      cz, diag, cur.rr0, cur.p0, omega, rt);
+            }
             if (inner && q >= k_begin && q < k_end) {
                 b0[e] = rq;
                 if (acc) r2a += (double)rt * (double)rt;
@@ -725,12 +1237,22 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
             const int sb = (1 + j + qb) & 1;
             const int i1 = 2 * ii + sb;
             if (inner && i1 < g.nx) {
-                const float diag = diag_x(g, i1) + dyy + diag_z(g, qb);
-                float rt = 0.f;
-                const float v = copy ? bm
-                                     : sor_point(sb ? rm1 : rw, sb ? re : rm1, ring[sl][row - 1][tx],
-                                                 ring[sl][row + 1][tx], rm2, rq, cx, cy, cz, diag,
-                                                 cur.rr1, bm, omega, rt);
+                float rt = 0.f, diag, v;
+                if constexpr (STR) {
+                    diag = mrow(g.mx, g.nx, M_DD, i1 + 1) + dyy + mrow(g.mz, g.nz, M_DD, qb + 1);
+                    v = copy ? bm
+                             : sor_point_w(sb ? rm1 : rw, sb ? re : rm1, ring[sl][row - 1][tx],
+                                           ring[sl][row + 1][tx], rm2, rq, mrow(g.mx, g.nx, M_WM, i1 + 1),
+                                           mrow(g.mx, g.nx, M_WP, i1 + 1), wsy, wny,
+                                           mrow(g.mz, g.nz, M_WM, qb + 1), mrow(g.mz, g.nz, M_WP, qb + 1),
+                                           diag, cur.rr1, bm, omega, rt);
+                } else {
+                    diag = diag_x(g, i1) + dyy + diag_z(g, qb);
+                    v = copy ? bm
+                             : sor_point(sb ? rm1 : rw, sb ? re : rm1, ring[sl][row - 1][tx],
+                                         ring[sl][row + 1][tx], rm2, rq, cx, cy, cz, diag,
+                                         cur.rr1, bm, omega, rt);
+                }
                 b1[e - g.SP] = v;
                 if (acc) {
                     const double rd = (double)rt;
@@ -770,6 +1292,275 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
     }
 }
 
+// ------------------------------------- two fused red-black iterations
+// Two whole SOR iterations in one pass (temporal blocking): the four
+// colour updates A (colour 0, iteration 1), B (colour 1, iteration 1),
+// C (colour 0, iteration 2) and D (colour 1, iteration 2) run in one k-march,
+// each one plane behind the previous: at step q, A on plane q, B on q-1,
+// C on q-2, D on q-3.  Reads come from the old arrays (a0, a1, r0, r1),
+// iteration 1 lives only in registers and LDS, and C and D go to the other
+// buffer pair (b0, b1): 12 bytes per cell for two iterations instead of
+// 24.  Each stage needs its predecessor on the cell's six neighbours, so a
+// block recomputes a ring that shrinks by one cell per stage: of its 64
+// lanes x 32 rows x (kt + 6) planes it writes the 58 x 26 x kt centre.
+// The per-cell arithmetic is that of the half-sweeps (sor_point /
+// sor_point_w), so the result equals four half-sweeps bit for bit.
+//
+// A block is 16 wavefronts of 64 lanes; each thread owns rows w and w + 16
+// of its lane.  Own-column neighbours along k come from registers, east /
+// west from cross-lane shuffles (edge lanes of stage A load theirs), north /
+// south from LDS rows of the stage before (two planes per stage ring: the
+// slot written at step q was last read at step q - 1, a barrier earlier).
+// With `second` false (the interval's iteration budget ends after the first
+// iteration) C and D copy the iteration-1 values; with `first` false too
+// the block copies a to b.  acc1 / acc2: leave the float64 partials of the
+// first / second iteration (the one that ends the check interval), as the
+// single-iteration kernel does.
+template <bool STR>
+__device__ __forceinline__ float rb_relax(const Geo& g, int i0, int j, int k, float west, float east,
+                                          float ps, float pn, float pb, float pt, float r, float p,
+                                          float omega, float& rt) {
+    if constexpr (STR) {
+        const float diag = mrow(g.mx, g.nx, M_DD, i0 + 1) + mrow(g.my, g.ny, M_DD, j + 1) +
+                           mrow(g.mz, g.nz, M_DD, k + 1);
+        return sor_point_w(west, east, ps, pn, pb, pt, mrow(g.mx, g.nx, M_WM, i0 + 1),
+                           mrow(g.mx, g.nx, M_WP, i0 + 1), mrow(g.my, g.ny, M_WM, j + 1),
+                           mrow(g.my, g.ny, M_WP, j + 1), mrow(g.mz, g.nz, M_WM, k + 1),
+                           mrow(g.mz, g.nz, M_WP, k + 1), diag, r, p, omega, rt);
+    } else {
+        const float diag = diag_x(g, i0) + diag_y(g, j) + diag_z(g, k);
+        return sor_point(west, east, ps, pn, pb, pt, g.cx, g.cy, g.cz, diag, r, p, omega, rt);
+    }
+}
+template <bool STR>
+__device__ __forceinline__ float rb_diag(const Geo& g, int i0, int j, int k) {
+    if constexpr (STR)
+        return mrow(g.mx, g.nx, M_DD, i0 + 1) + mrow(g.my, g.ny, M_DD, j + 1) + mrow(g.mz, g.nz, M_DD, k + 1);
+    else
+        return diag_x(g, i0) + diag_y(g, j) + diag_z(g, k);
+}
+
+template <bool STR>
+__device__ __forceinline__ void sor_rb2_body(const Geo& g, const float* __restrict__ a0,
+                                             const float* __restrict__ a1,
+                                             const float* __restrict__ r0c,
+                                             const float* __restrict__ r1c, float* __restrict__ b0,
+                                             float* __restrict__ b1, float omega, bool first,
+                                             bool second, bool acc1, bool acc2,
+                                             double* __restrict__ rel0, double* __restrict__ rel1,
+                                             unsigned lb, int kt) {
+    const bool acc = acc1 || acc2;   // partials of the iteration that ends the check interval
+    constexpr int R = kRb2RowsPerThread;
+    __shared__ float ringA[2][kRb2Rows][64];
+    __shared__ float ringB[2][kRb2Rows][64];
+    __shared__ float ringC[2][kRb2Rows][64];
+    __shared__ double red3[3][16];
+    const unsigned nbx = (unsigned)(g.H + kRb2TXO - 1) / kRb2TXO;
+    const unsigned nby = (unsigned)(g.ny + kRb2TYO - 1) / kRb2TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int ii = (int)bx * kRb2TXO - 3 + lane;
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
+    const bool lane_ok = ii >= 0 && ii < g.H;
+    const bool out_lane = lane >= 3 && lane <= 60;
+    const bool edge_lane = lane == 0 || lane == 63;
+    const int edge_off = lane == 0 ? -1 : 1;
+    int row[R], j[R];
+    bool col_ok[R], out_ok[R];
+    long long e0[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        row[t] = wv + 16 * t;
+        j[t] = (int)by * kRb2TYO - 3 + row[t];
+        col_ok[t] = lane_ok && j[t] >= 0 && j[t] < g.ny;
+        out_ok[t] = col_ok[t] && out_lane && row[t] >= 3 && row[t] <= 28;
+        e0[t] = col_ok[t] ? g.col(ii, j[t], k_begin - 3) : 0;
+    }
+    // per-row register pipelines (planes relative to the step q)
+    float bm[R], bc[R];                       // old colour 1 at q-1, q
+    float aQ[R], aM1[R], aM2[R];              // A at q, q-1, q-2
+    float bQ1[R], bQ2[R], bQ3[R];             // B at q-1, q-2, q-3
+    float cQ2[R], cQ3[R], cQ4[R];             // C at q-2, q-3, q-4
+    float r0q[R], r0m1[R], r0m2[R];           // r0 colour 0 at q, q-1, q-2
+    float r1m1[R], r1m2[R], r1m3[R];          // r0 colour 1 at q-1, q-2, q-3
+    struct Ld { float up, south, north, edge, p0, rr0, rr1; };
+    Ld cur[R], nxt[R], nxt2[R];   // loads of steps q, q+1, q+2 (issued two steps ahead)
+    const int q0 = k_begin - 3;
+    auto fetch = [&](int q, Ld* f) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const long long e = e0[t] + (long long)(q - q0) * g.SP;
+            const bool pl = col_ok[t] && q >= 0 && q < g.nz;
+            f[t].up = (col_ok[t] && q + 1 >= 0 && q + 1 <= g.nz) ? a1[e + g.SP] : 0.f;
+            f[t].south = pl ? a1[e - g.S] : 0.f;
+            f[t].north = pl ? a1[e + g.S] : 0.f;
+            f[t].edge = (pl && edge_lane) ? a1[e + edge_off] : 0.f;
+            f[t].p0 = pl ? a0[e] : 0.f;
+            f[t].rr0 = pl ? r0c[e] : 0.f;
+            f[t].rr1 = (col_ok[t] && q - 1 >= 0 && q - 1 < g.nz) ? r1c[e - g.SP] : 0.f;
+        }
+    };
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const bool okm = col_ok[t] && q0 - 1 >= -1;
+        bm[t] = okm ? a1[e0[t] - g.SP] : 0.f;
+        bc[t] = col_ok[t] && q0 >= -1 ? a1[e0[t]] : 0.f;
+        aQ[t] = aM1[t] = aM2[t] = 0.f;
+        bQ1[t] = bQ2[t] = bQ3[t] = 0.f;
+        cQ2[t] = cQ3[t] = cQ4[t] = 0.f;
+        r0q[t] = r0m1[t] = r0m2[t] = 0.f;
+        r1m1[t] = r1m2[t] = r1m3[t] = 0.f;
+    }
+    double sC = 0.0, sD = 0.0, dD = 0.0;
+    fetch(q0, cur);
+    fetch(q0 + 1, nxt);
+    for (int q = q0; q <= k_end + 2; ++q) {
+        if (q + 2 <= k_end + 2) fetch(q + 2, nxt2);
+        // ---- A: colour 0, iteration 1, plane q (old colour 1 around it)
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float be = __shfl_down(bc[t], 1, 64);
+            float bw = __shfl_up(bc[t], 1, 64);
+            if (lane == 63) be = cur[t].edge;
+            if (lane == 0) bw = cur[t].edge;
+            const int s = (j[t] + q) & 1;
+            const int i0 = 2 * ii + s;
+            float v = 0.f;
+            if (col_ok[t] && q >= 0 && q < g.nz && i0 < g.nx) {
+                float rt = 0.f;
+                v = first ? rb_relax<STR>(g, i0, j[t], q, s ? bc[t] : bw, s ? be : bc[t], cur[t].south,
+                                          cur[t].north, bm[t], cur[t].up, cur[t].rr0, cur[t].p0, omega, rt)
+                          : cur[t].p0;
+                if (acc1 && out_ok[t] && q >= k_begin && q < k_end) sC += (double)rt * (double)rt;
+            }
+            aM2[t] = aM1[t];
+            aM1[t] = aQ[t];
+            aQ[t] = v;
+            r0m2[t] = r0m1[t];
+            r0m1[t] = r0q[t];
+            r0q[t] = cur[t].rr0;
+            ringA[q & 1][row[t]][lane] = v;
+        }
+        __syncthreads();
+        // ---- B: colour 1, iteration 1, plane q-1 (A around it)
+        const int qb = q - 1;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const float ae = __shfl_down(aM1[t], 1, 64);
+            const float aw = __shfl_up(aM1[t], 1, 64);
+            const int s = (1 + j[t] + qb) & 1;
+            const int i1 = 2 * ii + s;
+            float v = 0.f, rtb = 0.f;
+            const float old1 = bm[t];   // old colour 1 at q-1
+            if (col_ok[t] && qb >= 0 && qb < g.nz && i1 < g.nx) {
+                const float sn = row[t] > 0 ? ringA[qb & 1][row[t] - 1][lane] : 0.f;
+                const float nn = row[t] < kRb2Rows - 1 ? ringA[qb & 1][row[t] + 1][lane] : 0.f;
+                v = first ? rb_relax<STR>(g, i1, j[t], qb, s ? aM1[t] : aw, s ? ae : aM1[t], sn, nn, aM2[t],
+                                          aQ[t], cur[t].rr1, old1, omega, rtb)
+                          : old1;
+            }
+            bQ3[t] = bQ2[t];
+            bQ2[t] = bQ1[t];
+            bQ1[t] = v;
+            r1m3[t] = r1m2[t];
+            r1m2[t] = r1m1[t];
+            r1m1[t] = cur[t].rr1;
+            if (acc1 && out_ok[t] && qb >= k_begin && qb < k_end && i1 < g.nx) {
+                sD += (double)rtb * (double)rtb;
+                const double dd = (double)rb_diag<STR>(g, i1, j[t], qb) * (double)rtb;
+                dD += dd * dd;
+            }
+            ringB[qb & 1][row[t]][lane] = v;
+        }
+        __syncthreads();
+        // ---- C: colour 0, iteration 2, plane q-2 (B around it)
+        const int qc = q - 2;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const float be2 = __shfl_down(bQ2[t], 1, 64);
+            const float bw2 = __shfl_up(bQ2[t], 1, 64);
+            const int s = (j[t] + qc) & 1;
+            const int i0 = 2 * ii + s;
+            float v = 0.f;
+            if (col_ok[t] && qc >= 0 && qc < g.nz && i0 < g.nx) {
+                const float sn = row[t] > 0 ? ringB[qc & 1][row[t] - 1][lane] : 0.f;
+                const float nn = row[t] < kRb2Rows - 1 ? ringB[qc & 1][row[t] + 1][lane] : 0.f;
+                float rt = 0.f;
+                v = second ? rb_relax<STR>(g, i0, j[t], qc, s ? bQ2[t] : bw2, s ? be2 : bQ2[t], sn, nn,
+                                           bQ3[t], bQ1[t], r0m2[t], aM2[t], omega, rt)
+                           : aM2[t];
+                if (out_ok[t] && qc >= k_begin && qc < k_end) {
+                    b0[e0[t] + (long long)(qc - q0) * g.SP] = v;
+                    if (acc2) sC += (double)rt * (double)rt;
+                }
+            }
+            cQ4[t] = cQ3[t];
+            cQ3[t] = cQ2[t];
+            cQ2[t] = v;
+            ringC[qc & 1][row[t]][lane] = v;
+        }
+        __syncthreads();
+        // ---- D: colour 1, iteration 2, plane q-3 (C around it)
+        const int qd = q - 3;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const float ce = __shfl_down(cQ3[t], 1, 64);
+            const float cw = __shfl_up(cQ3[t], 1, 64);
+            const int s = (1 + j[t] + qd) & 1;
+            const int i1 = 2 * ii + s;
+            if (out_ok[t] && qd >= k_begin && qd < k_end && i1 < g.nx) {
+                const float sn = ringC[qd & 1][row[t] - 1][lane];
+                const float nn = ringC[qd & 1][row[t] + 1][lane];
+                float rt = 0.f;
+                const float v = second ? rb_relax<STR>(g, i1, j[t], qd, s ? cQ3[t] : cw, s ? ce : cQ3[t], sn, nn,
+                                                       cQ4[t], cQ2[t], r1m3[t], bQ3[t], omega, rt)
+                                       : bQ3[t];
+                b1[e0[t] + (long long)(qd - q0) * g.SP] = v;
+                if (acc2) {
+                    const double rd = (double)rt;
+                    sD += rd * rd;
+                    const double dd = (double)rb_diag<STR>(g, i1, j[t], qd) * rd;
+                    dD += dd * dd;
+                }
+            }
+        }
+        // advance the old colour 1 and the loads
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            bm[t] = bc[t];
+            bc[t] = cur[t].up;
+            cur[t] = nxt[t];
+            nxt[t] = nxt2[t];
+        }
+    }
+    if (acc) {
+        const double va = wave_sum(sC), vb = wave_sum(sD), vd = wave_sum(dD);
+        if (lane == 0) {
+            red3[0][wv] = va;
+            red3[1][wv] = vb;
+            red3[2][wv] = vd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0, td = 0.0;
+            for (int w = 0; w < 16; ++w) {
+                ta += red3[0][w];
+                tb += red3[1][w];
+                td += red3[2][w];
+            }
+            rel0[2 * lb] = ta;
+            rel0[2 * lb + 1] = 0.0;
+            rel1[2 * lb] = tb;
+            rel1[2 * lb + 1] = td;
+        }
+    }
+}
+
 // ------------------------------------------------------------- fold
 // ph <- fl(ph + pd), pd <- exact remainder (Knuth's TwoSum), pointwise over
 // the whole colour arrays (padding stays 0 + 0 = 0).
@@ -788,19 +1579,52 @@ __device__ __forceinline__ void fold_body(long long n, float* __restrict__ ph0,
     pd[e] = err;
 }
 
-// (A x) at a cell in float64 from the float32 colour arrays x_own/x_oth.
+// The float64 operator of the residual, rebase and check: the diagonal
+// at 0-based cell (i0, j0, k0), and (A x) there from the float32 colour
+// arrays x_own / x_oth.  Uniform grids: 1/h^2 in float64; stretched grids:
+// the float64 weight tables.  (The sweeps use the float32 weights; with
+// the residual in float64 the fold-and-rebase cycle refines towards the
+// float64 operator's solution, so rounding of the weights -- exact for
+// power-of-two spacings, not otherwise -- does not bias the result.)
+__device__ __forceinline__ double wrow(const double* __restrict__ m, int n, int row, int c) {
+    return m[row * (n + 2) + c];
+}
+template <bool STR = false>
+__device__ __forceinline__ double diag64(const Geo& g, int i0, int j0, int k0) {
+    if constexpr (STR) {
+        return wrow(g.wx, g.nx, 2, i0 + 1) + wrow(g.wy, g.ny, 2, j0 + 1) + wrow(g.wz, g.nz, 2, k0 + 1);
+    } else {
+        const double dx = (i0 > 0 ? g.cxd : 0.0) + (i0 < g.nx - 1 ? g.cxd : (g.outflow ? 2.0 * g.cxd : 0.0));
+        const double dy = (j0 > 0 ? g.cyd : 0.0) + (j0 < g.ny - 1 ? g.cyd : 0.0);
+        const double dz = (k0 > 0 ? g.czd : 0.0) + (k0 < g.nz - 1 ? g.czd : 0.0);
+        return dx + dy + dz;
+    }
+}
+template <bool STR = false>
 __device__ __forceinline__ double apply_A64(const Geo& g, const float* xo, const float* xn,
-                                            long long e, int s, double d) {
-    const double nb = (double)g.cx * ((double)xn[e - 1 + s] + (double)xn[e + s]) +
-                      (double)g.cy * ((double)xn[e - g.S] + (double)xn[e + g.S]) +
-                      (double)g.cz * ((double)xn[e - g.SP] + (double)xn[e + g.SP]);
-    return nb - d * (double)xo[e];
+                                            long long e, int s, double d, int i0 = 0, int j0 = 0,
+                                            int k0 = 0) {
+    if constexpr (STR) {
+        const double nb = wrow(g.wx, g.nx, 0, i0 + 1) * (double)xn[e - 1 + s] +
+                          wrow(g.wx, g.nx, 1, i0 + 1) * (double)xn[e + s] +
+                          wrow(g.wy, g.ny, 0, j0 + 1) * (double)xn[e - g.S] +
+                          wrow(g.wy, g.ny, 1, j0 + 1) * (double)xn[e + g.S] +
+                          wrow(g.wz, g.nz, 0, k0 + 1) * (double)xn[e - g.SP] +
+                          wrow(g.wz, g.nz, 1, k0 + 1) * (double)xn[e + g.SP];
+        return nb - d * (double)xo[e];
+    } else {
+        const double nb = g.cxd * ((double)xn[e - 1 + s] + (double)xn[e + s]) +
+                          g.cyd * ((double)xn[e - g.S] + (double)xn[e + g.S]) +
+                          g.czd * ((double)xn[e - g.SP] + (double)xn[e + g.SP]);
+        return nb - d * (double)xo[e];
+    }
 }
 
 // ------------------------------------------------------------ rebase
 // After a fold: r0 = rhs - A ph in float64, stored in float32, and partials
 // of the float64 residual of the iterate, rhs - A (ph + pd).  Each thread
 // handles the two cells (one per colour) of its half-cells.
+template <bool STR = false>
 __device__ __forceinline__ void rebase_body(const Geo& g, const PBufs& P, double* __restrict__ part,
                                             unsigned lb, unsigned nb) {
     long long t0, t1;
@@ -815,10 +1639,11 @@ __device__ __forceinline__ void rebase_body(const Geo& g, const PBufs& P, double
             const int s = (c + j0 + k0) & 1;
             const int i0 = 2 * ii + s;
             if (i0 < g.nx) {
-                const double d = (double)diag_of(g, i0, j0, k0);
-                const double rb = (double)P.rhs[c][e] - apply_A64(g, P.ph[c], P.ph[1 - c], e, s, d);
+                const double d = diag64<STR>(g, i0, j0, k0);
+                const double rb =
+                    (double)P.rhs[c][e] - apply_A64<STR>(g, P.ph[c], P.ph[1 - c], e, s, d, i0, j0, k0);
                 P.r0[c][e] = (float)rb;
-                const double rt = rb - apply_A64(g, P.pd[c], P.pd[1 - c], e, s, d);
+                const double rt = rb - apply_A64<STR>(g, P.pd[c], P.pd[1 - c], e, s, d, i0, j0, k0);
                 acc += rt * rt;
             }
         }
@@ -830,6 +1655,7 @@ __device__ __forceinline__ void rebase_body(const Geo& g, const PBufs& P, double
 // ------------------------------------------------------------- check
 // Partials of the residual of the iterate from the correction:
 // r = r0 - A pd (float64).
+template <bool STR = false>
 __device__ __forceinline__ void check_body(const Geo& g, const PBufs& P, double* __restrict__ part,
                                            unsigned lb, unsigned nb) {
     long long t0, t1;
@@ -844,8 +1670,9 @@ __device__ __forceinline__ void check_body(const Geo& g, const PBufs& P, double*
             const int s = (c + j0 + k0) & 1;
             const int i0 = 2 * ii + s;
             if (i0 < g.nx) {
-                const double d = (double)diag_of(g, i0, j0, k0);
-                const double rt = (double)P.r0[c][e] - apply_A64(g, P.pd[c], P.pd[1 - c], e, s, d);
+                const double d = diag64<STR>(g, i0, j0, k0);
+                const double rt =
+                    (double)P.r0[c][e] - apply_A64<STR>(g, P.pd[c], P.pd[1 - c], e, s, d, i0, j0, k0);
                 acc += rt * rt;
             }
         }

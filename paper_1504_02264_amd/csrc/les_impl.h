@@ -52,6 +52,24 @@ struct Geo {
     int inflow;         // x- is INFLOW
     int u_last;         // last u-face index whose tendency is computed
     float s_xm, s_xp, s_ym, s_yp, s_zm, s_zp;  // tangential ghost signs
+    // Stretched axes (the paper's 1-D spacing arrays, section 2.5.3):
+    // stretched != 0 selects the kernels that read the per-axis metric
+    // tables mx, my, mz (device memory, kMetricRows rows of n+2 floats per
+    // axis, indexed by the 1-based cell or face index; see MetricRow).
+    // Uniform grids keep stretched = 0 and the scalar spacings above.
+    int stretched;
+    const float* mx;
+    const float* my;
+    const float* mz;
+    // The pressure operator in float64 for the residual, rebase and check
+    // (the sweeps use the float32 weights): uniform 1/h^2, or per axis of a
+    // stretched grid three rows of n + 2 doubles (M_WM, M_WP, M_DD order:
+    // rows 0, 1, 2), so the iteration refines towards the float64
+    // operator's solution however the float32 weights round.
+    double cxd, cyd, czd;
+    const double* wx;
+    const double* wy;
+    const double* wz;
 
     __host__ __device__ long long nat(int i, int j, int k) const {
         return (long long)k * sxy + (long long)j * sx + i;
@@ -61,6 +79,23 @@ struct Geo {
         return (long long)S + ((long long)(k0 + 1) * (ny + 2) + (j0 + 1)) * S + ii;
     }
 };
+
+// Rows of a per-axis metric table (float32, computed in float64 on the host
+// and rounded once), each n+2 entries indexed by the 1-based cell index c
+// (cells 1..n, ghosts 0 and n+1 mirror their neighbour's width) or by the
+// face index f (face f between cells f and f+1):
+//   M_IH   1 / h[c]                    (cell width h)
+//   M_IG   1 / g[f], g[f] = (h[f] + h[f+1]) / 2   (centre distance across face f)
+//   M_LO   h[f+1] / (h[f] + h[f+1])    weight of centre f in the linear
+//   M_HI   h[f] / (h[f] + h[f+1])      interpolation onto face f (and of f+1)
+//   M_WM   pressure-operator weight of the neighbour c-1 of cell c: 1/(h[c] g[c-1]),
+//          0 across a boundary face
+//   M_WP   weight of the neighbour c+1: 1/(h[c] g[c]), 0 across a boundary face
+//   M_DD   the axis' share of the diagonal, M_WM + M_WP (+ 2/h[c]^2 at the
+//          outflow face of the x axis, where p = 0 on the face)
+//   M_H23  h[c]^(2/3) (the filter width (hx hy hz)^(1/3) squared is the product)
+//   M_H    h[c]
+enum MetricRow { M_IH = 0, M_IG, M_LO, M_HI, M_WM, M_WP, M_DD, M_H23, M_H, kMetricRows };
 
 // Weight of the second inflow sample for the step that starts at time
 // step * dt: the linear interpolation between samples at t0 and t1, held
@@ -72,6 +107,23 @@ __host__ __device__ inline float inflow_weight_at(long long step, double dt, dou
     double w = (t - t0) / (t1 - t0);
     w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
     return (float)w;
+}
+
+// Fold-and-rebase schedule of the pressure solve.  The correction pd is
+// folded into the base ph (and r0 = rhs - A ph recomputed in float64)
+// after every R-th check interval, and during the first kEarlyFoldIters
+// iterations after every check interval that ends on a multiple of 8
+// iterations: early in a solve the corrections are as large as p itself
+// and float32 rounding relative to them would build up in the slowly
+// converging modes, so folding often there keeps the iterate within about
+// 1e-6 of the float64 one (128-iteration folds alone leave about 2e-5).
+// cidx is the 1-based number of the interval, which ends at iteration
+// cidx * K.
+constexpr int kEarlyFoldIters = 512;
+__host__ __device__ inline bool rebase_due_at(long long cidx, int K, int R) {
+    if (cidx % R == 0) return true;
+    const int e = K >= 8 ? 1 : 8 / K;
+    return cidx * (long long)K <= kEarlyFoldIters && cidx % e == 0;
 }
 
 // Control block of one pressure solve (device memory).
@@ -131,7 +183,8 @@ struct SolveParams {
 
 namespace les {
 // Captured runs of kSolveGraphChecks check intervals of one pressure
-// system (exec[0]: check intervals only; exec[1]: the last one a rebase).
+// system (exec[0]: check intervals only; exec[1]: the last one a rebase;
+// exec[2]: the early-fold phase, a rebase every few intervals).
 constexpr int kSolveGraphChecks = 8;
 struct SolveGraph {
     const float* pd = nullptr;
@@ -139,7 +192,7 @@ struct SolveGraph {
     const float* rhs = nullptr;
     int variant = -1, K = 0, R = 0;
     double omega = 0.0;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     uint64_t used = 0;
 };
 }  // namespace les
@@ -170,6 +223,7 @@ struct les_handle {
     double t0 = 0.0, t1 = 1.0;           // times of the two samples
     double dt = 0.0;                     // time step as given (the grid keeps it in float)
     std::vector<uint8_t> mask;
+    std::vector<double> widths[3];       // cell widths per axis of a stretched grid (else empty)
     // kernel timing (les_params.timing): event pool and pending brackets
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
@@ -213,6 +267,12 @@ hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const f
                            const float* w, const float* nut, float* fu, float* fv, float* fw,
                            float* su, float* sv, float* sw, const uint8_t* flags, float* us,
                            float* vs, float* ws, float nu, float alpha, float beta, int first);
+// nu_t, tendency, feedback forcing and AB2 fused in one LDS-tiled pass
+// (uniform grids); nu_t of every cell is stored as a diagnostic.
+hipError_t launch_step_tile(const Geo& g, hipStream_t st, const float* u, const float* v,
+                            const float* w, float* nut, float* fu, float* fv, float* fw, float* su,
+                            float* sv, float* sw, const uint8_t* flags, float* us, float* vs,
+                            float* ws, float c2, float nu, float alpha, float beta, int first);
 hipError_t launch_inflow(const Geo& g, hipStream_t st, float* us, const float* prof,
                          const float* prof1, float wt,
                          const uint8_t* flags, float amp, uint64_t seed, int64_t step);
@@ -235,7 +295,11 @@ hipError_t launch_check(const Geo& g, hipStream_t st, const PBufs& P, double* pa
 // planes per block are chosen per grid, fused_kt).
 struct SorVariant { int tx, kt, nw; };
 constexpr int kNumSplitVariants = 8;
-constexpr int kNumSorVariants = 12;
+constexpr int kNumSorVariants = 14;
+constexpr int kFirstRb2Variant = 12;   // variants 12, 13: two iterations per launch
+// tile of a two-iteration launch: 64 lanes x 32 rows computed, the centre
+// 58 half-cells x 26 rows written (three cells of ring per side)
+constexpr int kRb2Rows = 32, kRb2RowsPerThread = 2, kRb2TXO = 58, kRb2TYO = 26;
 
 // Planes per block of a fused variant on grid g: kt itself, or for kt = 0
 // the fewest that keep the whole grid resident at once, about two
@@ -253,6 +317,30 @@ __host__ __device__ inline int fused_kt(const Geo& g, int tx, int nw, int kt) {
 }
 extern const SorVariant kSorVariants[kNumSorVariants];
 inline bool sor_fused(int variant) { return variant >= kNumSplitVariants; }
+// two fused iterations per launch (needs a check interval that is a
+// multiple of 4, so that an interval ends on the buffer it started from)
+inline bool sor_fused2(int variant) { return variant >= kFirstRb2Variant; }
+
+// Planes per block of a two-iteration launch: the block marches kt + 6
+// planes, and with `per_cu` resident blocks per compute unit the launch
+// takes about ceil(blocks / (256 per_cu)) such marches; the kt that
+// minimises that product.
+inline int rb2_kt(const Geo& g, int per_cu) {
+    const long long nxy = (long long)((g.H + kRb2TXO - 1) / kRb2TXO) * ((g.ny + kRb2TYO - 1) / kRb2TYO);
+    const long long slots = 256LL * per_cu;
+    static const int kCand[] = {8, 12, 16, 24, 32, 48, 64, 96};
+    int best = 8;
+    long long best_cost = -1;
+    for (int kt : kCand) {
+        const long long nb = nxy * ((g.nz + kt - 1) / kt);
+        const long long cost = ((nb + slots - 1) / slots) * ((kt < g.nz ? kt : g.nz) + 6);
+        if (best_cost < 0 || cost < best_cost) {
+            best = kt;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
 int sor_default_variant(const Geo& g);
 // sweep blocks per launch: per half-sweep, or per iteration when fused
 unsigned sor_sweep_blocks(const Geo& g, int variant);
@@ -261,6 +349,10 @@ hipError_t launch_sor(const Geo& g, hipStream_t st, const PBufs& P, int colour, 
 // one fused iteration: parity 0 reads pd and writes pa, parity 1 the reverse
 hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parity, float omega,
                          int local_iter, double* rel0, double* rel1, const Ctl* ctl, int variant);
+// two fused iterations (local iterations local_iter and local_iter + 1),
+// buffers as launch_sor_rb
+hipError_t launch_sor_rb2(const Geo& g, hipStream_t st, const PBufs& P, int parity, float omega,
+                          int local_iter, double* rel0, double* rel1, const Ctl* ctl, int variant);
 hipError_t launch_project(const Geo& g, hipStream_t st, float* us, float* vs, float* ws,
                           const PBufs& P);
 hipError_t launch_bc(const Geo& g, hipStream_t st, float* u, float* v, float* w);
@@ -273,6 +365,11 @@ hipError_t launch_remove_mean_p(const Geo& g, hipStream_t st, const PBufs& P, do
 // residual rule), warm_take records a choice made on the host (trial and
 // forced modes), warm_post after the solve (capture target); warm_result
 // reads the choice of the last step.
+// Stand-alone solve of a pressure system whose rhs and start are in S
+// (les_api.hip); direct: every kernel launched itself, no graphs or timing
+// events (nothing is created on the device).
+int solve_system(les_handle* h, double tol, int32_t max_iter, les_solve_stats* st, const PBufs& S,
+                 bool direct);
 int warm_pre(les_handle* h);
 PBufs warm_candidate(les_handle* h);   // the candidate pair (ph, pd only)
 int warm_take(les_handle* h, int take, double r_prev, double r_net);

@@ -150,16 +150,18 @@ void twinned_free(les_handle* h) {
 }  // namespace les
 
 extern "C" int les_pressure_solve_twinned(les_handle* h, const float* d_rhs, float* d_p, double omega,
-                                          int32_t iters, les_solve_stats* st, double* ms) {
+                                          int32_t iters, les_solve_stats* st, double* ms,
+                                          void* stream) {
     if (!h) return LES_EINVAL;
     if (!d_rhs || !d_p) return tw_err(h, LES_EINVAL, "NULL rhs or p");
     if (iters < 0) return tw_err(h, LES_EINVAL, "iters < 0");
     if (!(omega > 0.0 && omega <= 1.0)) return tw_err(h, LES_EINVAL, "omega outside (0, 1]");
+    if (h->g.stretched) return tw_err(h, LES_EINVAL, "uniform grids only");
     const Geo& g = h->g;
     const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kTwRows - 1) / kTwRows),
                     (unsigned)g.nz);
     const size_t nblocks = (size_t)grid.x * grid.y * grid.z;
-    hipStream_t s = h->stream;
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
     if (!h->tw_q) {
         // installed in the handle only once both buffers exist and the
         // ghost ring is zero

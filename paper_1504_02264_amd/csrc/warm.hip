@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_w_resid(Geo g, PBufs P, int H, int W
             const int s = (c + j0 + k0) & 1;
             const int i0 = 2 * ii + s;
             if (i0 < g.nx) {
-                const double d = (double)diag_of(g, i0, j0, k0);
+                const double d = diag64(g, i0, j0, k0);
                 const double r = (double)P.rhs[c][e] - apply_A64(g, P.ph[c], P.ph[1 - c], e, s, d) -
                                  apply_A64(g, P.pd[c], P.pd[1 - c], e, s, d);
                 const float p = P.ph[c][e] + P.pd[c][e];
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_w_resid_cand(Geo g, PBufs P, WarmPai
             const int s = (c + j0 + k0) & 1;
             const int i0 = 2 * ii + s;
             if (i0 < g.nx) {
-                const double d = (double)diag_of(g, i0, j0, k0);
+                const double d = diag64(g, i0, j0, k0);
                 const double r = (double)P.rhs[c][e] - apply_A64(g, C.h[c], C.h[1 - c], e, s, d) -
                                  apply_A64(g, C.d[c], C.d[1 - c], e, s, d);
                 if (tn) tn[net_vox(g, W, H, i0, j0, k0)] = (float)r;
@@ -517,6 +517,7 @@ int les_warm_grid(const les_handle* h, int32_t* D, int32_t* H, int32_t* W) {
 int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t rule, int32_t param,
                        int32_t smooth) {
     if (!h) return LES_EINVAL;
+    if (n && h->g.stretched) return werr(h, LES_EINVAL, "no learned warm start on a stretched grid");
     if (smooth < 0 || smooth > 100000) return werr(h, LES_EINVAL, "smoothing passes");
     if (n && !(std::isfinite(target_scale) && target_scale > 0.0)) return werr(h, LES_EINVAL, "target_scale");
     if (rule < LES_WARM_RESIDUAL || rule > LES_WARM_ALWAYS) return werr(h, LES_EINVAL, "warm-start rule");
@@ -535,6 +536,7 @@ int les_set_warm_start(les_handle* h, lesnet* n, double target_scale, int32_t ru
 int les_set_capture(les_handle* h, float* d_x, float* d_t, int32_t smooth) {
     if (!h) return LES_EINVAL;
     if ((d_x == nullptr) != (d_t == nullptr)) return werr(h, LES_EINVAL, "capture buffers: both or neither");
+    if (d_x && h->g.stretched) return werr(h, LES_EINVAL, "no training-pair capture on a stretched grid");
     if (smooth < 0 || smooth > 100000) return werr(h, LES_EINVAL, "smoothing passes");
     WCK(hipStreamSynchronize(h->stream));
     h->cap_x = d_x;

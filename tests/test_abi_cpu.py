@@ -81,6 +81,34 @@ def test_create_rejects_bad_bc_sets(bc):
     assert rc == les.LES_EINVAL
 
 
+def _widths(n, v=1.0):
+    return np.full(n, v, np.float64)
+
+
+@pytest.mark.parametrize("bad", ["zero", "nan", "negative", "null", "singular", "small"])
+def test_create_stretched_rejects_bad_arguments(bad):
+    nx, ny, nz = 8, 6, 5
+    hx, hy, hz = _widths(nx), _widths(ny), _widths(nz, 0.5)
+    grid = les.Grid(nx, ny, nz)
+    p = None
+    if bad == "zero":
+        hz[2] = 0.0
+    elif bad == "nan":
+        hy[1] = float("nan")
+    elif bad == "negative":
+        hx[7] = -1.0
+    elif bad == "singular":   # stretched axes need the outflow face
+        p = les.default_params(bc=(les.FREESLIP,) * 6)
+    elif bad == "small":
+        grid = les.Grid(3, ny, nz)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    args = [ptr(hx), None if bad == "null" else ptr(hy), ptr(hz)]
+    rc = les.lib().les_create_stretched(C.byref(grid), *args, 0.05, None,
+                                        None if p is None else C.byref(p), C.byref(h))
+    assert rc == les.LES_EINVAL and not h.value
+
+
 def test_null_handle_calls():
     L = les.lib()
     assert L.les_step(None, 1, None) == les.LES_EINVAL

@@ -280,7 +280,8 @@ def test_full_size_stage_parity(name, max_iter):
 
 
 @pytest.mark.parametrize("name,fused,half,max_iter", [("C2", 8, 5, 400), ("C2", 10, 5, 400),
-                                                      ("C3", 9, 6, 40)])
+                                                      ("C2", 12, 5, 400), ("C3", 9, 6, 40),
+                                                      ("C3", 12, 6, 40)])
 def test_full_size_fused_equals_half_sweeps(name, fused, half, max_iter):
     """The sweep variants the autotuner picks for the benchmark grids (the
     fused red-black iterations) give, at full size, the fields of the
@@ -340,7 +341,7 @@ def test_fused_variants_truncated_interval(max_iter):
     try:
         rhs = random_rhs(nx, ny, nz, seed=12, smooth=1)
         out = []
-        for v in (5, 8, 9, 10, 11):
+        for v in (5, 8, 9, 10, 11, 12, 13):
             g.set_sor_variant(v)
             p, st, rc = g.pressure_solve(rhs, None, tol=1e-12, max_iter=max_iter)
             assert rc == les.LES_NOT_CONVERGED and st["iters"] == max_iter, v
@@ -356,14 +357,51 @@ def test_fused_variants_need_an_even_check_interval():
     try:
         with pytest.raises(les.LesError):
             g.set_sor_variant(8)
+        with pytest.raises(les.LesError):
+            g.set_sor_variant(12)
         g.set_sor_variant(5)
         _, us = g.autotune(reps=2)
         assert np.all(us[8:] == 0) and np.all(us[:8] > 0)
     finally:
         g.close()
+    # two iterations per launch need a multiple of 4; one per launch an even interval
+    g = les.LES(20, 18, 10, 2.0, 2.0, 1.0, 0.05, check_every=6)
+    try:
+        g.set_sor_variant(8)
+        with pytest.raises(les.LesError):
+            g.set_sor_variant(12)
+        _, us = g.autotune(reps=2)
+        assert np.all(us[12:] == 0) and np.all(us[:12] > 0)
+    finally:
+        g.close()
 
 
-@pytest.mark.parametrize("variant", [1, 8, 10])
+def test_two_iteration_variants_stop_inside_an_interval():
+    """A two-iteration launch whose second iteration lies past max_iter
+    does one iteration and copies; check intervals of 8 (four launches).
+    Same iterate as the half-sweeps for every cut."""
+    nx, ny, nz = 70, 61, 23
+    rhs = random_rhs(nx, ny, nz, seed=31, smooth=1)
+    for K in (4, 8):
+        g = les.LES(nx, ny, nz, 2.0, 2.0, 1.0, 0.05, check_every=K)
+        try:
+            for max_iter in (9, 10, 13, 15):
+                out = []
+                for v in (5, 12, 13):
+                    g.set_sor_variant(v)
+                    p, st, rc = g.pressure_solve(rhs, None, tol=1e-12, max_iter=max_iter)
+                    assert st["iters"] == max_iter
+                    out.append((p, st["reltmp2"]))
+                for p, r2 in out[1:]:
+                    assert np.array_equal(p, out[0][0])
+                    # the last iteration's sum of reltmp^2 (block partials in
+                    # another order, so equal up to float64 rounding)
+                    assert r2 == pytest.approx(out[0][1], rel=1e-9)
+        finally:
+            g.close()
+
+
+@pytest.mark.parametrize("variant", [1, 8, 10, 12])
 def test_graph_replay_equals_direct_launches(variant):
     """With kernel timing off the solver replays captured graphs of eight
     check intervals (one ending on the rebase interval); with timing on it
@@ -393,7 +431,7 @@ def test_step_independent_of_sor_variant():
     nx, ny, nz = 33, 17, 9
     mask, prof = urban_case(nx, ny, nz, 4, hmax=5)
     out = []
-    for v in (0, 7, 8, 9, 10, 11):
+    for v in (0, 7, 8, 9, 10, 11, 12, 13):
         g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask)
         g.set_sor_variant(v)
         g.set_inflow(prof, 0.01, 4)
@@ -477,3 +515,86 @@ def test_ensemble_with_singular_member_and_autotune():
     for a, b in ((a1, b1), (a2, b2)):
         for x, y in zip(a.get_fields(), b.get_fields()):
             assert np.array_equal(x, y)
+
+
+# ------------------------------------------- ensemble against the oracle
+def _ensemble_vs_oracle(specs, mode, variant, steps, max_iter):
+    """Step an ensemble of uneven members, then replay every member in the
+    oracle with the iteration counts the ensemble reports; each field of
+    each member within 1e-5 relative L2 (<= 1e-4 after more steps)."""
+    gs, os_ = [], []
+    for nx, ny, nz, mask, prof, seed in specs:
+        g = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask, max_iter=max_iter)
+        o = oracle.Oracle(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask, max_iter=max_iter)
+        g.set_inflow(prof, 0.01, seed)
+        o.set_inflow(prof, 0.01, seed)
+        gs.append(g)
+        os_.append(o)
+    ens = les.Ensemble(gs)
+    try:
+        ens.set_mode(mode)
+        ens.set_variant(variant)
+        rc, st, iters = ens.step(steps)
+        bar = 1e-5 if steps == 1 else 1e-4
+        for q, (g, o) in enumerate(zip(gs, os_)):
+            o.step(steps, forced=iters[:, q])
+            for name, a, b in zip("uvwp", g.get_fields(), o.get_fields()):
+                e = rel(a, b)
+                print(f"  member {q} {g.nx}x{g.ny}x{g.nz} {name}: rel L2 {e:.3e} iters {list(iters[:, q])}",
+                      flush=True)
+                assert e <= bar, (q, name)
+    finally:
+        ens.close()
+        for g in gs:
+            g.close()
+
+
+@pytest.mark.parametrize("variant", [-1, 9])
+@pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
+def test_ensemble_matches_oracle(mode, variant):
+    """Uneven small members (the shapes of the bitwise test), two steps."""
+    shapes = [(24, 20, 12), (33, 17, 9), (40, 24, 16), (17, 31, 10)]
+    specs = []
+    for q, s in enumerate(shapes):
+        mask, prof = _member(*s, seed=80 + q, alpha_pl=(0.1 + 0.05 * q) if q % 2 else None)
+        specs.append((*s, mask, prof, 90 + q))
+    print(f"[ensemble vs oracle] mode={mode} variant={variant}", flush=True)
+    _ensemble_vs_oracle(specs, mode, variant, steps=2, max_iter=20000)
+
+
+@pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
+def test_ensemble_benchmark_size_members_match_oracle(mode):
+    """Two members drawn from the benchmark's uneven ensemble (96-256 cells
+    horizontally, 64-90 vertically), on the fused sweeps for the batched
+    mode, one step with the solve capped at 200 iterations."""
+    from les_inputs import ensemble_members
+    specs = []
+    for w in ensemble_members(2):
+        mask, prof = make_workload_inputs(w)
+        specs.append((w.nx, w.ny, w.nz, mask, prof, w.seed))
+    print(f"[ensemble benchmark members vs oracle] mode={mode} "
+          f"{[(s[0], s[1], s[2]) for s in specs]}", flush=True)
+    _ensemble_vs_oracle(specs, mode, 9 if mode == les.ENSEMBLE_BATCHED else -1, steps=1, max_iter=200)
+
+
+def test_full_step_C2_fields_match_oracle():
+    """300 x 300 x 90 as benchmarked (autotuned fused sweep), one whole step
+    with the solve capped at 400 iterations: u, v, w, p against the oracle
+    replaying the same count."""
+    w = WORKLOADS["C2"]
+    print("[full step C2] max_iter=400", flush=True)
+    mask, prof = make_workload_inputs(w)
+    g, o = pair(w.nx, w.ny, w.nz, mask, w.dx, w.dy, w.dz, w.dt, max_iter=400)
+    try:
+        g.autotune(reps=5)
+        g.set_inflow(prof, w.noise_amp, w.seed)
+        o.set_inflow(prof, w.noise_amp, w.seed)
+        rc, st, iters = g.step(1)
+        assert iters[0] == 400
+        o.step(1, forced=iters)
+        for name, a, b in zip("uvwp", g.get_fields(), o.get_fields()):
+            e = rel(a, b)
+            print(f"  {name}: rel L2 {e:.3e}", flush=True)
+            assert e <= 1e-5, name
+    finally:
+        g.close()

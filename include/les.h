@@ -236,6 +236,25 @@ int les_pressure_solve_dev(les_handle* h, const float* d_rhs, float* d_p, double
                            int32_t max_iter, les_solve_stats* st, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * stand-alone solve of les_pressure_solve_dev with the same arguments,
+ * iterates and results, whose workspace is a static 64 MiB array of the
+ * library's own device memory (one per device, held until the process
+ * ends) instead of memory allocated on the handle's first solve.  It
+ * allocates nothing and creates no graphs or events; every kernel is
+ * launched on stream (NULL: the handle's own).  Grids whose ten colour
+ * arrays exceed 64 MiB (about 3 million cells; the paper's 150x150x90
+ * domain fits) are refused with LES_EINVAL.  Every call on a device shares
+ * that device's array: calls that overlap on one device (two streams, two
+ * threads, or a graph replayed while another call runs) race and give
+ * undefined results.  The workspace is cleared at each call.  Statuses as
+ * les_pressure_solve_dev.
+ */
+int les_pressure_solve_noalloc(les_handle* h, const float* d_rhs, float* d_p, double tol,
+                               int32_t max_iter, les_solve_stats* st, void* stream);
+
+/*
  * Twinned double-buffer relaxation (section 2.6: the paper's replacement
  * for the red-black scheme on the GPU), as a measured comparison solver;
  * the time step itself uses red-black SOR.  p is held as a pair (p_0, p_1)

@@ -28,6 +28,7 @@ EXPORTS = (
     "les_default_params", "les_create", "les_create_stretched", "les_destroy", "les_last_error",
     "les_set_stream",
     "les_set_inflow", "les_set_inflow_pair", "les_step", "les_pressure_solve", "les_pressure_solve_dev",
+    "les_pressure_solve_noalloc",
     "les_pressure_solve_twinned",
     "les_get_fields", "les_get_fields_dev", "les_set_fields", "les_get_aux", "les_get_ghosted",
     "les_get_step", "les_state_size", "les_get_state", "les_set_state", "les_bc_range",
@@ -158,6 +159,7 @@ def lib():
     L.les_step.argtypes = [P, C.c_int32, C.POINTER(StepStats)]
     L.les_pressure_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats)]
     L.les_pressure_solve_dev.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
+    L.les_pressure_solve_noalloc.argtypes = [P, P, P, C.c_double, C.c_int32, C.POINTER(SolveStats), P]
     L.les_pressure_solve_twinned.argtypes = [P, P, P, C.c_double, C.c_int32,
                                              C.POINTER(SolveStats), C.POINTER(C.c_double), P]
     L.les_get_fields.argtypes = [P, P, P, P, P]
@@ -326,6 +328,18 @@ class LES:
         rc = self._check(lib().les_pressure_solve_dev(self.h, C.c_void_p(d_rhs.data_ptr()),
                                                       C.c_void_p(d_p.data_ptr()), float(tol),
                                                       int(max_iter), C.byref(st), s),
+                         (LES_OK, LES_NOT_CONVERGED))
+        return st.as_dict(), rc
+
+    def pressure_solve_noalloc(self, d_rhs, d_p, tol=1e-5, max_iter=20000, stream=None):
+        """les_pressure_solve_noalloc: the device-pointer solve on the
+        library's static workspace (no device allocation); arguments and
+        ordering as pressure_solve_dev."""
+        st = SolveStats()
+        s = C.c_void_p(_current_stream() if stream is None else stream)
+        rc = self._check(lib().les_pressure_solve_noalloc(self.h, C.c_void_p(d_rhs.data_ptr()),
+                                                          C.c_void_p(d_p.data_ptr()), float(tol),
+                                                          int(max_iter), C.byref(st), s),
                          (LES_OK, LES_NOT_CONVERGED))
         return st.as_dict(), rc
 

@@ -113,6 +113,7 @@ def test_null_handle_calls():
     L = les.lib()
     assert L.les_step(None, 1, None) == les.LES_EINVAL
     assert L.les_get_fields(None, None, None, None, None) == les.LES_EINVAL
+    assert L.les_pressure_solve_noalloc(None, None, None, 1e-5, 10, None, None) == les.LES_EINVAL
     assert L.les_last_error(None) == b""
     L.les_destroy(None)
 

@@ -84,11 +84,13 @@ typedef struct {
     int32_t diagnostics;     /* 1: compute ||div u^{n+1}|| and max CFL on the last
                                 step of each les_step call (default 1) */
     int32_t timing;          /* 1: time kernels with HIP events on the handle's stream
-                                (every launch of the per-step kernels; for the SOR
-                                sweeps, one check interval in 8, its 2K back-to-back
-                                half-sweeps or K fused iterations between one event
-                                pair); les_get_timing.  0 (default): the solver
-                                replays check intervals from captured HIP graphs */
+                                (every launch of the per-step kernels and of the
+                                rebase; for the SOR sweeps, one check interval in 8,
+                                its 2K back-to-back half-sweeps, K fused iterations
+                                or K/2 two-iteration launches between one event
+                                pair, and that interval's residual check);
+                                les_get_timing.  0 (default): the solver replays
+                                check intervals from captured HIP graphs */
 } les_params;
 
 /* Per-call statistics of les_step.  Scalars describe the last step of the
@@ -323,9 +325,10 @@ int les_get_ghosted(les_handle* h, float* u, float* v, float* w);
 /* Kernel timing collected while les_params.timing = 1: for each kernel
  * family, the summed event-bracketed device time and the number of timed
  * launches.  Families: 0 nu_t, 1 tendency, 2 inflow, 3 rhs, 4 SOR sweep
- * launch (a half-sweep, or a whole iteration with the fused variants
- * 8-11), 5 residual check, 6 rebase, 7 projection, 8 boundary refresh.
- * reset = 1 clears the counters after reading. */
+ * launch (a half-sweep, a whole iteration with the fused variants 8-11,
+ * two with 12-13), 5 residual check (sampled like the sweeps: the launches
+ * count is that of the sampled intervals), 6 rebase, 7 projection, 8
+ * boundary refresh.  reset = 1 clears the counters after reading. */
 #define LES_NUM_KERNELS 9
 typedef struct {
     double ms[LES_NUM_KERNELS];

@@ -67,7 +67,6 @@ struct EnsDyn {
 
 // Offsets of each member's blocks in a stage's work list.
 struct EnsOffsets {
-    unsigned box[kMaxEnsemble + 1];
     unsigned tile[kMaxEnsemble + 1];
     unsigned cell[kMaxEnsemble + 1];
     unsigned half[kMaxEnsemble + 1];
@@ -102,26 +101,6 @@ __device__ __forceinline__ int owner(const unsigned* off, int n, unsigned L) {
 }
 
 // ------------------------------------------------------- batched stages
-__global__ __launch_bounds__(kBlock) void k_ens_nut(const EnsInst* I, const EnsDyn* D, int n,
-                                                    const EnsOffsets* O) {
-    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
-    const int q = owner(O->box, n, L);
-    const EnsInst& d = I[q];
-    const int a = D[q].cur;
-    nut_body(d.g, d.u[a], d.v[a], d.w[a], d.nut, d.c2, L - O->box[q]);
-}
-
-__global__ __launch_bounds__(kBlock) void k_ens_tendency(const EnsInst* I, const EnsDyn* D, int n,
-                                                         const EnsOffsets* O) {
-    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
-    const int q = owner(O->cell, n, L);
-    const EnsInst& d = I[q];
-    const int a = D[q].cur, b = 1 - a;
-    TendArgs A{d.u[a], d.v[a], d.w[a], d.nut, d.fu, d.fv, d.fw, d.su, d.sv, d.sw, d.flags,
-               d.u[b], d.v[b], d.w[b], d.nu, d.alpha, d.beta, D[q].first};
-    tendency_body(d.g, A, L - O->cell[q]);
-}
-
 __global__ __launch_bounds__(kTileThreads) void k_ens_step_tile(const EnsInst* I, const EnsDyn* D,
                                                               int n, const EnsOffsets* O) {
     __shared__ TileShared sh;
@@ -630,7 +609,6 @@ void build_descriptors(les_ensemble* e) {
         d.nred = red_blocks(h->g);
         max_iter_all = std::max(max_iter_all, h->prm.max_iter);
         d.kt_tile = tile_kt(h->g);
-        o.box[q + 1] = o.box[q] + box_blocks(h->g);
         o.tile[q + 1] = o.tile[q] + tile_blocks(h->g);
         o.cell[q + 1] = o.cell[q] + cell_blocks(h->g);
         o.half[q + 1] = o.half[q] + half_blocks(h->g);

@@ -8,17 +8,6 @@ namespace {
 
 __device__ __forceinline__ unsigned lblock() { return xcd_block(blockIdx.x, gridDim.x); }
 
-__global__ __launch_bounds__(kBlock) void k_nut(Geo g, const float* __restrict__ u,
-                                                const float* __restrict__ v,
-                                                const float* __restrict__ w,
-                                                float* __restrict__ nut, float c2) {
-    nut_body(g, u, v, w, nut, c2, lblock());
-}
-
-__global__ __launch_bounds__(kBlock) void k_tendency(Geo g, TendArgs a) {
-    tendency_body(g, a, lblock());
-}
-
 __global__ __launch_bounds__(kTileThreads) void k_step_tile(Geo g, TendArgs a, float* __restrict__ nut,
                                                           float c2, int kt) {
     __shared__ TileShared sh;
@@ -133,24 +122,20 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
-                      const float* w, float* nut, float c2) {
-    if (g.stretched)   // c2 is Cs^2 here; the filter width comes from the tables
-        hipLaunchKernelGGL(k_nut_str, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, c2);
-    else
-        hipLaunchKernelGGL(k_nut, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, c2);
+hipError_t launch_nut_str(const Geo& g, hipStream_t st, const float* u, const float* v,
+                          const float* w, float* nut, float cs2) {
+    if (!g.stretched) return hipErrorInvalidValue;   // uniform grids: launch_step_tile
+    hipLaunchKernelGGL(k_nut_str, dim3(box_blocks(g)), dim3(kBlock), 0, st, g, u, v, w, nut, cs2);
     return hipGetLastError();
 }
 
-hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const float* v,
-                           const float* w, const float* nut, float* fu, float* fv, float* fw,
-                           float* su, float* sv, float* sw, const uint8_t* flags, float* us,
-                           float* vs, float* ws, float nu, float alpha, float beta, int first) {
+hipError_t launch_tendency_str(const Geo& g, hipStream_t st, const float* u, const float* v,
+                               const float* w, const float* nut, float* fu, float* fv, float* fw,
+                               float* su, float* sv, float* sw, const uint8_t* flags, float* us,
+                               float* vs, float* ws, float nu, float alpha, float beta, int first) {
+    if (!g.stretched) return hipErrorInvalidValue;   // uniform grids: launch_step_tile
     TendArgs a{u, v, w, nut, fu, fv, fw, su, sv, sw, flags, us, vs, ws, nu, alpha, beta, first};
-    if (g.stretched)
-        hipLaunchKernelGGL(k_tendency_str, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
-    else
-        hipLaunchKernelGGL(k_tendency, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
+    hipLaunchKernelGGL(k_tendency_str, dim3(cell_blocks(g)), dim3(kBlock), 0, st, g, a);
     return hipGetLastError();
 }
 

@@ -348,7 +348,10 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
             if (e != hipSuccess) return e;
             return tm(KN_REBASE, cidx, [&] { return launch_rebase(g, st, P, part, rel0, rel1, nrel, ctl, 1); });
         }
-        return tm(KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); });
+        // the checks are sampled with the sweeps (one interval in 8): an
+        // event pair around every one of them would cost more than they do
+        if (sample) return tm(KN_CHECK, cidx, [&] { return launch_check(g, st, P, part, rel0, rel1, nrel, ctl); });
+        return launch_check(g, st, P, part, rel0, rel1, nrel, ctl);
     };
     // Without timing, aligned runs of kSolveGraphChecks intervals replay a
     // captured graph (its kernels read every decision from the control
@@ -844,12 +847,12 @@ int les_step(les_handle* h, int32_t n, les_step_stats* st) {
         const int a = h->cur, b = 1 - h->cur;
         const int first = h->have_old ? 0 : 1;
         if (g.stretched) {
-            CK(timed(h, KN_NUT, kNoTag, [&] { return launch_nut(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2); }));
+            CK(timed(h, KN_NUT, kNoTag, [&] { return launch_nut_str(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, c2); }));
             CK(timed(h, KN_TEND, kNoTag, [&] {
-                return launch_tendency(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
-                                       h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
-                                       h->f.u[b], h->f.v[b], h->f.w[b], (float)p.nu, (float)p.alpha,
-                                       (float)p.beta, first);
+                return launch_tendency_str(g, s, h->f.u[a], h->f.v[a], h->f.w[a], h->f.nut, h->f.fu,
+                                           h->f.fv, h->f.fw, h->f.su, h->f.sv, h->f.sw, h->f.flags,
+                                           h->f.u[b], h->f.v[b], h->f.w[b], (float)p.nu, (float)p.alpha,
+                                           (float)p.beta, first);
             }));
         } else {
             // nu_t, tendency, feedback and AB2 in one LDS-tiled pass

@@ -35,7 +35,7 @@ inline unsigned cell_blocks(const Geo& g) {
 inline unsigned half_blocks(const Geo& g) {
     return (unsigned)(((long long)g.H * g.ny * g.nz + kBlock - 1) / kBlock);
 }
-inline unsigned box_blocks(const Geo& g) {
+inline unsigned box_blocks(const Geo& g) {   // one thread per cell of the ghosted box
     return (unsigned)(((long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2) + kBlock - 1) / kBlock);
 }
 inline unsigned bc_blocks(const Geo& g) {
@@ -99,52 +99,13 @@ __device__ __forceinline__ float mrow(const float* __restrict__ m, int n, int ro
     return m[row * (n + 2) + c];
 }
 
-// ------------------------------------------------------------------ les
-// Smagorinsky eddy viscosity nu_t = (Cs Delta)^2 |S|, |S| = sqrt(2 S_ij S_ij)
-// (section 2.1, les).  S_ii from the two faces of the cell; S_ij (i != j)
-// is the mean of the four edge values around the cell, each edge value
-// being 1/2 (du_i/dx_j + du_j/dx_i) from the adjacent faces.  Covers the
-// whole ghosted box: a ghost cell takes the value of the nearest interior
-// cell (mirrored ghost ring).
-__device__ __forceinline__ void nut_body(const Geo& g, const float* __restrict__ u,
-                                         const float* __restrict__ v, const float* __restrict__ w,
-                                         float* __restrict__ nut, float c2, unsigned lb) {
-    const long long nbox = (long long)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
-    const long long t = (long long)lb * kBlock + threadIdx.x;
-    if (t >= nbox) return;
-    const unsigned pxy = (unsigned)(g.nx + 2) * (unsigned)(g.ny + 2);
-    const unsigned tt = (unsigned)t;
-    const int k = (int)(tt / pxy);
-    const unsigned r = tt - (unsigned)k * pxy;
-    const int j = (int)(r / (unsigned)(g.nx + 2));
-    const int i = (int)(r - (unsigned)j * (unsigned)(g.nx + 2));
-    const int ic = min(max(i, 1), g.nx), jc = min(max(j, 1), g.ny), kc = min(max(k, 1), g.nz);
-    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
-    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
-    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
-    const float s11 = (U(ic, jc, kc) - U(ic - 1, jc, kc)) * g.idx;
-    const float s22 = (V(ic, jc, kc) - V(ic, jc - 1, kc)) * g.idy;
-    const float s33 = (W(ic, jc, kc) - W(ic, jc, kc - 1)) * g.idz;
-    float s12 = 0.f, s13 = 0.f, s23 = 0.f;
-#pragma unroll
-    for (int da = -1; da <= 0; ++da)
-#pragma unroll
-        for (int db = -1; db <= 0; ++db) {
-            const int a = ic + da, b = jc + db;   // x-y edge (face a, face b)
-            s12 += (U(a, b + 1, kc) - U(a, b, kc)) * g.idy + (V(a + 1, b, kc) - V(a, b, kc)) * g.idx;
-            const int c = kc + db;                // x-z edge (face a, face c)
-            s13 += (U(a, jc, c + 1) - U(a, jc, c)) * g.idz + (W(a + 1, jc, c) - W(a, jc, c)) * g.idx;
-            const int b2 = jc + da;               // y-z edge (face b2, face c)
-            s23 += (V(ic, b2, c + 1) - V(ic, b2, c)) * g.idz + (W(ic, b2 + 1, c) - W(ic, b2, c)) * g.idy;
-        }
-    s12 *= 0.125f;   // 1/4 (mean of 4 edges) * 1/2 (symmetric part)
-    s13 *= 0.125f;
-    s23 *= 0.125f;
-    const float ss = 2.f * (s11 * s11 + s22 * s22 + s33 * s33) + 4.f * (s12 * s12 + s13 * s13 + s23 * s23);
-    nut[g.nat(i, j, k)] = c2 * sqrtf(ss);
-}
-
-// ------------------------------------------- velfg + feedbf + adam (fused)
+// ------------------------------------------------ les + velfg + feedbf + adam
+// Smagorinsky eddy viscosity (section 2.1, les): nu_t = (Cs Delta)^2 |S|,
+// |S| = sqrt(2 S_ij S_ij); S_ii from the two faces of the cell, S_ij (i != j)
+// the mean of the four edge values around the cell, each edge value being
+// 1/2 (du_i/dx_j + du_j/dx_i) from the adjacent faces; a ghost cell takes
+// the value of the nearest interior cell (mirrored ghost ring).
+//
 // Per cell (i,j,k) the tendencies of its east u-face, north v-face and top
 // w-face:  F = -(covx + covy + covz) + nu lap + div(2 nu_t S).
 // The cov pieces are the paper's velfg assembly (section 2.5.3): products
@@ -167,104 +128,6 @@ struct TendArgs {
     int first;
 };
 
-__device__ __forceinline__ void tendency_body(const Geo& g, const TendArgs& A, unsigned lb) {
-    const long long n = (long long)g.nx * g.ny * g.nz;
-    const long long t = (long long)lb * kBlock + threadIdx.x;
-    if (t >= n) return;
-    int i, j, k;
-    cell_of(g, t, i, j, k);
-    const float* __restrict__ u = A.u;
-    const float* __restrict__ v = A.v;
-    const float* __restrict__ w = A.w;
-    const float* __restrict__ nut = A.nut;
-    auto U = [&](int a, int b, int c) { return u[g.nat(a, b, c)]; };
-    auto V = [&](int a, int b, int c) { return v[g.nat(a, b, c)]; };
-    auto W = [&](int a, int b, int c) { return w[g.nat(a, b, c)]; };
-    auto N = [&](int a, int b, int c) { return nut[g.nat(a, b, c)]; };
-    // edge viscosities and strain rates
-    auto n12 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b + 1, c) + N(a + 1, b + 1, c)); };
-    auto n13 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a + 1, b, c) + N(a, b, c + 1) + N(a + 1, b, c + 1)); };
-    auto n23 = [&](int a, int b, int c) { return 0.25f * (N(a, b, c) + N(a, b + 1, c) + N(a, b, c + 1) + N(a, b + 1, c + 1)); };
-    auto e12 = [&](int a, int b, int c) { return 0.5f * ((U(a, b + 1, c) - U(a, b, c)) * g.idy + (V(a + 1, b, c) - V(a, b, c)) * g.idx); };
-    auto e13 = [&](int a, int b, int c) { return 0.5f * ((U(a, b, c + 1) - U(a, b, c)) * g.idz + (W(a + 1, b, c) - W(a, b, c)) * g.idx); };
-    auto e23 = [&](int a, int b, int c) { return 0.5f * ((V(a, b, c + 1) - V(a, b, c)) * g.idz + (W(a, b + 1, c) - W(a, b, c)) * g.idy); };
-
-    const long long e = g.nat(i, j, k);
-    const uint8_t fl = A.flags[e];
-    const float dt = g.dt;
-    const float nu = A.nu, alpha = A.alpha, beta = A.beta;
-
-    if (i <= g.u_last) {
-        const float uc = U(i, j, k);
-        const float um = U(i - 1, j, k), up = U(i + 1, j, k);
-        const float covx = 0.5f * (0.5f * (um + uc) * (uc - um) + 0.5f * (uc + up) * (up - uc)) * g.idx;
-        const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i + 1, j - 1, k)) * (uc - U(i, j - 1, k)) +
-                                   0.5f * (V(i, j, k) + V(i + 1, j, k)) * (U(i, j + 1, k) - uc)) * g.idy;
-        const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i + 1, j, k - 1)) * (uc - U(i, j, k - 1)) +
-                                   0.5f * (W(i, j, k) + W(i + 1, j, k)) * (U(i, j, k + 1) - uc)) * g.idz;
-        const float lap = (up - 2.f * uc + um) * g.cx + (U(i, j + 1, k) - 2.f * uc + U(i, j - 1, k)) * g.cy +
-                          (U(i, j, k + 1) - 2.f * uc + U(i, j, k - 1)) * g.cz;
-        const float sgs = 2.f * (N(i + 1, j, k) * (up - uc) * g.idx - N(i, j, k) * (uc - um) * g.idx) * g.idx +
-                          2.f * (n12(i, j, k) * e12(i, j, k) - n12(i, j - 1, k) * e12(i, j - 1, k)) * g.idy +
-                          2.f * (n13(i, j, k) * e13(i, j, k) - n13(i, j, k - 1) * e13(i, j, k - 1)) * g.idz;
-        float F = -(covx + covy + covz) + nu * lap + sgs;
-        if (fl & F_USOLID) {
-            const float s = A.su[e] + dt * uc;
-            A.su[e] = s;
-            F += alpha * s + beta * uc;
-        }
-        const float fo = A.first ? F : A.fu[e];
-        A.us[e] = uc + dt * (1.5f * F - 0.5f * fo);
-        A.fu[e] = F;
-    }
-    if (j <= g.ny - 1) {
-        const float vc = V(i, j, k);
-        const float vm = V(i, j - 1, k), vp = V(i, j + 1, k);
-        const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j + 1, k)) * (vc - V(i - 1, j, k)) +
-                                   0.5f * (U(i, j, k) + U(i, j + 1, k)) * (V(i + 1, j, k) - vc)) * g.idx;
-        const float covy = 0.5f * (0.5f * (vm + vc) * (vc - vm) + 0.5f * (vc + vp) * (vp - vc)) * g.idy;
-        const float covz = 0.5f * (0.5f * (W(i, j, k - 1) + W(i, j + 1, k - 1)) * (vc - V(i, j, k - 1)) +
-                                   0.5f * (W(i, j, k) + W(i, j + 1, k)) * (V(i, j, k + 1) - vc)) * g.idz;
-        const float lap = (V(i + 1, j, k) - 2.f * vc + V(i - 1, j, k)) * g.cx + (vp - 2.f * vc + vm) * g.cy +
-                          (V(i, j, k + 1) - 2.f * vc + V(i, j, k - 1)) * g.cz;
-        const float sgs = 2.f * (n12(i, j, k) * e12(i, j, k) - n12(i - 1, j, k) * e12(i - 1, j, k)) * g.idx +
-                          2.f * (N(i, j + 1, k) * (vp - vc) * g.idy - N(i, j, k) * (vc - vm) * g.idy) * g.idy +
-                          2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j, k - 1) * e23(i, j, k - 1)) * g.idz;
-        float F = -(covx + covy + covz) + nu * lap + sgs;
-        if (fl & F_VSOLID) {
-            const float s = A.sv[e] + dt * vc;
-            A.sv[e] = s;
-            F += alpha * s + beta * vc;
-        }
-        const float fo = A.first ? F : A.fv[e];
-        A.vs[e] = vc + dt * (1.5f * F - 0.5f * fo);
-        A.fv[e] = F;
-    }
-    if (k <= g.nz - 1) {
-        const float wc = W(i, j, k);
-        const float wm = W(i, j, k - 1), wp = W(i, j, k + 1);
-        const float covx = 0.5f * (0.5f * (U(i - 1, j, k) + U(i - 1, j, k + 1)) * (wc - W(i - 1, j, k)) +
-                                   0.5f * (U(i, j, k) + U(i, j, k + 1)) * (W(i + 1, j, k) - wc)) * g.idx;
-        const float covy = 0.5f * (0.5f * (V(i, j - 1, k) + V(i, j - 1, k + 1)) * (wc - W(i, j - 1, k)) +
-                                   0.5f * (V(i, j, k) + V(i, j, k + 1)) * (W(i, j + 1, k) - wc)) * g.idy;
-        const float covz = 0.5f * (0.5f * (wm + wc) * (wc - wm) + 0.5f * (wc + wp) * (wp - wc)) * g.idz;
-        const float lap = (W(i + 1, j, k) - 2.f * wc + W(i - 1, j, k)) * g.cx +
-                          (W(i, j + 1, k) - 2.f * wc + W(i, j - 1, k)) * g.cy + (wp - 2.f * wc + wm) * g.cz;
-        const float sgs = 2.f * (n13(i, j, k) * e13(i, j, k) - n13(i - 1, j, k) * e13(i - 1, j, k)) * g.idx +
-                          2.f * (n23(i, j, k) * e23(i, j, k) - n23(i, j - 1, k) * e23(i, j - 1, k)) * g.idy +
-                          2.f * (N(i, j, k + 1) * (wp - wc) * g.idz - N(i, j, k) * (wc - wm) * g.idz) * g.idz;
-        float F = -(covx + covy + covz) + nu * lap + sgs;
-        if (fl & F_WSOLID) {
-            const float s = A.sw[e] + dt * wc;
-            A.sw[e] = s;
-            F += alpha * s + beta * wc;
-        }
-        const float fo = A.first ? F : A.fw[e];
-        A.ws[e] = wc + dt * (1.5f * F - 0.5f * fo);
-        A.fw[e] = F;
-    }
-}
-
 // ------------------------- les + velfg + feedbf + adam, fused, LDS-tiled
 // One pass over the grid instead of two: a block owns a tile of kTileX x
 // kTileY cells and marches up its chunk of planes.  Every velocity plane
@@ -273,9 +136,8 @@ __device__ __forceinline__ void tendency_body(const Geo& g, const TendArgs& A, u
 // one-cell ring (three planes), and the tendency, feedback forcing and AB2
 // of the tile's cells read both from LDS.  nu_t of the tile's own cells is
 // also stored (the les_get_aux diagnostic); the tendency never reads it
-// back.  Per-cell arithmetic is that of nut_body and tendency_body
-// (same formulas and evaluation order); ghost-ring nu_t is the value of
-// the nearest interior cell, as there.
+// back.  Per-cell arithmetic as described above; ghost-ring nu_t is the
+// value of the nearest interior cell.
 //
 // March of a block over tendency planes [kb, ke): step p loads velocity
 // plane p+1 into registers (issued a step ahead), publishes plane p, then
@@ -715,8 +577,8 @@ __device__ __forceinline__ StrAxis str_axis(const float* m, int n) {
 
 // Smagorinsky nu_t on a stretched grid: (Cs Delta)^2 |S| with the cell's
 // own filter width Delta = (hx hy hz)^(1/3), i.e. Cs^2 hx^(2/3) hy^(2/3)
-// hz^(2/3); strain components as in nut_body, each difference over its
-// own distance.  Ghost ring: the nearest interior cell's value.
+// hz^(2/3); strain components as in the uniform pass, each difference
+// over its own distance.  Ghost ring: the nearest interior cell's value.
 __device__ __forceinline__ void nut_body_str(const Geo& g, const float* __restrict__ u,
                                              const float* __restrict__ v, const float* __restrict__ w,
                                              float* __restrict__ nut, float cs2, unsigned lb) {
@@ -766,7 +628,7 @@ __device__ __forceinline__ void nut_body_str(const Geo& g, const float* __restri
 // midpoint of (plain mean); an advecting velocity is interpolated onto an
 // edge from its own two faces with the same width weights.  Diffusion and
 // the subgrid stress are differences of one-sided fluxes over the control
-// volume.  Feedback forcing and AB2 as in tendency_body.
+// volume.  Feedback forcing and AB2 as in the uniform pass.
 __device__ __forceinline__ void tendency_body_str(const Geo& g, const TendArgs& A, unsigned lb) {
     const long long n = (long long)g.nx * g.ny * g.nz;
     const long long t = (long long)lb * kBlock + threadIdx.x;

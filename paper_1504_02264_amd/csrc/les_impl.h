@@ -261,12 +261,14 @@ enum FinOp { FIN_RHS2 = 0, FIN_RHS_SUM, FIN_PSUM, FIN_SETUP, FIN_CHECK, FIN_CHEC
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_finalize(hipStream_t st, int op, const double* part, int n, const double* rel0,
                            const double* rel1, int nrel, Ctl* ctl, double omega = 1.0);
-hipError_t launch_nut(const Geo& g, hipStream_t st, const float* u, const float* v,
-                      const float* w, float* nut, float c2);
-hipError_t launch_tendency(const Geo& g, hipStream_t st, const float* u, const float* v,
-                           const float* w, const float* nut, float* fu, float* fv, float* fw,
-                           float* su, float* sv, float* sw, const uint8_t* flags, float* us,
-                           float* vs, float* ws, float nu, float alpha, float beta, int first);
+// stretched grids: nu_t (cs2 = Cs^2; each cell's filter width from the
+// tables), then the tendency, feedback forcing and AB2 reading it
+hipError_t launch_nut_str(const Geo& g, hipStream_t st, const float* u, const float* v,
+                          const float* w, float* nut, float cs2);
+hipError_t launch_tendency_str(const Geo& g, hipStream_t st, const float* u, const float* v,
+                               const float* w, const float* nut, float* fu, float* fv, float* fw,
+                               float* su, float* sv, float* sw, const uint8_t* flags, float* us,
+                               float* vs, float* ws, float nu, float alpha, float beta, int first);
 // nu_t, tendency, feedback forcing and AB2 fused in one LDS-tiled pass
 // (uniform grids); nu_t of every cell is stored as a diagnostic.
 hipError_t launch_step_tile(const Geo& g, hipStream_t st, const float* u, const float* v,

@@ -112,6 +112,46 @@ def cpu_baseline(w, gpu_iters_per_step, sample_iters):
     }
 
 
+def young_omega(w):
+    """Young's optimal relaxation factor 2 / (1 + sqrt(1 - rho_J^2)) for the
+    urban operator of workload w, with the Jacobi radius estimated as
+    1 - lambda_min / d from the smoothest mode (a quarter cosine in x
+    between the Neumann inflow face and the Dirichlet outflow face:
+    lambda_min = 4 / dx^2 sin^2(pi / (4 nx))) and the interior diagonal d."""
+    import math
+    lam = 4.0 / w.dx ** 2 * math.sin(math.pi / (4 * w.nx)) ** 2
+    d = 2.0 * (1.0 / w.dx ** 2 + 1.0 / w.dy ** 2 + 1.0 / w.dz ** 2)
+    rho = 1.0 - lam / d
+    return 2.0 / (1.0 + math.sqrt(1.0 - rho * rho))
+
+
+def omega_study(les, torch, w, mask, g, variant, omega, steps=2):
+    """The state after the timed steps (checkpoint) continued for `steps`
+    steps with another relaxation factor, each solved to 1e-5: SOR
+    iterations and wall ms per step (timing off: graph replay)."""
+    blob = g.get_state()
+    t = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask, timing=0, max_iter=BENCH_MAX_ITER,
+                omega=omega)
+    rows = []
+    try:
+        t.set_state(blob)
+        t.set_sor_variant(variant)
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st, it = t.step(1)
+            torch.cuda.synchronize()
+            rows.append({"sor_iters": int(it[0]), "ms": (time.perf_counter() - t0) * 1e3,
+                         "resid": st["resid_last"], "converged": bool(rc == les.LES_OK)})
+            log(f"omega {omega:.5f}: {rows[-1]}")
+    finally:
+        t.close()
+    return {"omega": omega, "note": "study, not the configured step: Young's factor for this operator",
+            "steps": rows,
+            "sor_iters_per_step": sum(r["sor_iters"] for r in rows) / len(rows),
+            "ms_per_step": sum(r["ms"] for r in rows) / len(rows)}
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak, vendor figure
 
 
@@ -172,6 +212,67 @@ def bench_net(les, torch, D=64, H=128, W=128, reps=10):
         "train_step_tflops": t_tf,
         "train_step_frac": t_tf / MFMA_BF16_PEAK_TFLOPS,
     }
+
+
+def bench_warm_start_c2(args, les, torch):
+    """The learned start at 300x300x90 with every solve run to 1e-5: trained
+    on 8 random 64x128x128 crops per step of runs with building seeds 11-14
+    (converged targets), evaluated on whole held-out runs (seeds 21, 22):
+    SOR iterations and wall ms per step to the tolerance, plain SOR from the
+    previous step's pressure against the network's start (inference and
+    the smoothing of its proposal inside the time)."""
+    import numpy as np
+    from paper_1504_02264_amd import warmstart as ws
+    smooth = 16
+    conv = {"max_iter": BENCH_MAX_ITER}
+    Xs, Ts = [], []
+    t0 = time.perf_counter()
+    for seed in (11, 12, 13, 14):
+        log(f"C2 crops from seed {seed}")
+        X, T = ws.collect_crops("C2", seed, steps=2, skip=1, smooth=smooth, crops=8, rng_seed=seed, **conv)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = ws.mirror_y(torch.cat(Xs), torch.cat(Ts))
+    collect_s = time.perf_counter() - t0
+    net = les.Net(seed=0, lr=1e-3)
+    t0 = time.perf_counter()
+    scale, losses = ws.train(net, X, T, iters=3000, batch=4, lr=1e-3, lr_final=5e-5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, T, Xs, Ts
+    rows = {}
+    for seed in (21, 22):
+        log(f"C2 evaluation, seed {seed}")
+        b = ws.evaluate("C2", seed, steps=args.steps, net=None, skip=1, tune=True, **conv)
+        w = ws.evaluate("C2", seed, steps=args.steps, net=net, scale=scale, skip=1, rule=les.WARM_ALWAYS,
+                        smooth=smooth, tune=True, **conv)
+        for name, r in (("plain", b), ("always", w)):
+            d = rows.setdefault(name, {"iters": [], "ms": [], "resid": []})
+            d["iters"] += [int(x) for x in r["iters"]]
+            d["ms"].append(r["ms_per_step"])
+            d["resid"] += [float(x) for x in r["resid"]]
+    base = float(np.mean(rows["plain"]["ms"]))
+    out = {
+        "metric": "time to relative Poisson residual 1e-5 per step, learned start vs plain SOR (300x300x90)",
+        "value": float(np.mean(rows["always"]["ms"])),
+        "unit": "ms/step",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "dtype": "f32 LES, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": "C2 300x300x90 urban LES, every solve to relative residual 1e-5; network "
+                               "trained on 8 random 64x128x128 crops per step of building seeds 11-14 (converged "
+                               "targets, 64 crops and their mirror images in y, 3000 Adam steps), evaluated on "
+                               "seeds 21-22 after one plain step", "collect_s": collect_s, "train_s": train_s,
+                   "final_loss": losses[-1][1], "smooth_passes": smooth},
+        "rules": {k: {"sor_iters_per_step": v["iters"], "mean_sor_iters": float(np.mean(v["iters"])),
+                      "ms_per_step": float(np.mean(v["ms"])), "ms_vs_plain": float(np.mean(v["ms"])) / base,
+                      "resid_per_step": v["resid"]}
+                  for k, v in rows.items()},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
 
 
 def bench_warm_start_c3(args, les, torch):
@@ -247,6 +348,8 @@ def bench_warm_start(args, les, torch):
     from paper_1504_02264_amd import warmstart as ws
     if args.workload == "C3":
         return bench_warm_start_c3(args, les, torch)
+    if args.workload == "C2":
+        return bench_warm_start_c2(args, les, torch)
     smooth = 16
     Xs, Ts = [], []
     for seed in (11, 12, 13, 14):
@@ -421,6 +524,12 @@ def main():
                          "(C1 size; with --workload C3, trained on crops of 1024x1024x96 runs)")
     ap.add_argument("--twinned", action="store_true",
                     help="compare twinned double buffering with red-black SOR (JSON line of its own)")
+    ap.add_argument("--omega", type=float, default=1.8,
+                    help="SOR relaxation factor (the workloads' 1.8 by default; other values are a study, "
+                         "not the configured benchmark)")
+    ap.add_argument("--no-omega-study", action="store_true",
+                    help="skip the study that continues the timed state for 2 steps with Young's "
+                         "relaxation factor for the operator (reported beside the configured line)")
     ap.add_argument("--cpu-sample-iters", type=int, default=200)
     ap.add_argument("--oracle-sample", default=None, metavar="WORKLOAD",
                     help=argparse.SUPPRESS)   # child process of the single-thread CPU baseline
@@ -463,7 +572,7 @@ def main():
     # (a converged 300x300x90 step takes about 1.5e5 iterations at omega 1.8)
     max_iter = args.max_iter if args.max_iter is not None else BENCH_MAX_ITER
     g = les.LES(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.dt, mask,
-                timing=0 if args.no_timing else 1, max_iter=max_iter)
+                timing=0 if args.no_timing else 1, max_iter=max_iter, omega=args.omega)
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, device="cuda")
@@ -493,9 +602,9 @@ def main():
 
     value = cells * args.steps / dt_s
     n_capped = int(st["not_converged"])
-    solve = (f"red-black SOR omega=1.8 to relative residual 1e-5 (all {args.steps} timed steps converged)"
+    solve = (f"red-black SOR omega={args.omega:g} to relative residual 1e-5 (all {args.steps} timed steps converged)"
              if n_capped == 0 else
-             f"red-black SOR omega=1.8 toward relative residual 1e-5, capped at max_iter={max_iter} per step: "
+             f"red-black SOR omega={args.omega:g} toward relative residual 1e-5, capped at max_iter={max_iter} per step: "
              f"{n_capped} of {args.steps} timed steps stopped at the cap, last relative residual "
              f"{st['resid_last']:.2e}")
     out = {
@@ -543,14 +652,15 @@ def main():
         bytes_per_launch = (12.0 if fused else 8.0) * cells
         achieved = bytes_per_launch / t_launch / 1e9
         from paper_1504_02264_amd import profsum
+        # kernel names as the profiler prints them (uniform-grid instantiations)
         if two:
             kname, what = "k_sor_rb2<false>", "two fused red-black SOR iterations"
         elif fused:
             tx, kt, nw = les.SOR_VARIANTS[variant]
-            kname, what = f"k_sor_rb<{tx}, {nw}, {kt}>", "fused red-black SOR iteration"
+            kname, what = f"k_sor_rb<{tx}, {nw}, {kt}, false>", "fused red-black SOR iteration"
         else:
             tx, kt = les.SOR_VARIANTS[variant]
-            kname, what = f"k_sor<{tx}, {kt}>", "red-black SOR half-sweep"
+            kname, what = f"k_sor<{tx}, {kt}, false>", "red-black SOR half-sweep"
         pmc_file = os.path.join(ROOT, "profiles", f"k_sor_traffic_{w.nx}x{w.ny}x{w.nz}.txt")
         tr = profsum.read_traffic(pmc_file, kname)
         out["roofline"] = {
@@ -572,7 +682,13 @@ def main():
             "timed_launches": int(sor_n),
         }
         out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in timing.items()
-                                     if v[1] > 0 and k != "sor"}
+                                     if v[1] > 0 and k not in ("sor", "check")}
+        # the residual checks are sampled with the sweeps (one interval in 8):
+        # mean check time (skipped ones included) times the intervals per step
+        chk_ms, chk_n = timing["check"]
+        if chk_n > 0:
+            K = les.default_params().check_every
+            out["kernel_ms_per_step"]["check"] = chk_ms / chk_n * float(iters.mean()) / K
         # the SOR sweeps are sampled (one check interval in 8): scale to all
         out["kernel_ms_per_step"]["sor"] = (sor_ms / sor_n) / iters_per_launch * float(iters.mean())
         # device time of the pressure solve per timed step (sweeps, stopping
@@ -580,6 +696,9 @@ def main():
         out["solve_kernel_ms_per_step"] = (out["kernel_ms_per_step"]["sor"]
                                            + out["kernel_ms_per_step"].get("check", 0.0)
                                            + out["kernel_ms_per_step"].get("rebase", 0.0))
+    if not args.no_omega_study:
+        log("omega study: Young's relaxation factor from the timed state")
+        out["omega_study"] = omega_study(les, torch, w, mask, g, variant, young_omega(w))
     if not args.no_net:
         log("warm-start network: forward and train step on a 64x128x128 crop")
         out["warm_start_net"] = bench_net(les, torch)

@@ -58,13 +58,14 @@ def collect(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0):
 
 
 def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int = 0, crops: int = 8,
-                  crop=(64, 128, 128), rng_seed: int = 0, tune: bool = True):
+                  crop=(64, 128, 128), rng_seed: int = 0, tune: bool = True, **params):
     """Like collect, for grids larger than the training crop: after each of
     the last `steps` steps, `crops` random D x H x W windows (aligned to 4,
-    drawn from numpy PCG64(rng_seed)) of the step's input and target."""
+    drawn from numpy PCG64(rng_seed)) of the step's input and target;
+    params (e.g. max_iter) go to the handle's les_params."""
     import torch
 
-    g = make_case(base, seed, tune=tune)
+    g = make_case(base, seed, tune=tune, **params)
     try:
         if skip:
             g.step(skip)

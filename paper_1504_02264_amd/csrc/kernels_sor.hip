@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void k_sor(Geo g, int c, float* __restrict_
 }
 
 template <int TX, int NW, int KT, bool STR>
-__global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restrict__ a0,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(8))) void k_sor_rb(Geo g, const float* __restrict__ a0,
                                                     const float* __restrict__ a1,
                                                     const float* __restrict__ r0c,
                                                     const float* __restrict__ r1c,
@@ -34,8 +34,35 @@ __global__ __launch_bounds__(64 * NW) void k_sor_rb(Geo g, const float* __restri
     bool acc;
     const bool active = sweep_active(ctl, local_iter, acc);
     if (!active && ctl->done) return;
-    sor_rb_body<TX, NW, KT, STR>(g, a0, a1, r0c, r1c, b0, b1, omega,
-                                 active && acc && rel0 != nullptr, !active, rel0, rel1, lblock(), kt);
+    if constexpr (!STR) {
+        if (!active)
+            sor_rb_copy_u<TX, NW, KT>(g, a0, a1, b0, b1, lblock(), kt);
+        else if (acc && rel0 != nullptr)
+            sor_rb_body_u<TX, NW, KT, true>(g, a0, a1, r0c, r1c, b0, b1, omega, rel0, rel1, lblock(), kt);
+        else
+            sor_rb_body_u<TX, NW, KT, false>(g, a0, a1, r0c, r1c, b0, b1, omega, rel0, rel1, lblock(), kt);
+    } else {
+        sor_rb_body<TX, NW, KT, STR>(g, a0, a1, r0c, r1c, b0, b1, omega,
+                                     active && acc && rel0 != nullptr, !active, rel0, rel1, lblock(), kt);
+    }
+}
+
+// Uniform grids too large for the lean form's 32-bit buffer offsets.
+template <int TX, int NW, int KT>
+__global__ __launch_bounds__(64 * NW) void k_sor_rb_wide(Geo g, const float* __restrict__ a0,
+                                                         const float* __restrict__ a1,
+                                                         const float* __restrict__ r0c,
+                                                         const float* __restrict__ r1c,
+                                                         float* __restrict__ b0, float* __restrict__ b1,
+                                                         float omega, int local_iter,
+                                                         double* __restrict__ rel0,
+                                                         double* __restrict__ rel1,
+                                                         const Ctl* __restrict__ ctl, int kt) {
+    bool acc;
+    const bool active = sweep_active(ctl, local_iter, acc);
+    if (!active && ctl->done) return;
+    sor_rb_body<TX, NW, KT, false>(g, a0, a1, r0c, r1c, b0, b1, omega, active && acc && rel0 != nullptr,
+                                   !active, rel0, rel1, lblock(), kt);
 }
 
 template <bool STR>
@@ -183,8 +210,11 @@ hipError_t launch_sor_rb(const Geo& g, hipStream_t st, const PBufs& P, int parit
         if (g.stretched)                                                                            \
             hipLaunchKernelGGL((k_sor_rb<TX, NW, KT, true>), grid, dim3(64 * NW), 0, st, g, a0, a1,   \
                                P.r0[0], P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);   \
-        else                                                                                        \
+        else if (rb_lean_fits(g))                                                                   \
             hipLaunchKernelGGL((k_sor_rb<TX, NW, KT, false>), grid, dim3(64 * NW), 0, st, g, a0, a1,  \
+                               P.r0[0], P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);   \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_sor_rb_wide<TX, NW, KT>), grid, dim3(64 * NW), 0, st, g, a0, a1,    \
                                P.r0[0], P.r0[1], b0, b1, omega, local_iter, rel0, rel1, ctl, kt);   \
         break;
     switch (variant) {

@@ -8,6 +8,8 @@
 // float64.
 #pragma once
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "les_impl.h"
 
@@ -850,14 +852,23 @@ __device__ __forceinline__ void diag_body(const Geo& g, const float* __restrict_
 // correction p and its r0: returns p + reltmp, reltmp = omega (cn1
 // (sum_nb cn_nb p_nb - r0) - p).  Contraction is pinned (explicit fmaf,
 // no other fusion) so that every kernel that updates a cell rounds alike.
+// The two halves are separate so that a kernel holding cn1 = 1/diag already
+// (correctly rounded, as here) rounds exactly alike.
+__device__ __forceinline__ float sor_nb(float west, float east, float ps, float pn, float pb, float pt,
+                                        float cx, float cy, float cz) {
+#pragma clang fp contract(off)
+    return fmaf(cz, pb + pt, fmaf(cy, ps + pn, cx * (west + east)));
+}
+__device__ __forceinline__ float sor_relax(float nb, float inv, float r, float p, float omega,
+                                           float& reltmp) {
+#pragma clang fp contract(off)
+    reltmp = omega * fmaf(inv, nb - r, -p);
+    return p + reltmp;
+}
 __device__ __forceinline__ float sor_point(float west, float east, float ps, float pn, float pb,
                                            float pt, float cx, float cy, float cz, float diag,
                                            float r, float p, float omega, float& reltmp) {
-#pragma clang fp contract(off)
-    const float nb = fmaf(cz, pb + pt, fmaf(cy, ps + pn, cx * (west + east)));
-    const float inv = 1.0f / diag;
-    reltmp = omega * fmaf(inv, nb - r, -p);
-    return p + reltmp;
+    return sor_relax(sor_nb(west, east, ps, pn, pb, pt, cx, cy, cz), 1.0f / diag, r, p, omega, reltmp);
 }
 
 // The same update on a stretched grid: every neighbour has its own weight
@@ -1151,6 +1162,264 @@ __device__ __forceinline__ void sor_rb_body(const Geo& g, const float* __restric
             rel1[2 * lb] = tb;
             rel1[2 * lb + 1] = td;
         }
+    }
+}
+
+// ------------------------- fused red-black iteration, uniform grids (lean)
+// The iteration of sor_rb_body on a uniform grid, arranged for few vector
+// instructions per cell (the k-march of sor_rb_body issues ~140 vector
+// instructions per step and is bound by issue, not by memory).  Same lanes,
+// same tiles, same per-cell arithmetic (sor_nb / sor_relax with cn1 = 1/diag
+// correctly rounded), so the result equals sor_rb_body's bit for bit.
+//  * Addressing: one block-uniform origin walks up the planes (scalar
+//    registers); each lane holds constant 32-bit byte offsets from it for
+//    its column and the column's neighbours.  Lanes outside the grid address
+//    the zero padding column (half-index H, present in every row and plane),
+//    so they read zeros everywhere and produce exact zeros: no per-lane
+//    predicate on loads or values.
+//  * x-neighbours: of a cell's two neighbours of the other colour one lies
+//    in the lane's own column; the other (left or right, by plane parity) is
+//    loaded for colour 0 and taken from the neighbouring lane's new value by
+//    one ds_bpermute for colour 1.
+//  * cn1: per lane and parity for the interior and the end planes; zero for
+//    the missing cell at the end of an odd-length row, which then stays 0.
+//  * The march is unrolled by four over an LDS ring of four planes (guard
+//    rows above and below), so ring slots and parity are compile-time and
+//    the loads of plane q+1 stay in flight across step q.
+struct RbPar {
+    unsigned lx;    // byte offset of the other x-neighbour (own padding element outside the grid)
+    int src;        // ds_bpermute byte address of the lane holding that neighbour's new value
+    float dxy;      // x and y shares of the diagonal
+    float inv_mid;  // cn1 on planes with a neighbour above and below (0: no such cell)
+    float inv_end;  // cn1 on the bottom and top planes
+    bool store;     // the lane owns this cell of its tile
+};
+struct RbIn {
+    float up, south, north, xn, p0, rr0, rr1;
+};
+
+// Buffer access to a colour array: the resource's base sits 2 SP elements
+// before the array (so the block-uniform scalar offset of every plane from
+// -1 to nz+1 is non-negative) and each lane adds a 32-bit byte offset.
+// The whole array must lie within 4 GiB of that base (rb_lean_fits).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc colour_rsrc(const Geo& g, const float* p) {
+    const unsigned bytes = (unsigned)((g.ctot + 2 * g.SP) * 4);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(p - 2 * g.SP), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld(Rsrc r, unsigned voff, unsigned soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ float lane_perm(int byte_src, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_src, __float_as_int(v)));
+}
+
+template <int TX, int NW, int KT, bool ACC>
+__device__ __forceinline__ void sor_rb_body_u(const Geo& g, const float* __restrict__ a0,
+                                              const float* __restrict__ a1,
+                                              const float* __restrict__ r0c,
+                                              const float* __restrict__ r1c, float* __restrict__ b0,
+                                              float* __restrict__ b1, float omega,
+                                              double* __restrict__ rel0, double* __restrict__ rel1,
+                                              unsigned lb, int kt_run) {
+    constexpr int RPW = 64 / TX;
+    constexpr int TYB = RPW * NW;
+    constexpr int TXO = TX - 2, TYO = TYB - 2;
+    const int kt = KT > 0 ? KT : kt_run;
+    __shared__ float ring[4][TYB + 2][TX];   // row r of the tile at index r + 1
+    __shared__ double red3[3][NW];
+    const unsigned nbx = (unsigned)(g.H + TXO - 1) / TXO;
+    const unsigned nby = (unsigned)(g.ny + TYO - 1) / TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int tx = lane % TX;
+    const int row = (threadIdx.x >> 6) * RPW + lane / TX;
+    const int ii0 = (int)bx * TXO - 1, j0 = (int)by * TYO - 1;   // the tile's halo corner
+    const int ii = ii0 + tx, j = j0 + row;
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
+    const int qa = k_begin - 1;
+    const bool col_ok = ii >= 0 && ii < g.H && j >= 0 && j < g.ny;
+    const bool inner = col_ok && tx >= 1 && tx <= TX - 2 && row >= 1 && row <= TYB - 2;
+    // Byte offsets of the lane's column and its neighbours from the block's
+    // moving origin, which for step q sits one plane, one row and one
+    // element before the halo corner of plane q (so every offset is
+    // non-negative): own plane q, south, north, up (q+1), below (q-1).
+    // Lanes outside the grid take the padding column of a row inside it.
+    const int iic = col_ok ? ii : g.H, jc = min(max(j, 0), g.ny - 1);
+    const unsigned lc = (unsigned)(((jc - j0 + 1) * g.S + (iic - ii0) + 1) + g.SP) * 4u;
+    const unsigned ls = lc - (unsigned)g.S * 4u, ln = lc + (unsigned)g.S * 4u;
+    const unsigned lu = lc + (unsigned)g.SP * 4u, lbw = lc - (unsigned)g.SP * 4u;
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    const float dyy = diag_y(g, j);
+    const float dz_mid = g.cz + g.cz;      // diag_z of a plane with neighbours above and below
+    const float dz_end = diag_z(g, 0);     // and of the bottom and top planes (equal)
+    RbPar pe, po;                          // parity of the steps q - qa even / odd
+    {
+        const int se = (j + qa) & 1;
+        auto make = [&](int s, RbPar& P) {
+            const int i0 = 2 * ii + s;
+            const bool ok = col_ok && i0 < g.nx;
+            P.lx = col_ok ? (s ? lc + 4u : lc - 4u) : lc;
+            P.src = ((s ? lane + 1 : lane - 1) & 63) * 4;
+            P.dxy = diag_x(g, i0) + dyy;
+            P.inv_mid = ok ? 1.0f / (P.dxy + dz_mid) : 0.f;
+            P.inv_end = ok ? 1.0f / (P.dxy + dz_end) : 0.f;
+            P.store = inner && ok;
+        };
+        make(se, pe);
+        make(se ^ 1, po);
+    }
+    const Rsrc ra0 = colour_rsrc(g, a0), ra1 = colour_rsrc(g, a1), rr0c = colour_rsrc(g, r0c),
+               rr1c = colour_rsrc(g, r1c), rb0 = colour_rsrc(g, b0), rb1 = colour_rsrc(g, b1);
+    const unsigned sp4 = (unsigned)g.SP * 4u;
+    // scalar byte offset (from the resources' base) of the origin of step qa
+    const unsigned so0 =
+        (unsigned)((long long)g.S + ((long long)qa * (g.ny + 2) + (j0 + 1)) * g.S + ii0 - 1 - g.S + 2 * g.SP) *
+        4u;
+    // Loads of step q (origin so).  Planes -1 and nz are ghost planes; where
+    // a value is not needed (up above plane nz, rr1 below plane -1) the
+    // origin is moved to a plane that exists, so every load is unconditional.
+    auto fetch = [&](int q, unsigned so, RbIn& f, const RbPar& P) {
+        f.up = bld(ra1, lu, q + 1 <= g.nz ? so : so - sp4);
+        f.south = bld(ra1, ls, so);
+        f.north = bld(ra1, ln, so);
+        f.xn = bld(ra1, P.lx, so);
+        f.p0 = bld(ra0, lc, so);
+        f.rr0 = bld(rr0c, lc, so);
+        f.rr1 = bld(rr1c, lbw, q - 1 >= -1 ? so : so + sp4);
+    };
+    // old colour 1 on planes q-1 (bm) and q (bc); new colour 0 on planes q-2
+    // (rm2) and q-1 (rm1)
+    float bm = qa - 1 >= -1 ? bld(ra1, lbw, so0) : 0.f;
+    float bc = bld(ra1, lc, so0);
+    float rm2 = 0.f, rm1 = 0.f;
+    double r2a = 0.0, r2b = 0.0, d2b = 0.0;
+    const int rw = row + 1;
+
+    // one step of the march: colour 0 on plane q, colour 1 on plane q - 1;
+    // P is this step's parity, PN the next one's (for the loads of q + 1)
+    auto step = [&](auto slot_c, int q, unsigned so, const RbIn& cur, RbIn& nxt, const RbPar& P,
+                    const RbPar& PN) {
+        constexpr int SL = decltype(slot_c)::value;
+        constexpr int SLP = (SL + 3) & 3;   // the slot of plane q - 1
+        if (q < k_end) fetch(q + 1, so + sp4, nxt, PN);
+        float rq = 0.f;
+        if (q >= 0 && q < g.nz) {
+            const float inv = (q == 0 || q == g.nz - 1) ? P.inv_end : P.inv_mid;
+            float rt;
+            const float v = sor_relax(sor_nb(bc, cur.xn, cur.south, cur.north, bm, cur.up, cx, cy, cz), inv,
+                                      cur.rr0, cur.p0, omega, rt);
+            rq = v;
+            if (q >= k_begin && q < k_end && P.store) {
+                bst(rb0, lc, so, v);
+                if (ACC) r2a += (double)rt * (double)rt;
+            }
+        }
+        ring[SL][rw][tx] = rq;
+        __syncthreads();
+        const int qb = q - 1;
+        if (qb >= k_begin) {
+            const float oth = lane_perm(P.src, rm1);
+            const float ps = ring[SLP][rw - 1][tx], pn = ring[SLP][rw + 1][tx];
+            const bool end_plane = qb == 0 || qb == g.nz - 1;
+            const float inv = end_plane ? P.inv_end : P.inv_mid;
+            float rt;
+            const float v = sor_relax(sor_nb(rm1, oth, ps, pn, rm2, rq, cx, cy, cz), inv, cur.rr1, bm, omega,
+                                      rt);
+            if (P.store) {
+                bst(rb1, lbw, so, v);
+                if (ACC) {
+                    const float diag = P.dxy + (end_plane ? dz_end : dz_mid);
+                    const double rd = (double)rt;
+                    r2b += rd * rd;
+                    d2b += ((double)diag * rd) * ((double)diag * rd);
+                }
+            }
+        }
+        bm = bc;
+        bc = cur.up;
+        rm2 = rm1;
+        rm1 = rq;
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    using S3 = std::integral_constant<int, 3>;
+    RbIn A, B;
+    fetch(qa, so0, A, pe);
+    int q = qa;
+    unsigned so = so0;
+    for (; q + 3 <= k_end; q += 4, so += 4 * sp4) {
+        step(S0{}, q, so, A, B, pe, po);
+        step(S1{}, q + 1, so + sp4, B, A, po, pe);
+        step(S2{}, q + 2, so + 2 * sp4, A, B, pe, po);
+        step(S3{}, q + 3, so + 3 * sp4, B, A, po, pe);
+    }
+    if (q <= k_end) step(S0{}, q, so, A, B, pe, po);
+    if (q + 1 <= k_end) step(S1{}, q + 1, so + sp4, B, A, po, pe);
+    if (q + 2 <= k_end) step(S2{}, q + 2, so + 2 * sp4, A, B, pe, po);
+    if (ACC) {
+        const double va = wave_sum(r2a), vb = wave_sum(r2b), vd = wave_sum(d2b);
+        const int wid = threadIdx.x >> 6;
+        if (lane == 0) {
+            red3[0][wid] = va;
+            red3[1][wid] = vb;
+            red3[2][wid] = vd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0, td = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                ta += red3[0][w];
+                tb += red3[1][w];
+                td += red3[2][w];
+            }
+            rel0[2 * lb] = ta;
+            rel0[2 * lb + 1] = 0.0;
+            rel1[2 * lb] = tb;
+            rel1[2 * lb + 1] = td;
+        }
+    }
+}
+
+// An iteration past max_iter inside the last check interval, uniform grid:
+// the block copies its tile of both colours from a to b, so the result
+// stays in the buffer the interval ends on (the same cells sor_rb_body
+// copies; a missing cell at the end of an odd-length row holds 0 in both).
+template <int TX, int NW, int KT>
+__device__ __forceinline__ void sor_rb_copy_u(const Geo& g, const float* __restrict__ a0,
+                                              const float* __restrict__ a1, float* __restrict__ b0,
+                                              float* __restrict__ b1, unsigned lb, int kt_run) {
+    constexpr int RPW = 64 / TX;
+    constexpr int TYB = RPW * NW;
+    constexpr int TXO = TX - 2, TYO = TYB - 2;
+    const int kt = KT > 0 ? KT : kt_run;
+    const unsigned nbx = (unsigned)(g.H + TXO - 1) / TXO;
+    const unsigned nby = (unsigned)(g.ny + TYO - 1) / TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int tx = lane % TX;
+    const int row = (threadIdx.x >> 6) * RPW + lane / TX;
+    const int ii = (int)bx * TXO - 1 + tx, j = (int)by * TYO - 1 + row;
+    const bool inner = ii >= 0 && ii < g.H && j >= 0 && j < g.ny && tx >= 1 && tx <= TX - 2 && row >= 1 &&
+                       row <= TYB - 2;
+    if (!inner) return;
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
+    for (int k = k_begin; k < k_end; ++k) {
+        const long long e = g.col(ii, j, k);
+        b0[e] = a0[e];
+        b1[e] = a1[e];
     }
 }
 

@@ -322,6 +322,13 @@ inline bool sor_fused(int variant) { return variant >= kNumSplitVariants; }
 // two fused iterations per launch (needs a check interval that is a
 // multiple of 4, so that an interval ends on the buffer it started from)
 inline bool sor_fused2(int variant) { return variant >= kFirstRb2Variant; }
+// The fused iteration's uniform-grid form addresses each colour array through
+// a buffer resource whose base sits 2 SP elements before the array, so the
+// array and that lead must span at most 4 GiB; larger grids take the
+// general form.
+inline bool rb_lean_fits(const Geo& g) {
+    return (unsigned long long)(g.ctot + 2 * g.SP) * 4ull <= 0xFFFFFFFFull;
+}
 
 // Planes per block of a two-iteration launch: the block marches kt + 6
 // planes, and with `per_cu` resident blocks per compute unit the launch

@@ -330,6 +330,29 @@ def test_sor_variants_bitwise_identical():
     assert st["iters"] == ref[1] and np.array_equal(p, ref[0])
 
 
+@pytest.mark.parametrize("shape", [(4, 4, 4), (5, 7, 4), (9, 4, 5), (64, 4, 5), (4, 9, 6), (63, 31, 4),
+                                   (67, 35, 17), (5, 129, 4)])
+def test_fused_variants_on_small_and_ragged_grids(shape):
+    """The smallest grids (four planes: half of them a bottom or top plane;
+    four rows; four columns), odd row lengths and grids that end part-way
+    into a tile: every fused variant gives the half-sweeps' iterate bit for
+    bit and the same iteration count."""
+    nx, ny, nz = shape
+    g = les.LES(nx, ny, nz, 2.0, 3.0, 1.5, 0.05)
+    try:
+        rhs = random_rhs(nx, ny, nz, seed=nx + 7 * ny + 31 * nz, smooth=1)
+        out = []
+        for v in (1, 8, 9, 10, 11):
+            g.set_sor_variant(v)
+            p, st, rc = g.pressure_solve(rhs, None, tol=1e-5, max_iter=3000)
+            out.append((p, st["iters"], rc))
+        for p, it, rc in out[1:]:
+            assert it == out[0][1] and rc == out[0][2]
+            assert np.array_equal(p, out[0][0])
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("max_iter", [13, 14, 15, 16])
 def test_fused_variants_truncated_interval(max_iter):
     """A solve stopped by max_iter inside a check interval (K = 4) leaves

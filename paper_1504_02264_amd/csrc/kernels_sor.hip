@@ -80,8 +80,39 @@ __global__ __launch_bounds__(1024) void k_sor_rb2(Geo g, const float* __restrict
     const bool act2 = sweep_active(ctl, local_iter + 1, acc2);
     if (!act1 && ctl->done) return;
     const bool part = rel0 != nullptr;
-    sor_rb2_body<STR>(g, a0, a1, r0c, r1c, b0, b1, omega, act1, act1 && act2, part && act1 && acc1 && !act2,
-                      part && act1 && act2 && acc2, rel0, rel1, lblock(), kt);
+    const bool p1 = part && act1 && acc1 && !act2, p2 = part && act1 && act2 && acc2;
+    if constexpr (!STR) {
+        __shared__ Rb2Smem sm;
+        if (!act1)
+            sor_rb2_copy_u(g, a0, a1, b0, b1, lblock(), kt);
+        else if (p1 || p2)
+            sor_rb2_body_u<true>(sm, g, a0, a1, r0c, r1c, b0, b1, omega, act2, p1, p2, rel0, rel1, lblock(), kt);
+        else
+            sor_rb2_body_u<false>(sm, g, a0, a1, r0c, r1c, b0, b1, omega, act2, false, false, rel0, rel1,
+                                  lblock(), kt);
+    } else {
+        sor_rb2_body<STR>(g, a0, a1, r0c, r1c, b0, b1, omega, act1, act1 && act2, p1, p2, rel0, rel1, lblock(),
+                          kt);
+    }
+}
+
+// Uniform grids too large for the lean form's 32-bit buffer offsets.
+__global__ __launch_bounds__(1024) void k_sor_rb2_wide(Geo g, const float* __restrict__ a0,
+                                                      const float* __restrict__ a1,
+                                                      const float* __restrict__ r0c,
+                                                      const float* __restrict__ r1c,
+                                                      float* __restrict__ b0, float* __restrict__ b1,
+                                                      float omega, int local_iter,
+                                                      double* __restrict__ rel0,
+                                                      double* __restrict__ rel1,
+                                                      const Ctl* __restrict__ ctl, int kt) {
+    bool acc1, acc2;
+    const bool act1 = sweep_active(ctl, local_iter, acc1);
+    const bool act2 = sweep_active(ctl, local_iter + 1, acc2);
+    if (!act1 && ctl->done) return;
+    const bool part = rel0 != nullptr;
+    sor_rb2_body<false>(g, a0, a1, r0c, r1c, b0, b1, omega, act1, act1 && act2, part && act1 && acc1 && !act2,
+                        part && act1 && act2 && acc2, rel0, rel1, lblock(), kt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fold(long long n, float* __restrict__ ph0,
@@ -240,8 +271,11 @@ hipError_t launch_sor_rb2(const Geo& g, hipStream_t st, const PBufs& P, int pari
     if (g.stretched)
         hipLaunchKernelGGL(k_sor_rb2<true>, grid, dim3(1024), 0, st, g, a0, a1, P.r0[0], P.r0[1], b0, b1,
                            omega, local_iter, rel0, rel1, ctl, kt);
-    else
+    else if (rb_lean_fits(g))
         hipLaunchKernelGGL(k_sor_rb2<false>, grid, dim3(1024), 0, st, g, a0, a1, P.r0[0], P.r0[1], b0, b1,
+                           omega, local_iter, rel0, rel1, ctl, kt);
+    else
+        hipLaunchKernelGGL(k_sor_rb2_wide, grid, dim3(1024), 0, st, g, a0, a1, P.r0[0], P.r0[1], b0, b1,
                            omega, local_iter, rel0, rel1, ctl, kt);
     return hipGetLastError();
 }

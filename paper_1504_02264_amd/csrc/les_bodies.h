@@ -1692,6 +1692,333 @@ __device__ __forceinline__ void sor_rb2_body(const Geo& g, const float* __restri
     }
 }
 
+// ------------------------------ two fused iterations, uniform grids (lean)
+// The two iterations of sor_rb2_body on a uniform grid with the lean
+// sweep's arrangement: buffer loads at a block-uniform scalar offset plus a
+// per-lane byte offset, lanes outside the grid on the zero padding column
+// (cn1 = 0 there and at the missing cell of an odd-length row, so every
+// stage leaves them exactly 0), rows outside the grid skipped as a whole
+// (a row is one wavefront), one parity per step for all four stages and
+// both rows of a thread.  Load planes are clamped into the ghost planes -1
+// and nz, which hold zeros: exactly the values the stages take outside the
+// grid.  Register pipelines are indexed by plane modulo 3 and the march is
+// unrolled by six, so no value is moved between registers; one barrier per
+// step suffices (every stage reads the LDS rows of planes written in the
+// previous step, and the two-slot rings are rewritten only after that
+// step's barrier).  Same per-cell arithmetic as sor_rb2_body: bit for bit.
+// LDS of one block (declared once per kernel, shared by both instantiations)
+struct Rb2Smem {
+    float ringA[2][kRb2Rows + 2][64];   // tile row r at index r + 1 (guard rows 0 and kRb2Rows + 1)
+    float ringB[2][kRb2Rows + 2][64];
+    float ringC[2][kRb2Rows + 2][64];
+    double red3[3][16];
+};
+
+template <bool ACC>
+__device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const float* __restrict__ a0,
+                                               const float* __restrict__ a1,
+                                               const float* __restrict__ r0c,
+                                               const float* __restrict__ r1c, float* __restrict__ b0,
+                                               float* __restrict__ b1, float omega, bool second,
+                                               bool acc1, bool acc2, double* __restrict__ rel0,
+                                               double* __restrict__ rel1, unsigned lb, int kt) {
+    constexpr int R = kRb2RowsPerThread;
+    constexpr int NR = kRb2Rows;
+    static_assert(R == 2 && NR == 32, "one thread: rows w and w + 16 of a 32-row tile");
+    auto& ringA = sm.ringA;
+    auto& ringB = sm.ringB;
+    auto& ringC = sm.ringC;
+    auto& red3 = sm.red3;
+    const unsigned nbx = (unsigned)(g.H + kRb2TXO - 1) / kRb2TXO;
+    const unsigned nby = (unsigned)(g.ny + kRb2TYO - 1) / kRb2TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int ii0 = (int)bx * kRb2TXO - 3, j0 = (int)by * kRb2TYO - 3;
+    const int ii = ii0 + lane;
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
+    const int qs = k_begin - 3;
+    const bool lane_ok = ii >= 0 && ii < g.H;
+    const bool out_lane = lane >= 3 && lane <= 60;
+    // rows of this wavefront (uniform): wv and wv + 16
+    int jr[R];
+    bool row_ok[R], out_row[R];
+    float dyy[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int row = wv + 16 * t;
+        jr[t] = j0 + row;
+        row_ok[t] = jr[t] >= 0 && jr[t] < g.ny;
+        out_row[t] = row_ok[t] && row >= 3 && row <= NR - 4;
+        dyy[t] = diag_y(g, jr[t]);
+    }
+    // guard rows of the rings read as 0
+    if (threadIdx.x < 64) {
+        for (int s = 0; s < 2; ++s) {
+            ringA[s][0][lane] = ringA[s][NR + 1][lane] = 0.f;
+            ringB[s][0][lane] = ringB[s][NR + 1][lane] = 0.f;
+            ringC[s][0][lane] = ringC[s][NR + 1][lane] = 0.f;
+        }
+    }
+    // lane byte offsets from the row's origin on a plane (one plane, one row
+    // and one element before the lane-0 column of the row)
+    const int iic = lane_ok ? ii : g.H;
+    const unsigned lc = (unsigned)((iic - ii0) + 1 + g.S + g.SP) * 4u;
+    const unsigned ls = lc - (unsigned)g.S * 4u, ln = lc + (unsigned)g.S * 4u;
+    const float dz_mid = g.cz + g.cz, dz_end = diag_z(g, 0);
+    // per-parity lane constants (parity of the steps q - qs even / odd;
+    // all four stages of a step and both rows share it)
+    struct Par {
+        unsigned lx;         // stage A's x-neighbour of the other colour
+        int src;             // ds_bpermute source of stages B, C, D's x-neighbour
+        float dx;            // diag_x of the cell
+        float im[R], ie[R];  // cn1, interior and end planes, per row (0: no cell)
+        bool own;            // the lane owns its cell in the tile's output columns
+    } pe, po;
+    {
+        const int se = (j0 + wv + qs) & 1;
+        auto make = [&](int s, Par& P) {
+            const int i0 = 2 * ii + s;
+            const bool ok = lane_ok && i0 < g.nx;
+            P.lx = lane_ok ? (s ? lc + 4u : lc - 4u) : lc;
+            P.src = ((s ? lane + 1 : lane - 1) & 63) * 4;
+            P.dx = diag_x(g, i0);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const float dxy = P.dx + dyy[t];
+                P.im[t] = ok ? 1.0f / (dxy + dz_mid) : 0.f;
+                P.ie[t] = ok ? 1.0f / (dxy + dz_end) : 0.f;
+            }
+            P.own = ok && out_lane;
+        };
+        make(se, pe);
+        make(se ^ 1, po);
+    }
+    const Rsrc ra0 = colour_rsrc(g, a0), ra1 = colour_rsrc(g, a1), rr0c = colour_rsrc(g, r0c),
+               rr1c = colour_rsrc(g, r1c), rb0 = colour_rsrc(g, b0), rb1 = colour_rsrc(g, b1);
+    const unsigned sp4 = (unsigned)g.SP * 4u;
+    // scalar byte offset of row t's origin on plane p, p clamped into the
+    // planes -1 .. nz (those outside read the ghost planes' zeros)
+    unsigned so_row[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+        so_row[t] = (unsigned)(((long long)g.S + ((long long)(j0 + wv + 16 * t) + 1) * g.S + ii0 - 1 - g.S - g.SP +
+                                2 * g.SP) *
+                               4);
+    auto so_at = [&](int t, int p) -> unsigned {
+        const int pc = min(max(p, -1), g.nz);
+        return so_row[t] + (unsigned)(pc + 1) * sp4;
+    };
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    // pipelines, indexed by plane modulo 3 (plane p at (p - qs) % 3)
+    float oc[3][R];   // old colour 1
+    float av[3][R];   // A: colour 0, iteration 1
+    float bv[3][R];   // B: colour 1, iteration 1
+    float cv[3][R];   // C: colour 0, iteration 2
+    float r0v[3][R];  // r0 of colour 0
+    float r1v[3][R];  // r0 of colour 1
+    struct Ld { float up, south, north, xn, p0, rr0, rr1; } ld[R];
+    auto fetch = [&](int q, const Par& P) {   // loads of step q (plane q; rr1 of plane q - 1)
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (!row_ok[t]) {
+                ld[t] = Ld{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                continue;
+            }
+            const unsigned so = so_at(t, q);
+            ld[t].up = bld(ra1, lc, so_at(t, q + 1));
+            ld[t].south = bld(ra1, ls, so);
+            ld[t].north = bld(ra1, ln, so);
+            ld[t].xn = bld(ra1, P.lx, so);
+            ld[t].p0 = bld(ra0, lc, so);
+            ld[t].rr0 = bld(rr0c, lc, so);
+            ld[t].rr1 = bld(rr1c, lc, so_at(t, q - 1));
+        }
+    };
+    double sC = 0.0, sD = 0.0, dD = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        // old colour 1 on planes qs - 1 and qs (ghost zeros below the grid)
+        oc[2][t] = row_ok[t] ? bld(ra1, lc, so_at(t, qs - 1)) : 0.f;
+        oc[0][t] = row_ok[t] ? bld(ra1, lc, so_at(t, qs)) : 0.f;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) av[m][t] = bv[m][t] = cv[m][t] = r0v[m][t] = r1v[m][t] = 0.f;
+    }
+    fetch(qs, pe);
+    __syncthreads();   // guard rows written
+
+    // step q = qs + T: A on q, B on q-1, C on q-2, D on q-3
+    auto step = [&](auto tc, int q, const Par& P, const Par& PN) {
+        constexpr int T = decltype(tc)::value;
+        constexpr int M0 = T % 3, M1 = (T + 2) % 3, M2 = (T + 1) % 3;   // planes q, q-1, q-2 (q-3: M0)
+        constexpr int S0 = T & 1, S1 = (T + 1) & 1;                     // ring slots of q, q-1 (q-2: S0, q-3: S1)
+        const int qb = q - 1, qc = q - 2, qd = q - 3;
+        // ---- A: colour 0, iteration 1, plane q
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float v = 0.f;
+            if (row_ok[t] && q >= 0 && q < g.nz) {
+                const float inv = (q == 0 || q == g.nz - 1) ? P.ie[t] : P.im[t];
+                float rt;
+                v = sor_relax(sor_nb(oc[M0][t], ld[t].xn, ld[t].south, ld[t].north, oc[M1][t], ld[t].up, cx, cy,
+                                     cz),
+                              inv, ld[t].rr0, ld[t].p0, omega, rt);
+                if (ACC && acc1 && out_row[t] && P.own && q >= k_begin && q < k_end) sC += (double)rt * (double)rt;
+            }
+            av[M0][t] = v;
+            r0v[M0][t] = ld[t].rr0;
+            r1v[M1][t] = ld[t].rr1;
+            oc[M2][t] = ld[t].up;   // old colour 1 on plane q + 1 (slot of q - 2, no longer needed)
+            ringA[S0][wv + 16 * t + 1][lane] = v;
+        }
+        if (q < qs + 5 + (k_end - k_begin)) fetch(q + 1, PN);   // loads of the next step
+        // ---- B: colour 1, iteration 1, plane q-1
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float v = 0.f;
+            if (row_ok[t] && qb >= 0 && qb < g.nz) {
+                const float oth = lane_perm(P.src, av[M1][t]);
+                const int rw = wv + 16 * t + 1;
+                const float ps = ringA[S1][rw - 1][lane], pn = ringA[S1][rw + 1][lane];
+                const bool endp = qb == 0 || qb == g.nz - 1;
+                const float inv = endp ? P.ie[t] : P.im[t];
+                float rt;
+                v = sor_relax(sor_nb(av[M1][t], oth, ps, pn, av[M2][t], av[M0][t], cx, cy, cz), inv, r1v[M1][t],
+                              oc[M1][t], omega, rt);
+                if (ACC && acc1 && out_row[t] && P.own && qb >= k_begin && qb < k_end) {
+                    const double rd = (double)rt;
+                    sD += rd * rd;
+                    const double dd = (double)((P.dx + dyy[t]) + (endp ? dz_end : dz_mid)) * rd;
+                    dD += dd * dd;
+                }
+            }
+            bv[M1][t] = v;
+            ringB[S1][wv + 16 * t + 1][lane] = v;
+        }
+        // ---- C: colour 0, iteration 2, plane q-2
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float v = 0.f;
+            if (row_ok[t] && qc >= 0 && qc < g.nz) {
+                const float oth = lane_perm(P.src, bv[M2][t]);
+                const int rw = wv + 16 * t + 1;
+                const float ps = ringB[S0][rw - 1][lane], pn = ringB[S0][rw + 1][lane];
+                const float inv = (qc == 0 || qc == g.nz - 1) ? P.ie[t] : P.im[t];
+                float rt = 0.f;
+                const float w = sor_relax(sor_nb(bv[M2][t], oth, ps, pn, bv[M0][t], bv[M1][t], cx, cy, cz), inv,
+                                          r0v[M2][t], av[M2][t], omega, rt);
+                v = second ? w : av[M2][t];
+                if (out_row[t] && qc >= k_begin && qc < k_end) {
+                    if (P.own) bst(rb0, lc, so_at(t, qc), v);
+                    if (ACC && acc2 && P.own) sC += (double)rt * (double)rt;
+                }
+            }
+            cv[M2][t] = v;
+            ringC[S0][wv + 16 * t + 1][lane] = v;
+        }
+        // ---- D: colour 1, iteration 2, plane q-3
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (out_row[t] && qd >= k_begin && qd < k_end) {
+                const float oth = lane_perm(P.src, cv[M0][t]);
+                const int rw = wv + 16 * t + 1;
+                const float ps = ringC[S1][rw - 1][lane], pn = ringC[S1][rw + 1][lane];
+                const bool endp = qd == 0 || qd == g.nz - 1;
+                const float inv = endp ? P.ie[t] : P.im[t];
+                float rt = 0.f;
+                const float w = sor_relax(sor_nb(cv[M0][t], oth, ps, pn, cv[M1][t], cv[M2][t], cx, cy, cz), inv,
+                                          r1v[M0][t], bv[M0][t], omega, rt);
+                const float v = second ? w : bv[M0][t];
+                if (P.own) {
+                    bst(rb1, lc, so_at(t, qd), v);
+                    if (ACC && acc2) {
+                        const double rd = (double)rt;
+                        sD += rd * rd;
+                        const double dd = (double)((P.dx + dyy[t]) + (endp ? dz_end : dz_mid)) * rd;
+                        dD += dd * dd;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    const int q_last = k_end + 2;
+    int q = qs;
+    for (; q + 5 <= q_last; q += 6) {
+        step(I0{}, q, pe, po);
+        step(I1{}, q + 1, po, pe);
+        step(I2{}, q + 2, pe, po);
+        step(I3{}, q + 3, po, pe);
+        step(I4{}, q + 4, pe, po);
+        step(I5{}, q + 5, po, pe);
+    }
+    if (q <= q_last) step(I0{}, q, pe, po);
+    if (q + 1 <= q_last) step(I1{}, q + 1, po, pe);
+    if (q + 2 <= q_last) step(I2{}, q + 2, pe, po);
+    if (q + 3 <= q_last) step(I3{}, q + 3, po, pe);
+    if (q + 4 <= q_last) step(I4{}, q + 4, pe, po);
+    if (ACC) {
+        const double va = wave_sum(sC), vb = wave_sum(sD), vd = wave_sum(dD);
+        if (lane == 0) {
+            red3[0][wv] = va;
+            red3[1][wv] = vb;
+            red3[2][wv] = vd;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0, td = 0.0;
+            for (int w = 0; w < 16; ++w) {
+                ta += red3[0][w];
+                tb += red3[1][w];
+                td += red3[2][w];
+            }
+            rel0[2 * lb] = ta;
+            rel0[2 * lb + 1] = 0.0;
+            rel1[2 * lb] = tb;
+            rel1[2 * lb + 1] = td;
+        }
+    }
+}
+
+// Both iterations past max_iter (the first one already): the block copies
+// its output tile of both colours from a to b (rb2 tiling).
+__device__ __forceinline__ void sor_rb2_copy_u(const Geo& g, const float* __restrict__ a0,
+                                               const float* __restrict__ a1, float* __restrict__ b0,
+                                               float* __restrict__ b1, unsigned lb, int kt) {
+    const unsigned nbx = (unsigned)(g.H + kRb2TXO - 1) / kRb2TXO;
+    const unsigned nby = (unsigned)(g.ny + kRb2TYO - 1) / kRb2TYO;
+    const unsigned bx = lb % nbx;
+    const unsigned rr = lb / nbx;
+    const unsigned by = rr % nby;
+    const unsigned bk = rr / nby;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int ii = (int)bx * kRb2TXO - 3 + lane;
+    if (!(ii >= 0 && ii < g.H && lane >= 3 && lane <= 60)) return;
+    const int k_begin = (int)bk * kt;
+    const int k_end = min(g.nz, k_begin + kt);
+    for (int t = 0; t < kRb2RowsPerThread; ++t) {
+        const int row = wv + 16 * t;
+        const int j = (int)by * kRb2TYO - 3 + row;
+        if (j < 0 || j >= g.ny || row < 3 || row > kRb2Rows - 4) continue;
+        for (int k = k_begin; k < k_end; ++k) {
+            const long long e = g.col(ii, j, k);
+            b0[e] = a0[e];
+            b1[e] = a1[e];
+        }
+    }
+}
+
 // ------------------------------------------------------------- fold
 // ph <- fl(ph + pd), pd <- exact remainder (Knuth's TwoSum), pointwise over
 // the whole colour arrays (padding stays 0 + 0 = 0).

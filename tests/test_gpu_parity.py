@@ -342,7 +342,7 @@ def test_fused_variants_on_small_and_ragged_grids(shape):
     try:
         rhs = random_rhs(nx, ny, nz, seed=nx + 7 * ny + 31 * nz, smooth=1)
         out = []
-        for v in (1, 8, 9, 10, 11):
+        for v in (1, 8, 9, 10, 11, 12, 13):
             g.set_sor_variant(v)
             p, st, rc = g.pressure_solve(rhs, None, tol=1e-5, max_iter=3000)
             out.append((p, st["iters"], rc))

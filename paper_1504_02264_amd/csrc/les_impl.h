@@ -337,10 +337,9 @@ inline bool rb_lean_fits(const Geo& g) {
 inline int rb2_kt(const Geo& g, int per_cu) {
     const long long nxy = (long long)((g.H + kRb2TXO - 1) / kRb2TXO) * ((g.ny + kRb2TYO - 1) / kRb2TYO);
     const long long slots = 256LL * per_cu;
-    static const int kCand[] = {8, 12, 16, 24, 32, 48, 64, 96};
-    int best = 8;
+    int best = 4;
     long long best_cost = -1;
-    for (int kt : kCand) {
+    for (int kt = 4; kt <= 96; ++kt) {
         const long long nb = nxy * ((g.nz + kt - 1) / kt);
         const long long cost = ((nb + slots - 1) / slots) * ((kt < g.nz ? kt : g.nz) + 6);
         if (best_cost < 0 || cost < best_cost) {

@@ -1803,12 +1803,14 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     const unsigned sp4 = (unsigned)g.SP * 4u;
     // scalar byte offset of row t's origin on plane p, p clamped into the
     // planes -1 .. nz (those outside read the ghost planes' zeros)
+    // (rows outside the grid address the nearest row inside it: their loads
+    // stay in bounds and their values are never used)
     unsigned so_row[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t)
-        so_row[t] = (unsigned)(((long long)g.S + ((long long)(j0 + wv + 16 * t) + 1) * g.S + ii0 - 1 - g.S - g.SP +
-                                2 * g.SP) *
-                               4);
+    for (int t = 0; t < R; ++t) {
+        const int jc = min(max(jr[t], 0), g.ny - 1);
+        so_row[t] = (unsigned)(((long long)g.S + ((long long)jc + 1) * g.S + ii0 - 1 - g.S - g.SP + 2 * g.SP) * 4);
+    }
     auto so_at = [&](int t, int p) -> unsigned {
         const int pc = min(max(p, -1), g.nz);
         return so_row[t] + (unsigned)(pc + 1) * sp4;
@@ -1821,34 +1823,33 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     float cv[3][R];   // C: colour 0, iteration 2
     float r0v[3][R];  // r0 of colour 0
     float r1v[3][R];  // r0 of colour 1
-    struct Ld { float up, south, north, xn, p0, rr0, rr1; } ld[R];
-    auto fetch = [&](int q, const Par& P) {   // loads of step q (plane q; rr1 of plane q - 1)
+    // loads two steps ahead: step T reads buffer T & 1, then refills it with
+    // the loads of step T + 2
+    struct Ld { float up, south, north, xn, p0, rr0, rr1; } ld[2][R];
+    auto fetch = [&](int q, const Par& P, Ld* L) {   // loads of step q (plane q; rr1 of plane q - 1)
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            if (!row_ok[t]) {
-                ld[t] = Ld{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                continue;
-            }
             const unsigned so = so_at(t, q);
-            ld[t].up = bld(ra1, lc, so_at(t, q + 1));
-            ld[t].south = bld(ra1, ls, so);
-            ld[t].north = bld(ra1, ln, so);
-            ld[t].xn = bld(ra1, P.lx, so);
-            ld[t].p0 = bld(ra0, lc, so);
-            ld[t].rr0 = bld(rr0c, lc, so);
-            ld[t].rr1 = bld(rr1c, lc, so_at(t, q - 1));
+            L[t].up = bld(ra1, lc, so_at(t, q + 1));
+            L[t].south = bld(ra1, ls, so);
+            L[t].north = bld(ra1, ln, so);
+            L[t].xn = bld(ra1, P.lx, so);
+            L[t].p0 = bld(ra0, lc, so);
+            L[t].rr0 = bld(rr0c, lc, so);
+            L[t].rr1 = bld(rr1c, lc, so_at(t, q - 1));
         }
     };
     double sC = 0.0, sD = 0.0, dD = 0.0;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
         // old colour 1 on planes qs - 1 and qs (ghost zeros below the grid)
-        oc[2][t] = row_ok[t] ? bld(ra1, lc, so_at(t, qs - 1)) : 0.f;
-        oc[0][t] = row_ok[t] ? bld(ra1, lc, so_at(t, qs)) : 0.f;
+        oc[2][t] = bld(ra1, lc, so_at(t, qs - 1));
+        oc[0][t] = bld(ra1, lc, so_at(t, qs));
 #pragma unroll
         for (int m = 0; m < 3; ++m) av[m][t] = bv[m][t] = cv[m][t] = r0v[m][t] = r1v[m][t] = 0.f;
     }
-    fetch(qs, pe);
+    fetch(qs, pe, ld[0]);
+    fetch(qs + 1, po, ld[1]);
     __syncthreads();   // guard rows written
 
     // step q = qs + T: A on q, B on q-1, C on q-2, D on q-3
@@ -1857,6 +1858,7 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
         constexpr int M0 = T % 3, M1 = (T + 2) % 3, M2 = (T + 1) % 3;   // planes q, q-1, q-2 (q-3: M0)
         constexpr int S0 = T & 1, S1 = (T + 1) & 1;                     // ring slots of q, q-1 (q-2: S0, q-3: S1)
         const int qb = q - 1, qc = q - 2, qd = q - 3;
+        Ld* ldc = ld[S0];
         // ---- A: colour 0, iteration 1, plane q
 #pragma unroll
         for (int t = 0; t < R; ++t) {
@@ -1864,18 +1866,18 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
             if (row_ok[t] && q >= 0 && q < g.nz) {
                 const float inv = (q == 0 || q == g.nz - 1) ? P.ie[t] : P.im[t];
                 float rt;
-                v = sor_relax(sor_nb(oc[M0][t], ld[t].xn, ld[t].south, ld[t].north, oc[M1][t], ld[t].up, cx, cy,
+                v = sor_relax(sor_nb(oc[M0][t], ldc[t].xn, ldc[t].south, ldc[t].north, oc[M1][t], ldc[t].up, cx, cy,
                                      cz),
-                              inv, ld[t].rr0, ld[t].p0, omega, rt);
+                              inv, ldc[t].rr0, ldc[t].p0, omega, rt);
                 if (ACC && acc1 && out_row[t] && P.own && q >= k_begin && q < k_end) sC += (double)rt * (double)rt;
             }
             av[M0][t] = v;
-            r0v[M0][t] = ld[t].rr0;
-            r1v[M1][t] = ld[t].rr1;
-            oc[M2][t] = ld[t].up;   // old colour 1 on plane q + 1 (slot of q - 2, no longer needed)
+            r0v[M0][t] = ldc[t].rr0;
+            r1v[M1][t] = ldc[t].rr1;
+            oc[M2][t] = ldc[t].up;   // old colour 1 on plane q + 1 (slot of q - 2, no longer needed)
             ringA[S0][wv + 16 * t + 1][lane] = v;
         }
-        if (q < qs + 5 + (k_end - k_begin)) fetch(q + 1, PN);   // loads of the next step
+        if (q + 1 < qs + 5 + (k_end - k_begin)) fetch(q + 2, P, ldc);   // loads of step q + 2 (same parity)
         // ---- B: colour 1, iteration 1, plane q-1
 #pragma unroll
         for (int t = 0; t < R; ++t) {

@@ -16,7 +16,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libles.so")
+# PAPER_1504_02264_AMD_LIB points the binding at another build of the same
+# library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("PAPER_1504_02264_AMD_LIB") or os.path.join(_HERE, "libles.so")
 
 LES_OK, LES_NOT_CONVERGED = 0, 1
 LES_EINVAL, LES_ENOMEM, LES_EDEVICE, LES_ENONFINITE, LES_ESTATE = -1, -2, -3, -4, -5

@@ -123,6 +123,33 @@ enum {
 int lesnet_op(int32_t op, int32_t B, int32_t D, int32_t H, int32_t W, int32_t cin, int32_t cout,
               const float* d_a, const float* d_b, const float* d_c, float* d_out, void* stream);
 
+/* ---- training-set preparation on the device ----
+ * The learned part's data path: windows of captured pairs, their mirror
+ * images in y, mini-batch gathers and the target scaling, as library
+ * kernels.  All device pointers, ordered on `stream` (NULL: the default
+ * stream), no synchronisation, no allocation.  LES_EINVAL on NULL pointers
+ * or out-of-range sizes, LES_EDEVICE if a launch fails.
+ *
+ * lesnet_crop: copy the window [z, z+cd) x [y, y+ch) x [x, x+cw) of a
+ * [D][H][W][C] float32 array into d_dst [cd][ch][cw][C]; with mirror_y the
+ * window is reflected in y (row c of d_dst is source row y + ch - 1 - c).
+ * The y walls carry the same boundary condition on both sides, so the
+ * pressure operator commutes with that reflection and a reflected pair is
+ * a valid training pair.  d_src and d_dst must not overlap. */
+int lesnet_crop(const float* d_src, int32_t D, int32_t H, int32_t W, int32_t C, int32_t z, int32_t y,
+                int32_t x, int32_t cd, int32_t ch, int32_t cw, int32_t mirror_y, float* d_dst, void* stream);
+/* lesnet_gather: d_dst[b] = d_src[idx[b]] for b < n (1 <= n <= 64), items
+ * of `item` floats, d_src holding `count` items; idx is a host array. */
+int lesnet_gather(const float* d_src, int64_t item, int64_t count, const int32_t* idx, int32_t n,
+                  float* d_dst, void* stream);
+/* lesnet_sum_squares: *d_out (device float64) = sum of x^2 over n floats,
+ * accumulated in float64 in a fixed order (deterministic); d_x may be NULL
+ * when n is 0 (the sum is 0). */
+int lesnet_sum_squares(const float* d_x, int64_t n, double* d_out, void* stream);
+/* lesnet_scale_div: d_y = d_x / s elementwise (float32 division; d_y may be
+ * d_x); s finite and > 0; nothing to do (pointers unused) when n is 0. */
+int lesnet_scale_div(const float* d_x, int64_t n, float s, float* d_y, void* stream);
+
 /*
  * Coupling to an LES handle.  The network grid of a handle is (D, H, W) =
  * (nz, ny, nx) each rounded up to a multiple of 4; voxel (z, y, x) is cell

@@ -43,7 +43,8 @@ EXPORTS = (
     "lesnet_default_config", "lesnet_create", "lesnet_destroy", "lesnet_last_error",
     "lesnet_num_params", "lesnet_get_params", "lesnet_set_params", "lesnet_get_grads",
     "lesnet_forward", "lesnet_gradients", "lesnet_train_step", "lesnet_set_lr", "lesnet_op", "les_warm_grid",
-    "les_set_warm_start", "les_set_capture",
+    "les_set_warm_start", "les_set_capture", "lesnet_crop", "lesnet_gather", "lesnet_sum_squares",
+    "lesnet_scale_div",
 )
 ENSEMBLE_BATCHED, ENSEMBLE_PERSISTENT = 0, 1
 NUM_SOR_VARIANTS = 14
@@ -209,6 +210,10 @@ def lib():
     L.les_warm_grid.argtypes = [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
     L.les_set_warm_start.argtypes = [P, P, C.c_double, C.c_int32, C.c_int32, C.c_int32]
     L.les_set_capture.argtypes = [P, P, P, C.c_int32]
+    L.lesnet_crop.argtypes = [P, I, I, I, I, I, I, I, I, I, I, I, P, P]
+    L.lesnet_gather.argtypes = [P, C.c_int64, C.c_int64, P, I, P, P]
+    L.lesnet_sum_squares.argtypes = [P, C.c_int64, P, P]
+    L.lesnet_scale_div.argtypes = [P, C.c_int64, C.c_float, P, P]
     _lib = L
     return L
 
@@ -581,6 +586,72 @@ def set_capture(les: "LES", d_x=None, d_t=None, smooth: int = 0):
     les._check(lib().les_set_capture(les.h, C.c_void_p(d_x.data_ptr()) if d_x is not None else None,
                                      C.c_void_p(d_t.data_ptr()) if d_t is not None else None,
                                      int(smooth)))
+
+
+# ---- training-set preparation (lesnet.h): library kernels on torch memory
+
+
+def _dev(t, what):
+    if not (t.is_cuda and t.is_contiguous() and t.dtype.is_floating_point and t.element_size() == 4):
+        raise ValueError(f"{what}: expected a contiguous float32 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _net_check(rc, what):
+    if rc != LES_OK:
+        raise LesError(rc, what)
+
+
+def crop(src, window, out=None, mirror_y: bool = False):
+    """The window (z, y, x, cd, ch, cw) of src [D, H, W, C] or [D, H, W]
+    into out [cd, ch, cw(, C)] (allocated if None), reflected in y with
+    mirror_y (lesnet_crop)."""
+    import torch
+    z, y, x, cd, ch, cw = (int(v) for v in window)
+    D, H, W = src.shape[:3]
+    Cn = src.shape[3] if src.dim() == 4 else 1
+    shape = (cd, ch, cw, Cn) if src.dim() == 4 else (cd, ch, cw)
+    if out is None:
+        out = torch.empty(shape, device=src.device, dtype=torch.float32)
+    elif tuple(out.shape) != shape:
+        raise ValueError(f"crop: out has shape {tuple(out.shape)}, expected {shape}")
+    _net_check(lib().lesnet_crop(_dev(src, "crop"), D, H, W, Cn, z, y, x, cd, ch, cw, int(bool(mirror_y)),
+                                 _dev(out, "crop"), C.c_void_p(_current_stream())), "lesnet_crop")
+    return out
+
+
+def gather(src, idx, out=None):
+    """out[b] = src[idx[b]] along the first axis (lesnet_gather; at most 64
+    items)."""
+    import torch
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n = int(idx.size)
+    item = int(src[0].numel()) if src.shape[0] > 0 else 0
+    if out is None:
+        out = torch.empty((n,) + tuple(src.shape[1:]), device=src.device, dtype=torch.float32)
+    _net_check(lib().lesnet_gather(_dev(src, "gather"), item, int(src.shape[0]),
+                                   idx.ctypes.data_as(C.c_void_p), n, _dev(out, "gather"),
+                                   C.c_void_p(_current_stream())), "lesnet_gather")
+    return out
+
+
+def sum_squares(x) -> float:
+    """Sum of x^2 in float64, fixed-order (lesnet_sum_squares)."""
+    import torch
+    out = torch.empty(1, device=x.device, dtype=torch.float64)
+    _net_check(lib().lesnet_sum_squares(_dev(x, "sum_squares"), int(x.numel()), C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(_current_stream())), "lesnet_sum_squares")
+    return float(out.item())
+
+
+def scale_div(x, s: float, out=None):
+    """out = x / s elementwise in float32 (lesnet_scale_div)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(x)
+    _net_check(lib().lesnet_scale_div(_dev(x, "scale_div"), int(x.numel()), float(s), _dev(out, "scale_div"),
+                                      C.c_void_p(_current_stream())), "lesnet_scale_div")
+    return out
 
 
 def bc_range(nx: int, ny: int, nz: int) -> int:

@@ -73,8 +73,10 @@ def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int =
         cd, ch, cw = crop
         Xf = torch.empty((D, H, W, 3), device="cuda")
         Tf = torch.empty((D, H, W), device="cuda")
+        X = torch.empty((steps * crops, cd, ch, cw, 3), device="cuda")
+        T = torch.empty((steps * crops, cd, ch, cw), device="cuda")
         rng = np.random.default_rng(rng_seed)
-        Xs, Ts = [], []
+        n = 0
         for _ in range(steps):
             les.set_capture(g, Xf, Tf, smooth)
             g.step(1)
@@ -82,11 +84,12 @@ def collect_crops(base: str, seed: int, steps: int, skip: int = 0, smooth: int =
                 z = 4 * int(rng.integers(0, (D - cd) // 4 + 1))
                 y = 4 * int(rng.integers(0, (H - ch) // 4 + 1))
                 x = 4 * int(rng.integers(0, (W - cw) // 4 + 1))
-                Xs.append(Xf[z:z + cd, y:y + ch, x:x + cw].clone())
-                Ts.append(Tf[z:z + cd, y:y + ch, x:x + cw].clone())
+                les.crop(Xf, (z, y, x, cd, ch, cw), out=X[n])
+                les.crop(Tf, (z, y, x, cd, ch, cw), out=T[n])
+                n += 1
         les.set_capture(g, None, None)
         torch.cuda.synchronize()
-        return torch.stack(Xs), torch.stack(Ts)
+        return X, T
     finally:
         g.close()
 
@@ -98,7 +101,15 @@ def mirror_y(X, T):
     reflected alike) is as valid a training pair as the original."""
     import torch
 
-    return (torch.cat([X, X.flip(2)]).contiguous(), torch.cat([T, T.flip(2)]).contiguous())
+    n = X.shape[0]
+    Xm = torch.empty((2 * n,) + tuple(X.shape[1:]), device=X.device)
+    Tm = torch.empty((2 * n,) + tuple(T.shape[1:]), device=T.device)
+    D, H, W = T.shape[1:4]
+    for i in range(n):
+        for m in (0, 1):
+            les.crop(X[i], (0, 0, 0, D, H, W), out=Xm[i + m * n], mirror_y=bool(m))
+            les.crop(T[i], (0, 0, 0, D, H, W), out=Tm[i + m * n], mirror_y=bool(m))
+    return Xm, Tm
 
 
 def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=None,
@@ -109,18 +120,21 @@ def train(net: les.Net, X, T, iters: int, batch: int = 4, seed: int = 0, log=Non
     decays geometrically from lr to lr_final (default lr / 10)."""
     import torch
 
-    scale = float(torch.sqrt(torch.mean(T.double() ** 2)).item())
-    Tn = (T / scale).contiguous()
+    scale = float(np.sqrt(les.sum_squares(T) / T.numel()))
+    Tn = les.scale_div(T, scale)
     rng = np.random.default_rng(seed)
     losses = []
     n = X.shape[0]
+    nb = min(batch, n)
+    xb = torch.empty((nb,) + tuple(X.shape[1:]), device=X.device)
+    tb = torch.empty((nb,) + tuple(T.shape[1:]), device=T.device)
     for it in range(iters):
         if lr is not None:
             lf = lr / 10 if lr_final is None else lr_final
             net.set_lr(lr * (lf / lr) ** (it / max(iters - 1, 1)))
-        idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).cuda()
-        xb = X.index_select(0, idx).contiguous()
-        tb = Tn.index_select(0, idx).contiguous()
+        idx = rng.choice(n, size=nb, replace=False)
+        les.gather(X, idx, out=xb)
+        les.gather(Tn, idx, out=tb)
         want = (it % 50 == 0) or it == iters - 1
         loss = net.train_step(xb, tb, want_loss=want)
         if want:

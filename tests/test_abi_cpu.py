@@ -116,6 +116,12 @@ def test_null_handle_calls():
     assert L.les_pressure_solve_noalloc(None, None, None, 1e-5, 10, None, None) == les.LES_EINVAL
     assert L.les_last_error(None) == b""
     L.les_destroy(None)
+    # training-set preparation: argument checks come before any launch
+    assert L.lesnet_crop(None, 4, 4, 4, 3, 0, 0, 0, 4, 4, 4, 0, None, None) == les.LES_EINVAL
+    assert L.lesnet_gather(None, 8, 2, None, 1, None, None) == les.LES_EINVAL
+    assert L.lesnet_sum_squares(None, 8, None, None) == les.LES_EINVAL
+    assert L.lesnet_sum_squares(None, 0, None, None) == les.LES_EINVAL   # no output
+    assert L.lesnet_scale_div(None, 8, 1.0, None, None) == les.LES_EINVAL
 
 
 @pytest.mark.parametrize("shape", [(4, 4, 4), (5, 7, 4), (33, 17, 9), (64, 64, 32)])

@@ -103,18 +103,6 @@ def test_operator_commutes_with_y_reflection():
     assert not np.allclose(o.apply_A(p[:, :, ::-1]), Ap[:, :, ::-1], rtol=0, atol=1e-6 * np.abs(Ap).max())
 
 
-def test_mirror_y_pairs():
-    torch = pytest.importorskip("torch")
-    from paper_1504_02264_amd import warmstart as ws
-    X = torch.arange(2 * 4 * 6 * 8 * 3, dtype=torch.float32).reshape(2, 4, 6, 8, 3)
-    T = torch.arange(2 * 4 * 6 * 8, dtype=torch.float32).reshape(2, 4, 6, 8)
-    Xm, Tm = ws.mirror_y(X, T)
-    assert Xm.shape == (4, 4, 6, 8, 3) and Tm.shape == (4, 4, 6, 8)
-    assert torch.equal(Xm[:2], X) and torch.equal(Tm[:2], T)
-    assert torch.equal(Xm[3, 1, 0, 2], X[1, 1, 5, 2]) and torch.equal(Tm[2, 3, 1, 7], T[0, 3, 4, 7])
-    assert Xm.is_contiguous() and Tm.is_contiguous()
-
-
 # -------------------------------------------------------------------- P1
 @pytest.mark.parametrize("shape", [(6, 5, 4), (8, 6, 4), (12, 8, 6)])
 @pytest.mark.parametrize("bc", [URBAN_BC, ALL_WALLS])

@@ -144,15 +144,15 @@ __global__ __launch_bounds__(kNetBlock) void k_gemm(GemmArgs a) {
 // ------------------------------------------------------ convolution, LDS brick
 // The 27-tap gather (convolution forward, and its input gradient from the
 // masked output gradient) with the input staged in LDS.  A block owns
-// BZ x 4 x 16 output voxels (z, y, x) of one sample and loads the
-// (BZ+2) x 6 x 18 input voxels around them once (16-byte chunks of 8
+// BZ x BY x 16 output voxels (z, y, x) of one sample and loads the
+// (BZ+2) x (BY+2) x 18 input voxels around them once (16-byte chunks of 8
 // channels, zero outside the grid, the optional mask applied on load);
 // every A operand is then a 16-byte LDS read.  A tile (the MFMA's 16 M
 // rows) is one x-row of 16 voxels; wavefront w takes tiles w, w+4, ...;
 // each weight fragment is loaded once per K step for all of them.
-template <int NT, int CINP, int BZ>
+template <int NT, int CINP, int BZ, int BY>
 __global__ __launch_bounds__(kNetBlock) void k_conv_brick(GemmArgs a) {
-    constexpr int BX = 16, BY = 4;
+    constexpr int BX = 16;
     constexpr int HZ = BZ + 2, HY = BY + 2, HX = BX + 2;
     constexpr int CH = CINP / 8;       // 16-byte chunks per voxel
     constexpr int TPW = BZ * BY / 4;   // tiles per wavefront
@@ -1210,14 +1210,20 @@ int layer_wgrad_chunks(int up, int cin, int cout, int B, int D, int H, int W, lo
     return wgrad_brick_chunks(a, bpc);
 }
 
-// Convolutions (27-tap gathers) on the LDS-brick kernel.
+// Convolutions (27-tap gathers) on the LDS-brick kernel: bricks of
+// 4 x 4 x 16 outputs (2 x 4 x 16 for 64 input channels).  Taller bricks
+// (8 x 8 x 16 for 16 output channels, 4 x 8 x 16 for 32) feed more matrix
+// operations per K step but were slower over the whole forward pass at
+// 64 x 128 x 128 (0.676 against 0.565 ms): fewer resident blocks per
+// compute unit to hide the staging of the next brick.
 hipError_t conv_brick(hipStream_t s, const GemmArgs& a) {
     const int NT = a.cout / 16, C = a.cin_p;
-    const int bz = C == 64 ? 2 : 4;
-    const long long blocks = (long long)a.B * ((a.D + bz - 1) / bz) * ((a.H + 3) / 4) * ((a.W + 15) / 16);
+    const int bz = C == 64 ? 2 : 4, by = 4;
+    const long long blocks =
+        (long long)a.B * ((a.D + bz - 1) / bz) * ((a.H + by - 1) / by) * ((a.W + 15) / 16);
     const dim3 grid((unsigned)blocks);
 #define CB(nt, c, z) \
-    if (NT == nt && C == c) hipLaunchKernelGGL((k_conv_brick<nt, c, z>), grid, dim3(kNetBlock), 0, s, a)
+    if (NT == nt && C == c) hipLaunchKernelGGL((k_conv_brick<nt, c, z, 4>), grid, dim3(kNetBlock), 0, s, a)
     CB(1, 8, 4); else CB(1, 16, 4); else CB(1, 32, 4); else CB(1, 64, 2);
     else CB(2, 8, 4); else CB(2, 16, 4); else CB(2, 32, 4); else CB(2, 64, 2);
     else CB(4, 8, 4); else CB(4, 16, 4); else CB(4, 32, 4); else CB(4, 64, 2);

@@ -391,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_ens_sweep(const EnsInst* __restrict_
 // fused variant <TX, 16 wavefronts, KT>): parity 0 reads pd and writes pa,
 // 1 the reverse.
 template <int TX, int KT>
-__global__ __launch_bounds__(1024) void k_ens_sweep_rb(const EnsInst* __restrict__ I,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_ens_sweep_rb(
+                                                       const EnsInst* __restrict__ I,
                                                        const unsigned char* __restrict__ owner_of,
                                                        const EnsOffsets* __restrict__ O, int parity,
                                                        int it) {
@@ -405,8 +406,21 @@ __global__ __launch_bounds__(1024) void k_ens_sweep_rb(const EnsInst* __restrict
     const float* a1 = parity ? d.P.pa[1] : d.P.pd[1];
     float* b0 = parity ? d.P.pd[0] : d.P.pa[0];
     float* b1 = parity ? d.P.pd[1] : d.P.pa[1];
-    sor_rb_body<TX, 16, KT>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active,
-                            d.rel0, d.rel1, L - O->sweep[q], fused_kt(d.g, TX, 16, KT));
+    const unsigned lb = L - O->sweep[q];
+    const int kt = fused_kt(d.g, TX, 16, KT);
+    if (rb_lean_fits(d.g)) {   // members are uniform grids (stretched ones cannot join)
+        if (!active)
+            sor_rb_copy_u<TX, 16, KT>(d.g, a0, a1, b0, b1, lb, kt);
+        else if (acc)
+            sor_rb_body_u<TX, 16, KT, true>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, d.rel0, d.rel1,
+                                            lb, kt);
+        else
+            sor_rb_body_u<TX, 16, KT, false>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, d.rel0, d.rel1,
+                                             lb, kt);
+        return;
+    }
+    sor_rb_body<TX, 16, KT>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active, d.rel0,
+                            d.rel1, lb, kt);
 }
 
 // Launch of k_ens_sweep_rb for fused variant v over `grid` blocks.

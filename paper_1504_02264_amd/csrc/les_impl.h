@@ -326,7 +326,7 @@ inline bool sor_fused2(int variant) { return variant >= kFirstRb2Variant; }
 // a buffer resource whose base sits 2 SP elements before the array, so the
 // array and that lead must span at most 4 GiB; larger grids take the
 // general form.
-inline bool rb_lean_fits(const Geo& g) {
+__host__ __device__ inline bool rb_lean_fits(const Geo& g) {
     return (unsigned long long)(g.ctot + 2 * g.SP) * 4ull <= 0xFFFFFFFFull;
 }
 

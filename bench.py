@@ -688,6 +688,11 @@ def main():
             "launch_us": t_launch * 1e6,
             "iterations_per_launch": iters_per_launch,
             "us_per_iteration": t_launch * 1e6 / iters_per_launch,
+            # a launch of two iterations moves the bytes of one: the rate a
+            # one-iteration kernel (12 B/cell) would need for the same
+            # iteration time, as a fraction of the peak
+            "per_iteration_equivalent_frac": (12.0 * cells / (t_launch / iters_per_launch) / 1e9 / HBM_PEAK_GBS
+                                              if fused else None),
             "timed_launches": int(sor_n),
         }
         out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in timing.items()

@@ -144,14 +144,15 @@ struct TendArgs {
 // March of a block over tendency planes [kb, ke): step p loads velocity
 // plane p+1 into registers (issued a step ahead), publishes plane p, then
 // after a barrier computes nu_t on plane p-1 and after a second barrier
-// the tendency on plane p-2.  Five velocity slots keep the slot written at
-// step p (last read by the tendency of step p-2) clear of readers, and
-// three nu_t slots likewise, so two barriers per step suffice.
+// the tendency on plane p-2; a third barrier ends the step.  Four velocity
+// slots then keep the slot written at step p (last read by the tendency of
+// step p-1) clear of readers, and three nu_t slots likewise; the smaller
+// ring (47 KB) lets three blocks share a compute unit instead of two.
 constexpr int kTileX = 64, kTileY = 8;
 constexpr int kTileThreads = kTileX * kTileY;   // one wavefront per tile row
 constexpr int kTileLX = kTileX + 4, kTileLY = kTileY + 4;   // velocity: two-cell ring
 constexpr int kTileNX = kTileX + 2, kTileNY = kTileY + 2;   // nu_t: one-cell ring
-constexpr int kTileVS = 5;   // velocity plane slots
+constexpr int kTileVS = 4;   // velocity plane slots
 constexpr int kTileVel = kTileLX * kTileLY;     // entries of one velocity plane
 constexpr int kTileNut = kTileNX * kTileNY;
 
@@ -348,6 +349,7 @@ __device__ __forceinline__ void step_tile_body(const Geo& g, const TendArgs& A, 
                 A.fw[e] = F;
             }
         }
+        __syncthreads();   // the tendency's reads of this step end before the next publish
     }
 }
 

@@ -197,34 +197,68 @@ __global__ __launch_bounds__(kNetBlock) void k_conv_brick(GemmArgs a) {
     for (int tw = 0; tw < TPW; ++tw)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[tw][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // The K loop, fully unrolled (K = 27 taps x CINP channels, padded to a
+    // multiple of 32): lane group l >> 4 holds K values kgrp .. kgrp + 7 of
+    // each step, so its tap and channel chunk are compile-time per step up to
+    // the lane group, and the brick offset of a tap is a constant.  K values
+    // past 27 CINP (the padding of the last step) read tap 26 of the brick
+    // against weights that are zero there (the weight layouts pad with
+    // zeros), so no operand is masked.
+    constexpr int KP = (27 * CINP + 31) / 32 * 32;
+    auto tap_off = [](int t) {   // brick offset (16-byte chunks) of tap t, window shifted by one
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        return ((dz * HY + dy) * HX + dx) * CH;
+    };
+    const int lg = l >> 4;
+    int tb[TPW];   // brick chunk of each tile's lane voxel at tap 0, channel chunk 0
+#pragma unroll
+    for (int tw = 0; tw < TPW; ++tw) {
+        const int tile = wave + 4 * tw;
+        tb[tw] = (((tile / BY) * HY + (tile % BY)) * HX + m) * CH;
+    }
     // weight fragments one K step ahead: the next step's loads are in
     // flight while this step's matrix operations run
     bf16x8 bnext[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
-        bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + kgrp);
-    for (int k0 = 0; k0 < a.kp; k0 += 32) {
-        const int k = k0 + kgrp;
+        bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * KP + kgrp);
+    auto kstep = [&](int st) {
         bf16x8 bv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) bv[nt] = bnext[nt];
-        if (k0 + 32 < a.kp) {
+        if (st + 1 < KP / 32) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * a.kp + k + 32);
+                bnext[nt] = *reinterpret_cast<const bf16x8*>(a.wt + (size_t)(16 * nt + (l & 15)) * KP +
+                                                             32 * (st + 1) + kgrp);
         }
-        const bool kok = k < 27 * CINP;
-        const int t = k / CINP, ci = k % CINP;
-        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // 0..2: the window is shifted by one
+        // this lane group's tap and channel chunk: k = 32 st + 8 lg
+        int off;
+        if constexpr (CINP >= 32) {   // one tap per step for every lane: a block-uniform offset
+            const int t = min(32 * st / CINP, 26);
+            off = tap_off(t) + ((32 * st) % CINP) / 8 + lg;
+        } else if constexpr (CINP == 16) {
+            const int t0 = min(2 * st, 26), t1 = min(2 * st + 1, 26);
+            off = (lg >= 2 ? tap_off(t1) : tap_off(t0)) + (lg & 1);
+        } else {   // CINP == 8: four taps per step
+            const int t0 = min(4 * st, 26), t1 = min(4 * st + 1, 26), t2 = min(4 * st + 2, 26),
+                      t3 = min(4 * st + 3, 26);
+            off = lg == 0 ? tap_off(t0) : (lg == 1 ? tap_off(t1) : (lg == 2 ? tap_off(t2) : tap_off(t3)));
+        }
 #pragma unroll
         for (int tw = 0; tw < TPW; ++tw) {
-            const int tile = wave + 4 * tw;
-            const int tz = tile / BY, ty = tile % BY;
-            const bf16x8 av = kok ? brick[(((tz + dz) * HY + (ty + dy)) * HX + (m + dx)) * CH + ci / 8] : zero;
+            const bf16x8 av = brick[tb[tw] + off];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
                 acc[tw][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[tw][nt], 0, 0, 0);
         }
+    };
+    if constexpr (CINP >= 32) {
+#pragma unroll 1
+        for (int st = 0; st < KP / 32; ++st) kstep(st);   // uniform tap: scalar offsets
+    } else {
+#pragma unroll
+        for (int st = 0; st < KP / 32; ++st) kstep(st);   // per-lane-group taps: constants once unrolled
     }
 #pragma unroll
     for (int tw = 0; tw < TPW; ++tw) {
@@ -1237,7 +1271,7 @@ hipError_t conv_brick(hipStream_t s, const GemmArgs& a) {
 // wavefront while the grid keeps at least 1024 blocks, else 1.
 hipError_t gemm(hipStream_t s, const GemmArgs& a) {
     if (a.gather == G_TAP27 && !a.scatter_child &&
-        (a.cin_p == 8 || a.cin_p == 16 || a.cin_p == 32 || a.cin_p == 64))
+        (a.cin_p == 8 || a.cin_p == 16 || a.cin_p == 32 || a.cin_p == 64) && a.kp == (27 * a.cin_p + 31) / 32 * 32)
         return conv_brick(s, a);
     const long long M = (long long)a.B * a.D * a.H * a.W;
     const int NT = a.cout / 16;

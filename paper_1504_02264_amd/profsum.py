@@ -18,7 +18,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOR_SOURCES = ("csrc/les_bodies.h", "csrc/kernels_sor.hip")
+SOR_SOURCES = ("csrc/sor_bodies.h", "csrc/kernels_sor.hip")
 
 
 def sor_source_hash() -> str:

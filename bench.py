@@ -224,7 +224,8 @@ def bench_warm_start_c2(args, les, torch):
     import numpy as np
     from paper_1504_02264_amd import warmstart as ws
     smooth = 16
-    conv = {"max_iter": BENCH_MAX_ITER}
+    conv = {"max_iter": BENCH_MAX_ITER, "check_every": args.check_every,
+            "rebase_every": max(1, 128 // args.check_every)}
     Xs, Ts = [], []
     t0 = time.perf_counter()
     for seed in (11, 12, 13, 14):
@@ -261,7 +262,8 @@ def bench_warm_start_c2(args, les, torch):
         "steps": args.steps,
         "dtype": "f32 LES, bf16 network",
         "data": "synthetic",
-        "config": {"workload": "C2 300x300x90 urban LES, every solve to relative residual 1e-5; network "
+        "config": {"workload": f"C2 300x300x90 urban LES, every solve to relative residual 1e-5 (checked every "
+                               f"{args.check_every} iterations); network "
                                "trained on 8 random 64x128x128 crops per step of building seeds 11-14 (converged "
                                "targets, 64 crops and their mirror images in y, 3000 Adam steps), evaluated on "
                                "seeds 21-22 after one plain step", "collect_s": collect_s, "train_s": train_s,

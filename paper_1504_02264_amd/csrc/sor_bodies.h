@@ -966,8 +966,8 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 const float dxy = P.dx + dyy[t];
-                P.im[t] = ok ? 1.0f / (dxy + dz_mid) : 0.f;
-                P.ie[t] = ok ? 1.0f / (dxy + dz_end) : 0.f;
+                P.im[t] = ok && row_ok[t] ? 1.0f / (dxy + dz_mid) : 0.f;
+                P.ie[t] = ok && row_ok[t] ? 1.0f / (dxy + dz_end) : 0.f;
             }
             P.own = ok && out_lane;
         };
@@ -979,12 +979,12 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     const unsigned sp4 = (unsigned)g.SP * 4u;
     // scalar byte offset of row t's origin on plane p, p clamped into the
     // planes -1 .. nz (those outside read the ghost planes' zeros)
-    // (rows outside the grid address the nearest row inside it: their loads
-    // stay in bounds and their values are never used)
+    // (rows outside the grid address the ghost row -1, which holds zeros in
+    // every array; with cn1 = 0 their updates are exactly 0)
     unsigned so_row[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-        const int jc = min(max(jr[t], 0), g.ny - 1);
+        const int jc = row_ok[t] ? jr[t] : -1;
         so_row[t] = (unsigned)(((long long)g.S + ((long long)jc + 1) * g.S + ii0 - 1 - g.S - g.SP + 2 * g.SP) * 4);
     }
     auto so_at = [&](int t, int p) -> unsigned {
@@ -1028,9 +1028,24 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     fetch(qs + 1, po, ld[1]);
     __syncthreads();   // guard rows written
 
-    // step q = qs + T: A on q, B on q-1, C on q-2, D on q-3
-    auto step = [&](auto tc, int q, const Par& P, const Par& PN) {
+    // step q = qs + T: A on q, B on q-1, C on q-2, D on q-3.  Every stage
+    // runs on every row and plane (rows outside the grid and planes outside
+    // it come out as exact zeros through cn1 = 0), so no stage branches.
+    // INT: all four planes lie in 1 .. nz-2, so cn1 is the interior one,
+    // and the second iteration is live.
+    auto step = [&](auto tc, auto ic, int q, const Par& P) {
         constexpr int T = decltype(tc)::value;
+        constexpr bool INT = decltype(ic)::value;
+        // cn1 of row t on plane pl: 0 outside the grid's planes, where the
+        // update then returns p = 0 exactly (the ghost planes hold zeros)
+        auto inv_at = [&](int t, int pl) -> float {
+            if constexpr (INT) {
+                return P.im[t];
+            } else {
+                const float c = (pl == 0 || pl == g.nz - 1) ? P.ie[t] : P.im[t];
+                return (pl >= 0 && pl < g.nz) ? c : 0.f;
+            }
+        };
         constexpr int M0 = T % 3, M1 = (T + 2) % 3, M2 = (T + 1) % 3;   // planes q, q-1, q-2 (q-3: M0)
         constexpr int S0 = T & 1, S1 = (T + 1) & 1;                     // ring slots of q, q-1 (q-2: S0, q-3: S1)
         const int qb = q - 1, qc = q - 2, qd = q - 3;
@@ -1038,15 +1053,11 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
         // ---- A: colour 0, iteration 1, plane q
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            float v = 0.f;
-            if (row_ok[t] && q >= 0 && q < g.nz) {
-                const float inv = (q == 0 || q == g.nz - 1) ? P.ie[t] : P.im[t];
-                float rt;
-                v = sor_relax(sor_nb(oc[M0][t], ldc[t].xn, ldc[t].south, ldc[t].north, oc[M1][t], ldc[t].up, cx, cy,
-                                     cz),
-                              inv, ldc[t].rr0, ldc[t].p0, omega, rt);
-                if (ACC && acc1 && out_row[t] && P.own && q >= k_begin && q < k_end) sC += (double)rt * (double)rt;
-            }
+            float rt;
+            const float v = sor_relax(sor_nb(oc[M0][t], ldc[t].xn, ldc[t].south, ldc[t].north, oc[M1][t],
+                                             ldc[t].up, cx, cy, cz),
+                                      inv_at(t, q), ldc[t].rr0, ldc[t].p0, omega, rt);
+            if (ACC && acc1 && out_row[t] && q >= k_begin && q < k_end && P.own) sC += (double)rt * (double)rt;
             av[M0][t] = v;
             r0v[M0][t] = ldc[t].rr0;
             r1v[M1][t] = ldc[t].rr1;
@@ -1057,46 +1068,38 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
         // ---- B: colour 1, iteration 1, plane q-1
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            float v = 0.f;
-            if (row_ok[t] && qb >= 0 && qb < g.nz) {
-                const float oth = lane_perm(P.src, av[M1][t]);
-                const int rw = wv + 16 * t + 1;
-                const float ps = ringA[S1][rw - 1][lane], pn = ringA[S1][rw + 1][lane];
-                const bool endp = qb == 0 || qb == g.nz - 1;
-                const float inv = endp ? P.ie[t] : P.im[t];
-                float rt;
-                v = sor_relax(sor_nb(av[M1][t], oth, ps, pn, av[M2][t], av[M0][t], cx, cy, cz), inv, r1v[M1][t],
-                              oc[M1][t], omega, rt);
-                if (ACC && acc1 && out_row[t] && P.own && qb >= k_begin && qb < k_end) {
-                    const double rd = (double)rt;
-                    sD += rd * rd;
-                    const double dd = (double)((P.dx + dyy[t]) + (endp ? dz_end : dz_mid)) * rd;
-                    dD += dd * dd;
-                }
+            const float oth = lane_perm(P.src, av[M1][t]);
+            const int rw = wv + 16 * t + 1;
+            const float ps = ringA[S1][rw - 1][lane], pn = ringA[S1][rw + 1][lane];
+            float rt;
+            const float v = sor_relax(sor_nb(av[M1][t], oth, ps, pn, av[M2][t], av[M0][t], cx, cy, cz),
+                                      inv_at(t, qb), r1v[M1][t], oc[M1][t], omega, rt);
+            if (ACC && acc1 && out_row[t] && qb >= k_begin && qb < k_end && P.own) {
+                const double rd = (double)rt;
+                sD += rd * rd;
+                const bool endp = !INT && (qb == 0 || qb == g.nz - 1);
+                const double dd = (double)((P.dx + dyy[t]) + (endp ? dz_end : dz_mid)) * rd;
+                dD += dd * dd;
             }
             bv[M1][t] = v;
-            ringB[S1][wv + 16 * t + 1][lane] = v;
+            ringB[S1][rw][lane] = v;
         }
         // ---- C: colour 0, iteration 2, plane q-2
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            float v = 0.f;
-            if (row_ok[t] && qc >= 0 && qc < g.nz) {
-                const float oth = lane_perm(P.src, bv[M2][t]);
-                const int rw = wv + 16 * t + 1;
-                const float ps = ringB[S0][rw - 1][lane], pn = ringB[S0][rw + 1][lane];
-                const float inv = (qc == 0 || qc == g.nz - 1) ? P.ie[t] : P.im[t];
-                float rt = 0.f;
-                const float w = sor_relax(sor_nb(bv[M2][t], oth, ps, pn, bv[M0][t], bv[M1][t], cx, cy, cz), inv,
-                                          r0v[M2][t], av[M2][t], omega, rt);
-                v = second ? w : av[M2][t];
-                if (out_row[t] && qc >= k_begin && qc < k_end) {
-                    if (P.own) bst(rb0, lc, so_at(t, qc), v);
-                    if (ACC && acc2 && P.own) sC += (double)rt * (double)rt;
-                }
+            const float oth = lane_perm(P.src, bv[M2][t]);
+            const int rw = wv + 16 * t + 1;
+            const float ps = ringB[S0][rw - 1][lane], pn = ringB[S0][rw + 1][lane];
+            float rt;
+            const float w = sor_relax(sor_nb(bv[M2][t], oth, ps, pn, bv[M0][t], bv[M1][t], cx, cy, cz),
+                                      inv_at(t, qc), r0v[M2][t], av[M2][t], omega, rt);
+            const float v = (INT || second) ? w : av[M2][t];
+            if (out_row[t] && qc >= k_begin && qc < k_end && P.own) {
+                bst(rb0, lc, so_at(t, qc), v);
+                if (ACC && acc2) sC += (double)rt * (double)rt;
             }
             cv[M2][t] = v;
-            ringC[S0][wv + 16 * t + 1][lane] = v;
+            ringC[S0][rw][lane] = v;
         }
         // ---- D: colour 1, iteration 2, plane q-3
 #pragma unroll
@@ -1105,12 +1108,12 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
                 const float oth = lane_perm(P.src, cv[M0][t]);
                 const int rw = wv + 16 * t + 1;
                 const float ps = ringC[S1][rw - 1][lane], pn = ringC[S1][rw + 1][lane];
-                const bool endp = qd == 0 || qd == g.nz - 1;
+                const bool endp = !INT && (qd == 0 || qd == g.nz - 1);
                 const float inv = endp ? P.ie[t] : P.im[t];
                 float rt = 0.f;
                 const float w = sor_relax(sor_nb(cv[M0][t], oth, ps, pn, cv[M1][t], cv[M2][t], cx, cy, cz), inv,
                                           r1v[M0][t], bv[M0][t], omega, rt);
-                const float v = second ? w : bv[M0][t];
+                const float v = (INT || second) ? w : bv[M0][t];
                 if (P.own) {
                     bst(rb1, lc, so_at(t, qd), v);
                     if (ACC && acc2) {
@@ -1130,21 +1133,35 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     using I3 = std::integral_constant<int, 3>;
     using I4 = std::integral_constant<int, 4>;
     using I5 = std::integral_constant<int, 5>;
+    using Gen = std::false_type;
+    using Int = std::true_type;
     const int q_last = k_end + 2;
     int q = qs;
-    for (; q + 5 <= q_last; q += 6) {
-        step(I0{}, q, pe, po);
-        step(I1{}, q + 1, po, pe);
-        step(I2{}, q + 2, pe, po);
-        step(I3{}, q + 3, po, pe);
-        step(I4{}, q + 4, pe, po);
-        step(I5{}, q + 5, po, pe);
+    auto gen6 = [&](int q) {
+        step(I0{}, Gen{}, q, pe);
+        step(I1{}, Gen{}, q + 1, po);
+        step(I2{}, Gen{}, q + 2, pe);
+        step(I3{}, Gen{}, q + 3, po);
+        step(I4{}, Gen{}, q + 4, pe);
+        step(I5{}, Gen{}, q + 5, po);
+    };
+    // groups of six steps: those whose planes q-3 .. q+5 all lie in 1 .. nz-2
+    // form one run in the middle of the march (uniform bounds)
+    for (; q + 5 <= q_last && q - 3 < 1; q += 6) gen6(q);
+    for (; second && q + 5 <= q_last && q + 5 <= g.nz - 2; q += 6) {
+        step(I0{}, Int{}, q, pe);
+        step(I1{}, Int{}, q + 1, po);
+        step(I2{}, Int{}, q + 2, pe);
+        step(I3{}, Int{}, q + 3, po);
+        step(I4{}, Int{}, q + 4, pe);
+        step(I5{}, Int{}, q + 5, po);
     }
-    if (q <= q_last) step(I0{}, q, pe, po);
-    if (q + 1 <= q_last) step(I1{}, q + 1, po, pe);
-    if (q + 2 <= q_last) step(I2{}, q + 2, pe, po);
-    if (q + 3 <= q_last) step(I3{}, q + 3, po, pe);
-    if (q + 4 <= q_last) step(I4{}, q + 4, pe, po);
+    for (; q + 5 <= q_last; q += 6) gen6(q);
+    if (q <= q_last) step(I0{}, Gen{}, q, pe);
+    if (q + 1 <= q_last) step(I1{}, Gen{}, q + 1, po);
+    if (q + 2 <= q_last) step(I2{}, Gen{}, q + 2, pe);
+    if (q + 3 <= q_last) step(I3{}, Gen{}, q + 3, po);
+    if (q + 4 <= q_last) step(I4{}, Gen{}, q + 4, pe);
     if (ACC) {
         const double va = wave_sum(sC), vb = wave_sum(sD), vd = wave_sum(dD);
         if (lane == 0) {

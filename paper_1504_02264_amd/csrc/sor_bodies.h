@@ -890,6 +890,9 @@ struct Rb2Smem {
     double red3[3][16];
 };
 
+// plane modes of a two-iteration step (below): general, interior
+constexpr int kQGen = -1000, kQInt = -2000;
+
 template <bool ACC>
 __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const float* __restrict__ a0,
                                                const float* __restrict__ a1,
@@ -1031,21 +1034,42 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     // step q = qs + T: A on q, B on q-1, C on q-2, D on q-3.  Every stage
     // runs on every row and plane (rows outside the grid and planes outside
     // it come out as exact zeros through cn1 = 0), so no stage branches.
-    // INT: all four planes lie in 1 .. nz-2, so cn1 is the interior one,
-    // and the second iteration is live.
-    auto step = [&](auto tc, auto ic, int q, const Par& P) {
+    // The plane mode QM: kQInt when all four planes lie in 1 .. nz-2 (cn1 is
+    // the interior one), a plane number when q is known at compile time (the
+    // bottom of the column, with nz >= 10 so that no plane there is nz-1),
+    // kQGen otherwise; the first two imply a live second iteration.
+    auto step = [&](auto tc, auto qm, int q, const Par& P) {
         constexpr int T = decltype(tc)::value;
-        constexpr bool INT = decltype(ic)::value;
-        // cn1 of row t on plane pl: 0 outside the grid's planes, where the
-        // update then returns p = 0 exactly (the ghost planes hold zeros)
-        auto inv_at = [&](int t, int pl) -> float {
+        constexpr int QM = decltype(qm)::value;
+        constexpr bool INT = QM == kQInt;
+        constexpr bool KNOWN = QM > kQGen;
+        constexpr bool LIVE2 = INT || KNOWN;
+        // cn1 of row t on plane pl = q - S: 0 outside the grid's planes, where
+        // the update then returns p = 0 exactly (the ghost planes hold zeros)
+        auto inv_at = [&](auto sc, int t, int pl) -> float {
+            constexpr int S = decltype(sc)::value;
             if constexpr (INT) {
                 return P.im[t];
+            } else if constexpr (KNOWN) {
+                constexpr int pk = QM - S;
+                if constexpr (pk < 0) return 0.f;
+                else if constexpr (pk == 0) return P.ie[t];
+                else return P.im[t];
             } else {
                 const float c = (pl == 0 || pl == g.nz - 1) ? P.ie[t] : P.im[t];
                 return (pl >= 0 && pl < g.nz) ? c : 0.f;
             }
         };
+        auto end_plane = [&](auto sc, int pl) -> bool {
+            constexpr int S = decltype(sc)::value;
+            if constexpr (INT) return false;
+            else if constexpr (KNOWN) return QM - S == 0;
+            else return pl == 0 || pl == g.nz - 1;
+        };
+        using S0c = std::integral_constant<int, 0>;
+        using S1c = std::integral_constant<int, 1>;
+        using S2c = std::integral_constant<int, 2>;
+        using S3c = std::integral_constant<int, 3>;
         constexpr int M0 = T % 3, M1 = (T + 2) % 3, M2 = (T + 1) % 3;   // planes q, q-1, q-2 (q-3: M0)
         constexpr int S0 = T & 1, S1 = (T + 1) & 1;                     // ring slots of q, q-1 (q-2: S0, q-3: S1)
         const int qb = q - 1, qc = q - 2, qd = q - 3;
@@ -1056,7 +1080,7 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
             float rt;
             const float v = sor_relax(sor_nb(oc[M0][t], ldc[t].xn, ldc[t].south, ldc[t].north, oc[M1][t],
                                              ldc[t].up, cx, cy, cz),
-                                      inv_at(t, q), ldc[t].rr0, ldc[t].p0, omega, rt);
+                                      inv_at(S0c{}, t, q), ldc[t].rr0, ldc[t].p0, omega, rt);
             if (ACC && acc1 && out_row[t] && q >= k_begin && q < k_end && P.own) sC += (double)rt * (double)rt;
             av[M0][t] = v;
             r0v[M0][t] = ldc[t].rr0;
@@ -1073,11 +1097,11 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
             const float ps = ringA[S1][rw - 1][lane], pn = ringA[S1][rw + 1][lane];
             float rt;
             const float v = sor_relax(sor_nb(av[M1][t], oth, ps, pn, av[M2][t], av[M0][t], cx, cy, cz),
-                                      inv_at(t, qb), r1v[M1][t], oc[M1][t], omega, rt);
+                                      inv_at(S1c{}, t, qb), r1v[M1][t], oc[M1][t], omega, rt);
             if (ACC && acc1 && out_row[t] && qb >= k_begin && qb < k_end && P.own) {
                 const double rd = (double)rt;
                 sD += rd * rd;
-                const bool endp = !INT && (qb == 0 || qb == g.nz - 1);
+                const bool endp = end_plane(S1c{}, qb);
                 const double dd = (double)((P.dx + dyy[t]) + (endp ? dz_end : dz_mid)) * rd;
                 dD += dd * dd;
             }
@@ -1092,8 +1116,8 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
             const float ps = ringB[S0][rw - 1][lane], pn = ringB[S0][rw + 1][lane];
             float rt;
             const float w = sor_relax(sor_nb(bv[M2][t], oth, ps, pn, bv[M0][t], bv[M1][t], cx, cy, cz),
-                                      inv_at(t, qc), r0v[M2][t], av[M2][t], omega, rt);
-            const float v = (INT || second) ? w : av[M2][t];
+                                      inv_at(S2c{}, t, qc), r0v[M2][t], av[M2][t], omega, rt);
+            const float v = (LIVE2 || second) ? w : av[M2][t];
             if (out_row[t] && qc >= k_begin && qc < k_end && P.own) {
                 bst(rb0, lc, so_at(t, qc), v);
                 if (ACC && acc2) sC += (double)rt * (double)rt;
@@ -1108,12 +1132,12 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
                 const float oth = lane_perm(P.src, cv[M0][t]);
                 const int rw = wv + 16 * t + 1;
                 const float ps = ringC[S1][rw - 1][lane], pn = ringC[S1][rw + 1][lane];
-                const bool endp = !INT && (qd == 0 || qd == g.nz - 1);
-                const float inv = endp ? P.ie[t] : P.im[t];
+                const bool endp = end_plane(S3c{}, qd);
+                const float inv = inv_at(S3c{}, t, qd);
                 float rt = 0.f;
                 const float w = sor_relax(sor_nb(cv[M0][t], oth, ps, pn, cv[M1][t], cv[M2][t], cx, cy, cz), inv,
                                           r1v[M0][t], bv[M0][t], omega, rt);
-                const float v = (INT || second) ? w : bv[M0][t];
+                const float v = (LIVE2 || second) ? w : bv[M0][t];
                 if (P.own) {
                     bst(rb1, lc, so_at(t, qd), v);
                     if (ACC && acc2) {
@@ -1133,10 +1157,8 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
     using I3 = std::integral_constant<int, 3>;
     using I4 = std::integral_constant<int, 4>;
     using I5 = std::integral_constant<int, 5>;
-    using Gen = std::false_type;
-    using Int = std::true_type;
-    const int q_last = k_end + 2;
-    int q = qs;
+    using Gen = std::integral_constant<int, kQGen>;
+    using Int = std::integral_constant<int, kQInt>;
     auto gen6 = [&](int q) {
         step(I0{}, Gen{}, q, pe);
         step(I1{}, Gen{}, q + 1, po);
@@ -1145,19 +1167,43 @@ __device__ __forceinline__ void sor_rb2_body_u(Rb2Smem& sm, const Geo& g, const 
         step(I4{}, Gen{}, q + 4, pe);
         step(I5{}, Gen{}, q + 5, po);
     };
-    // groups of six steps: those whose planes q-3 .. q+5 all lie in 1 .. nz-2
-    // form one run in the middle of the march (uniform bounds)
-    for (; q + 5 <= q_last && q - 3 < 1; q += 6) gen6(q);
-    for (; second && q + 5 <= q_last && q + 5 <= g.nz - 2; q += 6) {
+    auto int6 = [&](int q) {
         step(I0{}, Int{}, q, pe);
         step(I1{}, Int{}, q + 1, po);
         step(I2{}, Int{}, q + 2, pe);
         step(I3{}, Int{}, q + 3, po);
         step(I4{}, Int{}, q + 4, pe);
         step(I5{}, Int{}, q + 5, po);
+    };
+    auto pl = [](auto c) { return std::integral_constant<int, decltype(c)::value>{}; };
+    const int q_last = k_end + 2;
+    int q = qs;
+    // the bottom column (qs = -3): its first twelve steps, planes -6 .. 8,
+    // with every plane known at compile time
+    if (k_begin == 0 && second && q_last >= qs + 11 && g.nz >= 10) {
+        step(I0{}, pl(std::integral_constant<int, -3>{}), -3, pe);
+        step(I1{}, pl(std::integral_constant<int, -2>{}), -2, po);
+        step(I2{}, pl(std::integral_constant<int, -1>{}), -1, pe);
+        step(I3{}, pl(std::integral_constant<int, 0>{}), 0, po);
+        step(I4{}, pl(std::integral_constant<int, 1>{}), 1, pe);
+        step(I5{}, pl(std::integral_constant<int, 2>{}), 2, po);
+        step(I0{}, pl(std::integral_constant<int, 3>{}), 3, pe);
+        step(I1{}, pl(std::integral_constant<int, 4>{}), 4, po);
+        step(I2{}, pl(std::integral_constant<int, 5>{}), 5, pe);
+        step(I3{}, pl(std::integral_constant<int, 6>{}), 6, po);
+        step(I4{}, pl(std::integral_constant<int, 7>{}), 7, pe);
+        step(I5{}, pl(std::integral_constant<int, 8>{}), 8, po);
+        q = qs + 12;
     }
+    // groups of six steps: those whose planes q-3 .. q+5 all lie in 1 .. nz-2
+    // form one run in the middle of the march (uniform bounds)
+    for (; q + 5 <= q_last && q - 3 < 1; q += 6) gen6(q);
+    for (; second && q + 5 <= q_last && q + 5 <= g.nz - 2; q += 6) int6(q);
     for (; q + 5 <= q_last; q += 6) gen6(q);
-    if (q <= q_last) step(I0{}, Gen{}, q, pe);
+    if (q <= q_last) {
+        if (second && q - 3 >= 1 && q <= g.nz - 2) step(I0{}, Int{}, q, pe);
+        else step(I0{}, Gen{}, q, pe);
+    }
     if (q + 1 <= q_last) step(I1{}, Gen{}, q + 1, po);
     if (q + 2 <= q_last) step(I2{}, Gen{}, q + 2, pe);
     if (q + 3 <= q_last) step(I3{}, Gen{}, q + 3, po);

@@ -425,15 +425,16 @@ int les_ensemble_step(les_ensemble* e, int32_t nsteps, les_ensemble_stats* st, i
  * reps pairs of launches each, and uses the fastest from the next step on.
  * les_ensemble_tuning reports the choice and the microseconds per
  * half-sweep of every variant (us_per_sweep[LES_NUM_SOR_VARIANTS]; for
- * 8-11 half a fused iteration, 0 where not timed).  The fused variants 8-11
- * run only in the batched mode with an even check_every and only as
- * the ensemble's choice (les_ensemble_autotune or les_ensemble_set_variant):
- * otherwise a member set to one runs its grid's default half-sweep, as
- * does a member whose own choice is a two-iteration variant (12-13). */
+ * 8-11 half a fused iteration, for 12-13 a quarter of a two-iteration
+ * launch, 0 where not timed).  The fused variants run only in the batched
+ * mode and only as the ensemble's choice (les_ensemble_autotune or
+ * les_ensemble_set_variant): 8-11 with an even check_every, 12-13 with a
+ * check_every that is a multiple of 4 and every member a uniform grid whose
+ * colour arrays span less than 2 GiB; otherwise a member set to one runs
+ * its grid's default half-sweep. */
 int les_ensemble_autotune(les_ensemble* e, int32_t reps);
-/* The sweep variant every member runs (0 .. 11), or -1: each member its
- * own; from the next step on.  LES_EINVAL otherwise (including the
- * two-iteration variants 12-13, which are single-handle only). */
+/* The sweep variant every member runs (0 .. LES_NUM_SOR_VARIANTS-1), or
+ * -1: each member its own; from the next step on.  LES_EINVAL otherwise. */
 int les_ensemble_set_variant(les_ensemble* e, int32_t variant);
 int les_ensemble_tuning(const les_ensemble* e, int32_t* variant, double* us_per_sweep);
 const char* les_ensemble_last_error(const les_ensemble* e);

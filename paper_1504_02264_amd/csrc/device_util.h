@@ -20,6 +20,21 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
     return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// A copy of a block-uniform object whose every 32-bit word passes through
+// readfirstlane, so that the compiler keeps it (and what is computed from it,
+// such as buffer offsets) in scalar registers even when it was loaded from
+// memory the compiler cannot prove unchanged.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T& src) {
+    static_assert(sizeof(T) % 4 == 0, "uniform_copy: whole 32-bit words");
+    T dst;
+    const int* s = reinterpret_cast<const int*>(&src);
+    int* d = reinterpret_cast<int*>(&dst);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+    return dst;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -51,6 +51,7 @@ struct EnsInst {
     int max_iter, K, R, variant, singular, inflow;
     unsigned nsweep, nred;
     int kt_tile;        // planes per block of the fused tendency pass
+    int kt_rb2;         // planes per block of a two-iteration sweep launch
 };
 
 // Per-member state that changes from step to step (device memory).
@@ -397,7 +398,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                                                        const EnsOffsets* __restrict__ O, int parity,
                                                        int it) {
     const unsigned L = xcd_block(blockIdx.x, gridDim.x);
-    const int q = owner_of[L];
+    // the member is block-uniform: keep its descriptor in scalar registers
+    const int q = __builtin_amdgcn_readfirstlane((int)owner_of[L]);
     const EnsInst& d = I[q];
     bool acc;
     const bool active = sweep_active(d.ctl, it, acc);
@@ -407,20 +409,85 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     float* b0 = parity ? d.P.pd[0] : d.P.pa[0];
     float* b1 = parity ? d.P.pd[1] : d.P.pa[1];
     const unsigned lb = L - O->sweep[q];
-    const int kt = fused_kt(d.g, TX, 16, KT);
-    if (rb_lean_fits(d.g)) {   // members are uniform grids (stretched ones cannot join)
+    // the geometry by value, as a kernel argument would be: a reference into
+    // global memory may alias the sweep's stores, and its fields are then
+    // reloaded and its helpers kept in memory
+    const Geo g = d.g;
+    const float* r0 = d.P.r0[0];
+    const float* r1 = d.P.r0[1];
+    const float omega = d.omega;
+    const int kt = fused_kt(g, TX, 16, KT);
+    if (rb_lean_fits(g)) {   // members are uniform grids (stretched ones cannot join)
         if (!active)
-            sor_rb_copy_u<TX, 16, KT>(d.g, a0, a1, b0, b1, lb, kt);
+            sor_rb_copy_u<TX, 16, KT>(g, a0, a1, b0, b1, lb, kt);
         else if (acc)
-            sor_rb_body_u<TX, 16, KT, true>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, d.rel0, d.rel1,
-                                            lb, kt);
+            sor_rb_body_u<TX, 16, KT, true>(g, a0, a1, r0, r1, b0, b1, omega, d.rel0, d.rel1, lb, kt);
         else
-            sor_rb_body_u<TX, 16, KT, false>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, d.rel0, d.rel1,
-                                             lb, kt);
+            sor_rb_body_u<TX, 16, KT, false>(g, a0, a1, r0, r1, b0, b1, omega, d.rel0, d.rel1, lb, kt);
         return;
     }
-    sor_rb_body<TX, 16, KT>(d.g, a0, a1, d.P.r0[0], d.P.r0[1], b0, b1, d.omega, active && acc, !active, d.rel0,
-                            d.rel1, lb, kt);
+    sor_rb_body<TX, 16, KT>(g, a0, a1, r0, r1, b0, b1, omega, active && acc, !active, d.rel0, d.rel1, lb, kt);
+}
+
+// Two fused red-black iterations of every member (local iterations it and
+// it + 1; the two-iteration variants, members all on the uniform-grid lean
+// form): parity 0 reads pd and writes pa, parity 1 the reverse.  A member's
+// blocks run k_sor_rb2's tiles on its own block range.
+__global__ __launch_bounds__(1024) void k_ens_sweep_rb2(const EnsInst* __restrict__ I,
+                                                        const unsigned char* __restrict__ owner_of,
+                                                        const EnsOffsets* __restrict__ O, int parity, int it) {
+    const unsigned L = xcd_block(blockIdx.x, gridDim.x);
+    const int q = __builtin_amdgcn_readfirstlane((int)owner_of[L]);
+    const EnsInst& d = I[q];
+    bool acc1, acc2;
+    const bool a1s = sweep_active(d.ctl, it, acc1);
+    const bool a2s = sweep_active(d.ctl, it + 1, acc2);
+    if (!a1s && d.ctl->done) return;
+    // The member's control decisions and descriptor are block-uniform:
+    // copied through scalar registers, so that the march's plane loop and
+    // the sweep's buffer offsets stay scalar (read from memory the compiler
+    // cannot prove unchanged, they would turn per-lane).
+    const int flags = __builtin_amdgcn_readfirstlane((a1s ? 1 : 0) | (a2s ? 2 : 0) | (acc1 ? 4 : 0) | (acc2 ? 8 : 0));
+    const bool act1 = flags & 1, act2 = flags & 2;
+    const bool p1 = act1 && (flags & 4) && !act2, p2 = act1 && act2 && (flags & 8);
+    struct Args {
+        Geo g;
+        const float* a0;
+        const float* a1;
+        float* b0;
+        float* b1;
+        const float* r0;
+        const float* r1;
+        double* rel0;
+        double* rel1;
+        float omega;
+        int kt;
+        unsigned lb;
+        unsigned pad;
+    } raw;
+    raw.g = d.g;
+    raw.a0 = parity ? d.P.pa[0] : d.P.pd[0];
+    raw.a1 = parity ? d.P.pa[1] : d.P.pd[1];
+    raw.b0 = parity ? d.P.pd[0] : d.P.pa[0];
+    raw.b1 = parity ? d.P.pd[1] : d.P.pa[1];
+    raw.r0 = d.P.r0[0];
+    raw.r1 = d.P.r0[1];
+    raw.rel0 = d.rel0;
+    raw.rel1 = d.rel1;
+    raw.omega = d.omega;
+    raw.kt = d.kt_rb2;
+    raw.lb = L - O->sweep[q];
+    raw.pad = 0;
+    const Args A = uniform_copy(raw);
+    __shared__ Rb2Smem sm;
+    if (!act1)
+        sor_rb2_copy_u(A.g, A.a0, A.a1, A.b0, A.b1, A.lb, A.kt);
+    else if (p1 || p2)
+        sor_rb2_body_u<true>(sm, A.g, A.a0, A.a1, A.r0, A.r1, A.b0, A.b1, A.omega, act2, p1, p2, A.rel0, A.rel1,
+                             A.lb, A.kt);
+    else
+        sor_rb2_body_u<false>(sm, A.g, A.a0, A.a1, A.r0, A.r1, A.b0, A.b1, A.omega, act2, false, false, A.rel0,
+                              A.rel1, A.lb, A.kt);
 }
 
 // Launch of k_ens_sweep_rb for fused variant v over `grid` blocks.
@@ -488,11 +555,19 @@ __global__ __launch_bounds__(kBlock) void k_zero(float* p, long long n) {
 }
 
 // 1 when every member is done (read by the host one batch behind).
-__global__ void k_ens_all_done(const EnsInst* __restrict__ I, int n, int* flag) {
+// flag: every member's solve has stopped; mask: bit q set when member q's has
+__global__ void k_ens_all_done(const EnsInst* __restrict__ I, int n, int* flag,
+                               unsigned long long* mask) {
     if (threadIdx.x != 0) return;
     int all = 1;
-    for (int q = 0; q < n; ++q) all &= (I[q].ctl->done != 0) ? 1 : 0;
+    unsigned long long m = 0;
+    for (int q = 0; q < n; ++q) {
+        const bool d = I[q].ctl->done != 0;
+        all &= d ? 1 : 0;
+        if (d) m |= 1ull << q;
+    }
     *flag = all;
+    *mask = m;
 }
 
 }  // namespace
@@ -521,6 +596,15 @@ struct les_ensemble {
     unsigned char* d_owner = nullptr;   // sweep block -> member (batched mode)
     int* d_flag = nullptr;
     int* h_flag = nullptr;              // pinned, 2 slots
+    unsigned long long* d_mask = nullptr;   // members whose solve has stopped, 2 slots
+    unsigned long long* h_mask = nullptr;   // pinned
+    // sweep work list over the members still iterating (batched mode):
+    // device copies and two pinned staging copies used in turn
+    unsigned char* d_owner_live = nullptr;
+    EnsOffsets* d_off_live = nullptr;
+    unsigned char* h_owner_live[2] = {nullptr, nullptr};
+    EnsOffsets* h_off_live[2] = {nullptr, nullptr};
+    unsigned owner_live_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipGraphExec_t chunk_graph = nullptr;
     int chunk_graph_checks = 0;
@@ -555,19 +639,24 @@ unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // Fused iterations run only when the ensemble itself chose one (every
 // member then runs it: one launch shape), in the batched mode and with an
-// even check interval.
+// even check interval; two iterations per launch need a check interval
+// that is a multiple of 4 and every member on the lean uniform-grid form.
 bool ens_fused(const les_ensemble* e) {
-    return e->variant >= 0 && sor_fused(e->variant) && !sor_fused2(e->variant) &&
-           e->mode == LES_ENSEMBLE_BATCHED && !(e->K & 1);
+    if (e->variant < 0 || !sor_fused(e->variant) || e->mode != LES_ENSEMBLE_BATCHED) return false;
+    if (!sor_fused2(e->variant)) return !(e->K & 1);
+    if (e->K & 3) return false;
+    for (int q = 0; q < e->n; ++q)
+        if (e->members[q]->g.stretched || !rb_lean_fits(e->members[q]->g)) return false;
+    return true;
 }
+bool ens_fused2(const les_ensemble* e) { return ens_fused(e) && sor_fused2(e->variant); }
 
 // The sweep variant a member runs in the ensemble: the ensemble's choice,
 // else the member's own; a fused variant where the ensemble cannot run it
 // becomes the grid's default half-sweep.
 int ens_variant(const les_ensemble* e, const les_handle* h) {
     const int v = e->variant >= 0 ? e->variant : h->sor_variant;
-    // (the two-iteration variants are single-handle only)
-    return (sor_fused(v) && (!ens_fused(e) || sor_fused2(v))) ? sor_default_variant(h->g) : v;
+    return (sor_fused(v) && !ens_fused(e)) ? sor_default_variant(h->g) : v;
 }
 
 // Host copies of the member descriptors and work-list offsets, from the
@@ -620,6 +709,7 @@ void build_descriptors(les_ensemble* e) {
         d.singular = h->g.outflow ? 0 : 1;
         d.inflow = h->g.inflow;
         d.nsweep = sor_sweep_blocks(h->g, d.variant);
+        d.kt_rb2 = sor_fused2(d.variant) ? rb2_kt(h->g, kSorVariants[d.variant].kt) : 0;
         d.nred = red_blocks(h->g);
         max_iter_all = std::max(max_iter_all, h->prm.max_iter);
         d.kt_tile = tile_kt(h->g);
@@ -686,17 +776,25 @@ int upload_owner_map(les_ensemble* e) {
 
 // One check interval of every member: 2K half-sweeps, the residual bound,
 // the fold of members due for a rebase, the check (or rebase), the decision.
-int enqueue_chunk(les_ensemble* e, hipStream_t s) {
+// The sweeps run over the work list (owner, off: sweep offsets, grid blocks).
+int enqueue_chunk(les_ensemble* e, hipStream_t s, const unsigned char* owner, const EnsOffsets* off,
+                  unsigned grid) {
     const int n = e->n;
     const EnsOffsets& o = e->h_off;
-    if (ens_fused(e)) {
-        for (int it = 0; it < e->K; ++it)
-            launch_ens_sweep_rb(e->variant, o.sweep[n], s, e->d_inst, e->d_owner, e->d_off, it & 1, it);
-    } else {
-        for (int it = 0; it < e->K; ++it)
-            for (int c = 0; c < 2; ++c)
-                hipLaunchKernelGGL(k_ens_sweep, dim3(o.sweep[n]), dim3(kBlock), 0, s, e->d_inst,
-                                   e->d_owner, e->d_off, c, it);
+    if (grid > 0) {
+        if (ens_fused2(e)) {   // K/2 launches, an even number: the interval ends on pd
+            for (int it = 0; it < e->K; it += 2)
+                hipLaunchKernelGGL(k_ens_sweep_rb2, dim3(grid), dim3(1024), 0, s, e->d_inst, owner, off,
+                                   (it >> 1) & 1, it);
+        } else if (ens_fused(e)) {
+            for (int it = 0; it < e->K; ++it)
+                launch_ens_sweep_rb(e->variant, grid, s, e->d_inst, owner, off, it & 1, it);
+        } else {
+            for (int it = 0; it < e->K; ++it)
+                for (int c = 0; c < 2; ++c)
+                    hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, s, e->d_inst, owner, off, c,
+                                       it);
+        }
     }
     hipLaunchKernelGGL(k_ens_bound, dim3(n), dim3(kBlock), 0, s, e->d_inst);
     hipLaunchKernelGGL(k_ens_fold, dim3(std::min(o.fold[n], kAuxBlocks)), dim3(kBlock), 0, s,
@@ -718,35 +816,112 @@ int run_batched_solve(les_ensemble* e, hipStream_t s) {
                        e->d_inst, n, e->d_off, 1);
     hipLaunchKernelGGL(k_ens_fin_check, dim3(n), dim3(kBlock), 0, s, e->d_inst, 1);
     ECK(hipGetLastError());
-    if (!e->chunk_graph) {
+    // kGraphChecks intervals captured over a sweep work list
+    auto capture = [&](const unsigned char* owner, const EnsOffsets* off, unsigned grid,
+                       hipGraphExec_t* ex) -> int {
         hipGraph_t gph = nullptr;
         ECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = LES_OK;
-        for (int q = 0; q < kGraphChecks && rc == LES_OK; ++q) rc = enqueue_chunk(e, s);
+        for (int q = 0; q < kGraphChecks && rc == LES_OK; ++q) rc = enqueue_chunk(e, s, owner, off, grid);
         hipError_t ce = hipStreamEndCapture(s, &gph);
         if (rc != LES_OK) return rc;
         ECK(ce);
-        ECK(hipGraphInstantiate(&e->chunk_graph, gph, nullptr, nullptr, 0));
-        ECK(hipGraphDestroy(gph));
+        const hipError_t ie = hipGraphInstantiate(ex, gph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gph);
+        ECK(ie);
+        return LES_OK;
+    };
+    if (!e->chunk_graph) {
+        const int rc = capture(e->d_owner, e->d_off, o.sweep[n], &e->chunk_graph);
+        if (rc != LES_OK) return rc;
         e->chunk_graph_checks = kGraphChecks;
     }
+    if (o.sweep[n] > e->owner_live_cap) {
+        ECK(hipStreamSynchronize(s));
+        if (e->d_owner_live) ECK(hipFree(e->d_owner_live));
+        e->d_owner_live = nullptr;
+        for (int k = 0; k < 2; ++k) {
+            if (e->h_owner_live[k]) ECK(hipHostFree(e->h_owner_live[k]));
+            e->h_owner_live[k] = nullptr;
+        }
+        ECK(hipMalloc(&e->d_owner_live, o.sweep[n]));
+        for (int k = 0; k < 2; ++k) ECK(hipHostMalloc((void**)&e->h_owner_live[k], o.sweep[n], hipHostMallocDefault));
+        e->owner_live_cap = o.sweep[n];
+    }
+    // Once members stop, the following batches sweep only the members still
+    // iterating (the stopped ones' blocks would only return at once, but a
+    // launch still dispatches them): the work list is rebuilt from the
+    // done-mask one batch behind and a graph captured over it.  Staging copy
+    // k % 2 is rewritten two rebuilds later, after an event recorded behind
+    // its upload has been waited on; the device copy is rewritten behind the
+    // launches that read it.
+    std::vector<hipGraphExec_t> live_graphs;
+    auto drop_live_graphs = [&]() {
+        if (live_graphs.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (hipGraphExec_t g : live_graphs) (void)hipGraphExecDestroy(g);
+        live_graphs.clear();
+    };
+    const unsigned long long all_members = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    unsigned long long listed = all_members;
+    hipGraphExec_t cur = e->chunk_graph;
+    int rebuilds = 0;
     const long long n_batches = (e->max_checks + kGraphChecks - 1) / kGraphChecks;
     int slot = 0;
     bool pending = false;
-    for (long long b = 0; b < n_batches; ++b) {
-        ECK(hipGraphLaunch(e->chunk_graph, s));
-        hipLaunchKernelGGL(k_ens_all_done, dim3(1), dim3(64), 0, s, e->d_inst, n, e->d_flag + slot);
-        ECK(hipGetLastError());
-        ECK(hipMemcpyAsync(&e->h_flag[slot], e->d_flag + slot, sizeof(int), hipMemcpyDeviceToHost, s));
-        ECK(hipEventRecord(e->ev[slot], s));
+    int rc = LES_OK;
+    for (long long b = 0; b < n_batches && rc == LES_OK; ++b) {
+        hipError_t he = hipGraphLaunch(cur, s);
+        if (he == hipSuccess) {
+            hipLaunchKernelGGL(k_ens_all_done, dim3(1), dim3(64), 0, s, e->d_inst, n, e->d_flag + slot,
+                               e->d_mask + slot);
+            he = hipGetLastError();
+        }
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(&e->h_flag[slot], e->d_flag + slot, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(&e->h_mask[slot], e->d_mask + slot, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess) he = hipEventRecord(e->ev[slot], s);
+        if (he == hipSuccess && pending) he = hipEventSynchronize(e->ev[1 - slot]);
+        if (he != hipSuccess) {
+            rc = ens_err(e, LES_EDEVICE, "batched solve launch", he);
+            break;
+        }
         if (pending) {
-            ECK(hipEventSynchronize(e->ev[1 - slot]));
             if (e->h_flag[1 - slot]) break;
+            const unsigned long long live = all_members & ~e->h_mask[1 - slot];
+            if (live != listed) {
+                const int k = rebuilds++ & 1;
+                EnsOffsets& lo = *e->h_off_live[k];
+                std::memset(&lo, 0, sizeof lo);
+                for (int q = 0; q < n; ++q) {
+                    const unsigned nb = ((live >> q) & 1) ? e->h_inst[q].nsweep : 0u;
+                    lo.sweep[q + 1] = lo.sweep[q] + nb;
+                    for (unsigned L = 0; L < nb; ++L) e->h_owner_live[k][lo.sweep[q] + L] = (unsigned char)q;
+                }
+                // offsets relative to the live list: a member's blocks keep
+                // their indices within the member (L - sweep[q])
+                he = hipMemcpyAsync(e->d_off_live, &lo, sizeof lo, hipMemcpyHostToDevice, s);
+                if (he == hipSuccess && lo.sweep[n] > 0)
+                    he = hipMemcpyAsync(e->d_owner_live, e->h_owner_live[k], lo.sweep[n], hipMemcpyHostToDevice, s);
+                if (he != hipSuccess) {
+                    rc = ens_err(e, LES_EDEVICE, "live work list upload", he);
+                    break;
+                }
+                hipGraphExec_t ex = nullptr;
+                rc = capture(e->d_owner_live, e->d_off_live, lo.sweep[n], &ex);
+                if (rc != LES_OK) break;
+                live_graphs.push_back(ex);
+                cur = ex;
+                listed = live;
+            }
         }
         pending = true;
         slot = 1 - slot;
     }
-    return LES_OK;
+    drop_live_graphs();
+    return rc;
 }
 
 int launch_solve(les_ensemble* e, hipStream_t s) {
@@ -810,6 +985,13 @@ int les_ensemble_create(int32_t n, les_handle* const* members, les_ensemble** ou
     if (hipMalloc(&e->d_flag, 2 * sizeof(int)) != hipSuccess) return fail(LES_ENOMEM);
     if (hipHostMalloc((void**)&e->h_flag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(LES_ENOMEM);
+    if (hipMalloc(&e->d_mask, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(LES_ENOMEM);
+    if (hipHostMalloc((void**)&e->h_mask, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+        return fail(LES_ENOMEM);
+    if (hipMalloc(&e->d_off_live, sizeof(EnsOffsets)) != hipSuccess) return fail(LES_ENOMEM);
+    for (int k = 0; k < 2; ++k)
+        if (hipHostMalloc((void**)&e->h_off_live[k], sizeof(EnsOffsets), hipHostMallocDefault) != hipSuccess)
+            return fail(LES_ENOMEM);
     for (int q = 0; q < 2; ++q)
         if (hipEventCreateWithFlags(&e->ev[q], hipEventDisableTiming) != hipSuccess) return fail(LES_EDEVICE);
     if (upload_owner_map(e) != LES_OK) return fail(LES_EDEVICE);
@@ -828,6 +1010,14 @@ void les_ensemble_destroy(les_ensemble* e) {
     if (e->d_owner) (void)hipFree(e->d_owner);
     if (e->d_flag) (void)hipFree(e->d_flag);
     if (e->h_flag) (void)hipHostFree(e->h_flag);
+    if (e->d_mask) (void)hipFree(e->d_mask);
+    if (e->h_mask) (void)hipHostFree(e->h_mask);
+    if (e->d_owner_live) (void)hipFree(e->d_owner_live);
+    if (e->d_off_live) (void)hipFree(e->d_off_live);
+    for (int k = 0; k < 2; ++k) {
+        if (e->h_owner_live[k]) (void)hipHostFree(e->h_owner_live[k]);
+        if (e->h_off_live[k]) (void)hipHostFree(e->h_off_live[k]);
+    }
     for (int q = 0; q < 2; ++q)
         if (e->ev[q]) (void)hipEventDestroy(e->ev[q]);
     if (e->d_inst) (void)hipFree(e->d_inst);
@@ -849,7 +1039,7 @@ int les_ensemble_set_mode(les_ensemble* e, int32_t mode) {
 }
 
 int les_ensemble_set_variant(les_ensemble* e, int32_t variant) {
-    if (!e || variant < -1 || variant >= kFirstRb2Variant) return LES_EINVAL;
+    if (!e || variant < -1 || variant >= kNumSorVariants) return LES_EINVAL;
     e->variant = variant;
     e->descriptors_dirty = true;
     return LES_OK;
@@ -878,9 +1068,9 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
     const int saved = e->variant;
     for (int v = 0; v < kNumSorVariants; ++v) {
         e->variant = v;
-        // persistent mode or an odd check interval; two iterations per
-        // launch are single-handle only
-        if (sor_fused2(v) || (sor_fused(v) && !ens_fused(e))) {
+        // persistent mode, an odd check interval (two iterations per
+        // launch: not a multiple of 4, or a member off the lean form)
+        if (sor_fused(v) && !ens_fused(e)) {
             e->tune_us[v] = 0.0;
             continue;
         }
@@ -893,11 +1083,15 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
         for (int q = 0; q < n; ++q)
             hipLaunchKernelGGL(k_ctl_probe_init, dim3(1), dim3(64), 0, e->stream, e->h_inst[q].ctl);
         const unsigned grid = e->h_off.sweep[n];
-        // two launches: two half-sweeps, or two fused iterations (half a
-        // fused iteration is charged per half-sweep below)
+        // two launches: two half-sweeps, two fused iterations or four (a
+        // quarter of a two-iteration launch, half a fused iteration, is
+        // charged per half-sweep below)
         auto pair = [&]() {
             for (int w = 0; w < 2; ++w) {
-                if (sor_fused(v))
+                if (sor_fused2(v))
+                    hipLaunchKernelGGL(k_ens_sweep_rb2, dim3(grid), dim3(1024), 0, e->stream, e->d_inst,
+                                       e->d_owner, e->d_off, w, 0);
+                else if (sor_fused(v))
                     launch_ens_sweep_rb(v, grid, e->stream, e->d_inst, e->d_owner, e->d_off, w, 0);
                 else
                     hipLaunchKernelGGL(k_ens_sweep, dim3(grid), dim3(kBlock), 0, e->stream, e->d_inst,
@@ -911,7 +1105,7 @@ int les_ensemble_autotune(les_ensemble* e, int32_t reps) {
         ECK(hipEventSynchronize(b));
         float ms = 0.f;
         ECK(hipEventElapsedTime(&ms, a, b));
-        const double us = 1e3 * ms / ((sor_fused(v) ? 4.0 : 2.0) * reps);
+        const double us = 1e3 * ms / ((sor_fused2(v) ? 8.0 : (sor_fused(v) ? 4.0 : 2.0)) * reps);
         e->tune_us[v] = us;
         if (us < best) {
             best = us;

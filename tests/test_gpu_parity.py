@@ -476,14 +476,14 @@ def _member(nx, ny, nz, seed, alpha_pl=None, **kw):
     return mask, prof
 
 
-@pytest.mark.parametrize("variant", [-1, 8, 9, 10])
+@pytest.mark.parametrize("variant", [-1, 8, 9, 10, 12, 13])
 @pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
 def test_ensemble_bitwise_equals_single_steps(mode, variant):
     """An ensemble step of uneven members equals stepping each member alone
     (same per-cell arithmetic, same per-member stopping decisions), in both
-    solve modes, on the members' own half-sweeps and on a fused variant
-    chosen for the whole ensemble (the persistent mode falls back to
-    half-sweeps there)."""
+    solve modes, on the members' own half-sweeps and on a fused or
+    two-iteration variant chosen for the whole ensemble (the persistent mode
+    falls back to half-sweeps there)."""
     shapes = [(24, 20, 12), (33, 17, 9), (40, 24, 16), (17, 31, 10)]
     ins = [_member(*s, seed=50 + q, alpha_pl=(0.1 + 0.05 * q) if q % 2 else None)
            for q, s in enumerate(shapes)]
@@ -512,6 +512,31 @@ def test_ensemble_bitwise_equals_single_steps(mode, variant):
         singles[q].step(1)
         for x, y in zip(ens_members[q].get_fields(), singles[q].get_fields()):
             assert np.array_equal(x, y)
+    ens.close()
+
+
+def test_ensemble_two_iteration_variant_needs_interval_multiple_of_4():
+    """With a check interval of 6 the ensemble cannot run two iterations
+    per launch: its members fall back to their grids' half-sweeps, and the
+    results still equal stepping each member alone."""
+    shapes = [(24, 20, 12), (17, 31, 10)]
+    ins = [_member(*s, seed=60 + q) for q, s in enumerate(shapes)]
+    ens_members, singles = [], []
+    for (nx, ny, nz), (mask, prof), q in zip(shapes, ins, range(len(shapes))):
+        a = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask, check_every=6)
+        b = les.LES(nx, ny, nz, 4.0, 4.0, 2.0, 0.05, mask, check_every=6)
+        for x in (a, b):
+            x.set_inflow(prof, 0.01, 80 + q)
+        ens_members.append(a)
+        singles.append(b)
+    ens = les.Ensemble(ens_members)
+    ens.set_variant(12)
+    rc, st, iters = ens.step(2)
+    for q, b in enumerate(singles):
+        _, _, it_b = b.step(2)
+        assert list(iters[:, q]) == list(it_b), q
+        for x, y in zip(ens_members[q].get_fields(), b.get_fields()):
+            assert np.array_equal(x, y), q
     ens.close()
 
 
@@ -572,7 +597,7 @@ def _ensemble_vs_oracle(specs, mode, variant, steps, max_iter):
             g.close()
 
 
-@pytest.mark.parametrize("variant", [-1, 9])
+@pytest.mark.parametrize("variant", [-1, 9, 12])
 @pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
 def test_ensemble_matches_oracle(mode, variant):
     """Uneven small members (the shapes of the bitwise test), two steps."""
@@ -585,19 +610,21 @@ def test_ensemble_matches_oracle(mode, variant):
     _ensemble_vs_oracle(specs, mode, variant, steps=2, max_iter=20000)
 
 
-@pytest.mark.parametrize("mode", [les.ENSEMBLE_BATCHED, les.ENSEMBLE_PERSISTENT])
-def test_ensemble_benchmark_size_members_match_oracle(mode):
+@pytest.mark.parametrize("mode,variant", [(les.ENSEMBLE_BATCHED, 9), (les.ENSEMBLE_BATCHED, 12),
+                                          (les.ENSEMBLE_PERSISTENT, -1)])
+def test_ensemble_benchmark_size_members_match_oracle(mode, variant):
     """Two members drawn from the benchmark's uneven ensemble (96-256 cells
-    horizontally, 64-90 vertically), on the fused sweeps for the batched
-    mode, one step with the solve capped at 200 iterations."""
+    horizontally, 64-90 vertically), on the fused or two-iteration sweeps
+    for the batched mode, one step with the solve capped at 200
+    iterations."""
     from les_inputs import ensemble_members
     specs = []
     for w in ensemble_members(2):
         mask, prof = make_workload_inputs(w)
         specs.append((w.nx, w.ny, w.nz, mask, prof, w.seed))
-    print(f"[ensemble benchmark members vs oracle] mode={mode} "
+    print(f"[ensemble benchmark members vs oracle] mode={mode} variant={variant} "
           f"{[(s[0], s[1], s[2]) for s in specs]}", flush=True)
-    _ensemble_vs_oracle(specs, mode, 9 if mode == les.ENSEMBLE_BATCHED else -1, steps=1, max_iter=200)
+    _ensemble_vs_oracle(specs, mode, variant, steps=1, max_iter=200)
 
 
 def test_full_step_C2_fields_match_oracle():

@@ -605,6 +605,12 @@ struct les_ensemble {
     unsigned char* h_owner_live[2] = {nullptr, nullptr};
     EnsOffsets* h_off_live[2] = {nullptr, nullptr};
     unsigned owner_live_cap = 0;
+    // two-iteration sweeps: planes per block and blocks of each member with
+    // every member iterating (restored at the start of a solve after the
+    // live work list changed them)
+    std::vector<int> base_kt;
+    std::vector<unsigned> base_nsweep;
+    bool kt_changed = false;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipGraphExec_t chunk_graph = nullptr;
     int chunk_graph_checks = 0;
@@ -650,6 +656,16 @@ bool ens_fused(const les_ensemble* e) {
     return true;
 }
 bool ens_fused2(const les_ensemble* e) { return ens_fused(e) && sor_fused2(e->variant); }
+
+// Planes per block of member h's two-iteration sweep (variant v) when n_live
+// members share the chip: the plane count for its share of the resident
+// blocks, never below the one for the grid alone (so its block count never
+// exceeds the variant's, for which its partial sums are sized).
+int ens_rb2_kt(const les_handle* h, int v, int n_live) {
+    const int per_cu = kSorVariants[v].kt;
+    const long long slots = std::max<long long>(1, 256LL * per_cu / std::max(1, n_live));
+    return std::max(rb2_kt(h->g, per_cu), rb2_kt_slots(h->g, slots));
+}
 
 // The sweep variant a member runs in the ensemble: the ensemble's choice,
 // else the member's own; a fused variant where the ensemble cannot run it
@@ -709,7 +725,11 @@ void build_descriptors(les_ensemble* e) {
         d.singular = h->g.outflow ? 0 : 1;
         d.inflow = h->g.inflow;
         d.nsweep = sor_sweep_blocks(h->g, d.variant);
-        d.kt_rb2 = sor_fused2(d.variant) ? rb2_kt(h->g, kSorVariants[d.variant].kt) : 0;
+        d.kt_rb2 = 0;
+        if (sor_fused2(d.variant)) {   // the ensemble's choice: the chip shared by all members
+            d.kt_rb2 = ens_rb2_kt(h, d.variant, n);
+            d.nsweep = rb2_blocks(h->g, d.kt_rb2);
+        }
         d.nred = red_blocks(h->g);
         max_iter_all = std::max(max_iter_all, h->prm.max_iter);
         d.kt_tile = tile_kt(h->g);
@@ -724,6 +744,13 @@ void build_descriptors(les_ensemble* e) {
         e->cells_total += (int64_t)h->g.nx * h->g.ny * h->g.nz;
     }
     e->max_checks = (max_iter_all + e->K - 1) / e->K;
+    e->base_kt.resize(n);
+    e->base_nsweep.resize(n);
+    for (int q = 0; q < n; ++q) {
+        e->base_kt[q] = e->h_inst[q].kt_rb2;
+        e->base_nsweep[q] = e->h_inst[q].nsweep;
+    }
+    e->kt_changed = false;
 }
 
 // The stage sequence before the solve (nu_t .. rhs, mean removal) and the
@@ -836,7 +863,24 @@ int run_batched_solve(les_ensemble* e, hipStream_t s) {
         if (rc != LES_OK) return rc;
         e->chunk_graph_checks = kGraphChecks;
     }
-    if (o.sweep[n] > e->owner_live_cap) {
+    // the live work list never holds more blocks than every member alone on
+    // its variant (two-iteration plane counts only grow as members share)
+    unsigned live_cap = o.sweep[n];
+    if (ens_fused2(e)) {
+        live_cap = 0;
+        for (int q = 0; q < n; ++q) live_cap += sor_sweep_blocks(e->members[q]->g, e->variant);
+        live_cap = std::max(live_cap, o.sweep[n]);
+    }
+    if (e->kt_changed) {   // the previous solve's live list changed plane counts
+        for (int q = 0; q < n; ++q) {
+            e->h_inst[q].kt_rb2 = e->base_kt[q];
+            e->h_inst[q].nsweep = e->base_nsweep[q];
+        }
+        ECK(hipMemcpyAsync(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice, s));
+        ECK(hipStreamSynchronize(s));   // the host copy is rewritten below
+        e->kt_changed = false;
+    }
+    if (live_cap > e->owner_live_cap) {
         ECK(hipStreamSynchronize(s));
         if (e->d_owner_live) ECK(hipFree(e->d_owner_live));
         e->d_owner_live = nullptr;
@@ -844,9 +888,9 @@ int run_batched_solve(les_ensemble* e, hipStream_t s) {
             if (e->h_owner_live[k]) ECK(hipHostFree(e->h_owner_live[k]));
             e->h_owner_live[k] = nullptr;
         }
-        ECK(hipMalloc(&e->d_owner_live, o.sweep[n]));
-        for (int k = 0; k < 2; ++k) ECK(hipHostMalloc((void**)&e->h_owner_live[k], o.sweep[n], hipHostMallocDefault));
-        e->owner_live_cap = o.sweep[n];
+        ECK(hipMalloc(&e->d_owner_live, live_cap));
+        for (int k = 0; k < 2; ++k) ECK(hipHostMalloc((void**)&e->h_owner_live[k], live_cap, hipHostMallocDefault));
+        e->owner_live_cap = live_cap;
     }
     // Once members stop, the following batches sweep only the members still
     // iterating (the stopped ones' blocks would only return at once, but a
@@ -892,6 +936,32 @@ int run_batched_solve(les_ensemble* e, hipStream_t s) {
             if (e->h_flag[1 - slot]) break;
             const unsigned long long live = all_members & ~e->h_mask[1 - slot];
             if (live != listed) {
+                // two-iteration sweeps: the live members' plane counts for
+                // their larger share of the chip (the member descriptors are
+                // rewritten behind the running batch; a blocking copy, so the
+                // host copy may change afterwards)
+                if (ens_fused2(e)) {
+                    const int n_live = __builtin_popcountll(live);
+                    bool upd = false;
+                    for (int q = 0; q < n; ++q) {
+                        if (!((live >> q) & 1)) continue;
+                        const int kt = ens_rb2_kt(e->members[q], e->variant, n_live);
+                        if (kt != e->h_inst[q].kt_rb2) {
+                            e->h_inst[q].kt_rb2 = kt;
+                            e->h_inst[q].nsweep = rb2_blocks(e->members[q]->g, kt);
+                            upd = true;
+                        }
+                    }
+                    if (upd) {
+                        he = hipMemcpyAsync(e->d_inst, e->h_inst.data(), sizeof(EnsInst) * n, hipMemcpyHostToDevice, s);
+                        if (he == hipSuccess) he = hipStreamSynchronize(s);
+                        if (he != hipSuccess) {
+                            rc = ens_err(e, LES_EDEVICE, "member descriptor upload", he);
+                            break;
+                        }
+                        e->kt_changed = true;
+                    }
+                }
                 const int k = rebuilds++ & 1;
                 EnsOffsets& lo = *e->h_off_live[k];
                 std::memset(&lo, 0, sizeof lo);

@@ -331,12 +331,12 @@ __host__ __device__ inline bool rb_lean_fits(const Geo& g) {
 }
 
 // Planes per block of a two-iteration launch: the block marches kt + 6
-// planes, and with `per_cu` resident blocks per compute unit the launch
-// takes about ceil(blocks / (256 per_cu)) such marches; the kt that
-// minimises that product.
-inline int rb2_kt(const Geo& g, int per_cu) {
+// planes, and with `slots` blocks resident at once (256 per_cu for a grid
+// alone on the chip, per_cu resident blocks per compute unit) the launch
+// takes about ceil(blocks / slots) such marches; the kt that minimises that
+// product.
+inline int rb2_kt_slots(const Geo& g, long long slots) {
     const long long nxy = (long long)((g.H + kRb2TXO - 1) / kRb2TXO) * ((g.ny + kRb2TYO - 1) / kRb2TYO);
-    const long long slots = 256LL * per_cu;
     int best = 4;
     long long best_cost = -1;
     for (int kt = 4; kt <= 96; ++kt) {
@@ -348,6 +348,12 @@ inline int rb2_kt(const Geo& g, int per_cu) {
         }
     }
     return best;
+}
+inline int rb2_kt(const Geo& g, int per_cu) { return rb2_kt_slots(g, 256LL * per_cu); }
+// blocks of a two-iteration launch with kt planes per block
+inline unsigned rb2_blocks(const Geo& g, int kt) {
+    return (unsigned)((g.H + kRb2TXO - 1) / kRb2TXO) * (unsigned)((g.ny + kRb2TYO - 1) / kRb2TYO) *
+           (unsigned)((g.nz + kt - 1) / kt);
 }
 int sor_default_variant(const Geo& g);
 // sweep blocks per launch: per half-sweep, or per iteration when fused

@@ -441,9 +441,11 @@ const char* les_ensemble_last_error(const les_ensemble* e);
 void les_ensemble_destroy(les_ensemble* e);
 
 /* How the members' pressure solves run (same arithmetic, same results):
- * LES_ENSEMBLE_BATCHED (default): one launch per half-sweep (and per check
- * phase) over all members' work, check intervals replayed from a HIP graph
- * in batches of 8, per-member stop flags on the device.
+ * LES_ENSEMBLE_BATCHED (default): one launch per half-sweep, fused iteration
+ * or two fused iterations (and per check phase) over all members' work,
+ * check intervals replayed from a HIP graph in batches of 8, per-member stop
+ * flags on the device; once members have stopped (seen one batch behind)
+ * the sweep launches cover only the members still iterating.
  * LES_ENSEMBLE_PERSISTENT: the whole solve of all members in one
  * cooperative launch with grid barriers between phases. */
 enum { LES_ENSEMBLE_BATCHED = 0, LES_ENSEMBLE_PERSISTENT = 1 };

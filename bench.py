@@ -544,7 +544,7 @@ def main():
                          "(C1 size; with --workload C3, trained on crops of 1024x1024x96 runs)")
     ap.add_argument("--twinned", action="store_true",
                     help="compare twinned double buffering with red-black SOR (JSON line of its own)")
-    ap.add_argument("--check-every", type=int, default=16, metavar="K",
+    ap.add_argument("--check-every", type=int, default=64, metavar="K",
                     help="residual check interval of the timed solves (fused sweeps need an even K, "
                          "the two-iteration form a multiple of 4)")
     ap.add_argument("--omega", type=float, default=1.8,

@@ -394,14 +394,19 @@ int run_solve(les_handle* h, const PBufs& P, double tol, int max_iter, les_solve
     const long long n_checks = max_iter > 0 ? ((long long)max_iter + K - 1) / K : 0;
     long long c = 0;
     // batches of 2, 2, 4 intervals (a solve that converges at once is
-    // noticed early), then 8, 16, 32, 64: from interval 8 on every batch
-    // starts on a multiple of kSolveGraphChecks
+    // noticed early), then 8, 16, 32, 64 (capped below): from interval 8 on
+    // every batch starts on a multiple of kSolveGraphChecks
     static const int kBatches[] = {2, 2, 4, 8, 16, 32, 64};
+    // a batch spans at most ~1024 iterations (a multiple of the graph's
+    // intervals): after convergence the launches still queued return at
+    // once but each still costs a dispatch, and at most about two batches
+    // are queued when the host sees the flag
+    const int batch_cap = std::max(kSolveGraphChecks, (1024 / std::max(K, 1)) / kSolveGraphChecks * kSolveGraphChecks);
     int bi = 0;
     int slot = 0;
     bool pending = false;
     while (c < n_checks) {
-        const long long nb = std::min<long long>(kBatches[bi], n_checks - c);
+        const long long nb = std::min<long long>(std::min(kBatches[bi], batch_cap), n_checks - c);
         long long q = 0;
         while (q < nb) {
             const long long c0 = c + q;   // intervals c0+1, ...
